@@ -1,0 +1,166 @@
+"""The method, step by step in FP64: shifted randomized T-HOSVD / ST-HOSVD.
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Follows, in the paper's order and notation:
+  * Algorithm 1 (deterministic T-HOSVD / ST-HOSVD): ``hosvd_full``.
+  * Algorithm 2 (shifted randomized T-HOSVD) and Algorithm 3 (shifted
+    randomized ST-HOSVD): ``randomized_hosvd`` with variant "t" / "st" and
+    shift "adaptive".
+  * Appendix Algorithm A.1 (the unshifted randomized model): the same routine
+    with shift "none" (alpha stays 0).
+
+Per mode k, on X = A (variant t) or X = the partially contracted core
+(variant st, dims r_1..r_{k-1}, n_k..n_d):
+  l_k   = min(r_k + p, n_k, m_k)             (oversampling p; clamp, see below)
+  Y     = X_(k) Omega_k ;  [Q, Sigma] = svd(Y, econ) ;  alpha_0 = 0
+  for t = 1..q:
+      M = X_(k) (X_(k)^T Q) - alpha_{t-1} Q ; [Q, Sigma] = svd(M, econ)
+      if Sigma(l_k, l_k) > alpha_{t-1}: alpha_t = (Sigma(l_k, l_k) + alpha_{t-1}) / 2
+      else alpha_t = alpha_{t-1}
+  U_k = Q(:, 1:r_k) ;  G <- G x_k U_k^T
+
+Readings where the paper is silent or loose (each also listed in the design doc):
+  * Algorithm 3 writes the shift in the power step without its subscript; it
+    is alpha_{t-1}, as in Algorithm 2.
+  * The else-branch of the shift update is not written: alpha_t = alpha_{t-1}.
+  * Sigma(l, l) is the l-th (smallest) singular value of the shifted iterate M.
+  * q = 0 is allowed (no power step; U_k from svd(X_(k) Omega_k)).
+  * l_k is clamped to min(r_k + p, n_k, m_k): the paper assumes l_k below both.
+  * svd returns singular values in descending order; U_k's column signs are
+    fixed by ``sign_fix`` (largest-magnitude entry of each column positive,
+    ties to the lowest row index).
+  * Processing order (1, ..., d), as in the paper's experiments.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+from .philox import gaussian_omega
+from .tensor import frob2, mode_product, reconstruct, unfold
+
+
+def svd_econ(y: np.ndarray):
+    """[Q, Sigma, ~] = svd(Y, 'econ'), descending Sigma (LAPACK)."""
+    q, s, _ = np.linalg.svd(y, full_matrices=False)
+    return q, s
+
+
+def sign_fix(u: np.ndarray) -> np.ndarray:
+    """Flip columns so each column's largest-|.| entry is positive (first on ties)."""
+    u = np.array(u, dtype=np.float64, copy=True)
+    if u.size == 0:
+        return u
+    idx = np.argmax(np.abs(u), axis=0)
+    s = np.sign(u[idx, np.arange(u.shape[1])])
+    s[s == 0] = 1.0
+    return u * s[None, :]
+
+
+def sketch_width(r: int, p: int, n: int, m: int) -> int:
+    return int(min(r + p, n, m))
+
+
+def sketch(x: np.ndarray, k: int, omega: np.ndarray) -> np.ndarray:
+    """Y = X_(k) Omega_k."""
+    return unfold(x, k) @ omega
+
+
+def shifted_power(x: np.ndarray, k: int, q_mat: np.ndarray, alpha: float) -> np.ndarray:
+    """M = X_(k) (X_(k)^T Q) - alpha Q."""
+    xk = unfold(x, k)
+    return xk @ (xk.T @ q_mat) - alpha * q_mat
+
+
+def shift_update(alpha: float, sigma_l: float) -> float:
+    """Midpoint rule: move alpha halfway to Sigma(l,l) when that is larger."""
+    return (sigma_l + alpha) / 2.0 if sigma_l > alpha else alpha
+
+
+def core_step(x: np.ndarray, k: int, u: np.ndarray) -> np.ndarray:
+    """X x_k U^T."""
+    return mode_product(x, u.T, k)
+
+
+@dataclasses.dataclass
+class ModeLog:
+    l: int
+    m: int
+    alphas: List[float]            # alpha_0 .. alpha_q
+    sigmas: List[np.ndarray]       # Sigma after the sketch svd and after each power step
+
+
+@dataclasses.dataclass
+class Result:
+    core: np.ndarray
+    factors: List[np.ndarray]
+    logs: List[ModeLog]
+
+
+OmegaProvider = Callable[[int, int, int], np.ndarray]
+
+
+def randomized_hosvd(a: np.ndarray, ranks: Sequence[int], p: int, q: int, *,
+                     shift: str = "adaptive", variant: str = "st", seed: int = 1,
+                     omega: Optional[OmegaProvider] = None) -> Result:
+    """Algorithm 2 (variant 't') / Algorithm 3 (variant 'st'); shift 'none' = Algorithm A.1."""
+    if shift not in ("adaptive", "none") or variant not in ("t", "st"):
+        raise ValueError("bad shift or variant")
+    a = np.asarray(a, dtype=np.float64)
+    d = a.ndim
+    g = a.copy()
+    factors: List[np.ndarray] = []
+    logs: List[ModeLog] = []
+    for k in range(d):
+        x = a if variant == "t" else g
+        n_k = x.shape[k]
+        m_k = x.size // n_k
+        r_k = int(ranks[k])
+        if not (1 <= r_k <= n_k and r_k <= m_k):
+            raise ValueError("infeasible rank at mode %d" % k)
+        l_k = sketch_width(r_k, p, n_k, m_k)
+        om = omega(k, m_k, l_k) if omega is not None else gaussian_omega(seed, k, m_k, l_k)
+        qm, s = svd_econ(sketch(x, k, om))
+        alpha = 0.0
+        alphas, sigmas = [alpha], [s]
+        for _t in range(q):
+            qm, s = svd_econ(shifted_power(x, k, qm, alpha))
+            if shift == "adaptive":
+                alpha = shift_update(alpha, s[l_k - 1])
+            alphas.append(alpha)
+            sigmas.append(s)
+        u_k = sign_fix(qm[:, :r_k])
+        factors.append(u_k)
+        g = core_step(g, k, u_k)
+        logs.append(ModeLog(l_k, m_k, alphas, sigmas))
+    return Result(g, factors, logs)
+
+
+def hosvd_full(a: np.ndarray, ranks: Sequence[int], variant: str = "st") -> Result:
+    """Algorithm 1: U_k from the full econ SVD of A_(k) (T) or G_(k) (ST)."""
+    a = np.asarray(a, dtype=np.float64)
+    g = a.copy()
+    factors, logs = [], []
+    for k in range(a.ndim):
+        x = a if variant == "t" else g
+        qm, s = svd_econ(unfold(x, k))
+        u_k = sign_fix(qm[:, :int(ranks[k])])
+        factors.append(u_k)
+        g = core_step(g, k, u_k)
+        logs.append(ModeLog(qm.shape[1], x.size // x.shape[k], [0.0], [s]))
+    return Result(g, factors, logs)
+
+
+def rel_error(a: np.ndarray, res: Result) -> float:
+    """RE = ||A - Ahat|| / ||A|| with Ahat = G x_1 U_1 ... x_d U_d, formed explicitly."""
+    ahat = reconstruct(res.core, res.factors)
+    return float(np.sqrt(frob2(a - ahat) / frob2(a)))
+
+
+def rel_error_identity(a: np.ndarray, core: np.ndarray) -> float:
+    """RE via ||A - Ahat||^2 = ||A||^2 - ||G||^2 (orthonormal factors)."""
+    na, ng = frob2(a), frob2(core)
+    return float(np.sqrt(max(na - ng, 0.0) / na))

@@ -1,0 +1,1 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the bench."""
