@@ -1,0 +1,201 @@
+#!/usr/bin/env python
+"""Throughput of shifted randomized (S)T-HOSVD on one MI355X.
+
+Prints ONE JSON line. A step is one whole solve (every mode: sketch, svd,
+q shifted power steps each with its svd and shift update, sign rule, core
+contraction) of a tensor already resident in HBM.
+
+Default workload: the 400^3 smooth-function tensor a_ijk = 1/(i+j+k-2) in
+FP32, ST-HOSVD, ranks (30,30,30), p = 10, q = 3, adaptive shift.
+Other workloads: --workload tucker3_60_fp64 | tucker4_120 | tucker3_1000.
+
+The dominant kernel's roofline figure comes from HIP events the library
+records around each launch of that kernel class (tucker_timing_*) during a
+second timed pass of the same K steps; achieved = summed algorithmic bytes
+(or flops) / summed event time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+METRIC = "Tucker approximations/sec at fixed rel. error; TTM HBM GB/s; p99 latency"
+
+CONFIGS = {
+    "hilbert3_400": dict(precision="fp32", variant="st", ranks=(30, 30, 30), p=10, q=3),
+    "tucker3_60_fp64": dict(precision="fp64", variant="t", ranks=(10, 10, 10), p=5, q=1),
+    "tucker4_120": dict(precision="bf16", variant="st", ranks=(20, 20, 20, 20), p=10, q=2),
+    "tucker3_1000": dict(precision="fp32", variant="st", ranks=(50, 50, 50), p=10, q=3),
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="hilbert3_400", choices=sorted(CONFIGS))
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "bf16"])
+    ap.add_argument("--q", type=int, default=None)
+    ap.add_argument("--shift", default="adaptive", choices=["adaptive", "none"])
+    ap.add_argument("--kernel", default="colreduce", help="kernel class reported in the roofline object")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    return ap.parse_args()
+
+
+def reconstruct_torch(G, U):
+    import torch
+    t = G
+    for k, u in enumerate(U):
+        t = torch.movedim(torch.tensordot(u, t, dims=([1], [k])), 0, k)
+    return t
+
+
+def cpu_baseline(workload, cfg, a_host, shift, q):
+    """The FP64 oracle, untuned, on the host cores: one whole solve of the same
+    workload when that takes seconds, else a bounded slab scaled by work."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import rhosvd as orc
+
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    a = a_host
+    scale = 1.0
+    sample = "one whole solve (FP64 oracle) of the same tensor"
+    if a.size > 3e8:
+        # slab along the last mode: same n_1, n_2; work of every product scales with numel
+        d = a.shape[-1]
+        keep = max(1, int(d * 2e8 / a.size))
+        a = np.ascontiguousarray(a[..., :keep])
+        scale = d / keep
+        sample = "one whole solve (FP64 oracle) of the %s slab, time scaled by %.1f (numel ratio)" % (
+            "x".join(map(str, a.shape)), scale)
+    a64 = a.astype(np.float64)
+    t0 = time.perf_counter()
+    orc.randomized_hosvd(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1)
+    dt = (time.perf_counter() - t0) * scale
+    return {"value": 1.0 / dt, "unit": "approximations/s", "cores": int(threads), "kind": "oracle",
+            "sample": sample, "seconds_per_solve": dt}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2506_04840_amd import _lib as T
+    from workloads import generators as gen
+
+    cfg = dict(CONFIGS[args.workload])
+    prec = args.precision or cfg["precision"]
+    q = cfg["q"] if args.q is None else args.q
+    dev = torch.device("cuda:0")
+    w = gen.WORKLOADS[args.workload]
+
+    if args.workload in ("hilbert3_400", "tucker3_60_fp64"):
+        a_host = gen.make_tensor(args.workload)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        A = torch.from_numpy(a_host).to(dev, dtype=dt)
+        a_host_store = A.double().cpu().numpy() if prec != "fp64" else a_host
+    else:
+        A = gen.build_on_device(args.workload, dev)
+        if prec == "fp64":
+            A = A.double()
+        a_host_store = None
+
+    solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
+                      sequential=(cfg["variant"] == "st"), device=dev)
+    for _ in range(args.warmup):
+        solver.run(A)
+    torch.cuda.synchronize()
+
+    # timed region: K whole solves
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        solver.run(A)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+
+    # relative error of the result (measurement, outside the timed region)
+    G, U = solver.G.double(), [u.double() for u in solver.U]
+    Ad = A.double()
+    re = float(torch.linalg.vector_norm(Ad - reconstruct_torch(G, U)) / torch.linalg.vector_norm(Ad))
+    del Ad
+
+    roof = None
+    if not args.no_kernel_timing:
+        T.timing_enable(args.kernel, capacity=65536)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            solver.run(A)
+        torch.cuda.synchronize()
+        tk = T.timing_read(args.kernel)
+        T.timing_disable()
+        sec = tk["ms"] * 1e-3
+        mk = "fp32" if (prec == "bf16" and args.kernel == "rowcontract") else prec
+        t_mem = tk["bytes"] / (HBM_PEAK_GBS * 1e9)
+        t_flop = tk["flops"] / (PEAK_TFLOPS[mk] * 1e12)
+        if t_flop > t_mem:
+            achieved = tk["flops"] / sec / 1e12
+            roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[mk], "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_TFLOPS[mk], 4), "traffic": None}
+        else:
+            achieved = tk["bytes"] / sec / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+        roof.update({"kernel": args.kernel, "launches": tk["launches"],
+                     "avg_launch_us": round(1e3 * tk["ms"] / max(tk["launches"], 1), 3),
+                     "alg_bytes_per_launch": tk["bytes"] / max(tk["launches"], 1),
+                     "alg_flops_per_launch": tk["flops"] / max(tk["launches"], 1)})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        if a_host_store is None:
+            a_host_store = A.double().cpu().numpy() if A.numel() <= 3e8 else A.float().cpu().numpy()
+        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q)
+
+    value = args.steps / elapsed
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "approximations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-operands/f32-acc"}[prec],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dims": list(A.shape), "ranks": list(cfg["ranks"]), "p": cfg["p"],
+                   "q": q, "shift": args.shift, "variant": cfg["variant"], "precision": prec,
+                   "rel_error": re},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,225 @@
+/*
+ * tucker.h - C ABI of the MI355X (gfx950) library for fixed-rank Tucker
+ * approximation by shifted randomized T-HOSVD and ST-HOSVD.
+ *
+ * The method is Algorithms 2 and 3 of Che, Wei, Wu, Yan, "Fixed-Rank
+ * Approximations in Tucker Format with Adaptive Shifts based on Fast
+ * Randomized Algorithms" (arXiv 2506.04840): for each mode k, a Gaussian
+ * sketch Y = X_(k) Omega_k, then q shifted power steps
+ * Y <- X_(k)(X_(k)^T Q) - alpha Q, each followed by an economy SVD and the
+ * midpoint shift update, then U_k = Q(:, 1:r_k) and G <- G x_k U_k^T.
+ * It solves the fixed-Tucker-rank problem of the paper's Problem 1.
+ *
+ * Conventions shared by every entry point:
+ *  - Tensors are dense, row-major (C order, last index fastest), with
+ *    order 1..TUCKER_MAX_ORDER. Modes are 0-based here; the paper counts from 1.
+ *  - The mode-k unfolding is never materialised. A tensor is viewed as
+ *    [P, n_k, S] with P = prod_{j<k} n_j and S = prod_{j>k} n_j, so that
+ *    X_(k)[i, p*S + s] = X[p, i, s].
+ *  - Matrices are row-major: Y, Q are n_k x l, U_k is n_k x r_k.
+ *  - Every data pointer is a DEVICE pointer owned by the caller. The library
+ *    allocates no caller-visible memory and frees nothing. Scratch comes from
+ *    a caller workspace whose size the *_workspace_bytes queries give.
+ *  - Every call is asynchronous on the given stream (NULL = default stream).
+ *    A call either enqueues all of its work and returns TUCKER_OK, or
+ *    enqueues nothing and returns a negative tucker_status for errors found
+ *    on the host (bad arguments, small workspace). Numeric events found on
+ *    the device are written to the device-resident tucker_info and are
+ *    readable once the stream is synchronised.
+ *  - Calls are reentrant given distinct workspaces. Two calls that share a
+ *    workspace must be ordered on one stream.
+ *  - Precision: TUCKER_FP64 keeps tensors, factors and products in FP64.
+ *    TUCKER_FP32 stores tensors and factors in FP32 and runs the mode
+ *    products in FP32 on the matrix cores. TUCKER_BF16 stores tensors and
+ *    factors in FP32, runs the sketch and power products with BF16 operands
+ *    and FP32 accumulation, and runs the core contraction in FP32. In every
+ *    precision the Gram matrices, Cholesky factors, small SVD and shift are
+ *    FP64.
+ */
+#ifndef TUCKER_H
+#define TUCKER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TUCKER_MAX_ORDER 8
+#define TUCKER_MAX_Q 16 /* largest power count q */
+#define TUCKER_MAX_L 64 /* largest sketch width l_k = min(r_k + p, n_k, m_k) */
+
+typedef enum {
+  TUCKER_OK = 0,
+  TUCKER_EINVAL = -1,      /* invalid argument (see each call) */
+  TUCKER_EWORKSPACE = -2,  /* workspace pointer null or smaller than required */
+  TUCKER_EDEVICE = -3,     /* a HIP call failed (launch error, no device) */
+  TUCKER_EUNSUPPORTED = -4 /* valid request outside what this build handles */
+} tucker_status;
+
+typedef enum { TUCKER_FP64 = 0, TUCKER_FP32 = 1, TUCKER_BF16 = 2 } tucker_precision;
+
+typedef enum {
+  TUCKER_SHIFT_ADAPTIVE = 0, /* the paper's midpoint shift (Algorithms 2, 3) */
+  TUCKER_SHIFT_NONE = 1      /* alpha = 0 throughout: appendix Algorithm A.1 */
+} tucker_shift;
+
+typedef struct {
+  int32_t order; /* d, 1..TUCKER_MAX_ORDER */
+  int32_t reserved;
+  int64_t dims[TUCKER_MAX_ORDER]; /* n_1..n_d, each >= 1 */
+} tucker_shape;
+
+/* Status bits of tucker_info.flags. */
+#define TUCKER_INFO_NONFINITE 1  /* a non-finite value reached an orthonormalisation */
+#define TUCKER_INFO_DEFICIENT 2  /* an iterate was numerically rank deficient; the basis
+                                    was completed with random orthonormal directions */
+#define TUCKER_INFO_L_CLAMPED 4  /* some l_k < r_k + p because n_k or m_k is smaller */
+
+/* Device-resident report of one solve (caller allocates sizeof(tucker_info)
+ * bytes of device memory). Written by the solve's kernels. */
+typedef struct {
+  int32_t flags;                                /* TUCKER_INFO_* bits */
+  int32_t l[TUCKER_MAX_ORDER];                  /* sketch width l_k used at each mode */
+  int32_t deficient[TUCKER_MAX_ORDER];          /* deficient columns seen at the last svd of mode k */
+  int32_t reserved;
+  double alpha[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1];   /* alpha_t^(k), t = 0..q */
+  double sigma_1[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1]; /* Sigma_k(1,1) after svd t (t=0: sketch) */
+  double sigma_l[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1]; /* Sigma_k(l,l) after svd t */
+  double normG2;                                /* ||G||_F^2 of the returned core (FP64 sum) */
+} tucker_info;
+
+/* Flags of tucker_shifted_power. */
+#define TUCKER_POWER_RAW 1 /* write only Y = X_(k)(X_(k)^T Q) - alpha Q (n_k x l, FP64) */
+
+/* Human-readable text for a tucker_status; also the last error's detail
+ * (thread-local) when the code matches the last failing call on this thread. */
+const char* tucker_status_string(int status);
+
+/* Workspace bytes for a whole solve (tucker_rthosvd when sequential == 0,
+ * tucker_rsthosvd when sequential != 0) with these arguments. Returns 0 when
+ * the arguments are invalid for that solve. */
+size_t tucker_workspace_bytes(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q,
+                              tucker_precision prec, int32_t sequential);
+
+/* Workspace bytes for one tucker_sketch / tucker_shifted_power / tucker_orth
+ * call on the mode-`mode` unfolding of `shape` with sketch width l. */
+size_t tucker_op_workspace_bytes(const tucker_shape* shape, int32_t mode, int64_t l,
+                                 tucker_precision prec);
+
+/* Omega_mode[row0 : row0 + rows, 0 : cols] of the Gaussian test matrix (the
+ * standard Gaussian matrix the paper draws for each mode, section 2 and the
+ * draw at the top of Algorithms 2 and 3), row-major into `out` (FP64 for
+ * TUCKER_FP64, FP32 otherwise), exactly as the sketch kernels use it.
+ * Generator: Philox4x32-10 with key = seed and counter = (row lo, row hi,
+ * col / 4, mode), Box-Muller on (w0,w1) for (col/2) even and (w2,w3) for odd.
+ * EINVAL: rows < 0, cols < 0, row0 < 0, mode outside 0..TUCKER_MAX_ORDER-1,
+ * out null with rows*cols > 0. */
+int tucker_fill_gaussian(uint64_t seed, int32_t mode, int64_t row0, int64_t rows, int64_t cols,
+                         tucker_precision prec, void* out, hipStream_t stream);
+
+/* Sketch Y = X_(mode) Omega_mode (Algorithms 2 and 3: the first product of
+ * each mode). X has `shape` (FP64 for TUCKER_FP64, FP32 otherwise). Omega
+ * is the m x l matrix of tucker_fill_gaussian(seed, mode, 0, m, l) with
+ * m = numel(X) / n_mode. Y: n_mode x l, FP64, overwritten.
+ * EINVAL: bad shape, mode, l < 1 or l > min(TUCKER_MAX_L, n_mode, m), null X/Y.
+ * EWORKSPACE: ws_bytes < tucker_op_workspace_bytes(shape, mode, l, prec). */
+int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_t l, uint64_t seed,
+                  tucker_precision prec, double* Y, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* One shifted power step (Algorithms 2 and 3, the inner loop):
+ * M = X_(mode) (X_(mode)^T Q) - alpha Q with Q n_mode x l in the storage
+ * precision and alpha a device double.
+ * flags & TUCKER_POWER_RAW: write M (FP64, n_mode x l) to `out`; sigma and
+ * alpha are left untouched.
+ * otherwise: [Q', Sigma] = svd(M, econ); write Q' (storage precision,
+ * n_mode x l, singular vectors in descending order of Sigma) to `out`,
+ * Sigma (l doubles) to `sigma` and apply the midpoint rule to *alpha in
+ * place: if Sigma(l,l) > alpha then alpha = (Sigma(l,l) + alpha) / 2.
+ * `out` must not alias Q. EINVAL / EWORKSPACE as for tucker_sketch, plus
+ * null Q, alpha or (non-raw) sigma. */
+int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X, int64_t l,
+                         const void* Q, double* alpha, int32_t flags, tucker_precision prec,
+                         void* out, double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* [Q, Sigma, ~] = svd(Y, 'econ') of an n x l FP64 matrix Y (the svd the
+ * paper applies to every iterate), by CholeskyQR with a shifted first pass
+ * and two re-orthogonalisation passes, then a one-sided Jacobi SVD of the
+ * l x l triangular factor, all in FP64. Q: n x l in the storage precision,
+ * columns ordered by descending Sigma; Sigma: l doubles. Numerically
+ * deficient columns are completed with random orthonormal directions and
+ * get Sigma = 0. Uses the workspace of tucker_op_workspace_bytes with a
+ * shape whose mode-0 size is n. EINVAL: n < l, l < 1, l > TUCKER_MAX_L, nulls. */
+int tucker_orth(int64_t n, int64_t l, const double* Y, tucker_precision prec, void* Q, double* sigma,
+                void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Core contraction step X_out = X x_mode U^T (Algorithms 2 and 3, the
+ * update of G after each mode; the mode-k product of section 2).
+ * U: n_mode x r in the storage precision. X_out has the dims of X with
+ * dims[mode] replaced by r, same layout convention, storage precision (the
+ * product runs in FP32 for TUCKER_BF16). No workspace.
+ * EINVAL: bad shape or mode, r < 1, r > TUCKER_MAX_L, nulls. */
+int tucker_core(const tucker_shape* shape, int32_t mode, const void* X, const void* U, int64_t r,
+                tucker_precision prec, void* Xout, hipStream_t stream);
+
+/* ||X||_F^2 of `numel` elements in the storage precision, FP64 accumulation
+ * in a fixed order, written to *out (device double). ws: device scratch of
+ * at least TUCKER_NORM2_WS_BYTES bytes. EINVAL: nulls, numel < 0. */
+#define TUCKER_NORM2_WS_BYTES 8192
+int tucker_norm2(const void* X, int64_t numel, tucker_precision prec, double* out, void* ws, size_t ws_bytes,
+                 hipStream_t stream);
+
+/* Shifted randomized T-HOSVD (Algorithm 2): every factor is computed from A;
+ * then G = A x_1 U_1^T ... x_d U_d^T.
+ * A: `shape`, storage precision. ranks: d host int64 values r_k with
+ * 1 <= r_k <= n_k and r_k <= prod_{j != k} n_j. p >= 0 oversampling,
+ * 0 <= q <= TUCKER_MAX_Q power steps. l_k = min(r_k + p, n_k, m_k) above
+ * TUCKER_MAX_L returns TUCKER_EUNSUPPORTED. seed selects Omega_k = tucker_fill_gaussian(seed, k, ...).
+ * G: r_1 x ... x r_d; U[k]: n_k x r_k (device pointers, storage precision;
+ * columns ordered by descending singular value, each column's largest-
+ * magnitude entry made positive). info: device tucker_info or NULL.
+ * EINVAL on any violated bound, EWORKSPACE when ws_bytes is smaller than
+ * tucker_workspace_bytes(shape, ranks, p, q, prec, 0). */
+int tucker_rthosvd(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                   tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                   tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Shifted randomized ST-HOSVD (Algorithm 3), processing order 1..d: mode k
+ * works on X = A x_1 U_1^T ... x_{k-1} U_{k-1}^T, so m_k = r_1..r_{k-1}
+ * n_{k+1}..n_d and the feasibility bound is r_k <= m_k. Arguments as for
+ * tucker_rthosvd, with workspace tucker_workspace_bytes(..., 1). */
+int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                    tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                    tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* ---- Launch timing (measurement only) ---------------------------------------
+ * When a kernel class is enabled, every launch of that class records a pair
+ * of HIP events on its launch stream (up to `capacity` launches; later ones
+ * are counted as dropped) and sums each launch's algorithmic HBM bytes and
+ * flops (the unfolding read once, plus the skinny operand and result; flops
+ * 2 * numel * width). One class at a time, process-wide. */
+#define TUCKER_KC_COLREDUCE 0   /* X_(k) B: sketch and the second half of a power step */
+#define TUCKER_KC_ROWCONTRACT 1 /* X_(k)^T W: first half of a power step and core step */
+#define TUCKER_KC_ORTH 2        /* one whole svd(Y, econ) sequence */
+#define TUCKER_KC_FILL 3        /* Gaussian test-matrix fill */
+#define TUCKER_KC_REDUCE 4      /* split-partial reduction with the -alpha Q term */
+/* EINVAL: bad class or capacity outside 1..2^20. EDEVICE: event creation failed. */
+int tucker_timing_enable(int32_t kernel_class, int32_t capacity);
+/* Waits for the recorded events; total device milliseconds, launch count,
+ * summed bytes and flops (bytes, flops may be NULL). EINVAL if the class is
+ * not the enabled one; EUNSUPPORTED (values still written) if launches were
+ * dropped for lack of capacity. */
+int tucker_timing_read(int32_t kernel_class, double* total_ms, int64_t* launches, double* bytes, double* flops);
+/* Forget recorded launches, keep the class enabled. */
+int tucker_timing_reset(void);
+/* Disable and free the events. */
+int tucker_timing_disable(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUCKER_H */

@@ -1,0 +1,336 @@
+"""ctypes binding of libtucker.so (the C ABI in include/tucker.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels. torch supplies device memory and the current stream. If the
+library is not built this module raises ImportError: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtucker.so")
+
+MAX_ORDER = 8
+MAX_Q = 16
+MAX_L = 64
+NORM2_WS_BYTES = 8192
+
+FP64, FP32, BF16 = 0, 1, 2
+SHIFT_ADAPTIVE, SHIFT_NONE = 0, 1
+POWER_RAW = 1
+INFO_NONFINITE, INFO_DEFICIENT, INFO_L_CLAMPED = 1, 2, 4
+
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+_SHIFT = {"adaptive": SHIFT_ADAPTIVE, "none": SHIFT_NONE}
+
+
+class TuckerError(RuntimeError):
+    pass
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dims", ctypes.c_int64 * MAX_ORDER)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("flags", ctypes.c_int32),
+        ("l", ctypes.c_int32 * MAX_ORDER),
+        ("deficient", ctypes.c_int32 * MAX_ORDER),
+        ("reserved", ctypes.c_int32),
+        ("alpha", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
+        ("sigma_1", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
+        ("sigma_l", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
+        ("normG2", ctypes.c_double),
+    ]
+
+
+INFO_BYTES = ctypes.sizeof(Info)
+
+# Every symbol of include/tucker.h with its ctypes signature.
+_P, _I32, _I64, _U64, _SZ, _D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.c_size_t, ctypes.c_double)
+_SHAPE_P = ctypes.POINTER(Shape)
+SIGNATURES = {
+    "tucker_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "tucker_workspace_bytes": (_SZ, [_SHAPE_P, _P, _I32, _I32, ctypes.c_int, _I32]),
+    "tucker_op_workspace_bytes": (_SZ, [_SHAPE_P, _I32, _I64, ctypes.c_int]),
+    "tucker_fill_gaussian": (ctypes.c_int, [_U64, _I32, _I64, _I64, _I64, ctypes.c_int, _P, _P]),
+    "tucker_sketch": (ctypes.c_int, [_SHAPE_P, _I32, _P, _I64, _U64, ctypes.c_int, _P, _P, _SZ, _P]),
+    "tucker_shifted_power": (ctypes.c_int, [_SHAPE_P, _I32, _P, _I64, _P, _P, _I32, ctypes.c_int, _P, _P, _P, _SZ,
+                                            _P]),
+    "tucker_orth": (ctypes.c_int, [_I64, _I64, _P, ctypes.c_int, _P, _P, _P, _SZ, _P]),
+    "tucker_core": (ctypes.c_int, [_SHAPE_P, _I32, _P, _P, _I64, ctypes.c_int, _P, _P]),
+    "tucker_norm2": (ctypes.c_int, [_P, _I64, ctypes.c_int, _P, _P, _SZ, _P]),
+    "tucker_rthosvd": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P, _P,
+                                      _SZ, _P]),
+    "tucker_rsthosvd": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P, _P,
+                                       _SZ, _P]),
+    "tucker_timing_enable": (ctypes.c_int, [_I32, _I32]),
+    "tucker_timing_read": (ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "tucker_timing_reset": (ctypes.c_int, []),
+    "tucker_timing_disable": (ctypes.c_int, []),
+}
+
+KC = {"colreduce": 0, "rowcontract": 1, "orth": 2, "fill": 3, "reduce": 4}
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libtucker.so is not built (python -m paper_2506_04840_amd.build)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int) -> None:
+    if rc == 0:
+        return
+    msg = lib.tucker_status_string(rc).decode()
+    if rc == -1:
+        raise ValueError(msg)
+    raise TuckerError("tucker status %d: %s" % (rc, msg))
+
+
+def _shape(dims: Sequence[int]) -> Shape:
+    s = Shape()
+    s.order = len(dims)  # the library rejects orders above MAX_ORDER
+    for k, n in enumerate(list(dims)[:MAX_ORDER]):
+        s.dims[k] = int(n)
+    return s
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def precision_of(t: torch.Tensor, precision: Optional[str]) -> int:
+    if precision is None:
+        return FP64 if t.dtype == torch.float64 else FP32
+    p = _PREC[precision]
+    want = torch.float64 if p == FP64 else torch.float32
+    if t.dtype != want:
+        raise ValueError("precision %s needs a %s tensor, got %s" % (precision, want, t.dtype))
+    return p
+
+
+def storage_dtype(prec: int) -> torch.dtype:
+    return torch.float64 if prec == FP64 else torch.float32
+
+
+def _dev(t: torch.Tensor, name: str) -> int:
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def workspace_bytes(dims, ranks, p, q, precision: int, sequential: bool) -> int:
+    r = (ctypes.c_int64 * len(ranks))(*[int(x) for x in ranks])
+    s = _shape(dims)
+    return int(lib.tucker_workspace_bytes(ctypes.byref(s), r, int(p), int(q), precision, 1 if sequential else 0))
+
+
+def op_workspace_bytes(dims, mode, l, precision: int) -> int:
+    s = _shape(dims)
+    return int(lib.tucker_op_workspace_bytes(ctypes.byref(s), int(mode), int(l), precision))
+
+
+def read_info(info: torch.Tensor) -> dict:
+    raw = bytes(info.cpu().numpy().tobytes())
+    st = Info.from_buffer_copy(raw)
+    return {
+        "flags": int(st.flags),
+        "l": [int(x) for x in st.l],
+        "deficient": [int(x) for x in st.deficient],
+        "alpha": [[float(x) for x in row] for row in st.alpha],
+        "sigma_1": [[float(x) for x in row] for row in st.sigma_1],
+        "sigma_l": [[float(x) for x in row] for row in st.sigma_l],
+        "normG2": float(st.normG2),
+    }
+
+
+class Solver:
+    """A solve configuration with its workspace, reusable across calls.
+
+    The workspace and outputs are allocated once (torch, on the tensor's
+    device); run() only enqueues the library's launch sequence.
+    """
+
+    def __init__(self, dims, ranks, p=10, q=1, shift="adaptive", seed=1, precision="fp32", sequential=True,
+                 device="cuda"):
+        self.dims = tuple(int(x) for x in dims)
+        self.ranks = tuple(int(x) for x in ranks)
+        self.p, self.q, self.seed = int(p), int(q), int(seed)
+        self.prec = _PREC[precision]
+        self.shift = _SHIFT[shift]
+        self.sequential = bool(sequential)
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(self.dims, self.ranks, self.p, self.q, self.prec, self.sequential)
+        if nbytes == 0:
+            # reproduce the detailed error
+            self._call(dry=True)
+        dt = storage_dtype(self.prec)
+        self.ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+        self.G = torch.empty(self.ranks, dtype=dt, device=self.device)
+        self.U = [torch.empty((n, r), dtype=dt, device=self.device) for n, r in zip(self.dims, self.ranks)]
+        self.info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=self.device)
+        self._uptr = (ctypes.c_void_p * len(self.U))(*[u.data_ptr() for u in self.U])
+        self._shape = _shape(self.dims)
+        self._ranks = (ctypes.c_int64 * len(self.ranks))(*self.ranks)
+
+    def _call(self, A: Optional[torch.Tensor] = None, dry: bool = False):
+        fn = lib.tucker_rsthosvd if self.sequential else lib.tucker_rthosvd
+        if dry:
+            s = _shape(self.dims)
+            r = (ctypes.c_int64 * len(self.ranks))(*self.ranks)
+            _check(fn(ctypes.byref(s), None, r, self.p, self.q, self.shift, self.seed, self.prec, None, None, None,
+                      None, 0, None))
+            return
+        _check(fn(ctypes.byref(self._shape), ctypes.c_void_p(A.data_ptr()), self._ranks, self.p, self.q, self.shift,
+                  ctypes.c_uint64(self.seed), self.prec, ctypes.c_void_p(self.G.data_ptr()), self._uptr,
+                  ctypes.c_void_p(self.info.data_ptr()), ctypes.c_void_p(self.ws.data_ptr()),
+                  ctypes.c_size_t(self.ws.numel()), _stream(self.device)))
+
+    def run(self, A: torch.Tensor):
+        if tuple(A.shape) != self.dims:
+            raise ValueError("tensor shape %s != solver dims %s" % (tuple(A.shape), self.dims))
+        _dev(A, "A")
+        if A.dtype != storage_dtype(self.prec):
+            raise ValueError("tensor dtype %s does not match the solver precision" % A.dtype)
+        self._call(A)
+        return self.G, self.U
+
+
+def rsthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None):
+    """Shifted randomized ST-HOSVD (Algorithm 3). Returns (G, [U_k], info dict)."""
+    prec = precision_of(A, precision)
+    s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], True, A.device)
+    s.run(A.contiguous())
+    return s.G, s.U, read_info(s.info)
+
+
+def rthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None):
+    """Shifted randomized T-HOSVD (Algorithm 2). Returns (G, [U_k], info dict)."""
+    prec = precision_of(A, precision)
+    s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], False, A.device)
+    s.run(A.contiguous())
+    return s.G, s.U, read_info(s.info)
+
+
+def fill_gaussian(seed: int, mode: int, rows: int, cols: int, precision: str = "fp64", row0: int = 0,
+                  device="cuda") -> torch.Tensor:
+    prec = _PREC[precision]
+    out = torch.empty((rows, cols), dtype=storage_dtype(prec), device=device)
+    _check(lib.tucker_fill_gaussian(ctypes.c_uint64(seed), mode, row0, rows, cols, prec,
+                                    ctypes.c_void_p(out.data_ptr()) if out.numel() else None, _stream(out.device)))
+    return out
+
+
+def sketch(X: torch.Tensor, mode: int, l: int, seed: int = 1, precision: Optional[str] = None) -> torch.Tensor:
+    """Y = X_(mode) Omega_mode, FP64 n x l."""
+    prec = precision_of(X, precision)
+    s = _shape(X.shape)
+    Y = torch.empty((X.shape[mode], l), dtype=torch.float64, device=X.device)
+    nbytes = op_workspace_bytes(X.shape, mode, l, prec)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=X.device)
+    _check(lib.tucker_sketch(ctypes.byref(s), mode, ctypes.c_void_p(_dev(X, "X")), l, ctypes.c_uint64(seed), prec,
+                             ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                             _stream(X.device)))
+    return Y
+
+
+def shifted_power(X: torch.Tensor, mode: int, Q: torch.Tensor, alpha: torch.Tensor, raw: bool = False,
+                  precision: Optional[str] = None):
+    """One shifted power step. raw: returns M = X_(k)(X_(k)^T Q) - alpha Q (FP64).
+    Otherwise returns (Q', Sigma) and updates the device scalar alpha in place."""
+    prec = precision_of(X, precision)
+    if Q.dtype != storage_dtype(prec) or alpha.dtype != torch.float64:
+        raise ValueError("Q must use the storage dtype and alpha must be float64")
+    n = X.shape[mode]
+    l = Q.shape[1]
+    s = _shape(X.shape)
+    nbytes = op_workspace_bytes(X.shape, mode, l, prec)
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=X.device)
+    if raw:
+        out = torch.empty((n, l), dtype=torch.float64, device=X.device)
+        sigma = None
+    else:
+        out = torch.empty((n, l), dtype=storage_dtype(prec), device=X.device)
+        sigma = torch.empty(l, dtype=torch.float64, device=X.device)
+    _check(lib.tucker_shifted_power(ctypes.byref(s), mode, ctypes.c_void_p(_dev(X, "X")), l,
+                                    ctypes.c_void_p(_dev(Q, "Q")), ctypes.c_void_p(_dev(alpha, "alpha")),
+                                    POWER_RAW if raw else 0, prec, ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(sigma.data_ptr()) if sigma is not None else None,
+                                    ctypes.c_void_p(ws.data_ptr()), nbytes, _stream(X.device)))
+    return out if raw else (out, sigma)
+
+
+def orth(Y: torch.Tensor, precision: str = "fp64") -> Tuple[torch.Tensor, torch.Tensor]:
+    """[Q, Sigma] = svd(Y, econ) of an FP64 n x l matrix."""
+    prec = _PREC[precision]
+    if Y.dtype != torch.float64:
+        raise ValueError("Y must be float64")
+    n, l = Y.shape
+    nbytes = op_workspace_bytes((n, max(l, 1)), 0, l, FP64) if l <= min(n, MAX_L) else 0
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=Y.device)
+    Q = torch.empty((n, l), dtype=storage_dtype(prec), device=Y.device)
+    sigma = torch.empty(l, dtype=torch.float64, device=Y.device)
+    _check(lib.tucker_orth(n, l, ctypes.c_void_p(_dev(Y, "Y")), prec, ctypes.c_void_p(Q.data_ptr()),
+                           ctypes.c_void_p(sigma.data_ptr()), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                           _stream(Y.device)))
+    return Q, sigma
+
+
+def core(X: torch.Tensor, mode: int, U: torch.Tensor, precision: Optional[str] = None) -> torch.Tensor:
+    """X x_mode U^T."""
+    prec = precision_of(X, precision)
+    r = U.shape[1]
+    dims = list(X.shape)
+    dims[mode] = r
+    out = torch.empty(dims, dtype=X.dtype, device=X.device)
+    s = _shape(X.shape)
+    _check(lib.tucker_core(ctypes.byref(s), mode, ctypes.c_void_p(_dev(X, "X")), ctypes.c_void_p(_dev(U, "U")), r,
+                           prec, ctypes.c_void_p(out.data_ptr()), _stream(X.device)))
+    return out
+
+
+def norm2(X: torch.Tensor) -> torch.Tensor:
+    prec = FP64 if X.dtype == torch.float64 else FP32
+    out = torch.empty(1, dtype=torch.float64, device=X.device)
+    ws = torch.empty(NORM2_WS_BYTES, dtype=torch.uint8, device=X.device)
+    _check(lib.tucker_norm2(ctypes.c_void_p(_dev(X, "X")), X.numel(), prec, ctypes.c_void_p(out.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), NORM2_WS_BYTES, _stream(X.device)))
+    return out
+
+
+def timing_enable(kernel: str, capacity: int = 4096) -> None:
+    _check(lib.tucker_timing_enable(KC[kernel], capacity))
+
+
+def timing_read(kernel: str) -> dict:
+    ms, n, by, fl = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+    rc = lib.tucker_timing_read(KC[kernel], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(by), ctypes.byref(fl))
+    if rc not in (0, -4):
+        _check(rc)
+    return {"ms": ms.value, "launches": n.value, "bytes": by.value, "flops": fl.value, "dropped": rc == -4}
+
+
+def timing_reset() -> None:
+    _check(lib.tucker_timing_reset())
+
+
+def timing_disable() -> None:
+    _check(lib.tucker_timing_disable())

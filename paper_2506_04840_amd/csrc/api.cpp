@@ -1,0 +1,469 @@
+// C ABI driver: argument checks, workspace carving and the launch sequence of
+// shifted randomized T-HOSVD (Algorithm 2) and ST-HOSVD (Algorithm 3).
+// Every call validates on the host first and either enqueues all its work on
+// the caller's stream or returns an error having enqueued nothing. Nothing
+// here waits on the device: the shift branch runs in a kernel, so a whole
+// solve is one stream of launches.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "internal.hpp"
+#include "tucker.h"
+
+using namespace tk;
+
+namespace {
+
+thread_local std::string g_err_text;
+thread_local int g_err_code = 0;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err_text = buf;
+  g_err_code = code;
+  return code;
+}
+
+int dev_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(TUCKER_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return TUCKER_OK;
+}
+
+bool valid_prec(int p) { return p == TUCKER_FP64 || p == TUCKER_FP32 || p == TUCKER_BF16; }
+
+// Checks a shape; fills numel. Returns 0 or an error code (with detail).
+int check_shape(const tucker_shape* s, int64_t* numel) {
+  if (s == nullptr) return fail(TUCKER_EINVAL, "shape is null");
+  if (s->order < 1 || s->order > TUCKER_MAX_ORDER)
+    return fail(TUCKER_EINVAL, "order %d outside 1..%d", s->order, TUCKER_MAX_ORDER);
+  int64_t n = 1;
+  for (int k = 0; k < s->order; ++k) {
+    if (s->dims[k] < 1) return fail(TUCKER_EINVAL, "dims[%d] = %lld < 1", k, (long long)s->dims[k]);
+    if (n > ((int64_t)1 << 62) / s->dims[k]) return fail(TUCKER_EINVAL, "tensor size overflows int64");
+    n *= s->dims[k];
+  }
+  *numel = n;
+  return TUCKER_OK;
+}
+
+View3 view_of(const int64_t* dims, int d, int k) {
+  View3 v{1, dims[k], 1};
+  for (int j = 0; j < k; ++j) v.P *= dims[j];
+  for (int j = k + 1; j < d; ++j) v.S *= dims[j];
+  return v;
+}
+
+struct Plan {
+  int d;
+  int64_t dims[TUCKER_MAX_ORDER];
+  int64_t r[TUCKER_MAX_ORDER];
+  int l[TUCKER_MAX_ORDER];
+  int64_t m[TUCKER_MAX_ORDER];
+  View3 v[TUCKER_MAX_ORDER];  // view of the tensor each mode's products read
+  bool st;
+  int32_t flags;
+  int64_t xbuf_elems;   // largest intermediate of the core chain
+  int64_t omz_elems;    // largest m_k * l_k (Omega / Z)
+  int64_t nl_max;       // largest n_k * l_k
+  int64_t n_max;
+  int l_max;
+  size_t part_bytes;
+  size_t orth_bytes;
+};
+
+int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q, tucker_precision prec,
+              bool st, Plan* pl) {
+  int64_t numel;
+  int rc = check_shape(shape, &numel);
+  if (rc) return rc;
+  if (ranks == nullptr) return fail(TUCKER_EINVAL, "ranks is null");
+  if (p < 0) return fail(TUCKER_EINVAL, "oversampling p = %d < 0", p);
+  if (q < 0 || q > TUCKER_MAX_Q) return fail(TUCKER_EINVAL, "power count q = %d outside 0..%d", q, TUCKER_MAX_Q);
+  if (!valid_prec(prec)) return fail(TUCKER_EINVAL, "bad precision %d", (int)prec);
+  const int d = shape->order;
+  pl->d = d;
+  pl->st = st;
+  pl->flags = 0;
+  int64_t cur[TUCKER_MAX_ORDER];
+  for (int k = 0; k < d; ++k) {
+    pl->dims[k] = shape->dims[k];
+    cur[k] = shape->dims[k];
+    pl->r[k] = ranks[k];
+    if (ranks[k] < 1 || ranks[k] > shape->dims[k])
+      return fail(TUCKER_EINVAL, "rank r[%d] = %lld outside 1..n[%d] = %lld", k, (long long)ranks[k], k,
+                  (long long)shape->dims[k]);
+  }
+  pl->xbuf_elems = 1;
+  pl->omz_elems = 1;
+  pl->nl_max = 1;
+  pl->n_max = 1;
+  pl->l_max = 1;
+  pl->part_bytes = 256;
+  pl->orth_bytes = 256;
+  for (int k = 0; k < d; ++k) {
+    const int64_t* src = st ? cur : pl->dims;
+    int64_t nk = src[k], mk = 1;
+    for (int j = 0; j < d; ++j)
+      if (j != k) mk *= src[j];
+    if (pl->r[k] > mk)
+      return fail(TUCKER_EINVAL,
+                  "rank r[%d] = %lld exceeds the other modes' product m = %lld (no unfolding has that rank)", k,
+                  (long long)pl->r[k], (long long)mk);
+    const int64_t lk = std::min<int64_t>(std::min<int64_t>(pl->r[k] + p, nk), mk);
+    if (lk > TUCKER_MAX_L)
+      return fail(TUCKER_EUNSUPPORTED, "sketch width l[%d] = %lld exceeds %d", k, (long long)lk, TUCKER_MAX_L);
+    if (lk < pl->r[k] + p) pl->flags |= TUCKER_INFO_L_CLAMPED;
+    pl->l[k] = (int)lk;
+    pl->m[k] = mk;
+    pl->v[k] = view_of(src, d, k);
+    pl->omz_elems = std::max(pl->omz_elems, mk * lk);
+    pl->nl_max = std::max(pl->nl_max, nk * lk);
+    pl->n_max = std::max(pl->n_max, nk);
+    pl->l_max = std::max(pl->l_max, (int)lk);
+    pl->part_bytes = std::max(pl->part_bytes, colreduce_part_bytes(pl->v[k], (int)lk, prec));
+    pl->orth_bytes = std::max(pl->orth_bytes, orth_ws_bytes(nk, (int)lk));
+    if (st) cur[k] = pl->r[k];
+  }
+  // core chain intermediates (same sizes for T and ST): after contracting mode k
+  int64_t chain[TUCKER_MAX_ORDER];
+  for (int k = 0; k < d; ++k) chain[k] = pl->dims[k];
+  for (int k = 0; k + 1 < d; ++k) {
+    chain[k] = pl->r[k];
+    int64_t e = 1;
+    for (int j = 0; j < d; ++j) e *= chain[j];
+    pl->xbuf_elems = std::max(pl->xbuf_elems, e);
+  }
+  return TUCKER_OK;
+}
+
+struct SolveWs {
+  void* xbuf[2];
+  void* omz;
+  void* part;
+  double* y64;
+  void* qt;
+  double* q64;
+  double* sigma;
+  double* alpha;
+  double* normpart;
+  void* orth;
+};
+
+size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveWs* w) {
+  const size_t es = elem_bytes(prec);
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  w->xbuf[0] = take((size_t)pl.xbuf_elems * es);
+  w->xbuf[1] = take((size_t)pl.xbuf_elems * es);
+  w->omz = take((size_t)pl.omz_elems * es);
+  w->part = take(pl.part_bytes);
+  w->y64 = (double*)take((size_t)pl.nl_max * 8);
+  w->qt = take((size_t)pl.nl_max * es);
+  w->q64 = (double*)take((size_t)pl.nl_max * 8);
+  w->sigma = (double*)take(TUCKER_MAX_L * 8);
+  w->alpha = (double*)take(TUCKER_MAX_ORDER * 8);
+  w->normpart = (double*)take(1024 * 8);
+  w->orth = take(pl.orth_bytes);
+  return off;
+}
+
+uint64_t completion_seed(uint64_t seed, int mode) {
+  return (seed ^ 0x6A09E667F3BCC909ull) * 0x9E3779B97F4A7C15ull + (uint64_t)(mode + 1);
+}
+
+// Sketch of one mode and its svd: Y = X_(k) Omega_k, [Q, Sigma] = svd(Y), alpha_0 = 0.
+int sketch_mode(const Plan& pl, int k, const void* X, uint64_t seed, tucker_precision prec, tucker_info* info,
+                const SolveWs& w, hipStream_t st) {
+  const View3 v = pl.v[k];
+  const int l = pl.l[k];
+  const int64_t n = v.n, m = pl.m[k];
+  const int nsplit = colreduce_splits(v, l);
+  const OrthWs ows = carve_orth(w.orth, n, l);
+  const uint64_t cseed = completion_seed(seed, k);
+  double* alpha = w.alpha + k;
+  hipError_t e;
+  // Y = X_(k) Omega_k
+  e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, v.S, w.omz,
+                           st);
+  if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
+  if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
+  if (e == hipSuccess) e = launch_set_double(alpha, 0.0, st);
+  if (e == hipSuccess) e = launch_orth(n, l, w.y64, prec, w.qt, w.q64, w.sigma, nullptr, info, k, 0, ows, cseed, st);
+  return e == hipSuccess ? TUCKER_OK : dev_check(e, "sketch launch");
+}
+
+// q shifted power steps, each followed by its svd and (adaptive) the midpoint shift update.
+int power_steps(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
+                tucker_info* info, const SolveWs& w, hipStream_t st) {
+  const View3 v = pl.v[k];
+  const int l = pl.l[k];
+  const int64_t n = v.n;
+  const int nsplit = colreduce_splits(v, l);
+  const OrthWs ows = carve_orth(w.orth, n, l);
+  const uint64_t cseed = completion_seed(seed, k);
+  double* alpha = w.alpha + k;
+  hipError_t e = hipSuccess;
+  for (int t = 1; t <= q && e == hipSuccess; ++t) {
+    // Z = X_(k)^T Q in the [P, l, S] layout, then Y = X_(k) Z - alpha Q
+    e = launch_rowcontract(prec, v, X, w.qt, l, w.omz, st);
+    if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
+    if (e == hipSuccess)
+      e = launch_reduce_splits(prec, w.part, nsplit, n * l, w.q64, TUCKER_FP64, alpha, w.y64, st);
+    if (e == hipSuccess)
+      e = launch_orth(n, l, w.y64, prec, w.qt, w.q64, w.sigma, shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr, info,
+                      k, t, ows, cseed, st);
+  }
+  return e == hipSuccess ? TUCKER_OK : dev_check(e, "power step launch");
+}
+
+int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+          tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
+          void* ws, size_t ws_bytes, hipStream_t st) {
+  Plan pl;
+  int rc = make_plan(shape, ranks, p, q, prec, st_variant, &pl);
+  if (rc) return rc;
+  if (shift != TUCKER_SHIFT_ADAPTIVE && shift != TUCKER_SHIFT_NONE) return fail(TUCKER_EINVAL, "bad shift mode");
+  if (A == nullptr || G == nullptr || U == nullptr) return fail(TUCKER_EINVAL, "null tensor, core or factor array");
+  for (int k = 0; k < pl.d; ++k)
+    if (U[k] == nullptr) return fail(TUCKER_EINVAL, "U[%d] is null", k);
+  SolveWs w;
+  const size_t need = solve_ws_layout(pl, prec, nullptr, &w);
+  if (ws == nullptr || ws_bytes < need)
+    return fail(TUCKER_EWORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, need);
+  solve_ws_layout(pl, prec, (char*)ws, &w);
+
+  hipError_t e = hipSuccess;
+  if (info != nullptr) {
+    int32_t ls[TUCKER_MAX_ORDER];
+    for (int k = 0; k < pl.d; ++k) ls[k] = pl.l[k];
+    e = launch_info_init(info, ls, pl.d, pl.flags, st);
+    if (e != hipSuccess) return dev_check(e, "info init");
+  }
+  const tucker_precision core_mk = prec == TUCKER_BF16 ? TUCKER_FP32 : prec;
+  const void* X = A;
+  int64_t cur[TUCKER_MAX_ORDER];
+  for (int k = 0; k < pl.d; ++k) cur[k] = pl.dims[k];
+
+  for (int k = 0; k < pl.d; ++k) {
+    const void* Xk = st_variant ? X : A;
+    rc = sketch_mode(pl, k, Xk, seed, prec, info, w, st);
+    if (!rc) rc = power_steps(pl, k, Xk, q, shift, seed, prec, info, w, st);
+    if (rc) return rc;
+    e = launch_signfix(prec, w.qt, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], st);
+    if (e != hipSuccess) return dev_check(e, "sign rule launch");
+    if (st_variant) {
+      void* out = (k == pl.d - 1) ? G : w.xbuf[k & 1];
+      e = launch_rowcontract(core_mk, pl.v[k], X, U[k], (int)pl.r[k], out, st);
+      if (e != hipSuccess) return dev_check(e, "core launch");
+      X = out;
+    }
+  }
+  if (!st_variant) {
+    for (int k = 0; k < pl.d; ++k) {
+      const View3 v = view_of(cur, pl.d, k);
+      void* out = (k == pl.d - 1) ? G : w.xbuf[k & 1];
+      e = launch_rowcontract(core_mk, v, X, U[k], (int)pl.r[k], out, st);
+      if (e != hipSuccess) return dev_check(e, "core launch");
+      X = out;
+      cur[k] = pl.r[k];
+    }
+  }
+  if (info != nullptr) {
+    int64_t gn = 1;
+    for (int k = 0; k < pl.d; ++k) gn *= pl.r[k];
+    e = launch_norm2(prec, G, gn, w.normpart, &info->normG2, st);
+    if (e != hipSuccess) return dev_check(e, "norm launch");
+  }
+  return TUCKER_OK;
+}
+
+int check_op(const tucker_shape* shape, int32_t mode, int64_t l, tucker_precision prec, View3* v, int64_t* m) {
+  int64_t numel;
+  int rc = check_shape(shape, &numel);
+  if (rc) return rc;
+  if (!valid_prec(prec)) return fail(TUCKER_EINVAL, "bad precision %d", (int)prec);
+  if (mode < 0 || mode >= shape->order) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", mode, shape->order - 1);
+  *v = view_of(shape->dims, shape->order, mode);
+  *m = numel / v->n;
+  if (l < 1 || l > TUCKER_MAX_L || l > v->n || l > *m)
+    return fail(TUCKER_EINVAL, "l = %lld outside 1..min(%d, n = %lld, m = %lld)", (long long)l, TUCKER_MAX_L,
+                (long long)v->n, (long long)*m);
+  return TUCKER_OK;
+}
+
+struct OpWs {
+  void* omz;
+  void* part;
+  double* y64;
+  void* orth;
+};
+
+size_t op_ws_layout(const View3& v, int64_t m, int l, tucker_precision prec, char* base, OpWs* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += align_up(bytes);
+    return p;
+  };
+  w->omz = take((size_t)m * l * elem_bytes(prec));
+  w->part = take(colreduce_part_bytes(v, l, prec));
+  w->y64 = (double*)take((size_t)v.n * l * 8);
+  w->orth = take(orth_ws_bytes(v.n, l));
+  return off;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tucker_status_string(int status) {
+  if (status != 0 && status == g_err_code && !g_err_text.empty()) return g_err_text.c_str();
+  switch (status) {
+    case TUCKER_OK: return "ok";
+    case TUCKER_EINVAL: return "invalid argument";
+    case TUCKER_EWORKSPACE: return "workspace too small";
+    case TUCKER_EDEVICE: return "device error";
+    case TUCKER_EUNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+size_t tucker_workspace_bytes(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q,
+                              tucker_precision prec, int32_t sequential) {
+  Plan pl;
+  if (make_plan(shape, ranks, p, q, prec, sequential != 0, &pl)) return 0;
+  SolveWs w;
+  return solve_ws_layout(pl, prec, nullptr, &w);
+}
+
+size_t tucker_op_workspace_bytes(const tucker_shape* shape, int32_t mode, int64_t l, tucker_precision prec) {
+  View3 v;
+  int64_t m;
+  if (check_op(shape, mode, l, prec, &v, &m)) return 0;
+  OpWs w;
+  return op_ws_layout(v, m, (int)l, prec, nullptr, &w);
+}
+
+int tucker_fill_gaussian(uint64_t seed, int32_t mode, int64_t row0, int64_t rows, int64_t cols,
+                         tucker_precision prec, void* out, hipStream_t stream) {
+  if (!valid_prec(prec)) return fail(TUCKER_EINVAL, "bad precision %d", (int)prec);
+  if (rows < 0 || cols < 0 || row0 < 0) return fail(TUCKER_EINVAL, "negative rows, cols or row0");
+  if (mode < 0 || mode >= TUCKER_MAX_ORDER) return fail(TUCKER_EINVAL, "mode %d outside 0..7", mode);
+  if (cols > ((int64_t)1 << 30) || rows > ((int64_t)1 << 40)) return fail(TUCKER_EINVAL, "matrix too large");
+  if (rows * cols == 0) return TUCKER_OK;
+  if (out == nullptr) return fail(TUCKER_EINVAL, "out is null");
+  return dev_check(launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)mode, row0,
+                                        rows, (int)cols, 1, out, stream),
+                   "fill launch");
+}
+
+int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_t l, uint64_t seed,
+                  tucker_precision prec, double* Y, void* ws, size_t ws_bytes, hipStream_t stream) {
+  View3 v;
+  int64_t m;
+  int rc = check_op(shape, mode, l, prec, &v, &m);
+  if (rc) return rc;
+  if (X == nullptr || Y == nullptr) return fail(TUCKER_EINVAL, "null X or Y");
+  OpWs w;
+  const size_t need = op_ws_layout(v, m, (int)l, prec, nullptr, &w);
+  if (ws == nullptr || ws_bytes < need) return fail(TUCKER_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
+  op_ws_layout(v, m, (int)l, prec, (char*)ws, &w);
+  const int nsplit = colreduce_splits(v, (int)l);
+  hipError_t e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)mode, 0, m,
+                                      (int)l, v.S, w.omz, stream);
+  if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
+  if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, v.n * l, nullptr, prec, nullptr, Y, stream);
+  return dev_check(e, "sketch launch");
+}
+
+int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X, int64_t l, const void* Q,
+                         double* alpha, int32_t flags, tucker_precision prec, void* out, double* sigma, void* ws,
+                         size_t ws_bytes, hipStream_t stream) {
+  View3 v;
+  int64_t m;
+  int rc = check_op(shape, mode, l, prec, &v, &m);
+  if (rc) return rc;
+  const bool raw = (flags & TUCKER_POWER_RAW) != 0;
+  if (X == nullptr || Q == nullptr || alpha == nullptr || out == nullptr || (!raw && sigma == nullptr))
+    return fail(TUCKER_EINVAL, "null argument");
+  if (out == Q) return fail(TUCKER_EINVAL, "out aliases Q");
+  OpWs w;
+  const size_t need = op_ws_layout(v, m, (int)l, prec, nullptr, &w);
+  if (ws == nullptr || ws_bytes < need) return fail(TUCKER_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
+  op_ws_layout(v, m, (int)l, prec, (char*)ws, &w);
+  const int nsplit = colreduce_splits(v, (int)l);
+  double* y = raw ? (double*)out : w.y64;
+  hipError_t e = launch_rowcontract(prec, v, X, Q, (int)l, w.omz, stream);
+  if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
+  if (e == hipSuccess)
+    e = launch_reduce_splits(prec, w.part, nsplit, v.n * l, Q, prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32,
+                             alpha, y, stream);
+  if (e == hipSuccess && !raw) {
+    const OrthWs ows = carve_orth(w.orth, v.n, (int)l);
+    e = launch_orth(v.n, (int)l, y, prec, out, nullptr, sigma, alpha, nullptr, -1, -1, ows,
+                    completion_seed(0x5eedull, mode), stream);
+  }
+  return dev_check(e, "power step launch");
+}
+
+int tucker_orth(int64_t n, int64_t l, const double* Y, tucker_precision prec, void* Q, double* sigma, void* ws,
+                size_t ws_bytes, hipStream_t stream) {
+  if (!valid_prec(prec)) return fail(TUCKER_EINVAL, "bad precision %d", (int)prec);
+  if (l < 1 || l > TUCKER_MAX_L || n < l) return fail(TUCKER_EINVAL, "need 1 <= l <= min(n, %d)", TUCKER_MAX_L);
+  if (Y == nullptr || Q == nullptr || sigma == nullptr) return fail(TUCKER_EINVAL, "null argument");
+  const size_t need = orth_ws_bytes(n, (int)l);
+  if (ws == nullptr || ws_bytes < need) return fail(TUCKER_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
+  const OrthWs ows = carve_orth(ws, n, (int)l);
+  return dev_check(launch_orth(n, (int)l, Y, prec, Q, nullptr, sigma, nullptr, nullptr, -1, -1, ows,
+                               completion_seed(0x0a7bull, 0), stream),
+                   "orth launch");
+}
+
+int tucker_core(const tucker_shape* shape, int32_t mode, const void* X, const void* U, int64_t r,
+                tucker_precision prec, void* Xout, hipStream_t stream) {
+  int64_t numel;
+  int rc = check_shape(shape, &numel);
+  if (rc) return rc;
+  if (!valid_prec(prec)) return fail(TUCKER_EINVAL, "bad precision %d", (int)prec);
+  if (mode < 0 || mode >= shape->order) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", mode, shape->order - 1);
+  if (r < 1 || r > TUCKER_MAX_L) return fail(TUCKER_EINVAL, "r = %lld outside 1..%d", (long long)r, TUCKER_MAX_L);
+  if (X == nullptr || U == nullptr || Xout == nullptr) return fail(TUCKER_EINVAL, "null argument");
+  const View3 v = view_of(shape->dims, shape->order, mode);
+  return dev_check(launch_rowcontract(prec == TUCKER_BF16 ? TUCKER_FP32 : prec, v, X, U, (int)r, Xout, stream),
+                   "core launch");
+}
+
+int tucker_norm2(const void* X, int64_t numel, tucker_precision prec, double* out, void* ws, size_t ws_bytes,
+                 hipStream_t stream) {
+  if (!valid_prec(prec)) return fail(TUCKER_EINVAL, "bad precision %d", (int)prec);
+  if (numel < 0 || X == nullptr || out == nullptr) return fail(TUCKER_EINVAL, "null argument or negative size");
+  if (ws == nullptr || ws_bytes < TUCKER_NORM2_WS_BYTES)
+    return fail(TUCKER_EWORKSPACE, "workspace %zu < %d", ws_bytes, TUCKER_NORM2_WS_BYTES);
+  return dev_check(launch_norm2(prec, X, numel, (double*)ws, out, stream), "norm launch");
+}
+
+int tucker_rthosvd(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                   tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
+                   void* ws, size_t ws_bytes, hipStream_t stream) {
+  return solve(false, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream);
+}
+
+int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                    tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                    tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
+  return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Shared device helpers for the Tucker kernels (gfx950 / CDNA4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tucker.h"
+
+namespace tk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+constexpr int kMaxL = TUCKER_MAX_L;   // widest sketch handled by the kernels
+
+// Which matrix-core instruction a product runs on.
+enum MfmaKind { MF_F32 = 0, MF_F64 = 1, MF_BF16 = 2 };
+
+// Tensor X viewed as row-major [P, n, S]; the mode-k unfolding is
+// X_(k)[i, p*S + s] = X[p, i, s] (columns in row-major order of the other modes).
+struct View {
+  int64_t P, n, S;
+};
+
+// Round-to-nearest-even float -> bf16 bits (inputs are finite in this path;
+// NaN keeps a quiet NaN pattern).
+__device__ __forceinline__ unsigned short f32_to_bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mfma_f64(double a, double b, doublex4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC 2011) and the Box-Muller map that define
+// the Gaussian test matrices Omega_k. Addressing of Omega_k[c, j]:
+//   counter = (c mod 2^32, c div 2^32, j div 4, k), key = (seed lo, seed hi)
+//   pair (w0,w1) for even j div 2, (w2,w3) for odd; u = (w + 1/2) 2^-32
+//   value = sqrt(-2 ln u_a) * (cos 2 pi u_b for even j, sin 2 pi u_b for odd j)
+// ---------------------------------------------------------------------------
+struct U32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U32x4 philox4x32_10(U32x4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = U32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// Four consecutive entries Omega[c, 4g .. 4g+3].
+__device__ __forceinline__ void gaussian4_f64(uint64_t seed, uint32_t mode, uint64_t c, uint32_t g,
+                                              double out[4]) {
+  U32x4 w = philox4x32_10(U32x4{(uint32_t)c, (uint32_t)(c >> 32), g, mode}, (uint32_t)seed,
+                          (uint32_t)(seed >> 32));
+  const double sc = 2.3283064365386963e-10;  // 2^-32
+  double ua = ((double)w.x + 0.5) * sc, ub = ((double)w.y + 0.5) * sc;
+  double r = sqrt(-2.0 * log(ua)), sn, cs;
+  sincospi(2.0 * ub, &sn, &cs);
+  out[0] = r * cs;
+  out[1] = r * sn;
+  ua = ((double)w.z + 0.5) * sc;
+  ub = ((double)w.w + 0.5) * sc;
+  r = sqrt(-2.0 * log(ua));
+  sincospi(2.0 * ub, &sn, &cs);
+  out[2] = r * cs;
+  out[3] = r * sn;
+}
+
+__device__ __forceinline__ void gaussian4_f32(uint64_t seed, uint32_t mode, uint64_t c, uint32_t g,
+                                              float out[4]) {
+  U32x4 w = philox4x32_10(U32x4{(uint32_t)c, (uint32_t)(c >> 32), g, mode}, (uint32_t)seed,
+                          (uint32_t)(seed >> 32));
+  const float sc = 2.3283064365386963e-10f;
+  const float half = 1.16415321826934814e-10f;  // 2^-33
+  float ua = fmaf((float)w.x, sc, half), ub = fmaf((float)w.y, sc, half);
+  float r = sqrtf(-2.0f * logf(ua)), sn, cs;
+  sincospif(2.0f * ub, &sn, &cs);
+  out[0] = r * cs;
+  out[1] = r * sn;
+  ua = fmaf((float)w.z, sc, half);
+  ub = fmaf((float)w.w, sc, half);
+  r = sqrtf(-2.0f * logf(ua));
+  sincospif(2.0f * ub, &sn, &cs);
+  out[2] = r * cs;
+  out[3] = r * sn;
+}
+
+}  // namespace tk

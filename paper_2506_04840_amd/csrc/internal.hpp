@@ -1,0 +1,103 @@
+// Host-side launchers shared by the C-ABI driver and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tucker.h"
+
+namespace tk {
+
+struct View3 {
+  int64_t P, n, S;  // X viewed as row-major [P, n, S]
+};
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Kernel classes of the opt-in launch timing (values of TUCKER_KC_*).
+enum KernelClass { KC_COLREDUCE = 0, KC_ROWCONTRACT = 1, KC_ORTH = 2, KC_FILL = 3, KC_REDUCE = 4, KC_COUNT = 5 };
+
+// Records a HIP event pair around the launches in its scope when `cls` is the
+// enabled class; bytes and flops are the launch's algorithmic traffic and work.
+class TimingScope {
+ public:
+  TimingScope(int cls, hipStream_t st, double bytes, double flops);
+  ~TimingScope();
+  TimingScope(const TimingScope&) = delete;
+  TimingScope& operator=(const TimingScope&) = delete;
+
+ private:
+  int slot_;
+  hipStream_t st_;
+};
+inline size_t elem_bytes(tucker_precision p) { return p == TUCKER_FP64 ? 8 : 4; }
+
+// ---- Gaussian test matrix -------------------------------------------------
+// Writes Omega[row0 + c, j] for c < rows, j < cols into out at
+// ((c / S) * cols + j) * S + (c % S): S = 1 gives a row-major rows x cols
+// matrix, S > 1 the [P, cols, S] layout the column-reduction kernel reads.
+hipError_t launch_fill_gaussian(tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0,
+                                int64_t rows, int cols, int64_t S, void* out, hipStream_t st);
+
+// ---- mode products ----------------------------------------------------------
+// Column reduction: part[split][i][j] = sum over the split's columns c of
+// X_(k)[i, c] * B[c, j], B stored as [P, l, S]. Output type: double for
+// FP64, float otherwise.
+int colreduce_splits(const View3& v, int l);
+size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec);
+hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* B, int l,
+                            void* part, int nsplit, hipStream_t st);
+
+// Y[e] = sum_s part[s][e] - (qsub ? alpha * qsub[e] : 0), FP64 out.
+// qsub_prec gives qsub's element type (FP64 or FP32 storage).
+hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, int nsplit, int64_t nl,
+                                const void* qsub, tucker_precision qsub_prec, const double* alpha,
+                                double* Y, hipStream_t st);
+
+// Row contraction: out[p, j, s] = sum_i X[p, i, s] * W[i, j], W row-major
+// n x lw, out [P, lw, S]. mk selects the matrix-core type (TUCKER_BF16 runs
+// BF16 operands with FP32 accumulation on FP32 data).
+hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X, const void* W, int lw,
+                              void* out, hipStream_t st);
+
+// ||X||^2 with FP64 accumulation; part must hold norm2_blocks() doubles.
+int norm2_blocks(int64_t numel);
+hipError_t launch_norm2(tucker_precision prec, const void* X, int64_t numel, double* part, double* out,
+                        hipStream_t st);
+
+// ---- orthonormalisation (FP64) --------------------------------------------
+struct OrthWs {
+  double* Qa;     // n x l
+  double* Qb;     // n x l
+  double* part;   // gram partials [nblk][l][l]
+  double* R;      // 3 x l x l
+  double* Racc;   // l x l
+  double* Wm;     // l x l
+  int* defic;     // 3 x 64
+  int* status;    // 4 ints: [0] flags, [1] deficient count
+};
+size_t orth_ws_bytes(int64_t n, int l);
+OrthWs carve_orth(void* base, int64_t n, int l);
+
+// [Q, Sigma] = svd(Y, econ). Y FP64 n x l. Q written in `prec` storage to
+// q_out and, when q64 != nullptr, also in FP64. sigma: l doubles.
+// When alpha != nullptr the midpoint shift update is applied to *alpha.
+// When info != nullptr, Sigma(1,1), Sigma(l,l) and alpha are logged at
+// [mode][step], and status bits are or-ed into info->flags.
+hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec, void* q_out, double* q64,
+                       double* sigma, double* alpha, tucker_info* info, int mode, int step,
+                       const OrthWs& ws, uint64_t cseed, hipStream_t st);
+
+// U[:, j] = sign_j * Q[:, j] for j < r: each column's largest-magnitude entry
+// made positive (lowest row index on ties).
+hipError_t launch_signfix(tucker_precision prec, const void* Q, int64_t n, int l, int r, void* U,
+                          hipStream_t st);
+
+// Small helpers.
+hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t count, double* dst,
+                                 hipStream_t st);
+hipError_t launch_info_init(tucker_info* info, const int32_t* l, int d, int32_t flags, hipStream_t st);
+hipError_t launch_set_double(double* dst, double v, hipStream_t st);
+
+}  // namespace tk

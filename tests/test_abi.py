@@ -1,0 +1,90 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments on the host before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tucker.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tucker_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_five_entry_points():
+    names = _declared_functions()
+    for n in ("tucker_sketch", "tucker_shifted_power", "tucker_core", "tucker_rthosvd", "tucker_rsthosvd"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2506_04840_amd import _lib
+    for name in _declared_functions():
+        assert hasattr(_lib.lib, name), name
+        assert name in _lib.SIGNATURES, name
+
+
+def test_info_struct_layout():
+    from paper_2506_04840_amd import _lib
+    assert _lib.INFO_BYTES == 4 + 4 * 8 + 4 * 8 + 4 + 3 * 8 * 17 * 8 + 8
+
+
+def _ws(dims, ranks, p, q, prec, seq):
+    from paper_2506_04840_amd import _lib
+    return _lib.workspace_bytes(dims, ranks, p, q, prec, seq)
+
+
+def test_workspace_query_and_validation():
+    from paper_2506_04840_amd import _lib
+    assert _ws((60, 60, 60), (10, 10, 10), 5, 1, _lib.FP64, False) > 0
+    assert _ws((1000, 1000, 1000), (50, 50, 50), 10, 3, _lib.FP32, True) > 4e8
+    # infeasible Tucker rank: r_3 = 32 > r_1 r_2 = 16 in ST
+    assert _ws((40, 40, 40), (4, 4, 32), 2, 1, _lib.FP32, True) == 0
+    # rank above the mode size, negative p, q too large, l too wide, bad order
+    assert _ws((10, 10, 10), (11, 2, 2), 2, 1, _lib.FP32, True) == 0
+    assert _ws((10, 10, 10), (2, 2, 2), -1, 1, _lib.FP32, True) == 0
+    assert _ws((10, 10, 10), (2, 2, 2), 1, 17, _lib.FP32, True) == 0
+    assert _ws((100, 100, 100), (60, 60, 60), 10, 1, _lib.FP32, True) == 0
+    assert _ws((3,) * 9, (1,) * 9, 1, 1, _lib.FP32, True) == 0
+
+
+def test_error_codes_before_any_launch():
+    from paper_2506_04840_amd import _lib
+    s = _lib._shape((10, 10, 10))
+    r = (ctypes.c_int64 * 3)(2, 2, 2)
+    rc = _lib.lib.tucker_rsthosvd(ctypes.byref(s), None, r, 2, 1, 0, 1, 1, None, None, None, None, 0, None)
+    assert rc == -1
+    assert "null" in _lib.lib.tucker_status_string(rc).decode()
+    big = (ctypes.c_int64 * 3)(60, 60, 60)
+    s2 = _lib._shape((100, 100, 100))
+    rc = _lib.lib.tucker_rsthosvd(ctypes.byref(s2), ctypes.c_void_p(16), big, 10, 1, 0, 1, 1, ctypes.c_void_p(16),
+                                  None, None, None, 0, None)
+    assert rc == -4
+    # workspace too small is reported as such
+    rc = _lib.lib.tucker_sketch(ctypes.byref(s), 0, ctypes.c_void_p(16), 4, 1, 1, ctypes.c_void_p(16),
+                                ctypes.c_void_p(16), 8, None)
+    assert rc == -2
+    # l above n
+    rc = _lib.lib.tucker_sketch(ctypes.byref(s), 0, ctypes.c_void_p(16), 11, 1, 1, ctypes.c_void_p(16),
+                                ctypes.c_void_p(16), 1 << 30, None)
+    assert rc == -1
+    rc = _lib.lib.tucker_core(ctypes.byref(s), 3, ctypes.c_void_p(16), ctypes.c_void_p(16), 2, 1,
+                              ctypes.c_void_p(16), None)
+    assert rc == -1
+    rc = _lib.lib.tucker_orth(10, 11, ctypes.c_void_p(16), 0, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                              ctypes.c_void_p(16), 1 << 20, None)
+    assert rc == -1
+    rc = _lib.lib.tucker_fill_gaussian(1, 9, 0, 10, 10, 0, ctypes.c_void_p(16), None)
+    assert rc == -1
+
+
+def test_python_binding_rejects_host_tensors():
+    import torch
+    from paper_2506_04840_amd import _lib
+    with pytest.raises(ValueError):
+        _lib._dev(torch.zeros(3), "X")

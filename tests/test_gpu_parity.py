@@ -1,0 +1,304 @@
+"""GPU parity: each C-ABI call against the FP64 oracle on the same seeded inputs.
+
+Tolerances (written here, derived in the design doc): FP64 1e-10 and FP32 1e-5,
+relative to the natural scale of each quantity (Cauchy-Schwarz scale for a
+product entry, ||A|| for a reconstruction, Sigma_1 for a shift); subspace
+sine distance <= 1e-4 where the oracle's spectral gap is at least 1e-2
+(FP32) / 1e-6 (FP64) of Sigma_1.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import philox as orc_rng
+from oracle import rhosvd as orc
+from oracle.tensor import reconstruct, unfold
+from workloads import generators as gen
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_04840_amd import _lib
+    return _lib
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+DT = {"fp64": torch.float64, "fp32": torch.float32, "bf16": torch.float32}
+
+
+# --------------------------------------------------------------- generator
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fill_gaussian_matches_oracle(T, prec):
+    for (seed, mode, row0, rows, cols) in [(1, 0, 0, 1000, 13), (7, 2, 12345, 257, 64), (3, 1, (1 << 32) - 5, 20, 5)]:
+        g = _np(T.fill_gaussian(seed, mode, rows, cols, prec, row0=row0))
+        o = orc_rng.gaussian_block(seed, mode, np.arange(row0, row0 + rows), np.arange(cols))
+        err = np.abs(g - o)
+        if prec == "fp64":
+            assert err.max() < 1e-12
+        else:
+            # FP32 Box-Muller: relative 1e-6 except where u_a rounds near 1 (tiny values)
+            assert np.all(err <= 2e-6 * np.abs(o) + 1e-3)
+            assert np.mean(err) < 1e-6
+
+
+# --------------------------------------------------------------- products
+
+SHAPES = [
+    ((60, 60, 60), 0, 15), ((60, 60, 60), 1, 15), ((60, 60, 60), 2, 15),
+    ((37, 130, 29), 1, 33), ((37, 130, 29), 2, 29), ((131, 7, 45), 0, 64),
+    ((5, 6, 7, 8), 2, 7), ((9, 10, 11, 12), 3, 12), ((300, 40), 0, 40), ((200,), 0, 1),
+]
+
+
+def _row_col_scale(xk, b):
+    return np.sqrt(np.sum(xk ** 2, axis=1))[:, None] * np.sqrt(np.sum(b ** 2, axis=0))[None, :]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,mode,l", SHAPES)
+def test_sketch_matches_oracle(T, prec, dims, mode, l):
+    a = gen.rng(3).standard_normal(dims)
+    x = _dev(a, DT[prec])
+    xa = _np(x)
+    y = _np(T.sketch(x, mode, l, seed=11, precision=prec))
+    xk = unfold(xa, mode)
+    om = orc_rng.gaussian_omega(11, mode, xk.shape[1], l)
+    ref = orc.sketch(xa, mode, om)
+    assert np.all(np.abs(y - ref) <= TOL[prec] * _row_col_scale(xk, om))
+
+
+def test_sketch_bf16_is_close(T):
+    a = gen.rng(4).standard_normal((64, 50, 70))
+    x = _dev(a, torch.float32)
+    y = _np(T.sketch(x, 1, 40, seed=2, precision="bf16"))
+    xa = _np(x)
+    xk = unfold(xa, 1)
+    ref = orc.sketch(xa, 1, orc_rng.gaussian_omega(2, 1, xk.shape[1], 40))
+    # bf16 operands: ~2^-9 relative per product, random signs
+    assert np.all(np.abs(y - ref) <= 2e-2 * _row_col_scale(xk, orc_rng.gaussian_omega(2, 1, xk.shape[1], 40)))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,mode,l", SHAPES[:8])
+def test_power_step_raw_matches_oracle(T, prec, dims, mode, l):
+    g = gen.rng(5)
+    a = g.standard_normal(dims)
+    x = _dev(a, DT[prec])
+    xa = _np(x)
+    q0 = np.linalg.qr(g.standard_normal((dims[mode], l)))[0]
+    q = _dev(q0, DT[prec])
+    qa = _np(q)
+    alpha = 0.37 * float(np.linalg.norm(a) ** 2) / dims[mode]
+    al = torch.tensor([alpha], dtype=torch.float64, device="cuda")
+    m = _np(T.shifted_power(x, mode, q, al, raw=True, precision=prec))
+    ref = orc.shifted_power(xa, mode, qa, alpha)
+    scale = np.linalg.norm(xa) ** 2
+    assert np.max(np.abs(m - ref)) <= TOL[prec] * scale
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,mode,r", [((60, 60, 60), 0, 10), ((37, 130, 29), 1, 20), ((37, 130, 29), 2, 5),
+                                         ((5, 6, 7, 8), 1, 3), ((9, 10, 11, 12), 3, 12), ((300, 40), 1, 33),
+                                         ((100, 3, 70), 2, 64)])
+def test_core_matches_oracle(T, prec, dims, mode, r):
+    g = gen.rng(6)
+    a = g.standard_normal(dims)
+    u0 = np.linalg.qr(g.standard_normal((dims[mode], r)))[0] if r <= dims[mode] else g.standard_normal((dims[mode], r))
+    x, u = _dev(a, DT[prec]), _dev(u0, DT[prec])
+    out = _np(T.core(x, mode, u, precision=prec))
+    ref = orc.core_step(_np(x), mode, _np(u))
+    assert out.shape == ref.shape
+    xk = unfold(_np(x), mode)
+    scale = np.sqrt(np.sum(_np(u) ** 2, axis=0)).max() * np.sqrt(np.sum(xk ** 2, axis=0)).max()
+    assert np.max(np.abs(out - ref)) <= TOL[prec] * scale
+
+
+# --------------------------------------------------------------- svd econ
+
+def _matrix_with_spectrum(n, l, s, seed):
+    g = gen.rng(seed)
+    u = np.linalg.qr(g.standard_normal((n, l)))[0]
+    v = np.linalg.qr(g.standard_normal((l, l)))[0]
+    return (u * s[None, :]) @ v.T
+
+
+@pytest.mark.parametrize("n,l,kind", [(60, 15, "flat"), (400, 40, "graded"), (1000, 60, "graded"), (130, 64, "flat"),
+                                      (77, 33, "severe"), (256, 40, "deficient"), (50, 50, "graded"),
+                                      (90, 20, "zero_tail")])
+def test_orth_matches_lapack(T, n, l, kind):
+    if kind == "flat":
+        s = np.linspace(2.0, 1.0, l)
+    elif kind == "graded":
+        s = np.logspace(0, -6, l)
+    elif kind == "severe":
+        s = np.logspace(0, -14, l)
+    elif kind == "deficient":
+        s = np.concatenate([np.logspace(0, -3, l - 7), np.zeros(7)])
+    else:
+        s = np.concatenate([np.logspace(0, -2, l - 3), np.zeros(3)])
+    y = _matrix_with_spectrum(n, l, s, seed=n + l)
+    q, sig = T.orth(_dev(y, torch.float64), "fp64")
+    q, sig = _np(q), _np(sig)
+    s_ref = np.linalg.svd(y, compute_uv=False)
+    # orthonormal columns, descending values, values within u-level of Sigma_1
+    assert np.max(np.abs(q.T @ q - np.eye(l))) < 1e-12
+    assert np.all(np.diff(sig) <= 1e-15 * sig[0])
+    assert np.max(np.abs(sig - s_ref)) < 1e-12 * s_ref[0]
+    # range: Y = Q Q^T Y
+    assert np.linalg.norm(y - q @ (q.T @ y)) < 1e-12 * np.linalg.norm(y)
+    # leading singular vectors match LAPACK up to sign where separated
+    u_ref = np.linalg.svd(y, full_matrices=False)[0]
+    for j in range(l - 1):
+        gap = min(abs(s_ref[j] - s_ref[j + 1]), abs(s_ref[j - 1] - s_ref[j]) if j else np.inf)
+        if gap > 1e-6 * s_ref[0] and s_ref[j] > 1e-8 * s_ref[0]:
+            c = abs(float(q[:, j] @ u_ref[:, j]))
+            assert c > 1 - 1e-8, (j, c)
+
+
+# --------------------------------------------------------------- whole solves
+
+def _align_signs(ug, uo):
+    d = np.sign(np.sum(ug * uo, axis=0))
+    d[d == 0] = 1.0
+    return d
+
+
+def _compare_solve(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, check_core=True):
+    from paper_2506_04840_amd import _lib as T
+    fn = T.rsthosvd if variant == "st" else T.rthosvd
+    G, U, info = fn(a_dev, ranks, p=p, q=q, shift=shift, seed=seed, precision=prec)
+    torch.cuda.synchronize()
+    g, us = _np(G), [_np(u) for u in U]
+    res = orc.randomized_hosvd(a64, ranks, p, q, shift=shift, variant=variant, seed=seed)
+    tol = TOL["fp64" if prec == "fp64" else "fp32"]
+    na = np.linalg.norm(a64)
+    # (i) reconstruction
+    d_rec = np.linalg.norm(reconstruct(g, us) - reconstruct(res.core, res.factors)) / na
+    assert d_rec <= tol, d_rec
+    # orthonormal factors
+    for u in us:
+        assert np.max(np.abs(u.T @ u - np.eye(u.shape[1]))) < (1e-12 if prec == "fp64" else 1e-5)
+    gap_need = 1e-6 if prec == "fp64" else 1e-2
+    for k, lg in enumerate(res.logs):
+        s = lg.sigmas[-1]
+        r = ranks[k]
+        # (iii) shifts and Sigma(l,l), in units of Sigma_1
+        for t in range(q + 1):
+            assert abs(info["alpha"][k][t] - lg.alphas[t]) <= tol * lg.sigmas[t][0], (k, t)
+            assert abs(info["sigma_l"][k][t] - lg.sigmas[t][-1]) <= tol * lg.sigmas[t][0], (k, t)
+            assert abs(info["sigma_1"][k][t] - lg.sigmas[t][0]) <= tol * lg.sigmas[t][0], (k, t)
+        assert info["l"][k] == lg.l
+        # (ii) subspace where the gap allows
+        if r < len(s) and (s[r - 1] - s[r]) >= gap_need * s[0]:
+            uo = res.factors[k]
+            sin = np.linalg.norm(us[k] - uo @ (uo.T @ us[k]), 2)
+            assert sin <= 1e-4, (k, sin)
+    # (iv) core entrywise after sign alignment, when every mode is separated
+    if check_core:
+        gg = g.copy()
+        ok = True
+        for k, lg in enumerate(res.logs):
+            s = lg.sigmas[-1]
+            r = ranks[k]
+            sep = np.all(np.abs(np.diff(s[:r + 1 if r < len(s) else r])) >= gap_need * s[0])
+            ok = ok and sep
+            d = _align_signs(us[k], res.factors[k])
+            gg = np.moveaxis(np.moveaxis(gg, k, -1) * d, -1, k)
+        if ok:
+            assert np.max(np.abs(gg - res.core)) <= 10 * tol * np.linalg.norm(res.core)
+    return G, U, info, res
+
+
+def test_solve_tucker3_60_fp64_thosvd(T):
+    a = gen.make_tensor("tucker3_60_fp64")
+    x = _dev(a, torch.float64)
+    _, _, info, res = _compare_solve(x, a, (10, 10, 10), 5, 1, "adaptive", "t", "fp64")
+    re = orc.rel_error(a, res)
+    assert 0.5e-3 < re < 2e-3
+
+
+@pytest.mark.parametrize("variant", ["t", "st"])
+@pytest.mark.parametrize("q", [0, 1, 2, 3])
+def test_solve_fp64_small_all_q(T, variant, q):
+    a, _, _ = gen.random_tucker((33, 45, 28), (5, 6, 4), 0.05, seed=21)
+    _compare_solve(_dev(a, torch.float64), a, (5, 6, 4), 6, q, "adaptive", variant, "fp64")
+
+
+@pytest.mark.parametrize("shift", ["adaptive", "none"])
+@pytest.mark.parametrize("q", [0, 1, 2, 3])
+def test_solve_hilbert_fp32(T, shift, q):
+    a = gen.hilbert_tensor((96, 96, 96)).astype(np.float32)
+    x = _dev(a, torch.float32)
+    _compare_solve(x, a.astype(np.float64), (30, 30, 30), 10, q, shift, "st", "fp32")
+
+
+def test_solve_order4_fp32(T):
+    a, _, _ = gen.random_tucker((24, 26, 22, 25), (5, 5, 5, 5), 1e-2, seed=8)
+    a32 = a.astype(np.float32)
+    _compare_solve(_dev(a32, torch.float32), a32.astype(np.float64), (5, 5, 5, 5), 10, 2, "adaptive", "st", "fp32")
+
+
+def test_solve_bf16_reports_close_error(T):
+    a, _, _ = gen.random_tucker((40, 44, 36, 30), (6, 6, 6, 6), 1e-2, seed=9)
+    a32 = a.astype(np.float32)
+    G, U, info = T.rsthosvd(_dev(a32, torch.float32), (6, 6, 6, 6), p=10, q=2, precision="bf16")
+    re_g = np.linalg.norm(a32 - reconstruct(_np(G), [_np(u) for u in U])) / np.linalg.norm(a32)
+    res = orc.randomized_hosvd(a32.astype(np.float64), (6, 6, 6, 6), 10, 2, variant="st", seed=1)
+    re_o = orc.rel_error(a32.astype(np.float64), res)
+    assert re_g <= re_o * 1.05
+
+
+def test_exact_rank_recovery_and_deficiency(T):
+    a, _, _ = gen.random_tucker((30, 32, 34), (4, 5, 3), 0.0, seed=12)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        x = _dev(a, DT[prec])
+        for q in (0, 2):
+            G, U, info = T.rsthosvd(x, (4, 5, 3), p=6, q=q, precision=prec)
+            xa = _np(x)
+            re = np.linalg.norm(xa - reconstruct(_np(G), [_np(u) for u in U])) / np.linalg.norm(xa)
+            assert re < tol, (prec, q, re)
+            for u in U:
+                uu = _np(u)
+                assert np.max(np.abs(uu.T @ uu - np.eye(uu.shape[1]))) < 1e-5
+
+
+def test_deterministic_bitwise(T):
+    a = gen.hilbert_tensor((70, 80, 90)).astype(np.float32)
+    x = _dev(a, torch.float32)
+    r1 = T.rsthosvd(x, (12, 12, 12), p=8, q=3)
+    r2 = T.rsthosvd(x, (12, 12, 12), p=8, q=3)
+    assert torch.equal(r1[0], r2[0])
+    for u1, u2 in zip(r1[1], r2[1]):
+        assert torch.equal(u1, u2)
+
+
+def test_q_le_1_shift_invariance_bitwise(T):
+    a, _, _ = gen.random_tucker((50, 40, 45), (5, 5, 5), 0.1, seed=2)
+    x = _dev(a.astype(np.float32), torch.float32)
+    for q in (0, 1):
+        ra = T.rsthosvd(x, (5, 5, 5), p=5, q=q, shift="adaptive")
+        rn = T.rsthosvd(x, (5, 5, 5), p=5, q=q, shift="none")
+        assert torch.equal(ra[0], rn[0])
+
+
+def test_edge_shapes(T):
+    # order 1 and 2, n = r, clamped l, tiny modes, ragged tails
+    cases = [((200,), (1,), 3, 1), ((64, 48), (10, 10), 4, 2), ((16, 17, 18), (16, 3, 2), 5, 1),
+             ((3, 100, 5), (3, 9, 5), 10, 2), ((129, 2, 257), (7, 2, 11), 4, 1)]
+    for dims, ranks, p, q in cases:
+        a, _, _ = gen.random_tucker(dims, tuple(min(r + 1, n) for r, n in zip(ranks, dims)), 0.05, seed=len(dims))
+        _compare_solve(_dev(a, torch.float64), a, ranks, p, q, "adaptive", "st", "fp64", check_core=False)
