@@ -85,7 +85,7 @@ typedef struct {
   int32_t flags;                                /* TUCKER_INFO_* bits */
   int32_t l[TUCKER_MAX_ORDER];                  /* sketch width l_k used at each mode */
   int32_t deficient[TUCKER_MAX_ORDER];          /* deficient columns seen at the last svd of mode k */
-  int32_t reserved;
+  int32_t jacobi_sweeps;                        /* most sweeps any small SVD of the solve took */
   double alpha[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1];   /* alpha_t^(k), t = 0..q */
   double sigma_1[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1]; /* Sigma_k(1,1) after svd t (t=0: sketch) */
   double sigma_l[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1]; /* Sigma_k(l,l) after svd t */

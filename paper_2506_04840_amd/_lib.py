@@ -41,7 +41,7 @@ class Info(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("l", ctypes.c_int32 * MAX_ORDER),
         ("deficient", ctypes.c_int32 * MAX_ORDER),
-        ("reserved", ctypes.c_int32),
+        ("jacobi_sweeps", ctypes.c_int32),
         ("alpha", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
         ("sigma_1", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
         ("sigma_l", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
@@ -155,6 +155,7 @@ def read_info(info: torch.Tensor) -> dict:
         "flags": int(st.flags),
         "l": [int(x) for x in st.l],
         "deficient": [int(x) for x in st.deficient],
+        "jacobi_sweeps": int(st.jacobi_sweeps),
         "alpha": [[float(x) for x in row] for row in st.alpha],
         "sigma_1": [[float(x) for x in row] for row in st.sigma_1],
         "sigma_l": [[float(x) for x in row] for row in st.sigma_l],

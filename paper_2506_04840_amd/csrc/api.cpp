@@ -149,7 +149,8 @@ struct SolveWs {
   void* omz;
   void* part;
   double* y64;
-  void* qt;
+  void* qt;    // Q j-major (l x n), storage precision: the power step's X^T Q operand
+  void* ut;    // U_k j-major (r x n), storage precision: the core step's operand
   double* q64;
   double* sigma;
   double* alpha;
@@ -171,6 +172,7 @@ size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveW
   w->part = take(pl.part_bytes);
   w->y64 = (double*)take((size_t)pl.nl_max * 8);
   w->qt = take((size_t)pl.nl_max * es);
+  w->ut = take((size_t)pl.nl_max * es);
   w->q64 = (double*)take((size_t)pl.nl_max * 8);
   w->sigma = (double*)take(TUCKER_MAX_L * 8);
   w->alpha = (double*)take(TUCKER_MAX_ORDER * 8);
@@ -195,12 +197,13 @@ int sketch_mode(const Plan& pl, int k, const void* X, uint64_t seed, tucker_prec
   double* alpha = w.alpha + k;
   hipError_t e;
   // Y = X_(k) Omega_k
-  e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, v.S, w.omz,
+  e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, true, w.omz,
                            st);
   if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
   if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_set_double(alpha, 0.0, st);
-  if (e == hipSuccess) e = launch_orth(n, l, w.y64, prec, w.qt, w.q64, w.sigma, nullptr, info, k, 0, ows, cseed, st);
+  if (e == hipSuccess)
+    e = launch_orth(n, l, w.y64, prec, nullptr, w.qt, w.q64, w.sigma, nullptr, info, k, 0, ows, cseed, st);
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "sketch launch");
 }
 
@@ -216,14 +219,14 @@ int power_steps(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   double* alpha = w.alpha + k;
   hipError_t e = hipSuccess;
   for (int t = 1; t <= q && e == hipSuccess; ++t) {
-    // Z = X_(k)^T Q in the [P, l, S] layout, then Y = X_(k) Z - alpha Q
-    e = launch_rowcontract(prec, v, X, w.qt, l, w.omz, st);
+    // Z = X_(k)^T Q (j-major), then Y = X_(k) Z - alpha Q
+    e = launch_rowcontract(prec, v, X, w.qt, 1, n, l, w.omz, true, st);
     if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
     if (e == hipSuccess)
       e = launch_reduce_splits(prec, w.part, nsplit, n * l, w.q64, TUCKER_FP64, alpha, w.y64, st);
     if (e == hipSuccess)
-      e = launch_orth(n, l, w.y64, prec, w.qt, w.q64, w.sigma, shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr, info,
-                      k, t, ows, cseed, st);
+      e = launch_orth(n, l, w.y64, prec, nullptr, w.qt, w.q64, w.sigma, shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr,
+                      info, k, t, ows, cseed, st);
   }
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "power step launch");
 }
@@ -261,11 +264,11 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
     rc = sketch_mode(pl, k, Xk, seed, prec, info, w, st);
     if (!rc) rc = power_steps(pl, k, Xk, q, shift, seed, prec, info, w, st);
     if (rc) return rc;
-    e = launch_signfix(prec, w.qt, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], st);
+    e = launch_signfix(prec, w.q64, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], w.ut, st);
     if (e != hipSuccess) return dev_check(e, "sign rule launch");
     if (st_variant) {
       void* out = (k == pl.d - 1) ? G : w.xbuf[k & 1];
-      e = launch_rowcontract(core_mk, pl.v[k], X, U[k], (int)pl.r[k], out, st);
+      e = launch_rowcontract(core_mk, pl.v[k], X, w.ut, 1, pl.v[k].n, (int)pl.r[k], out, false, st);
       if (e != hipSuccess) return dev_check(e, "core launch");
       X = out;
     }
@@ -274,7 +277,7 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
     for (int k = 0; k < pl.d; ++k) {
       const View3 v = view_of(cur, pl.d, k);
       void* out = (k == pl.d - 1) ? G : w.xbuf[k & 1];
-      e = launch_rowcontract(core_mk, v, X, U[k], (int)pl.r[k], out, st);
+      e = launch_rowcontract(core_mk, v, X, U[k], pl.r[k], 1, (int)pl.r[k], out, false, st);
       if (e != hipSuccess) return dev_check(e, "core launch");
       X = out;
       cur[k] = pl.r[k];
@@ -365,7 +368,7 @@ int tucker_fill_gaussian(uint64_t seed, int32_t mode, int64_t row0, int64_t rows
   if (rows * cols == 0) return TUCKER_OK;
   if (out == nullptr) return fail(TUCKER_EINVAL, "out is null");
   return dev_check(launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)mode, row0,
-                                        rows, (int)cols, 1, out, stream),
+                                        rows, (int)cols, false, out, stream),
                    "fill launch");
 }
 
@@ -382,7 +385,7 @@ int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_
   op_ws_layout(v, m, (int)l, prec, (char*)ws, &w);
   const int nsplit = colreduce_splits(v, (int)l);
   hipError_t e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)mode, 0, m,
-                                      (int)l, v.S, w.omz, stream);
+                                      (int)l, true, w.omz, stream);
   if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
   if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, v.n * l, nullptr, prec, nullptr, Y, stream);
   return dev_check(e, "sketch launch");
@@ -405,14 +408,14 @@ int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X,
   op_ws_layout(v, m, (int)l, prec, (char*)ws, &w);
   const int nsplit = colreduce_splits(v, (int)l);
   double* y = raw ? (double*)out : w.y64;
-  hipError_t e = launch_rowcontract(prec, v, X, Q, (int)l, w.omz, stream);
+  hipError_t e = launch_rowcontract(prec, v, X, Q, l, 1, (int)l, w.omz, true, stream);
   if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
   if (e == hipSuccess)
     e = launch_reduce_splits(prec, w.part, nsplit, v.n * l, Q, prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32,
                              alpha, y, stream);
   if (e == hipSuccess && !raw) {
     const OrthWs ows = carve_orth(w.orth, v.n, (int)l);
-    e = launch_orth(v.n, (int)l, y, prec, out, nullptr, sigma, alpha, nullptr, -1, -1, ows,
+    e = launch_orth(v.n, (int)l, y, prec, out, nullptr, nullptr, sigma, alpha, nullptr, -1, -1, ows,
                     completion_seed(0x5eedull, mode), stream);
   }
   return dev_check(e, "power step launch");
@@ -426,7 +429,7 @@ int tucker_orth(int64_t n, int64_t l, const double* Y, tucker_precision prec, vo
   const size_t need = orth_ws_bytes(n, (int)l);
   if (ws == nullptr || ws_bytes < need) return fail(TUCKER_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
   const OrthWs ows = carve_orth(ws, n, (int)l);
-  return dev_check(launch_orth(n, (int)l, Y, prec, Q, nullptr, sigma, nullptr, nullptr, -1, -1, ows,
+  return dev_check(launch_orth(n, (int)l, Y, prec, Q, nullptr, nullptr, sigma, nullptr, nullptr, -1, -1, ows,
                                completion_seed(0x0a7bull, 0), stream),
                    "orth launch");
 }
@@ -441,7 +444,8 @@ int tucker_core(const tucker_shape* shape, int32_t mode, const void* X, const vo
   if (r < 1 || r > TUCKER_MAX_L) return fail(TUCKER_EINVAL, "r = %lld outside 1..%d", (long long)r, TUCKER_MAX_L);
   if (X == nullptr || U == nullptr || Xout == nullptr) return fail(TUCKER_EINVAL, "null argument");
   const View3 v = view_of(shape->dims, shape->order, mode);
-  return dev_check(launch_rowcontract(prec == TUCKER_BF16 ? TUCKER_FP32 : prec, v, X, U, (int)r, Xout, stream),
+  return dev_check(launch_rowcontract(prec == TUCKER_BF16 ? TUCKER_FP32 : prec, v, X, U, r, 1, (int)r, Xout, false,
+                                      stream),
                    "core launch");
 }
 

@@ -34,16 +34,15 @@ class TimingScope {
 inline size_t elem_bytes(tucker_precision p) { return p == TUCKER_FP64 ? 8 : 4; }
 
 // ---- Gaussian test matrix -------------------------------------------------
-// Writes Omega[row0 + c, j] for c < rows, j < cols into out at
-// ((c / S) * cols + j) * S + (c % S): S = 1 gives a row-major rows x cols
-// matrix, S > 1 the [P, cols, S] layout the column-reduction kernel reads.
+// Writes Omega[row0 + c, j] for c < rows, j < cols: jmajor -> out[j * rows + c]
+// (the [cols, rows] layout the column reduction reads), else out[c * cols + j].
 hipError_t launch_fill_gaussian(tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0,
-                                int64_t rows, int cols, int64_t S, void* out, hipStream_t st);
+                                int64_t rows, int cols, bool jmajor, void* out, hipStream_t st);
 
 // ---- mode products ----------------------------------------------------------
 // Column reduction: part[split][i][j] = sum over the split's columns c of
-// X_(k)[i, c] * B[c, j], B stored as [P, l, S]. Output type: double for
-// FP64, float otherwise.
+// X_(k)[i, c] * B[c, j], B stored j-major as Bt[j * m + c] (m = P S).
+// Output type: double for FP64, float otherwise.
 int colreduce_splits(const View3& v, int l);
 size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec);
 hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* B, int l,
@@ -55,11 +54,14 @@ hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, in
                                 const void* qsub, tucker_precision qsub_prec, const double* alpha,
                                 double* Y, hipStream_t st);
 
-// Row contraction: out[p, j, s] = sum_i X[p, i, s] * W[i, j], W row-major
-// n x lw, out [P, lw, S]. mk selects the matrix-core type (TUCKER_BF16 runs
-// BF16 operands with FP32 accumulation on FP32 data).
-hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X, const void* W, int lw,
-                              void* out, hipStream_t st);
+// Row contraction: out(p, j, s) = sum_i X[p, i, s] * W(i, j) with
+// W(i, j) = W[i * wsi + j * wsj] (row-major n x lw: wsi = lw, wsj = 1;
+// j-major: wsi = 1, wsj = n). out_jmajor: out[j * m + p * S + s] (the layout
+// the column reduction reads), else the tensor layout [P, lw, S].
+// mk selects the matrix-core type (TUCKER_BF16 runs BF16 operands with FP32
+// accumulation on FP32 data).
+hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X, const void* W, int64_t wsi,
+                              int64_t wsj, int lw, void* out, bool out_jmajor, hipStream_t st);
 
 // ||X||^2 with FP64 accumulation; part must hold norm2_blocks() doubles.
 int norm2_blocks(int64_t numel);
@@ -80,18 +82,20 @@ struct OrthWs {
 size_t orth_ws_bytes(int64_t n, int l);
 OrthWs carve_orth(void* base, int64_t n, int l);
 
-// [Q, Sigma] = svd(Y, econ). Y FP64 n x l. Q written in `prec` storage to
-// q_out and, when q64 != nullptr, also in FP64. sigma: l doubles.
+// [Q, Sigma] = svd(Y, econ). Y FP64 n x l. Q is written (each when not
+// nullptr) to q_out (n x l, `prec` storage), qt (j-major l x n, `prec`
+// storage) and q64 (n x l, FP64). sigma: l doubles.
 // When alpha != nullptr the midpoint shift update is applied to *alpha.
 // When info != nullptr, Sigma(1,1), Sigma(l,l) and alpha are logged at
 // [mode][step], and status bits are or-ed into info->flags.
-hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec, void* q_out, double* q64,
-                       double* sigma, double* alpha, tucker_info* info, int mode, int step,
+hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec, void* q_out, void* qt,
+                       double* q64, double* sigma, double* alpha, tucker_info* info, int mode, int step,
                        const OrthWs& ws, uint64_t cseed, hipStream_t st);
 
-// U[:, j] = sign_j * Q[:, j] for j < r: each column's largest-magnitude entry
-// made positive (lowest row index on ties).
-hipError_t launch_signfix(tucker_precision prec, const void* Q, int64_t n, int l, int r, void* U,
+// U[:, j] = sign_j * Q[:, j] for j < r (Q FP64 n x l): each column's
+// largest-magnitude entry made positive (lowest row index on ties). U is
+// n x r and Ut (when not nullptr) j-major r x n, both in `prec` storage.
+hipError_t launch_signfix(tucker_precision prec, const double* Q, int64_t n, int l, int r, void* U, void* Ut,
                           hipStream_t st);
 
 // Small helpers.

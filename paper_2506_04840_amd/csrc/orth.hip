@@ -14,26 +14,31 @@
 // dependent on the previous ones: its row of R is zero and the solve puts a
 // random Gaussian direction in that column, which the next pass
 // orthonormalises. Those columns end with Sigma = 0.
+//
+// Launches per call: gram(Y), 3 x pass(p), svd, rotate. Each pass kernel sums
+// the previous pass's Gram partials in block order and factors W itself (the
+// same bits in every block), solves its 64 rows and writes the Gram partial
+// of its output rows for the next pass.
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace tk {
 
-constexpr int OR_RB = 64;      // rows per workgroup in gram / solve kernels
-constexpr int OR_LS = kMaxL + 1;  // LDS row stride for l x l matrices
+constexpr int OR_RB = 64;         // rows per workgroup in the gram / pass kernels
+constexpr int OR_LS = kMaxL + 1;  // LDS row stride for 64-wide matrices
 
 size_t orth_ws_bytes(int64_t n, int l) {
   const size_t nl = (size_t)n * l * sizeof(double);
   const size_t nblk = (size_t)((n + OR_RB - 1) / OR_RB);
   size_t b = 0;
-  b += align_up(nl);                                  // Qa
-  b += align_up(nl);                                  // Qb
-  b += align_up(nblk * l * l * sizeof(double));       // gram partials
+  b += align_up(nl);                                          // Qa
+  b += align_up(nl);                                          // Qb
+  b += 2 * align_up(nblk * l * l * sizeof(double));           // gram partials, ping-pong
   b += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));  // R1..R3
   b += align_up((size_t)kMaxL * kMaxL * sizeof(double));      // Racc
   b += align_up((size_t)kMaxL * kMaxL * sizeof(double));      // Wm
-  b += align_up(3 * kMaxL * sizeof(int));             // deficiency flags
-  b += align_up(4 * sizeof(int));                     // status
+  b += align_up(3 * kMaxL * sizeof(int));                     // deficiency flags
+  b += align_up(4 * sizeof(int));                             // status
   return b;
 }
 
@@ -44,7 +49,7 @@ OrthWs carve_orth(void* base, int64_t n, int l) {
   OrthWs w;
   w.Qa = (double*)p; p += align_up(nl);
   w.Qb = (double*)p; p += align_up(nl);
-  w.part = (double*)p; p += align_up(nblk * l * l * sizeof(double));
+  w.part = (double*)p; p += 2 * align_up(nblk * l * l * sizeof(double));
   w.R = (double*)p; p += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
   w.Racc = (double*)p; p += align_up((size_t)kMaxL * kMaxL * sizeof(double));
   w.Wm = (double*)p; p += align_up((size_t)kMaxL * kMaxL * sizeof(double));
@@ -53,224 +58,434 @@ OrthWs carve_orth(void* base, int64_t n, int l) {
   return w;
 }
 
-// Gram partials of a 64-row block: part[blk][a][b] = sum_r Y[r][a] Y[r][b].
-__device__ __forceinline__ void block_gram(const double (*Zs)[OR_LS], int l, double* __restrict__ part_blk) {
-  for (int e = threadIdx.x; e < l * l; e += 256) {
-    const int a = e / l, b = e - (e / l) * l;
-    double s = 0.0;
-#pragma unroll 8
-    for (int r = 0; r < OR_RB; ++r) s = fma(Zs[r][a], Zs[r][b], s);
-    part_blk[e] = s;
-  }
+// Full-precision reciprocal and reciprocal square root: hardware estimate plus
+// two Newton steps (each squares the relative error).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return r;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
 }
 
-template <typename TIN>
-__global__ __launch_bounds__(256) void k_gram(const TIN* __restrict__ Y, int64_t n, int l, double* __restrict__ part) {
-  __shared__ double Zs[OR_RB][OR_LS];
-  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
-  for (int e = threadIdx.x; e < OR_RB * l; e += 256) {
-    const int r = e / l, j = e - (e / l) * l;
-    Zs[r][j] = (r0 + r < n) ? (double)Y[(r0 + r) * l + j] : 0.0;
-  }
-  __syncthreads();
-  block_gram(Zs, l, part + (size_t)blockIdx.x * l * l);
+// Entry (row, col) of a completion direction for a deficient column: a value
+// uniform in [-1, 1) from the splitmix64 finaliser of (seed, tag, row, col).
+// Any direction in general position works: the next pass orthonormalises it.
+__device__ __forceinline__ double completion_entry(uint64_t seed, uint32_t tag, uint64_t row, uint32_t col) {
+  uint64_t z = seed ^ (row * 0x9E3779B97F4A7C15ull) ^ ((uint64_t)col << 32) ^ ((uint64_t)tag << 48);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(int64_t)z * 1.0842021724855044e-19;  // 2^-63
 }
 
-// Q_out = Q_in R^-1 row by row (forward substitution on the upper factor);
-// deficient columns get a Gaussian direction / sqrt(n). Optionally the Gram
-// partials of Q_out for the next pass.
-__global__ __launch_bounds__(256) void k_solve_gram(const double* __restrict__ Qin, int64_t n, int l,
-                                                    const double* __restrict__ R, const int* __restrict__ defic,
-                                                    uint64_t cseed, uint32_t ctag, double* __restrict__ Qout,
-                                                    double* __restrict__ part) {
-  __shared__ double Rs[kMaxL][OR_LS];
-  __shared__ double Zs[OR_RB][OR_LS];
-  __shared__ int dfs[kMaxL];
-  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
-  for (int e = threadIdx.x; e < l * l; e += 256) {
-    const int a = e / l, b = e - (e / l) * l;
-    Rs[a][b] = R[e];
+// Sum over the 8 lanes of an aligned octet with DPP moves (no LDS traffic):
+// xor-1 and xor-2 inside each quad, then the row half-mirror joins the quads.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+  const uint64_t u = __double_as_longlong(v);
+  int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+  if (ctrl_sel == 0) {
+    lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
+  } else if (ctrl_sel == 1) {
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
+  } else {
+    lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
+    hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false);
   }
-  if ((int)threadIdx.x < l) dfs[threadIdx.x] = defic[threadIdx.x];
-  for (int e = threadIdx.x; e < OR_RB * l; e += 256) {
-    const int r = e / l, j = e - (e / l) * l;
-    Zs[r][j] = (r0 + r < n) ? Qin[(r0 + r) * l + j] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x < OR_RB) {
-    const int r = threadIdx.x;
-    const int64_t i = r0 + r;
-    if (i < n) {
-      const double inv_sqrt_n = 1.0 / sqrt((double)n);
-      for (int j = 0; j < l; ++j) {
-        double z;
-        if (dfs[j]) {
-          double g4[4];
-          gaussian4_f64(cseed, ctag, (uint64_t)i, (uint32_t)(j >> 2), g4);
-          z = g4[j & 3] * inv_sqrt_n;
-        } else {
-          double s = Zs[r][j];
-          for (int k = 0; k < j; ++k) s = fma(-Zs[r][k], Rs[k][j], s);
-          z = s / Rs[j][j];
-        }
-        Zs[r][j] = z;
-      }
-      for (int j = 0; j < l; ++j) Qout[i * l + j] = Zs[r][j];
+  return __longlong_as_double(((int64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double octet_sum(double v) {
+  v += dpp_f64(v, 0);
+  v += dpp_f64(v, 1);
+  v += dpp_f64(v, 2);
+  return v;
+}
+
+// Gram of 64 rows held in LDS, for the 2-D thread grid (ta, tb) = (tid/16, tid%16):
+// the thread owns W[ta + 16 i][tb + 16 j], i, j < LP/16.
+template <int LP>
+__device__ __forceinline__ void block_gram_store(const double (*Zs)[OR_LS], int l, double* __restrict__ part_blk) {
+  constexpr int NB = LP / 16;
+  const int ta = threadIdx.x >> 4, tb = threadIdx.x & 15;
+  double acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = 0.0;
+#pragma unroll 2
+  for (int r = 0; r < OR_RB; ++r) {
+    double za[NB], zb[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      za[i] = Zs[r][ta + 16 * i];
+      zb[i] = Zs[r][tb + 16 * i];
     }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) acc[i][j] = fma(za[i], zb[j], acc[i][j]);
   }
-  if (part == nullptr) return;
-  __syncthreads();
-  block_gram(Zs, l, part + (size_t)blockIdx.x * l * l);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int a = ta + 16 * i, b = tb + 16 * j;
+      if (a < l && b < l) part_blk[a * l + b] = acc[i][j];
+    }
 }
 
-// Sum the Gram partials in block order, optionally shift, then Cholesky
-// W = R^T R (R upper) with deficiency detection. Racc <- R * Racc (or R).
-__global__ __launch_bounds__(256) void k_chol(const double* __restrict__ part, int nblk, int64_t n, int l,
-                                              int shifted, double tau, double* __restrict__ Rout,
-                                              int* __restrict__ defic, double* __restrict__ Racc, int accumulate,
-                                              int* __restrict__ status) {
-  __shared__ double W[kMaxL][OR_LS];
+template <int LP>
+__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Y, int64_t n, int l, double* __restrict__ part) {
+  __shared__ double Zs[OR_RB][OR_LS];
+  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
+  for (int e = threadIdx.x; e < OR_RB * LP; e += 256) {
+    const int r = e / LP, j = e % LP;
+    Zs[r][j] = (r0 + r < n && j < l) ? Y[(r0 + r) * l + j] : 0.0;
+  }
+  __syncthreads();
+  block_gram_store<LP>(Zs, l, part + (size_t)blockIdx.x * l * l);
+}
+
+// One CholeskyQR pass over 64 rows per block.
+//   W = sum_b part_in[b] (+ s I when shifted); R = chol(W) with deficiency
+//   flags; Qout rows = Qin rows R^-1 (deficient columns: Gaussian / sqrt(n));
+//   part_out[blk] = Gram of this block's Qout rows (if part_out != nullptr).
+// Block 0 also writes R and the flags for the small SVD.
+template <int LP>
+__global__ __launch_bounds__(256) void k_pass(const double* __restrict__ Qin, int64_t n, int l,
+                                              const double* __restrict__ part_in, int nblk, int shifted, double tau,
+                                              uint64_t cseed, uint32_t ctag, double* __restrict__ Qout,
+                                              double* __restrict__ part_out, double* __restrict__ Rg,
+                                              int* __restrict__ defic_g, int* __restrict__ status) {
+  constexpr int NB = LP / 16;
   __shared__ double Rl[kMaxL][OR_LS];
-  __shared__ double Ra[kMaxL][OR_LS];
-  __shared__ double red[256];
+  __shared__ double Zs[OR_RB][OR_LS];
+  __shared__ double rrow[kMaxL];
+  __shared__ double inv_diag[kMaxL];
+  __shared__ int dfs[kMaxL];
+  __shared__ double red[2][16];
+  __shared__ double piv;
   __shared__ int bad;
+
   const int tid = threadIdx.x;
+  const int ta = tid >> 4, tb = tid & 15;
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int e = tid; e < l * l; e += 256) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * l * l + e];
-    const int a = e / l, c = e - (e / l) * l;
-    W[a][c] = s;
-    if (!isfinite(s)) bad = 1;
-    if (accumulate) Ra[a][c] = Racc[e];
+
+  // 1. W in registers: thread owns W[ta + 16 i][tb + 16 j]; the partials are
+  //    summed in block order, four blocks of loads in flight at a time
+  double W[NB][NB];
+  double mytr = 0.0, mymax = 0.0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) W[i][j] = 0.0;
+  for (int b0 = 0; b0 < nblk; b0 += 4) {
+    double v[4][NB][NB];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int a = ta + 16 * i, b = tb + 16 * j;
+          v[q][i][j] = (b0 + q < nblk && a < l && b < l) ? part_in[(size_t)(b0 + q) * l * l + a * l + b] : 0.0;
+        }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) W[i][j] += v[q][i][j];
   }
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (!isfinite(W[i][j])) bad = 1;
   __syncthreads();
-  double tr = 0.0;
-  for (int a = tid; a < l; a += 256) tr += W[a][a];
-  red[tid] = tr;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  const double trace = red[0];
-  __syncthreads();
-  if (shifted) {
-    const double u = 1.1102230246251565e-16;
-    const double s = 11.0 * ((double)n * l + (double)l * (l + 1)) * u * trace;
-    for (int a = tid; a < l; a += 256) W[a][a] += s;
-  }
-  __syncthreads();
-  double md = 0.0;
-  for (int a = tid; a < l; a += 256) md = fmax(md, W[a][a]);
-  red[tid] = md;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-    __syncthreads();
-  }
-  const double maxdiag = red[0];
   const bool anybad = bad != 0;
+  // trace (diagonal owners: ta == tb, i == j)
+  if (ta == tb) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) mytr += W[i][i];
+    red[0][ta] = mytr;
+  }
   __syncthreads();
-  int ndef = 0;
-  for (int j = 0; j < l; ++j) {
-    const double d = W[j][j];
-    const bool dep = !(d > tau * maxdiag) || anybad;
-    const double rjj = dep ? 0.0 : sqrt(d);
-    for (int k = tid; k < l; k += 256) {
-      double v = 0.0;
-      if (!dep && k >= j) v = (k == j) ? rjj : W[j][k] / rjj;
-      Rl[j][k] = v;
+  double trace = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) trace += red[0][t];
+  const double shift = shifted ? 11.0 * ((double)n * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * trace : 0.0;
+  if (ta == tb) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      W[i][i] += shift;
+      mymax = fmax(mymax, W[i][i]);
     }
-    if (tid == 0) defic[j] = dep ? 1 : 0;
+    red[1][ta] = mymax;
+  }
+  __syncthreads();
+  double maxdiag = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) maxdiag = fmax(maxdiag, red[1][t]);
+
+  // 2. right-looking Cholesky, W = R^T R, R upper
+  int ndef = 0;
+  for (int k = 0; k < l; ++k) {
+    const int kt = k & 15, ki = k >> 4;
+    if (ta == kt && tb == kt) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i == ki) piv = W[i][i];
+    }
+    __syncthreads();
+    const double d = piv;
+    const bool dep = !(d > tau * maxdiag) || anybad;
+    const double inv = dep ? 0.0 : rsq_nr(d);  // 1 / sqrt(d)
+    const double rkk = d * inv;
+    if (ta == kt) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i == ki) {
+#pragma unroll
+          for (int j = 0; j < NB; ++j) {
+            const int b = tb + 16 * j;
+            if (b < l) {
+              double v = 0.0;
+              if (!dep && b >= k) v = (b == k) ? rkk : W[i][j] * inv;
+              rrow[b] = v;
+              Rl[k][b] = v;
+            }
+          }
+        }
+    }
+    if (tid == 0) {
+      dfs[k] = dep ? 1 : 0;
+      inv_diag[k] = inv;
+    }
     ndef += dep ? 1 : 0;
     __syncthreads();
-    const int m = l - j - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int a = j + 1 + e / m, b = j + 1 + (e - (e / m) * m);
-      W[a][b] = fma(-Rl[j][a], Rl[j][b], W[a][b]);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int a = ta + 16 * i;
+      if (a > k && a < l) {
+        const double ra = rrow[a];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const int b = tb + 16 * j;
+          if (b > k && b < l) W[i][j] = fma(-ra, rrow[b], W[i][j]);
+        }
+      }
     }
-    __syncthreads();
   }
-  for (int e = tid; e < l * l; e += 256) {
-    const int a = e / l, c = e - (e / l) * l;
-    Rout[e] = Rl[a][c];
-    double s;
-    if (accumulate) {
-      s = 0.0;
-      for (int k = a; k <= c; ++k) s = fma(Rl[a][k], Ra[k][c], s);
-    } else {
-      s = Rl[a][c];
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < l * l; e += 256) Rg[e] = Rl[e / l][e % l];
+    if (tid < l) defic_g[tid] = dfs[tid];
+    if (tid == 0) {
+      if (anybad) atomicOr(&status[0], TUCKER_INFO_NONFINITE);
+      if (ndef) {
+        atomicOr(&status[0], TUCKER_INFO_DEFICIENT);
+        atomicMax(&status[1], ndef);
+      }
     }
-    Racc[e] = s;
   }
-  if (tid == 0) {
-    if (anybad) atomicOr(&status[0], TUCKER_INFO_NONFINITE);
-    if (ndef) {
-      atomicOr(&status[0], TUCKER_INFO_DEFICIENT);
-      atomicMax(&status[1], ndef);
+
+  // 3. forward substitution z R = y for the block's 64 rows: 4 lanes per row
+  //    (one quad), each summing a fixed quarter of the dot product, combined
+  //    by two DPP exchanges; the row lives in LDS.
+  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
+  for (int e = tid; e < OR_RB * LP; e += 256) {
+    const int r = e / LP, j = e % LP;
+    Zs[r][j] = (r0 + r < n && j < l) ? Qin[(r0 + r) * l + j] : 0.0;
+  }
+  __syncthreads();
+  {
+    const int r = tid >> 2, t = tid & 3;
+    const int64_t i = r0 + r;
+    const double inv_sqrt_n = rsqrt((double)n);
+    for (int j = 0; j < l; ++j) {
+      double z;
+      if (dfs[j]) {
+        z = (i < n) ? completion_entry(cseed, ctag, (uint64_t)i, (uint32_t)j) * inv_sqrt_n : 0.0;
+      } else {
+        double s = 0.0, s2 = 0.0;
+        int k = t;
+        for (; k + 4 < j; k += 8) {
+          s = fma(Zs[r][k], Rl[k][j], s);
+          s2 = fma(Zs[r][k + 4], Rl[k + 4][j], s2);
+        }
+        if (k < j) s = fma(Zs[r][k], Rl[k][j], s);
+        s += s2;
+        s += dpp_f64(s, 0);
+        s += dpp_f64(s, 1);
+        z = (Zs[r][j] - s) * inv_diag[j];
+      }
+      if (t == 0) Zs[r][j] = z;
     }
+  }
+  __syncthreads();
+  for (int e = tid; e < OR_RB * l; e += 256) {
+    const int r = e / l, j = e % l;
+    if (r0 + r < n) Qout[(r0 + r) * l + j] = Zs[r][j];
+  }
+  if (part_out == nullptr) return;
+  __syncthreads();
+  block_gram_store<LP>(Zs, l, part_out + (size_t)blockIdx.x * l * l);
+}
+
+// C = A B for 64-wide LDS matrices (full product; the zero triangles add
+// exact zeros), thread grid (ta, tb) owning C[ta + 16 i][tb + 16 j].
+__device__ __forceinline__ void tile_matmul(const double (*Am)[OR_LS], const double (*Bm)[OR_LS], int l,
+                                            double (&c)[4][4]) {
+  const int ta = threadIdx.x >> 4, tb = threadIdx.x & 15;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[i][j] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < l; ++k) {
+    double x[4], y[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      x[i] = Am[ta + 16 * i][k];
+      y[i] = Bm[k][tb + 16 * i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[i][j] = fma(x[i], y[j], c[i][j]);
   }
 }
 
-// One-sided Jacobi SVD of R^T (l x l, from Racc), then sort. Writes
-// Wm = left singular vectors of R (columns, descending), sigma, the shift
-// update and the info log. One workgroup; 8 threads per column pair.
-__global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Racc, int l, double* __restrict__ Wm,
+// Rotation (c, s) that orthogonalises two columns with squared norms al, be
+// and inner product ga: t = sign(d) g / (|d| + sqrt(d^2 + g^2)), d = be - al,
+// g = 2 ga. The angle is computed in FP32 on power-of-two-scaled inputs (any
+// angle is a valid rotation; this one annihilates ga to ~1e-7 relative), then
+// c = 1 / sqrt(1 + t^2) in FP64 by Newton, so c^2 + s^2 = 1 to rounding.
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double& c, double& s) {
+  const double d = be - al, g = 2.0 * ga;
+  const int e = ilogb(fmax(fabs(d), fabs(g)));
+  const float df = (float)ldexp(d, -e), gf = (float)ldexp(g, -e);
+  const float h = sqrtf(fmaf(df, df, gf * gf));
+  const float tf = copysignf(1.0f, df) * gf * __builtin_amdgcn_rcpf(fabsf(df) + h);
+  const double t = (double)tf;
+  const double x = fma(t, t, 1.0);
+  double y = (double)__builtin_amdgcn_rsqf((float)x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  c = y;
+  s = y * t;
+}
+
+// Racc = R3 R2 R1, one-sided Jacobi on Racc^T, sort, shift update, log.
+// Writes Wm (left singular vectors of R as columns, descending) and sigma.
+// RPT = rows per lane (8 lanes per column pair cover 8 * RPT >= l rows).
+template <int RPT>
+__global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg, int l, double* __restrict__ Wm,
                                                    double* __restrict__ sigma, double* __restrict__ alpha,
                                                    tucker_info* __restrict__ info, int mode, int step,
                                                    int* __restrict__ status) {
   __shared__ double A[kMaxL][OR_LS];  // A[a][x] = column a of R^T = row a of R
   __shared__ double J[kMaxL][OR_LS];  // J[a][x] = column a of the rotation
+  __shared__ unsigned char sched[kMaxL - 1][kMaxL];  // pairs per round
   __shared__ double sv[kMaxL];
   __shared__ int perm[kMaxL];
   __shared__ int rotated;
   const int tid = threadIdx.x;
+  const int ta = tid >> 4, tb = tid & 15;
   const int lp = (l + 1) & ~1;
+  // R = R3 R2 R1 (upper triangular): J <- R1, A <- R2; c = A J; J <- c; A <- R3; c = A J
   for (int e = tid; e < kMaxL * kMaxL; e += 256) {
-    const int a = e / kMaxL, x = e - (e / kMaxL) * kMaxL;
-    A[a][x] = (a < l && x < l) ? Racc[a * l + x] : 0.0;
-    J[a][x] = (a == x) ? 1.0 : 0.0;
+    const int r = e >> 6, x = e & 63;
+    J[r][x] = (r < l && x < l) ? Rg[r * l + x] : 0.0;
+    A[r][x] = (r < l && x < l) ? Rg[kMaxL * kMaxL + r * l + x] : 0.0;
   }
   __syncthreads();
+  double c[4][4];
+  tile_matmul(A, J, l, c);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) J[ta + 16 * i][tb + 16 * j] = c[i][j];
+  for (int e = tid; e < kMaxL * kMaxL; e += 256) {
+    const int r = e >> 6, x = e & 63;
+    A[r][x] = (r < l && x < l) ? Rg[2 * kMaxL * kMaxL + r * l + x] : 0.0;
+  }
+  __syncthreads();
+  tile_matmul(A, J, l, c);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r = ta + 16 * i, x = tb + 16 * j;
+      A[r][x] = c[i][j];
+      J[r][x] = (r == x) ? 1.0 : 0.0;
+    }
+  // round-robin schedule (circle method: player 0 fixed, the others rotate);
+  // for odd l the extra player is the zero column l, which never rotates
+  for (int e = tid; e < (lp - 1) * (lp / 2); e += 256) {
+    const int rnd = e / (lp / 2), pr = e % (lp / 2);
+    const int x0 = pr, x1 = lp - 1 - pr;
+    const int pa = (x0 == 0) ? 0 : 1 + (x0 - 1 + rnd) % (lp - 1);
+    const int pb = (x1 == 0) ? 0 : 1 + (x1 - 1 + rnd) % (lp - 1);
+    sched[rnd][2 * pr] = (unsigned char)pa;
+    sched[rnd][2 * pr + 1] = (unsigned char)pb;
+  }
+  __syncthreads();
+
+  // 8 lanes per column pair, lane `sub` owns rows sub + 8 q, q < RPT (rows
+  // at or beyond l are zero in A and in the first l columns of J)
   const int pair = tid >> 3, sub = tid & 7;
   const double tol = 2.220446049250313e-16 * l;
-  for (int sweep = 0; sweep < 60; ++sweep) {
+  const double tol2 = tol * tol;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    sweeps = sweep + 1;
     if (tid == 0) rotated = 0;
     __syncthreads();
     for (int rnd = 0; rnd < lp - 1; ++rnd) {
       if (pair < lp / 2) {
-        // circle method: player 0 fixed, players 1..lp-1 rotate
-        const int x0 = pair, x1 = lp - 1 - pair;
-        const int a = (x0 == 0) ? 0 : 1 + (x0 - 1 + rnd) % (lp - 1);
-        const int b = (x1 == 0) ? 0 : 1 + (x1 - 1 + rnd) % (lp - 1);
-        double al = 0.0, be = 0.0, ga = 0.0;
-        if (a < l && b < l) {
-          for (int x = sub; x < l; x += 8) {
-            const double u = A[a][x], v = A[b][x];
-            al = fma(u, u, al);
-            be = fma(v, v, be);
-            ga = fma(u, v, ga);
+        const int pa = sched[rnd][2 * pair], pb = sched[rnd][2 * pair + 1];
+        double u[RPT], v[RPT], ju[RPT], jv[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          u[q] = A[pa][sub + 8 * q];
+          v[q] = A[pb][sub + 8 * q];
+          ju[q] = J[pa][sub + 8 * q];
+          jv[q] = J[pb][sub + 8 * q];
+        }
+        double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPT; q += 2) {
+          al0 = fma(u[q], u[q], al0);
+          be0 = fma(v[q], v[q], be0);
+          ga0 = fma(u[q], v[q], ga0);
+          if (q + 1 < RPT) {
+            al1 = fma(u[q + 1], u[q + 1], al1);
+            be1 = fma(v[q + 1], v[q + 1], be1);
+            ga1 = fma(u[q + 1], v[q + 1], ga1);
           }
         }
+        const double al = octet_sum(al0 + al1), be = octet_sum(be0 + be1), ga = octet_sum(ga0 + ga1);
+        if (ga * ga > tol2 * al * be) {
+          double cs, sn;
+          jacobi_rotation(al, be, ga, cs, sn);
 #pragma unroll
-        for (int off = 1; off < 8; off <<= 1) {
-          al += __shfl_xor(al, off, 8);
-          be += __shfl_xor(be, off, 8);
-          ga += __shfl_xor(ga, off, 8);
-        }
-        if (a < l && b < l && ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int x = sub; x < kMaxL; x += 8) {
-            const double u = A[a][x], v = A[b][x];
-            A[a][x] = c * u - s * v;
-            A[b][x] = s * u + c * v;
-            const double ju = J[a][x], jv = J[b][x];
-            J[a][x] = c * ju - s * jv;
-            J[b][x] = s * ju + c * jv;
+          for (int q = 0; q < RPT; ++q) {
+            A[pa][sub + 8 * q] = cs * u[q] - sn * v[q];
+            A[pb][sub + 8 * q] = sn * u[q] + cs * v[q];
+            J[pa][sub + 8 * q] = cs * ju[q] - sn * jv[q];
+            J[pb][sub + 8 * q] = sn * ju[q] + cs * jv[q];
           }
           if (sub == 0) rotated = 1;
         }
@@ -280,24 +495,24 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Ra
     if (!rotated) break;
     __syncthreads();
   }
-  for (int a = tid; a < l; a += 256) {
-    double s = 0.0;
-    for (int x = 0; x < l; ++x) s = fma(A[a][x], A[a][x], s);
-    sv[a] = isfinite(s) ? sqrt(s) : 0.0;
+  for (int r = tid; r < l; r += 256) {
+    double s2 = 0.0;
+    for (int x = 0; x < l; ++x) s2 = fma(A[r][x], A[r][x], s2);
+    sv[r] = isfinite(s2) ? sqrt(s2) : 0.0;
   }
   __syncthreads();
-  for (int a = tid; a < l; a += 256) {
+  for (int r = tid; r < l; r += 256) {
     int rank = 0;
-    for (int b = 0; b < l; ++b) rank += (sv[b] > sv[a] || (sv[b] == sv[a] && b < a)) ? 1 : 0;
-    perm[rank] = a;
+    for (int q = 0; q < l; ++q) rank += (sv[q] > sv[r] || (sv[q] == sv[r] && q < r)) ? 1 : 0;
+    perm[rank] = r;
   }
   __syncthreads();
-  // Wm[x][j] = J[perm[j]][x]
   for (int e = tid; e < l * l; e += 256) {
-    const int x = e / l, j = e - (e / l) * l;
+    const int x = e / l, j = e % l;
     Wm[e] = J[perm[j]][x];
   }
-  for (int j = tid; j < l; j += 256) sigma[j] = sv[perm[j]];
+  if (sigma != nullptr)
+    for (int j = tid; j < l; j += 256) sigma[j] = sv[perm[j]];
   if (tid == 0) {
     const double s1 = sv[perm[0]], sl = sv[perm[l - 1]];
     double al = 0.0;
@@ -312,6 +527,7 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Ra
       info->alpha[mode][step] = al;
       info->flags |= status[0];
       info->deficient[mode] = status[1];
+      info->jacobi_sweeps = max(info->jacobi_sweeps, sweeps);
     }
   }
 }
@@ -320,12 +536,9 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Ra
 template <typename T>
 __global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ Q3, int64_t n, int l,
                                                 const double* __restrict__ Wm, T* __restrict__ qout,
-                                                double* __restrict__ q64) {
+                                                T* __restrict__ qt, double* __restrict__ q64) {
   __shared__ double Ws[kMaxL][OR_LS];
-  for (int e = threadIdx.x; e < l * l; e += 256) {
-    const int a = e / l, b = e - (e / l) * l;
-    Ws[a][b] = Wm[e];
-  }
+  for (int e = threadIdx.x; e < l * l; e += 256) Ws[e / l][e % l] = Wm[e];
   __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n * l) return;
@@ -334,7 +547,8 @@ __global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ Q3, i
   const double* row = Q3 + i * l;
   double s = 0.0;
   for (int k = 0; k < l; ++k) s = fma(row[k], Ws[k][j], s);
-  qout[e] = (T)s;
+  if (qout != nullptr) qout[e] = (T)s;
+  if (qt != nullptr) qt[(int64_t)j * n + i] = (T)s;
   if (q64 != nullptr) q64[e] = s;
 }
 
@@ -342,38 +556,54 @@ __global__ void k_clear_status(int* status) {
   if (threadIdx.x < 4) status[threadIdx.x] = 0;
 }
 
-hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec, void* q_out, double* q64,
-                       double* sigma, double* alpha, tucker_info* info, int mode, int step, const OrthWs& ws,
-                       uint64_t cseed, hipStream_t st) {
+template <int LP>
+static void orth_passes(int64_t n, int l, const double* Y, const OrthWs& ws, uint64_t cseed, int step, hipStream_t st) {
   const int nblk = (int)((n + OR_RB - 1) / OR_RB);
-  TimingScope ts(KC_ORTH, st, 8.0 * n * l * 8, 3.0 * 2.0 * n * l * l);
+  const size_t pstride = align_up((size_t)nblk * l * l * sizeof(double)) / sizeof(double);
+  double* p0 = ws.part;
+  double* p1 = ws.part + pstride;
   // pass 1 carries the shift, so its pivots sit far above tau1; passes 2 and 3
   // flag a column whose pivot is below the rounding level of an n-row Gram
   const double tau1 = 1e-15, tau = fmax(1e-14, 4.0 * (double)n * 2.220446049250313e-16);
+  const uint32_t tag = 0x100u + 16u * (uint32_t)step;
+  hipLaunchKernelGGL((k_gram<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, p0);
+  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, p0, nblk, 1, tau1, cseed, tag + 1, ws.Qa, p1,
+                     ws.R, ws.defic, ws.status);
+  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, ws.Qa, n, l, p1, nblk, 0, tau, cseed, tag + 2, ws.Qb,
+                     p0, ws.R + kMaxL * kMaxL, ws.defic + kMaxL, ws.status);
+  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, ws.Qb, n, l, p0, nblk, 0, tau, cseed, tag + 3, ws.Qa,
+                     (double*)nullptr, ws.R + 2 * kMaxL * kMaxL, ws.defic + 2 * kMaxL, ws.status);
+}
+
+hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec, void* q_out, void* qt,
+                       double* q64, double* sigma, double* alpha, tucker_info* info, int mode, int step,
+                       const OrthWs& ws, uint64_t cseed, hipStream_t st) {
+  TimingScope ts(KC_ORTH, st, 8.0 * n * l * 8, 3.0 * 2.0 * n * l * l);
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, ws.status);
-  // pass 1 (shifted)
-  hipLaunchKernelGGL((k_gram<double>), dim3(nblk), dim3(256), 0, st, Y, n, l, ws.part);
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, st, ws.part, nblk, n, l, 1, tau1, ws.R, ws.defic, ws.Racc, 0,
-                     ws.status);
-  hipLaunchKernelGGL(k_solve_gram, dim3(nblk), dim3(256), 0, st, Y, n, l, ws.R, ws.defic, cseed,
-                     (uint32_t)(0x100 + 16 * step + 1), ws.Qa, ws.part);
-  // pass 2
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, st, ws.part, nblk, n, l, 0, tau, ws.R + kMaxL * kMaxL,
-                     ws.defic + kMaxL, ws.Racc, 1, ws.status);
-  hipLaunchKernelGGL(k_solve_gram, dim3(nblk), dim3(256), 0, st, ws.Qa, n, l, ws.R + kMaxL * kMaxL,
-                     ws.defic + kMaxL, cseed, (uint32_t)(0x100 + 16 * step + 2), ws.Qb, ws.part);
-  // pass 3
-  hipLaunchKernelGGL(k_chol, dim3(1), dim3(256), 0, st, ws.part, nblk, n, l, 0, tau, ws.R + 2 * kMaxL * kMaxL,
-                     ws.defic + 2 * kMaxL, ws.Racc, 1, ws.status);
-  hipLaunchKernelGGL(k_solve_gram, dim3(nblk), dim3(256), 0, st, ws.Qb, n, l, ws.R + 2 * kMaxL * kMaxL,
-                     ws.defic + 2 * kMaxL, cseed, (uint32_t)(0x100 + 16 * step + 3), ws.Qa, (double*)nullptr);
-  hipLaunchKernelGGL(k_small_svd, dim3(1), dim3(256), 0, st, ws.Racc, l, ws.Wm, sigma, alpha, info, mode, step,
-                     ws.status);
+  switch ((l + 15) / 16) {
+    case 1: orth_passes<16>(n, l, Y, ws, cseed, step, st); break;
+    case 2: orth_passes<32>(n, l, Y, ws, cseed, step, st); break;
+    case 3: orth_passes<48>(n, l, Y, ws, cseed, step, st); break;
+    case 4: orth_passes<64>(n, l, Y, ws, cseed, step, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  switch ((l + 15) / 16) {
+    case 1: hipLaunchKernelGGL((k_small_svd<2>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
+                               step, ws.status); break;
+    case 2: hipLaunchKernelGGL((k_small_svd<4>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
+                               step, ws.status); break;
+    case 3: hipLaunchKernelGGL((k_small_svd<6>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
+                               step, ws.status); break;
+    default: hipLaunchKernelGGL((k_small_svd<8>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
+                                step, ws.status); break;
+  }
   const unsigned rb = (unsigned)((n * l + 255) / 256);
   if (prec == TUCKER_FP64)
-    hipLaunchKernelGGL((k_rotate<double>), dim3(rb), dim3(256), 0, st, ws.Qa, n, l, ws.Wm, (double*)q_out, q64);
+    hipLaunchKernelGGL((k_rotate<double>), dim3(rb), dim3(256), 0, st, ws.Qa, n, l, ws.Wm, (double*)q_out,
+                       (double*)qt, q64);
   else
-    hipLaunchKernelGGL((k_rotate<float>), dim3(rb), dim3(256), 0, st, ws.Qa, n, l, ws.Wm, (float*)q_out, q64);
+    hipLaunchKernelGGL((k_rotate<float>), dim3(rb), dim3(256), 0, st, ws.Qa, n, l, ws.Wm, (float*)q_out, (float*)qt,
+                       q64);
   return hipGetLastError();
 }
 
@@ -381,14 +611,15 @@ hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec,
 // Sign rule and truncation: one workgroup per kept column.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_signfix(const T* __restrict__ Q, int64_t n, int l, int r, T* __restrict__ U) {
+__global__ __launch_bounds__(256) void k_signfix(const double* __restrict__ Q, int64_t n, int l, int r,
+                                                 T* __restrict__ U, T* __restrict__ Ut) {
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
   const int j = blockIdx.x;
   double best = -1.0;
   int64_t bidx = 0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double v = fabs((double)Q[i * l + j]);
+    const double v = fabs(Q[i * l + j]);
     if (v > best) {
       best = v;
       bidx = i;
@@ -408,15 +639,20 @@ __global__ __launch_bounds__(256) void k_signfix(const T* __restrict__ Q, int64_
     }
     __syncthreads();
   }
-  const T sgn = (Q[bi[0] * l + j] < T(0)) ? T(-1) : T(1);
-  for (int64_t i = threadIdx.x; i < n; i += 256) U[i * r + j] = sgn * Q[i * l + j];
+  const double sgn = (Q[bi[0] * l + j] < 0.0) ? -1.0 : 1.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const T v = (T)(sgn * Q[i * l + j]);
+    U[i * r + j] = v;
+    if (Ut != nullptr) Ut[(int64_t)j * n + i] = v;
+  }
 }
 
-hipError_t launch_signfix(tucker_precision prec, const void* Q, int64_t n, int l, int r, void* U, hipStream_t st) {
+hipError_t launch_signfix(tucker_precision prec, const double* Q, int64_t n, int l, int r, void* U, void* Ut,
+                          hipStream_t st) {
   if (prec == TUCKER_FP64)
-    hipLaunchKernelGGL((k_signfix<double>), dim3(r), dim3(256), 0, st, (const double*)Q, n, l, r, (double*)U);
+    hipLaunchKernelGGL((k_signfix<double>), dim3(r), dim3(256), 0, st, Q, n, l, r, (double*)U, (double*)Ut);
   else
-    hipLaunchKernelGGL((k_signfix<float>), dim3(r), dim3(256), 0, st, (const float*)Q, n, l, r, (float*)U);
+    hipLaunchKernelGGL((k_signfix<float>), dim3(r), dim3(256), 0, st, Q, n, l, r, (float*)U, (float*)Ut);
   return hipGetLastError();
 }
 

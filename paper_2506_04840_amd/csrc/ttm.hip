@@ -1,57 +1,58 @@
 // Mode-k products on the in-place unfolding X_(k)[i, p*S + s] = X[p, i, s].
 //
-// Two shapes of contraction cover the method's three products:
-//  * column reduction  part = X_(k) B         (sketch Y = X_(k) Omega_k, and
-//    the second half of the power step Y = X_(k) Z): a long reduction over
-//    the m_k columns, split over workgroups and summed in a fixed order;
-//  * row contraction   out = X_(k)^T W        (Z = X_(k)^T Q of the power step
-//    and the core step X x_k U^T): a short reduction over n_k rows per
+// Two contractions cover the method's three products:
+//  * column reduction  part = X_(k) B   (sketch Y = X_(k) Omega_k and the
+//    second half of the power step Y = X_(k) Z): a long reduction over the
+//    m_k columns, split over workgroups, summed in a fixed order later;
+//  * row contraction   out = X_(k)^T W  (Z = X_(k)^T Q of the power step and
+//    the core step X x_k U^T): a short reduction over the n_k rows per
 //    column tile, written in the [P, lw, S] layout of the result tensor.
-// Both run on 16x16 matrix-core tiles: v_mfma_f32_16x16x4_f32 (FP32),
-// v_mfma_f64_16x16x4_f64 (FP64) or v_mfma_f32_16x16x32_bf16 (BF16 operands,
-// FP32 accumulation). Two load layouts: ROWS tiles run along s inside one p
-// (contiguous rows of S elements), COLS handles S == 1 where each column of
-// the unfolding is a contiguous n-vector.
+//
+// Operands go from HBM straight into matrix-core registers with 16-byte
+// loads; there is no LDS staging and no barrier in the main loops:
+//  * when the reduction index is the contiguous one (column reduction with
+//    S > 1, row contraction with S == 1) a lane loads KC consecutive
+//    reduction elements and feeds them to consecutive MFMA k-steps; A and B
+//    use the same k order, so the sum is unchanged;
+//  * when the output row index is the contiguous one (column reduction with
+//    S == 1, row contraction with S > 1) the MV elements of a 16-byte vector
+//    go to MV interleaved 16-row tiles.
+// Instructions: v_mfma_f32_16x16x4_f32 (FP32), v_mfma_f64_16x16x4_f64 (FP64),
+// v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation).
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace tk {
 
 template <int MK>
-struct MfmaTraits;
+struct Pol;
 template <>
-struct MfmaTraits<MF_F32> {
-  using lds_t = float;
+struct Pol<MF_F32> {
+  using T = float;
   using acc_t = floatx4;
   using part_t = float;
-  static constexpr int K = 4;
-  static constexpr int PAD = 1;
+  static constexpr int KL = 1;  // reduction elements per lane per MFMA
+  static constexpr int KC = 4;  // consecutive reduction elements per 16-byte load
+  static constexpr int MV = 4;  // consecutive output rows per 16-byte load
 };
 template <>
-struct MfmaTraits<MF_F64> {
-  using lds_t = double;
+struct Pol<MF_F64> {
+  using T = double;
   using acc_t = doublex4;
   using part_t = double;
-  static constexpr int K = 4;
-  static constexpr int PAD = 1;
+  static constexpr int KL = 1;
+  static constexpr int KC = 2;
+  static constexpr int MV = 2;
 };
 template <>
-struct MfmaTraits<MF_BF16> {
-  using lds_t = unsigned short;
+struct Pol<MF_BF16> {
+  using T = float;
   using acc_t = floatx4;
   using part_t = float;
-  static constexpr int K = 32;
-  static constexpr int PAD = 8;  // keeps 16-byte alignment of 8-element rows
+  static constexpr int KL = 8;
+  static constexpr int KC = 8;
+  static constexpr int MV = 4;
 };
-
-template <int MK, typename T>
-__device__ __forceinline__ typename MfmaTraits<MK>::lds_t to_lds(T v) {
-  if constexpr (MK == MF_BF16) {
-    return f32_to_bf16_bits((float)v);
-  } else {
-    return (typename MfmaTraits<MK>::lds_t)v;
-  }
-}
 
 // Row of the 16x16 result held by (lane, element v): the FP32 and BF16
 // instructions return 4 consecutive rows per lane group, the FP64 one
@@ -65,211 +66,339 @@ __device__ __forceinline__ int mfma_drow(int lane, int v) {
   }
 }
 
-// One K-step of a 16x16 tile: A row `arow`, B row `brow` (both stored with
-// the contraction index contiguous), at contraction offset kk.
 template <int MK>
-__device__ __forceinline__ typename MfmaTraits<MK>::acc_t mfma_step(const typename MfmaTraits<MK>::lds_t* arow,
-                                                                   const typename MfmaTraits<MK>::lds_t* brow,
-                                                                   int kk, int lane,
-                                                                   typename MfmaTraits<MK>::acc_t acc) {
+__device__ __forceinline__ typename Pol<MK>::acc_t mma(const typename Pol<MK>::T* a, const typename Pol<MK>::T* b,
+                                                      typename Pol<MK>::acc_t c) {
   if constexpr (MK == MF_F32) {
-    return mfma_f32(arow[kk + (lane >> 4)], brow[kk + (lane >> 4)], acc);
+    return mfma_f32(a[0], b[0], c);
   } else if constexpr (MK == MF_F64) {
-    return mfma_f64(arow[kk + (lane >> 4)], brow[kk + (lane >> 4)], acc);
+    return mfma_f64(a[0], b[0], c);
   } else {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(arow + kk + 8 * (lane >> 4));
-    const bf16x8 b = *reinterpret_cast<const bf16x8*>(brow + kk + 8 * (lane >> 4));
-    return mfma_bf16(a, b, acc);
+    const bf16x8 av = {(__bf16)a[0], (__bf16)a[1], (__bf16)a[2], (__bf16)a[3],
+                       (__bf16)a[4], (__bf16)a[5], (__bf16)a[6], (__bf16)a[7]};
+    const bf16x8 bv = {(__bf16)b[0], (__bf16)b[1], (__bf16)b[2], (__bf16)b[3],
+                       (__bf16)b[4], (__bf16)b[5], (__bf16)b[6], (__bf16)b[7]};
+    return mfma_bf16(av, bv, c);
   }
 }
 
-// ---------------------------------------------------------------------------
-// Column reduction. Workgroup = 256 threads (4 waves) owning BM = 128 rows of
-// the output and a contiguous range of column tiles (TC = 32 columns each).
-// Wave w owns rows [32w, 32w+32) = 2 x 16-row blocks; NJ 16-column blocks.
-// ---------------------------------------------------------------------------
-constexpr int CR_BM = 128;
-constexpr int CR_TC = 32;
-
-template <typename T, int MK, int NJ, bool COLS>
-__global__ __launch_bounds__(256) void k_colreduce(const T* __restrict__ X, const T* __restrict__ B, int64_t P,
-                                                   int64_t n, int64_t S, int l, int64_t tiles_per_p,
-                                                   int64_t ntiles, int nsplit,
-                                                   typename MfmaTraits<MK>::part_t* __restrict__ part) {
-  using Tr = MfmaTraits<MK>;
-  using LT = typename Tr::lds_t;
-  constexpr int BM = CR_BM, TC = CR_TC, LP = NJ * 16, STR = TC + Tr::PAD;
-  __shared__ __attribute__((aligned(16))) LT Xs[BM * STR];
-  __shared__ __attribute__((aligned(16))) LT Bs[LP * STR];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t i0 = (int64_t)blockIdx.y * BM;
-  const int split = blockIdx.x;
-  const int64_t t_begin = ntiles * split / nsplit;
-  const int64_t t_end = ntiles * (split + 1) / nsplit;
-
-  typename Tr::acc_t acc[2][NJ];
+// N consecutive elements at p; `cnt` of them exist (<= 0: none). With VEC
+// the caller guarantees 16-byte alignment of p whenever cnt >= N.
+template <typename T, int N, bool VEC>
+__device__ __forceinline__ void load_n(const T* __restrict__ p, int cnt, T* out) {
+  if (VEC && cnt >= N) {
+    static_assert((sizeof(T) * N) % 16 == 0, "vector width");
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < NJ; ++b) acc[a][b] = typename Tr::acc_t{0, 0, 0, 0};
-
-  for (int64_t t = t_begin; t < t_end; ++t) {
-    int64_t p, s0;
-    int tw;
-    if constexpr (COLS) {
-      p = t * TC;
-      s0 = 0;
-      tw = (int)min<int64_t>(TC, P - p);
-    } else {
-      p = t / tiles_per_p;
-      s0 = (t - p * tiles_per_p) * TC;
-      tw = (int)min<int64_t>(TC, S - s0);
+    for (int q = 0; q < (int)(sizeof(T) * N / 16); ++q) {
+      const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(p) + 16 * q);
+      *reinterpret_cast<float4*>(reinterpret_cast<char*>(out) + 16 * q) = v;
     }
-    __syncthreads();
-    if constexpr (!COLS) {
-      const T* xb = X + (p * n) * S + s0;
-      const int c = tid & (TC - 1);
-#pragma unroll 4
-      for (int it = 0; it < BM / 8; ++it) {
-        const int r = (tid >> 5) + it * 8;
-        const int64_t i = i0 + r;
-        T v = (i < n && c < tw) ? xb[i * S + c] : T(0);
-        Xs[r * STR + c] = to_lds<MK>(v);
-      }
-      const T* bb = B + ((int64_t)p * l) * S + s0;
+  } else {
 #pragma unroll
-      for (int it = 0; it < LP / 8; ++it) {
-        const int j = (tid >> 5) + it * 8;
-        T v = (j < l && c < tw) ? bb[(int64_t)j * S + c] : T(0);
-        Bs[j * STR + c] = to_lds<MK>(v);
-      }
-    } else {
-      const int r = tid & (BM - 1);
-      const int64_t i = i0 + r;
-#pragma unroll 4
-      for (int it = 0; it < TC / 2; ++it) {
-        const int c = (tid >> 7) + it * 2;
-        T v = (i < n && c < tw) ? X[(p + c) * n + i] : T(0);
-        Xs[r * STR + c] = to_lds<MK>(v);
-      }
-      for (int e = tid; e < TC * LP; e += 256) {
-        const int c = e / LP, j = e - (e / LP) * LP;
-        T v = (j < l && c < tw) ? B[(p + c) * l + j] : T(0);
-        Bs[j * STR + c] = to_lds<MK>(v);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TC; kk += Tr::K) {
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi) {
-        const LT* arow = Xs + (wave * 32 + mi * 16 + (lane & 15)) * STR;
-#pragma unroll
-        for (int nj = 0; nj < NJ; ++nj) {
-          const LT* brow = Bs + (nj * 16 + (lane & 15)) * STR;
-          acc[mi][nj] = mfma_step<MK>(arow, brow, kk, lane, acc[mi][nj]);
-        }
-      }
-    }
+    for (int e = 0; e < N; ++e) out[e] = (e < cnt) ? p[e] : T(0);
   }
-  // D[row = mfma_drow(lane, v)][col = lane % 16] of each 16x16 block
+}
+
+// Workgroup -> (split, row block) so that the workgroups of one split, which
+// read the same slice of the skinny operand, run on the same XCD (workgroups
+// are dealt to the 8 XCDs round robin).
+__device__ __forceinline__ bool xcd_decode(int bid, int nsplit, int nblocks, int* split, int* rblock) {
+  const int x = bid & 7, li = bid >> 3;
+  *rblock = li % nblocks;
+  *split = (li / nblocks) * 8 + x;
+  return *split < nsplit;
+}
+
+// Copy of a KB-element fragment.
+template <typename T, int KB>
+__device__ __forceinline__ void copy_frag(T* dst, const T* src) {
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int e = 0; e < KB; ++e) dst[e] = src[e];
+}
+
+// ---------------------------------------------------------------------------
+// Column reduction, S > 1: part[split][i][j] = sum over the split's columns c
+// of X_(k)[i, c] Bt[j, c]; the reduction runs along s (contiguous). A
+// workgroup is 4 waves on 4 consecutive groups of 64 rows and one split of
+// the column steps (each step 4 * KC columns of one p), so the 4 waves read
+// the same Bt slice close together (L1 reuse). Each wave writes its rows'
+// partials directly.
+// ---------------------------------------------------------------------------
+template <int MK, int NJ, bool VEC>
+__global__ __launch_bounds__(256) void k_cr_rows(const typename Pol<MK>::T* __restrict__ X,
+                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
+                                                 int l, int64_t m, int64_t steps_per_p, int64_t nsteps, int nsplit,
+                                                 int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
+  using Po = Pol<MK>;
+  using T = typename Po::T;
+  // 32 contiguous bytes per lane and row: four lanes cover a 128-byte line
+  constexpr int KC = 32 / (int)sizeof(T), STEP = 4 * KC;
+  int split, rb;
+  if (!xcd_decode(blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mm = lane & 15, g = lane >> 4;
+  const int64_t r0 = ((int64_t)rb * 4 + wave) * 64;
+  if (r0 >= n) return;
+  const int64_t t0 = nsteps * split / nsplit, t1 = nsteps * (split + 1) / nsplit;
+
+  typename Po::acc_t acc[4][NJ];
 #pragma unroll
-    for (int nj = 0; nj < NJ; ++nj)
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NJ; ++b) acc[a][b] = typename Po::acc_t{0, 0, 0, 0};
+
+  auto fetch = [&](int64_t t, T (&fa)[4][KC], T (&fb)[NJ][KC]) {
+    const int64_t p = t / steps_per_p;
+    const int64_t c0 = (t - p * steps_per_p) * STEP + KC * g;
+    const int cnt = t < t1 ? (int)min<int64_t>(KC, S - c0) : 0;
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm) {
+      const int64_t row = r0 + 16 * tm + mm;
+      load_n<T, KC, VEC>(X + (p * n + row) * S + c0, row < n ? cnt : 0, fa[tm]);
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = 16 * u + mm;
+      load_n<T, KC, VEC>(Bt + (int64_t)j * m + p * S + c0, j < l ? cnt : 0, fb[u]);
+    }
+  };
+  auto compute = [&](T (&fa)[4][KC], T (&fb)[NJ][KC]) {
+#pragma unroll
+    for (int e = 0; e < KC; e += Po::KL)
+#pragma unroll
+      for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][e], &fb[u][e], acc[tm][u]);
+  };
+  // two register stages: step t computes while t + 1 and t + 2 are in flight
+  T xa0[4][KC], xb0[NJ][KC], xa1[4][KC], xb1[NJ][KC];
+  fetch(t0, xa0, xb0);
+  fetch(t0 + 1, xa1, xb1);
+  for (int64_t t = t0; t < t1; t += 2) {
+    compute(xa0, xb0);
+    fetch(t + 2, xa0, xb0);  // zero-filled past the end of the split
+    compute(xa1, xb1);       // zeros when t + 1 is past the end
+    fetch(t + 3, xa1, xb1);
+  }
+#pragma unroll
+  for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+    for (int u = 0; u < NJ; ++u)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int64_t row = i0 + wave * 32 + mi * 16 + mfma_drow<MK>(lane, v);
-        const int col = nj * 16 + (lane & 15);
-        if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[mi][nj][v];
+        const int64_t row = r0 + 16 * tm + mfma_drow<MK>(lane, v);
+        const int col = 16 * u + mm;
+        if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[tm][u][v];
       }
 }
 
-static int64_t cr_tiles(const View3& v, int64_t* tiles_per_p) {
-  if (v.S == 1) {
-    *tiles_per_p = 0;
-    return (v.P + CR_TC - 1) / CR_TC;
+// ---------------------------------------------------------------------------
+// Column reduction, S == 1: X is [P, n] with rows p contiguous along i (the
+// output row index). A batch covers 4 * KB consecutive p; k-slot g of the
+// MFMA takes p = pbase + KB g + q, q < KB, for both operands.
+// ---------------------------------------------------------------------------
+template <int MK, int NJ, bool VEC, bool BVEC>
+__global__ __launch_bounds__(256) void k_cr_cols(const typename Pol<MK>::T* __restrict__ X,
+                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t P, int64_t n,
+                                                 int l, int64_t nsteps, int nsplit, int nrblocks,
+                                                 typename Pol<MK>::part_t* __restrict__ part) {
+  using Po = Pol<MK>;
+  using T = typename Po::T;
+  constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
+  constexpr int KB = (KL == 1) ? 4 : KL;
+  int split, rb;
+  if (!xcd_decode(blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mm = lane & 15, g = lane >> 4;
+  const int64_t r0 = ((int64_t)rb * 4 + wave) * 64;
+  if (r0 >= n) return;
+  const int64_t t0 = nsteps * split / nsplit, t1 = nsteps * (split + 1) / nsplit;
+
+  typename Po::acc_t acc[4][NJ];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NJ; ++b) acc[a][b] = typename Po::acc_t{0, 0, 0, 0};
+
+  auto fetch = [&](int64_t t, T (&fa)[4][KB], T (&fb)[NJ][KB]) {
+    const int64_t pq = t * 4 * KB + KB * g;
+    const int pcnt = t < t1 ? (int)min<int64_t>(KB, P - pq) : 0;
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const int64_t p = pq + q;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const int64_t base = r0 + h * 16 * MV + MV * mm;
+        T v[MV];
+        load_n<T, MV, VEC>(X + p * n + base, q < pcnt ? (int)min<int64_t>(MV, n - base) : 0, v);
+#pragma unroll
+        for (int vv = 0; vv < MV; ++vv) fa[h * MV + vv][q] = v[vv];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = 16 * u + mm;
+      load_n<T, KB, BVEC>(Bt + (int64_t)j * P + pq, j < l ? pcnt : 0, fb[u]);
+    }
+  };
+  auto compute = [&](T (&fa)[4][KB], T (&fb)[NJ][KB]) {
+#pragma unroll
+    for (int q = 0; q < KB; q += KL)
+#pragma unroll
+      for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][q], &fb[u][q], acc[tm][u]);
+  };
+  T a0[4][KB], b0[NJ][KB], a1[4][KB], b1[NJ][KB];
+  fetch(t0, a0, b0);
+  fetch(t0 + 1, a1, b1);
+  for (int64_t t = t0; t < t1; t += 2) {
+    compute(a0, b0);
+    fetch(t + 2, a0, b0);
+    compute(a1, b1);
+    fetch(t + 3, a1, b1);
   }
-  *tiles_per_p = (v.S + CR_TC - 1) / CR_TC;
-  return v.P * *tiles_per_p;
+  // tile tm = h * MV + vv holds output rows r0 + h*16*MV + MV*dr + vv
+#pragma unroll
+  for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+    for (int u = 0; u < NJ; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int h = tm / MV, vv = tm % MV;
+        const int64_t row = r0 + h * 16 * MV + MV * mfma_drow<MK>(lane, v) + vv;
+        const int col = 16 * u + mm;
+        if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[tm][u][v];
+      }
+}
+
+static void cr_geom(tucker_precision prec, const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
+  const int kc = prec == TUCKER_FP64 ? 4 : 8;  // 32 contiguous bytes per lane in k_cr_rows
+  const int kb = prec == TUCKER_BF16 ? 8 : 4;
+  if (v.S == 1) {
+    *spp = 0;
+    *nsteps = (v.P + 4 * kb - 1) / (4 * kb);
+  } else {
+    *spp = (v.S + 4 * kc - 1) / (4 * kc);
+    *nsteps = v.P * *spp;
+  }
+  *nrblocks = (int)((v.n + 255) / 256);
+}
+
+int colreduce_splits_prec(const View3& v, tucker_precision prec) {
+  int64_t nsteps, spp;
+  int nrb;
+  cr_geom(prec, v, &nsteps, &spp, &nrb);
+  const int64_t waves_per_split = std::min<int64_t>((v.n + 63) / 64, 4 * (int64_t)nrb);
+  // about 2048 waves (2 per SIMD), each wave at least 8 steps; a multiple of 8
+  // so the XCD mapping has no holes
+  int64_t ns = (2048 + waves_per_split - 1) / waves_per_split;
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nsteps / 8));
+  if (ns > 8) ns = ns / 8 * 8;
+  return (int)std::max<int64_t>(1, ns);
 }
 
 int colreduce_splits(const View3& v, int l) {
   (void)l;
-  int64_t tpp;
-  const int64_t ntiles = cr_tiles(v, &tpp);
-  const int64_t rowblocks = (v.n + CR_BM - 1) / CR_BM;
-  // about 1024 workgroups in flight (4 per CU), at least 2 tiles each
-  int64_t ns = (1024 + rowblocks - 1) / rowblocks;
-  ns = std::min<int64_t>(ns, std::max<int64_t>(1, ntiles / 2));
-  return (int)std::max<int64_t>(1, ns);
+  return colreduce_splits_prec(v, TUCKER_FP32);
 }
 
 size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec) {
-  return (size_t)colreduce_splits(v, l) * (size_t)v.n * (size_t)l * elem_bytes(prec);
+  const int ns = std::max(colreduce_splits_prec(v, prec), colreduce_splits_prec(v, TUCKER_FP32));
+  return (size_t)ns * (size_t)v.n * (size_t)l * elem_bytes(prec);
 }
 
-template <typename T, int MK, int NJ>
-static hipError_t cr_launch(const View3& v, const void* X, const void* B, int l, void* part, int nsplit,
+template <int MK, int NJ>
+static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l, void* part, int nsplit,
                             hipStream_t st) {
-  int64_t tpp;
-  const int64_t ntiles = cr_tiles(v, &tpp);
-  dim3 grid((unsigned)nsplit, (unsigned)((v.n + CR_BM - 1) / CR_BM));
-  using PT = typename MfmaTraits<MK>::part_t;
-  if (v.S == 1)
-    hipLaunchKernelGGL((k_colreduce<T, MK, NJ, true>), grid, dim3(256), 0, st, (const T*)X, (const T*)B, v.P,
-                       v.n, v.S, l, tpp, ntiles, nsplit, (PT*)part);
-  else
-    hipLaunchKernelGGL((k_colreduce<T, MK, NJ, false>), grid, dim3(256), 0, st, (const T*)X, (const T*)B, v.P,
-                       v.n, v.S, l, tpp, ntiles, nsplit, (PT*)part);
+  using Po = Pol<MK>;
+  using T = typename Po::T;
+  using PT = typename Po::part_t;
+  const tucker_precision prec = MK == MF_F64 ? TUCKER_FP64 : (MK == MF_BF16 ? TUCKER_BF16 : TUCKER_FP32);
+  int64_t nsteps, spp;
+  int nrb;
+  cr_geom(prec, v, &nsteps, &spp, &nrb);
+  const unsigned blocks = (unsigned)(((nsplit + 7) / 8) * 8 * nrb);
+  const uintptr_t xa = (uintptr_t)X, ba = (uintptr_t)Bt;
+  const int64_t m = v.P * v.S;
+  constexpr int VE = 16 / (int)sizeof(T);  // elements per 16-byte vector
+  if (v.S == 1) {
+    const bool vec = (v.n % Po::MV == 0) && (xa % 16 == 0);
+    const bool bvec = (v.P % VE == 0) && (ba % 16 == 0);
+#define TK_CR_COLS(V, BV)                                                                                     \
+  hipLaunchKernelGGL((k_cr_cols<MK, NJ, V, BV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, \
+                     v.n, l, nsteps, nsplit, nrb, (PT*)part)
+    if (vec && bvec) TK_CR_COLS(true, true);
+    else if (vec) TK_CR_COLS(true, false);
+    else if (bvec) TK_CR_COLS(false, true);
+    else TK_CR_COLS(false, false);
+#undef TK_CR_COLS
+  } else {
+    const bool vec = (v.S % VE == 0) && (xa % 16 == 0) && (ba % 16 == 0);
+    if (vec)
+      hipLaunchKernelGGL((k_cr_rows<MK, NJ, true>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
+                         v.S, l, m, spp, nsteps, nsplit, nrb, (PT*)part);
+    else
+      hipLaunchKernelGGL((k_cr_rows<MK, NJ, false>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
+                         v.S, l, m, spp, nsteps, nsplit, nrb, (PT*)part);
+  }
   return hipGetLastError();
 }
 
-template <typename T, int MK>
-static hipError_t cr_dispatch(const View3& v, const void* X, const void* B, int l, void* part, int nsplit,
+template <int MK>
+static hipError_t cr_dispatch(const View3& v, const void* X, const void* Bt, int l, void* part, int nsplit,
                               hipStream_t st) {
-  const int nj = (l + 15) / 16;
-  switch (nj) {
-    case 1: return cr_launch<T, MK, 1>(v, X, B, l, part, nsplit, st);
-    case 2: return cr_launch<T, MK, 2>(v, X, B, l, part, nsplit, st);
-    case 3: return cr_launch<T, MK, 3>(v, X, B, l, part, nsplit, st);
-    case 4: return cr_launch<T, MK, 4>(v, X, B, l, part, nsplit, st);
+  switch ((l + 15) / 16) {
+    case 1: return cr_launch<MK, 1>(v, X, Bt, l, part, nsplit, st);
+    case 2: return cr_launch<MK, 2>(v, X, Bt, l, part, nsplit, st);
+    case 3: return cr_launch<MK, 3>(v, X, Bt, l, part, nsplit, st);
+    case 4: return cr_launch<MK, 4>(v, X, Bt, l, part, nsplit, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* B, int l,
+hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* Bt, int l,
                             void* part, int nsplit, hipStream_t st) {
   const double N = (double)v.P * v.n * v.S, es = (double)elem_bytes(prec);
   TimingScope ts(KC_COLREDUCE, st, N * es + N / v.n * l * es, 2.0 * N * l);
   switch (prec) {
-    case TUCKER_FP64: return cr_dispatch<double, MF_F64>(v, X, B, l, part, nsplit, st);
-    case TUCKER_FP32: return cr_dispatch<float, MF_F32>(v, X, B, l, part, nsplit, st);
-    case TUCKER_BF16: return cr_dispatch<float, MF_BF16>(v, X, B, l, part, nsplit, st);
+    case TUCKER_FP64: return cr_dispatch<MF_F64>(v, X, Bt, l, part, nsplit, st);
+    case TUCKER_FP32: return cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, st);
+    case TUCKER_BF16: return cr_dispatch<MF_BF16>(v, X, Bt, l, part, nsplit, st);
   }
   return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of the split partials, with the -alpha Q term.
+// 8 threads per element, each summing a fixed eighth of the splits; the eight
+// partial sums are added in lane order, so the result does not depend on
+// scheduling.
 // ---------------------------------------------------------------------------
 template <typename PT, typename QT>
 __global__ __launch_bounds__(256) void k_reduce_splits(const PT* __restrict__ part, int nsplit, int64_t nl,
                                                        const QT* __restrict__ qsub,
                                                        const double* __restrict__ alpha, double* __restrict__ Y) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= nl) return;
+  const int sub = threadIdx.x & 7;
+  const int64_t e = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
   double s = 0.0;
-  for (int sp = 0; sp < nsplit; ++sp) s += (double)part[(int64_t)sp * nl + e];
-  if (qsub != nullptr) s -= (*alpha) * (double)qsub[e];
-  Y[e] = s;
+  if (e < nl) {
+    const int s0 = (int)((int64_t)nsplit * sub / 8), s1 = (int)((int64_t)nsplit * (sub + 1) / 8);
+    for (int sp = s0; sp < s1; ++sp) s += (double)part[(int64_t)sp * nl + e];
+  }
+  double t[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) t[q] = __shfl(s, (int)(threadIdx.x & ~7u) + q, 64);
+  if (sub != 0 || e >= nl) return;
+  double y = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+  if (qsub != nullptr) y -= (*alpha) * (double)qsub[e];
+  Y[e] = y;
 }
 
 hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, int nsplit, int64_t nl,
                                 const void* qsub, tucker_precision qsub_prec, const double* alpha, double* Y,
                                 hipStream_t st) {
-  const unsigned blocks = (unsigned)((nl + 255) / 256);
+  const unsigned blocks = (unsigned)((nl + 31) / 32);
   if (blocks == 0) return hipSuccess;
   TimingScope ts(KC_REDUCE, st, (double)nsplit * nl * elem_bytes(part_prec) + 8.0 * nl, 0.0);
   const bool pd = part_prec == TUCKER_FP64, qd = qsub_prec == TUCKER_FP64;
@@ -289,128 +418,239 @@ hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, in
 }
 
 // ---------------------------------------------------------------------------
-// Row contraction. Workgroup = 256 threads owning TC = 64 columns of the
-// unfolding (wave w: columns [16w, 16w+16)) and all lw outputs per column;
-// it streams the n rows in chunks of BK = 32.
+// Row contraction, S > 1: out(p, j, s) = sum_i X[p, i, s] W(i, j), with
+// W(i, j) = W[i * wsi + j * wsj] and out(p, j, s) = out[p * osp + j * osj + s].
+// Output rows are s (contiguous). Each wave owns a 64-column tile of one p
+// (4 interleaved 16-row MFMA tiles), 4 waves per workgroup, all n rows per
+// wave, in batches of 4 * KB rows: k-slot g takes i = i0 + KB g + q, q < KB.
 // ---------------------------------------------------------------------------
-constexpr int RC_TC = 64;
-constexpr int RC_BK = 32;
+template <int MK, int NJ, bool VEC, bool WVEC>
+__global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __restrict__ X,
+                                                 const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
+                                                 int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
+                                                 int64_t ntiles, typename Pol<MK>::T* __restrict__ out, int64_t osp,
+                                                 int64_t osj) {
+  using Po = Pol<MK>;
+  using T = typename Po::T;
+  constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
+  constexpr int KB = (KL == 1) ? 4 : KL, ROWS = 4 * KB;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mm = lane & 15, g = lane >> 4;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  if (tile >= ntiles) return;
+  const int64_t p = tile / tiles_per_p;
+  const int64_t s0 = (tile - p * tiles_per_p) * 64;
+  const T* xp = X + p * n * S;
 
-template <typename T, int MK, int NJ, bool COLS>
-__global__ __launch_bounds__(256) void k_rowcontract(const T* __restrict__ X, const T* __restrict__ W, int64_t P,
-                                                     int64_t n, int64_t S, int lw, int64_t tiles_per_p,
-                                                     T* __restrict__ out) {
-  using Tr = MfmaTraits<MK>;
-  using LT = typename Tr::lds_t;
-  constexpr int TC = RC_TC, BK = RC_BK, LP = NJ * 16, STR = BK + Tr::PAD;
-  __shared__ __attribute__((aligned(16))) LT Xs[TC * STR];  // [c][i]
-  __shared__ __attribute__((aligned(16))) LT Ws[LP * STR];  // [j][i]
+  typename Po::acc_t acc[4][NJ];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NJ; ++b) acc[a][b] = typename Po::acc_t{0, 0, 0, 0};
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t t = blockIdx.x;
-  int64_t p, s0;
-  int tw;
-  if constexpr (COLS) {
-    p = t * TC;
-    s0 = 0;
-    tw = (int)min<int64_t>(TC, P - p);
-  } else {
-    p = t / tiles_per_p;
-    s0 = (t - p * tiles_per_p) * TC;
-    tw = (int)min<int64_t>(TC, S - s0);
+  auto fetch = [&](int64_t i0, T (&fa)[4][KB], T (&fb)[NJ][KB]) {
+    const int64_t iq = i0 + KB * g;
+    const int icnt = (int)min<int64_t>(KB, n - iq);
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+      const int64_t i = iq + q;
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const int64_t base = s0 + h * 16 * MV + MV * mm;
+        T v[MV];
+        load_n<T, MV, VEC>(xp + i * S + base, q < icnt ? (int)min<int64_t>(MV, S - base) : 0, v);
+#pragma unroll
+        for (int vv = 0; vv < MV; ++vv) fa[h * MV + vv][q] = v[vv];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = 16 * u + mm;
+      if constexpr (WVEC) {
+        load_n<T, KB, true>(W + (int64_t)j * wsj + iq, j < lw ? icnt : 0, fb[u]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < KB; ++q) fb[u][q] = (q < icnt && j < lw) ? W[(iq + q) * wsi + (int64_t)j * wsj] : T(0);
+      }
+    }
+  };
+  auto compute = [&](T (&fa)[4][KB], T (&fb)[NJ][KB]) {
+#pragma unroll
+    for (int q = 0; q < KB; q += KL)
+#pragma unroll
+      for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][q], &fb[u][q], acc[tm][u]);
+  };
+  T a0[4][KB], b0[NJ][KB], a1[4][KB], b1[NJ][KB];
+  fetch(0, a0, b0);
+  fetch(ROWS, a1, b1);
+  for (int64_t i0 = 0; i0 < n; i0 += 2 * ROWS) {
+    compute(a0, b0);
+    fetch(i0 + 2 * ROWS, a0, b0);  // zero-filled past row n
+    compute(a1, b1);
+    fetch(i0 + 3 * ROWS, a1, b1);
   }
-
-  typename Tr::acc_t acc[NJ];
+  // tile tm = h * MV + vv, result row dr -> column s0 + h*16*MV + MV*dr + vv
+  T* op = out + p * osp;
 #pragma unroll
-  for (int b = 0; b < NJ; ++b) acc[b] = typename Tr::acc_t{0, 0, 0, 0};
-
-  for (int64_t i0 = 0; i0 < n; i0 += BK) {
-    __syncthreads();
-    if constexpr (!COLS) {
-      const T* xb = X + (p * n) * S + s0;
-      const int c = tid & (TC - 1);
-#pragma unroll
-      for (int it = 0; it < BK / 4; ++it) {
-        const int r = (tid >> 6) + it * 4;
-        const int64_t i = i0 + r;
-        T v = (i < n && c < tw) ? xb[i * S + c] : T(0);
-        Xs[c * STR + r] = to_lds<MK>(v);
-      }
-    } else {
-      const int r = tid & (BK - 1);
-      const int64_t i = i0 + r;
-#pragma unroll
-      for (int it = 0; it < TC / 8; ++it) {
-        const int c = (tid >> 5) + it * 8;
-        T v = (i < n && c < tw) ? X[(p + c) * n + i] : T(0);
-        Xs[c * STR + r] = to_lds<MK>(v);
-      }
-    }
-    for (int e = tid; e < BK * LP; e += 256) {
-      const int r = e / LP, j = e - (e / LP) * LP;
-      const int64_t i = i0 + r;
-      T v = (i < n && j < lw) ? W[i * lw + j] : T(0);
-      Ws[j * STR + r] = to_lds<MK>(v);
-    }
-    __syncthreads();
-    const LT* arow = Xs + (wave * 16 + (lane & 15)) * STR;
-#pragma unroll
-    for (int kk = 0; kk < BK; kk += Tr::K) {
-#pragma unroll
-      for (int nj = 0; nj < NJ; ++nj) {
-        const LT* brow = Ws + (nj * 16 + (lane & 15)) * STR;
-        acc[nj] = mfma_step<MK>(arow, brow, kk, lane, acc[nj]);
-      }
-    }
-  }
-#pragma unroll
-  for (int nj = 0; nj < NJ; ++nj)
+  for (int u = 0; u < NJ; ++u) {
+    const int j = 16 * u + mm;
+    if (j >= lw) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int c = wave * 16 + mfma_drow<MK>(lane, v);
-      const int j = nj * 16 + (lane & 15);
-      if (c < tw && j < lw) {
-        if constexpr (COLS)
-          out[(p + c) * lw + j] = (T)acc[nj][v];
-        else
-          out[(p * lw + j) * S + s0 + c] = (T)acc[nj][v];
+      const int dr = mfma_drow<MK>(lane, v);
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const int64_t c = s0 + h * 16 * MV + MV * dr;
+        T* dst = op + (int64_t)j * osj + c;
+        if constexpr (VEC && MV == 4) {
+          if (c + 3 < S) {
+            *reinterpret_cast<float4*>(dst) = make_float4((float)acc[h * MV + 0][u][v], (float)acc[h * MV + 1][u][v],
+                                                          (float)acc[h * MV + 2][u][v], (float)acc[h * MV + 3][u][v]);
+            continue;
+          }
+        }
+#pragma unroll
+        for (int vv = 0; vv < MV; ++vv)
+          if (c + vv < S) dst[vv] = (T)acc[h * MV + vv][u][v];
       }
     }
+  }
 }
 
-template <typename T, int MK, int NJ>
-static hipError_t rc_launch(const View3& v, const void* X, const void* W, int lw, void* out, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// Row contraction, S == 1: X is [P, n] (rows p contiguous along i, the
+// reduction index); out(p, j) = out[p * osp + j * osj]; each wave owns 64
+// rows p, 4 waves per workgroup.
+// ---------------------------------------------------------------------------
+template <int MK, int NJ, bool VEC, bool WVEC>
+__global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __restrict__ X,
+                                                 const typename Pol<MK>::T* __restrict__ W, int64_t P, int64_t n,
+                                                 int lw, int64_t wsi, int64_t wsj, typename Pol<MK>::T* __restrict__ out,
+                                                 int64_t osp, int64_t osj) {
+  using Po = Pol<MK>;
+  using T = typename Po::T;
+  constexpr int KC = Po::KC;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mm = lane & 15, g = lane >> 4;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  if (p0 >= P) return;
+
+  typename Po::acc_t acc[4][NJ];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < NJ; ++b) acc[a][b] = typename Po::acc_t{0, 0, 0, 0};
+
+  auto fetch = [&](int64_t i0, T (&fa)[4][KC], T (&fb)[NJ][KC]) {
+    const int64_t ib = i0 + KC * g;
+    const int cnt = (int)min<int64_t>(KC, n - ib);
+#pragma unroll
+    for (int tm = 0; tm < 4; ++tm) {
+      const int64_t p = p0 + 16 * tm + mm;
+      load_n<T, KC, VEC>(X + p * n + ib, p < P ? cnt : 0, fa[tm]);
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = 16 * u + mm;
+      if constexpr (WVEC) {
+        load_n<T, KC, true>(W + (int64_t)j * wsj + ib, j < lw ? cnt : 0, fb[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < KC; ++e) fb[u][e] = (e < cnt && j < lw) ? W[(ib + e) * wsi + (int64_t)j * wsj] : T(0);
+      }
+    }
+  };
+  auto compute = [&](T (&fa)[4][KC], T (&fb)[NJ][KC]) {
+#pragma unroll
+    for (int e = 0; e < KC; e += Po::KL)
+#pragma unroll
+      for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][e], &fb[u][e], acc[tm][u]);
+  };
+  T a0[4][KC], b0[NJ][KC], a1[4][KC], b1[NJ][KC];
+  fetch(0, a0, b0);
+  fetch(4 * KC, a1, b1);
+  for (int64_t i0 = 0; i0 < n; i0 += 8 * KC) {
+    compute(a0, b0);
+    fetch(i0 + 8 * KC, a0, b0);  // zero-filled past row n
+    compute(a1, b1);
+    fetch(i0 + 12 * KC, a1, b1);
+  }
+#pragma unroll
+  for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+    for (int u = 0; u < NJ; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t p = p0 + 16 * tm + mfma_drow<MK>(lane, v);
+        const int j = 16 * u + mm;
+        if (p < P && j < lw) out[p * osp + (int64_t)j * osj] = (T)acc[tm][u][v];
+      }
+}
+
+template <int MK, int NJ>
+static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_t wsi, int64_t wsj, int lw, void* out,
+                            bool out_jmajor, hipStream_t st) {
+  using Po = Pol<MK>;
+  using T = typename Po::T;
+  constexpr int VE = 16 / (int)sizeof(T);
+  const uintptr_t xa = (uintptr_t)X, wa = (uintptr_t)W, oa = (uintptr_t)out;
+  const int64_t m = v.P * v.S;
+  const bool wvec = (wsi == 1) && (wsj % VE == 0) && (wa % 16 == 0);
   if (v.S == 1) {
-    const int64_t tiles = (v.P + RC_TC - 1) / RC_TC;
-    hipLaunchKernelGGL((k_rowcontract<T, MK, NJ, true>), dim3((unsigned)tiles), dim3(256), 0, st, (const T*)X,
-                       (const T*)W, v.P, v.n, v.S, lw, (int64_t)0, (T*)out);
+    const int64_t osp = out_jmajor ? 1 : lw, osj = out_jmajor ? m : 1;
+    const int64_t waves = (v.P + 63) / 64;
+    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const bool vec = (v.n % Po::KC == 0) && (xa % 16 == 0);
+#define TK_RC_COLS(V, WV)                                                                                    \
+  hipLaunchKernelGGL((k_rc_cols<MK, NJ, V, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.P, \
+                     v.n, lw, wsi, wsj, (T*)out, osp, osj)
+    if (vec && wvec) TK_RC_COLS(true, true);
+    else if (vec) TK_RC_COLS(true, false);
+    else if (wvec) TK_RC_COLS(false, true);
+    else TK_RC_COLS(false, false);
+#undef TK_RC_COLS
   } else {
-    const int64_t tpp = (v.S + RC_TC - 1) / RC_TC;
-    hipLaunchKernelGGL((k_rowcontract<T, MK, NJ, false>), dim3((unsigned)(v.P * tpp)), dim3(256), 0, st,
-                       (const T*)X, (const T*)W, v.P, v.n, v.S, lw, tpp, (T*)out);
+    const int64_t osp = out_jmajor ? v.S : (int64_t)lw * v.S, osj = out_jmajor ? m : v.S;
+    const int64_t tpp = (v.S + 63) / 64;
+    const int64_t ntiles = v.P * tpp;
+    const unsigned blocks = (unsigned)((ntiles + 3) / 4);
+    const bool vec = (v.S % Po::MV == 0) && (xa % 16 == 0) && (oa % 16 == 0) && (osj % VE == 0) && (osp % VE == 0);
+#define TK_RC_ROWS(V, WV)                                                                                        \
+  hipLaunchKernelGGL((k_rc_rows<MK, NJ, V, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
+                     lw, wsi, wsj, tpp, ntiles, (T*)out, osp, osj)
+    if (vec && wvec) TK_RC_ROWS(true, true);
+    else if (vec) TK_RC_ROWS(true, false);
+    else if (wvec) TK_RC_ROWS(false, true);
+    else TK_RC_ROWS(false, false);
+#undef TK_RC_ROWS
   }
   return hipGetLastError();
 }
 
-template <typename T, int MK>
-static hipError_t rc_dispatch(const View3& v, const void* X, const void* W, int lw, void* out, hipStream_t st) {
+template <int MK>
+static hipError_t rc_dispatch(const View3& v, const void* X, const void* W, int64_t wsi, int64_t wsj, int lw,
+                              void* out, bool out_jmajor, hipStream_t st) {
   switch ((lw + 15) / 16) {
-    case 1: return rc_launch<T, MK, 1>(v, X, W, lw, out, st);
-    case 2: return rc_launch<T, MK, 2>(v, X, W, lw, out, st);
-    case 3: return rc_launch<T, MK, 3>(v, X, W, lw, out, st);
-    case 4: return rc_launch<T, MK, 4>(v, X, W, lw, out, st);
+    case 1: return rc_launch<MK, 1>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
+    case 2: return rc_launch<MK, 2>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
+    case 3: return rc_launch<MK, 3>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
+    case 4: return rc_launch<MK, 4>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X, const void* W, int lw, void* out,
-                              hipStream_t st) {
+hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X, const void* W, int64_t wsi,
+                              int64_t wsj, int lw, void* out, bool out_jmajor, hipStream_t st) {
   const double N = (double)v.P * v.n * v.S, es = (double)elem_bytes(mk);
   TimingScope ts(KC_ROWCONTRACT, st, N * es + N / v.n * lw * es, 2.0 * N * lw);
   switch (mk) {
-    case TUCKER_FP64: return rc_dispatch<double, MF_F64>(v, X, W, lw, out, st);
-    case TUCKER_FP32: return rc_dispatch<float, MF_F32>(v, X, W, lw, out, st);
-    case TUCKER_BF16: return rc_dispatch<float, MF_BF16>(v, X, W, lw, out, st);
+    case TUCKER_FP64: return rc_dispatch<MF_F64>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
+    case TUCKER_FP32: return rc_dispatch<MF_F32>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
+    case TUCKER_BF16: return rc_dispatch<MF_BF16>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
   }
   return hipErrorInvalidValue;
 }
@@ -420,7 +660,7 @@ hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill_gaussian(uint64_t seed, uint32_t mode, int64_t row0, int64_t rows,
-                                                       int cols, int64_t S, T* __restrict__ out) {
+                                                       int cols, int64_t ld, int jmajor, T* __restrict__ out) {
   const int groups = (cols + 3) / 4;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= rows * groups) return;
@@ -432,26 +672,25 @@ __global__ __launch_bounds__(256) void k_fill_gaussian(uint64_t seed, uint32_t m
   } else {
     gaussian4_f32(seed, mode, (uint64_t)(row0 + c), (uint32_t)g, v);
   }
-  const int64_t pp = c / S, ss = c - pp * S;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int j = 4 * g + q;
-    if (j < cols) out[(pp * cols + j) * S + ss] = v[q];
+    if (j < cols) out[jmajor ? (int64_t)j * ld + c : c * cols + j] = v[q];
   }
 }
 
 hipError_t launch_fill_gaussian(tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0, int64_t rows,
-                                int cols, int64_t S, void* out, hipStream_t st) {
+                                int cols, bool jmajor, void* out, hipStream_t st) {
   const int64_t work = rows * (int64_t)((cols + 3) / 4);
   if (work == 0) return hipSuccess;
   TimingScope ts(KC_FILL, st, (double)rows * cols * elem_bytes(prec), 0.0);
   const unsigned blocks = (unsigned)((work + 255) / 256);
   if (prec == TUCKER_FP64)
-    hipLaunchKernelGGL((k_fill_gaussian<double>), dim3(blocks), dim3(256), 0, st, seed, mode, row0, rows, cols, S,
-                       (double*)out);
+    hipLaunchKernelGGL((k_fill_gaussian<double>), dim3(blocks), dim3(256), 0, st, seed, mode, row0, rows, cols, rows,
+                       jmajor ? 1 : 0, (double*)out);
   else
-    hipLaunchKernelGGL((k_fill_gaussian<float>), dim3(blocks), dim3(256), 0, st, seed, mode, row0, rows, cols, S,
-                       (float*)out);
+    hipLaunchKernelGGL((k_fill_gaussian<float>), dim3(blocks), dim3(256), 0, st, seed, mode, row0, rows, cols, rows,
+                       jmajor ? 1 : 0, (float*)out);
   return hipGetLastError();
 }
 
