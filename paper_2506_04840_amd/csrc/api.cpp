@@ -185,9 +185,46 @@ uint64_t completion_seed(uint64_t seed, int mode) {
   return (seed ^ 0x6A09E667F3BCC909ull) * 0x9E3779B97F4A7C15ull + (uint64_t)(mode + 1);
 }
 
-// Sketch of one mode and its svd: Y = X_(k) Omega_k, [Q, Sigma] = svd(Y), alpha_0 = 0.
-int sketch_mode(const Plan& pl, int k, const void* X, uint64_t seed, tucker_precision prec, tucker_info* info,
-                const SolveWs& w, hipStream_t st) {
+// Side stream for the small SVDs of the intermediate iterates (one per host
+// thread and device, default priority, created on first use). The SVD of
+// step t only feeds step t + 1 through alpha_t and the basis change Wm, both
+// applied after step t + 1's two tensor products, so those products run on
+// the caller's stream while the SVD runs beside them.
+struct SideCtx {
+  int dev = -1;
+  hipStream_t s = nullptr;
+  hipEvent_t qr_done = nullptr, svd_done = nullptr;
+};
+thread_local SideCtx g_side[16];
+
+int side_ctx(SideCtx** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_check(e, "hipGetDevice");
+  if (dev < 0 || dev >= 16) return fail(TUCKER_EDEVICE, "device ordinal %d outside 0..15", dev);
+  SideCtx& c = g_side[dev];
+  if (c.s == nullptr) {
+    e = hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.qr_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.svd_done, hipEventDisableTiming);
+    if (e != hipSuccess) return dev_check(e, "side stream setup");
+    c.dev = dev;
+  }
+  *out = &c;
+  return TUCKER_OK;
+}
+
+// One mode of Algorithm 2 / 3 up to U_k (before truncation):
+//   Y = X_(k) Omega_k; [Q, Sigma] = svd(Y); alpha_0 = 0;
+//   q times: Y = X_(k) (X_(k)^T Q) - alpha Q; [Q, Sigma] = svd(Y); shift update.
+// Each svd is split into its CholeskyQR part (Y = Q3 R, on the caller's
+// stream) and the small SVD R = J Sigma V^T (side stream except for the last
+// one). Step t + 1 runs its products on Q3 instead of Q = Q3 J; the reduce
+// subtracts alpha_t Q3 and the next Gram kernel applies J: (X X^T Q3 -
+// alpha Q3) J = X X^T Q - alpha Q, the same iterate. On return ws.q64 holds
+// the left singular vectors of the last iterate (FP64, n x l, descending).
+int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
+                tucker_info* info, const SolveWs& w, hipStream_t st) {
   const View3 v = pl.v[k];
   const int l = pl.l[k];
   const int64_t n = v.n, m = pl.m[k];
@@ -195,40 +232,40 @@ int sketch_mode(const Plan& pl, int k, const void* X, uint64_t seed, tucker_prec
   const OrthWs ows = carve_orth(w.orth, n, l);
   const uint64_t cseed = completion_seed(seed, k);
   double* alpha = w.alpha + k;
+  double* alpha_upd = shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr;
+  SideCtx* side = nullptr;
+  if (q > 0) {
+    const int rc = side_ctx(&side);
+    if (rc) return rc;
+  }
   hipError_t e;
-  // Y = X_(k) Omega_k
+  // sketch: Y = X_(k) Omega_k, then its CholeskyQR
   e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, true, w.omz,
                            st);
   if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
   if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_set_double(alpha, 0.0, st);
-  if (e == hipSuccess)
-    e = launch_orth(n, l, w.y64, prec, nullptr, w.qt, w.q64, w.sigma, nullptr, info, k, 0, ows, cseed, st);
-  return e == hipSuccess ? TUCKER_OK : dev_check(e, "sketch launch");
-}
-
-// q shifted power steps, each followed by its svd and (adaptive) the midpoint shift update.
-int power_steps(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
-                tucker_info* info, const SolveWs& w, hipStream_t st) {
-  const View3 v = pl.v[k];
-  const int l = pl.l[k];
-  const int64_t n = v.n;
-  const int nsplit = colreduce_splits(v, l);
-  const OrthWs ows = carve_orth(w.orth, n, l);
-  const uint64_t cseed = completion_seed(seed, k);
-  double* alpha = w.alpha + k;
-  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, prec, w.qt, ows, cseed, 0, st);
   for (int t = 1; t <= q && e == hipSuccess; ++t) {
-    // Z = X_(k)^T Q (j-major), then Y = X_(k) Z - alpha Q
-    e = launch_rowcontract(prec, v, X, w.qt, 1, n, l, w.omz, true, st);
+    // small SVD of step t - 1 beside the products of step t
+    e = hipEventRecord(side->qr_done, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->qr_done, 0);
+    if (e == hipSuccess)
+      e = launch_orth_svd(l, ows, w.sigma, t == 1 ? nullptr : alpha_upd, info, k, t - 1, side->s);
+    if (e == hipSuccess) e = hipEventRecord(side->svd_done, side->s);
+    // Z = X_(k)^T Q3 (j-major), Y' = X_(k) Z
+    if (e == hipSuccess) e = launch_rowcontract(prec, v, X, w.qt, 1, n, l, w.omz, true, st);
     if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
+    // Y = (Y' - alpha Q3) J, then its CholeskyQR
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->svd_done, 0);
     if (e == hipSuccess)
-      e = launch_reduce_splits(prec, w.part, nsplit, n * l, w.q64, TUCKER_FP64, alpha, w.y64, st);
-    if (e == hipSuccess)
-      e = launch_orth(n, l, w.y64, prec, nullptr, w.qt, w.q64, w.sigma, shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr,
-                      info, k, t, ows, cseed, st);
+      e = launch_reduce_splits(prec, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
+    if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, prec, w.qt, ows, cseed, t, st);
   }
-  return e == hipSuccess ? TUCKER_OK : dev_check(e, "power step launch");
+  // last small SVD on the caller's stream, then Q = Q3 J
+  if (e == hipSuccess) e = launch_orth_svd(l, ows, w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q, st);
+  if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, nullptr, w.q64, st);
+  return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch");
 }
 
 int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
@@ -261,8 +298,7 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
 
   for (int k = 0; k < pl.d; ++k) {
     const void* Xk = st_variant ? X : A;
-    rc = sketch_mode(pl, k, Xk, seed, prec, info, w, st);
-    if (!rc) rc = power_steps(pl, k, Xk, q, shift, seed, prec, info, w, st);
+    rc = mode_factor(pl, k, Xk, q, shift, seed, prec, info, w, st);
     if (rc) return rc;
     e = launch_signfix(prec, w.q64, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], w.ut, st);
     if (e != hipSuccess) return dev_check(e, "sign rule launch");
@@ -429,7 +465,7 @@ int tucker_orth(int64_t n, int64_t l, const double* Y, tucker_precision prec, vo
   const size_t need = orth_ws_bytes(n, (int)l);
   if (ws == nullptr || ws_bytes < need) return fail(TUCKER_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
   const OrthWs ows = carve_orth(ws, n, (int)l);
-  return dev_check(launch_orth(n, (int)l, Y, prec, Q, nullptr, nullptr, sigma, nullptr, nullptr, -1, -1, ows,
+  return dev_check(launch_orth(n, (int)l, const_cast<double*>(Y), prec, Q, nullptr, nullptr, sigma, nullptr, nullptr, -1, -1, ows,
                                completion_seed(0x0a7bull, 0), stream),
                    "orth launch");
 }

@@ -70,25 +70,34 @@ hipError_t launch_norm2(tucker_precision prec, const void* X, int64_t numel, dou
 
 // ---- orthonormalisation (FP64) --------------------------------------------
 struct OrthWs {
-  double* Qa;     // n x l
-  double* Qb;     // n x l
-  double* part;   // gram partials [nblk][l][l]
-  double* R;      // 3 x l x l
-  double* Racc;   // l x l
-  double* Wm;     // l x l
+  double* Qa;     // n x l: Q1, then Q2 and Q3 in place
+  double* part;   // gram partials, ping-pong [2][nblk][l][l]
+  double* R;      // 3 x kMaxL^2: R1, R2, R3 (each l x l row-major)
+  double* Wm;     // l x l left singular vectors of R (columns, descending)
   int* defic;     // 3 x 64
-  int* status;    // 4 ints: [0] flags, [1] deficient count
+  int* status;    // [0] flags, [1] deficient count, [2] 1 when pass 3 was skipped
 };
 size_t orth_ws_bytes(int64_t n, int l);
 OrthWs carve_orth(void* base, int64_t n, int l);
 
-// [Q, Sigma] = svd(Y, econ). Y FP64 n x l. Q is written (each when not
-// nullptr) to q_out (n x l, `prec` storage), qt (j-major l x n, `prec`
-// storage) and q64 (n x l, FP64). sigma: l doubles.
-// When alpha != nullptr the midpoint shift update is applied to *alpha.
-// When info != nullptr, Sigma(1,1), Sigma(l,l) and alpha are logged at
+// CholeskyQR part of svd(Y): Y (FP64 n x l) = Q3 R with Q3 in ws.Qa and the R
+// factors in ws.R. With Wrot != nullptr, Y is first replaced in place by
+// Y Wrot (l x l). qt (when not nullptr) receives Q3 j-major (l x n) in the
+// storage precision `prec`.
+hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucker_precision prec, void* qt,
+                          const OrthWs& ws, uint64_t cseed, int step, hipStream_t st);
+// Small SVD of R after launch_orth_qr: ws.Wm, sigma (l doubles, descending)
+// and, when alpha != nullptr, the midpoint shift update of *alpha. When
+// info != nullptr, Sigma(1,1), Sigma(l,l) and alpha are logged at
 // [mode][step], and status bits are or-ed into info->flags.
-hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec, void* q_out, void* qt,
+hipError_t launch_orth_svd(int l, const OrthWs& ws, double* sigma, double* alpha, tucker_info* info, int mode,
+                           int step, hipStream_t st);
+// Q = Q3 Wm to q_out (n x l, `prec` storage), qt (j-major l x n, `prec`
+// storage) and q64 (n x l, FP64), each when not nullptr.
+hipError_t launch_orth_rotate(int64_t n, int l, const OrthWs& ws, tucker_precision prec, void* q_out, void* qt,
+                              double* q64, hipStream_t st);
+// [Q, Sigma] = svd(Y, econ): launch_orth_qr + launch_orth_svd + launch_orth_rotate on one stream.
+hipError_t launch_orth(int64_t n, int l, double* Y, tucker_precision prec, void* q_out, void* qt,
                        double* q64, double* sigma, double* alpha, tucker_info* info, int mode, int step,
                        const OrthWs& ws, uint64_t cseed, hipStream_t st);
 

@@ -3,22 +3,29 @@
 // shifted power step (Algorithms 2 and 3).
 //
 // Route, all in FP64:
-//   pass 1  W = Y^T Y + s I, R1 = chol(W), Q1 = Y R1^-1        (shifted CholeskyQR,
-//           s = 11 (n l + l (l+1)) u ||Y||_F^2, Fukaya et al. 2020)
+//   pass 1  D = 2^floor(log4 diag(Y^T Y)) (exact column scaling),
+//           W = D^-1 Y^T Y D^-1 + s I, R~ = chol(W), Q1 = (Y D^-1) R~^-1, R1 = R~ D
+//           (shifted CholeskyQR on Y D^-1, s = 11 (n l + l (l+1)) u ||Y D^-1||_F^2,
+//           Fukaya et al. 2020)
 //   pass 2  R2 = chol(Q1^T Q1), Q2 = Q1 R2^-1
-//   pass 3  R3 = chol(Q2^T Q2), Q3 = Q2 R3^-1                   (re-orthogonalisation)
-//   R = R3 R2 R1 (so Y = Q3 R), one-sided Jacobi on R^T: R^T J = B with
+//   pass 3  R3 = chol(Q2^T Q2), Q3 = Q2 R3^-1, run only when R2 is not within
+//           1e-4 of I (otherwise Q1 was already well conditioned and Q2 is
+//           orthonormal to rounding, the CholeskyQR2 regime)
+//   R = R3 R2 R1 (so Y = Q3 R); one-sided Jacobi on R^T: R^T J = B with
 //   orthogonal columns, hence R = J diag(|B_j|) (B/|B|)^T and the left
 //   singular vectors of Y are Q3 J. Columns sorted by descending Sigma.
+// The scaling makes the shifted pass insensitive to graded column norms: the
+// iterates of the power steps have nearly orthogonal columns of very
+// different lengths, and for them two passes suffice.
 // A Cholesky pivot below tau * max(diag) marks the column numerically
 // dependent on the previous ones: its row of R is zero and the solve puts a
-// random Gaussian direction in that column, which the next pass
-// orthonormalises. Those columns end with Sigma = 0.
+// random direction in that column, which the next pass orthonormalises.
+// Those columns end with Sigma = 0.
 //
-// Launches per call: gram(Y), 3 x pass(p), svd, rotate. Each pass kernel sums
-// the previous pass's Gram partials in block order and factors W itself (the
-// same bits in every block), solves its 64 rows and writes the Gram partial
-// of its output rows for the next pass.
+// Launches: gram(Y) [optionally first Y <- Y Wm in place], 3 x pass, svd,
+// rotate. Each pass kernel sums the previous Gram partials in block order and
+// factors W itself (the same bits in every block), solves its 64 rows in
+// place and writes the Gram partial of its output rows for the next pass.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -32,10 +39,8 @@ size_t orth_ws_bytes(int64_t n, int l) {
   const size_t nblk = (size_t)((n + OR_RB - 1) / OR_RB);
   size_t b = 0;
   b += align_up(nl);                                          // Qa
-  b += align_up(nl);                                          // Qb
   b += 2 * align_up(nblk * l * l * sizeof(double));           // gram partials, ping-pong
   b += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));  // R1..R3
-  b += align_up((size_t)kMaxL * kMaxL * sizeof(double));      // Racc
   b += align_up((size_t)kMaxL * kMaxL * sizeof(double));      // Wm
   b += align_up(3 * kMaxL * sizeof(int));                     // deficiency flags
   b += align_up(4 * sizeof(int));                             // status
@@ -48,24 +53,16 @@ OrthWs carve_orth(void* base, int64_t n, int l) {
   const size_t nblk = (size_t)((n + OR_RB - 1) / OR_RB);
   OrthWs w;
   w.Qa = (double*)p; p += align_up(nl);
-  w.Qb = (double*)p; p += align_up(nl);
   w.part = (double*)p; p += 2 * align_up(nblk * l * l * sizeof(double));
   w.R = (double*)p; p += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
-  w.Racc = (double*)p; p += align_up((size_t)kMaxL * kMaxL * sizeof(double));
   w.Wm = (double*)p; p += align_up((size_t)kMaxL * kMaxL * sizeof(double));
   w.defic = (int*)p; p += align_up(3 * kMaxL * sizeof(int));
   w.status = (int*)p; p += align_up(4 * sizeof(int));
   return w;
 }
 
-// Full-precision reciprocal and reciprocal square root: hardware estimate plus
-// two Newton steps (each squares the relative error).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = r * fma(-x, r, 2.0);
-  r = r * fma(-x, r, 2.0);
-  return r;
-}
+// Full-precision reciprocal square root: hardware estimate plus two Newton
+// steps (each squares the relative error).
 __device__ __forceinline__ double rsq_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * fma(-0.5 * x * y, y, 1.5);
@@ -84,113 +81,152 @@ __device__ __forceinline__ double completion_entry(uint64_t seed, uint32_t tag, 
   return (double)(int64_t)z * 1.0842021724855044e-19;  // 2^-63
 }
 
-// Sum over the 8 lanes of an aligned octet with DPP moves (no LDS traffic):
-// xor-1 and xor-2 inside each quad, then the row half-mirror joins the quads.
-__device__ __forceinline__ double dpp_f64(double v, int ctrl_sel) {
+// 64-bit DPP move of a double (two 32-bit halves, same control).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov_f64(double v) {
   const uint64_t u = __double_as_longlong(v);
-  int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
-  if (ctrl_sel == 0) {
-    lo = __builtin_amdgcn_mov_dpp(lo, 0xB1, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_mov_dpp(hi, 0xB1, 0xF, 0xF, false);
-  } else if (ctrl_sel == 1) {
-    lo = __builtin_amdgcn_mov_dpp(lo, 0x4E, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_mov_dpp(hi, 0x4E, 0xF, 0xF, false);
-  } else {
-    lo = __builtin_amdgcn_mov_dpp(lo, 0x141, 0xF, 0xF, false);
-    hi = __builtin_amdgcn_mov_dpp(hi, 0x141, 0xF, 0xF, false);
-  }
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
   return __longlong_as_double(((int64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
+
+// Sum over the 8 lanes of an aligned octet (no LDS traffic): xor-1 and xor-2
+// inside each quad, then the row half-mirror joins the two quads. Every lane
+// of the octet ends with the same bits.
 __device__ __forceinline__ double octet_sum(double v) {
-  v += dpp_f64(v, 0);
-  v += dpp_f64(v, 1);
-  v += dpp_f64(v, 2);
+  v += dpp_mov_f64<0xB1>(v);
+  v += dpp_mov_f64<0x4E>(v);
+  v += dpp_mov_f64<0x141>(v);
   return v;
 }
 
-// Gram of 64 rows held in LDS, for the 2-D thread grid (ta, tb) = (tid/16, tid%16):
-// the thread owns W[ta + 16 i][tb + 16 j], i, j < LP/16.
-template <int LP>
-__device__ __forceinline__ void block_gram_store(const double (*Zs)[OR_LS], int l, double* __restrict__ part_blk) {
-  constexpr int NB = LP / 16;
-  const int ta = threadIdx.x >> 4, tb = threadIdx.x & 15;
-  double acc[NB][NB];
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = 0.0;
-#pragma unroll 2
-  for (int r = 0; r < OR_RB; ++r) {
-    double za[NB], zb[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      za[i] = Zs[r][ta + 16 * i];
-      zb[i] = Zs[r][tb + 16 * i];
-    }
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int j = 0; j < NB; ++j) acc[i][j] = fma(za[i], zb[j], acc[i][j]);
+// Value of lane `src` (0..3, a compile-time constant after unrolling) of each quad.
+__device__ __forceinline__ double quad_bcast(double v, int src) {
+  switch (src) {
+    case 0: return dpp_mov_f64<0x00>(v);
+    case 1: return dpp_mov_f64<0x55>(v);
+    case 2: return dpp_mov_f64<0xAA>(v);
+    default: return dpp_mov_f64<0xFF>(v);
   }
-#pragma unroll
-  for (int i = 0; i < NB; ++i)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const int a = ta + 16 * i, b = tb + 16 * j;
-      if (a < l && b < l) part_blk[a * l + b] = acc[i][j];
-    }
 }
 
+// Gram Z^T Z of the 64 rows held in Zs, on the FP64 matrix cores: the upper
+// 16 x 16 tiles are dealt round robin to the 4 waves (each tile a chain of 16
+// k-steps over the rows) and stored to both triangles of part_blk (l x l).
 template <int LP>
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ Y, int64_t n, int l, double* __restrict__ part) {
+__device__ __forceinline__ void block_gram_mfma(const double (*Zs)[OR_LS], int l, double* __restrict__ part_blk) {
+  constexpr int NB = LP / 16, NT = NB * (NB + 1) / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mm = lane & 15, g = lane >> 4;
+  for (int tile = wave; tile < NT; tile += 4) {
+    int I = 0, J = tile;
+    while (J >= NB - I) {
+      J -= NB - I;
+      ++I;
+    }
+    J += I;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < OR_RB; k0 += 4) acc = mfma_f64(Zs[k0 + g][16 * I + mm], Zs[k0 + g][16 * J + mm], acc);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = 16 * I + g + 4 * v, b = 16 * J + mm;
+      if (a < l && b < l) {
+        part_blk[a * l + b] = acc[v];
+        if (I != J) part_blk[b * l + a] = acc[v];
+      }
+    }
+  }
+}
+
+// Gram partials of Y, 64 rows per block. With Wm, the rows are first rotated
+// in place, Y <- Y Wm (the basis change that turns the iterate of a power
+// step run on an unrotated basis into the iterate of the rotated one).
+template <int LP>
+__global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n, int l,
+                                              const double* __restrict__ Wm, double* __restrict__ part) {
+  constexpr int NB = LP / 16;
   __shared__ double Zs[OR_RB][OR_LS];
+  __shared__ double Ws[kMaxL][OR_LS];
+  const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
-  for (int e = threadIdx.x; e < OR_RB * LP; e += 256) {
+  for (int e = tid; e < OR_RB * LP; e += 256) {
     const int r = e / LP, j = e % LP;
     Zs[r][j] = (r0 + r < n && j < l) ? Y[(r0 + r) * l + j] : 0.0;
   }
+  if (Wm != nullptr)
+    for (int e = tid; e < LP * LP; e += 256) {
+      const int x = e / LP, j = e % LP;
+      Ws[x][j] = (x < l && j < l) ? Wm[x * l + j] : 0.0;
+    }
   __syncthreads();
-  block_gram_store<LP>(Zs, l, part + (size_t)blockIdx.x * l * l);
+  if (Wm != nullptr) {
+    // wave w: rows 16 w .. 16 w + 15, all column tiles
+    const int lane = tid & 63, w = tid >> 6, mm = lane & 15, g = lane >> 4;
+    doublex4 acc[NB];
+#pragma unroll
+    for (int J = 0; J < NB; ++J) acc[J] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < LP; k0 += 4) {
+      const double a = Zs[16 * w + mm][k0 + g];
+#pragma unroll
+      for (int J = 0; J < NB; ++J) acc[J] = mfma_f64(a, Ws[k0 + g][16 * J + mm], acc[J]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int J = 0; J < NB; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Zs[16 * w + g + 4 * v][16 * J + mm] = acc[J][v];
+    __syncthreads();
+    for (int e = tid; e < OR_RB * l; e += 256) {
+      const int r = e / l, j = e % l;
+      if (r0 + r < n) Y[(r0 + r) * l + j] = Zs[r][j];
+    }
+  }
+  block_gram_mfma<LP>(Zs, l, part + (size_t)blockIdx.x * l * l);
 }
 
-// One CholeskyQR pass over 64 rows per block.
-//   W = sum_b part_in[b] (+ s I when shifted); R = chol(W) with deficiency
-//   flags; Qout rows = Qin rows R^-1 (deficient columns: Gaussian / sqrt(n));
-//   part_out[blk] = Gram of this block's Qout rows (if part_out != nullptr).
-// Block 0 also writes R and the flags for the small SVD.
+// One CholeskyQR pass over 64 rows per block (role 0: pass 1, shifted and
+// scaled; role 1: pass 2, decides whether pass 3 runs; role 2: pass 3).
+//   W = sum_b part_in[b] (scaled and shifted for role 0); R = chol(W) with
+//   deficiency flags; Qout rows = Qin rows R^-1 (deficient columns: random
+//   direction / sqrt(n)); part_out[blk] = Gram of this block's Qout rows.
+// Qout may alias Qin (each block reads its rows before writing them).
+// Block 0 writes R (role 0: R~ D) and the flags for the small SVD.
+// The last pass that runs also writes Q j-major in the storage precision to
+// qt (when not null).
 template <int LP>
-__global__ __launch_bounds__(256) void k_pass(const double* __restrict__ Qin, int64_t n, int l,
-                                              const double* __restrict__ part_in, int nblk, int shifted, double tau,
-                                              uint64_t cseed, uint32_t ctag, double* __restrict__ Qout,
+__global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int l, const double* __restrict__ part_in,
+                                              int nblk, int role, double tau, uint64_t cseed, uint32_t ctag,
+                                              double* Qout, void* __restrict__ qt, int qt_f64,
                                               double* __restrict__ part_out, double* __restrict__ Rg,
                                               int* __restrict__ defic_g, int* __restrict__ status) {
-  constexpr int NB = LP / 16;
-  __shared__ double Rl[kMaxL][OR_LS];
+  constexpr int NB = LP / 16, MW = LP / 4;
+  constexpr int PF = NB <= 3 ? 8 : 4;  // Gram partials in flight per thread
   __shared__ double Zs[OR_RB][OR_LS];
-  __shared__ double rrow[kMaxL];
-  __shared__ double inv_diag[kMaxL];
-  __shared__ int dfs[kMaxL];
+  __shared__ double Rp[LP][4][MW];     // Rp[j][t][m] = R[j][t + 4 m]
+  __shared__ double pbuf[2][4][LP];    // panel rows of the trailing matrix
+  __shared__ double inv_diag[LP];
   __shared__ double red[2][16];
-  __shared__ double piv;
-  __shared__ int bad;
+  __shared__ int esc[LP];
+  __shared__ int flag_s;
 
+  if (role == 2 && status[2] != 0) return;  // pass 3 not needed (same value in every block)
   const int tid = threadIdx.x;
   const int ta = tid >> 4, tb = tid & 15;
-  if (tid == 0) bad = 0;
-  __syncthreads();
+  if (tid == 0) flag_s = 0;
 
   // 1. W in registers: thread owns W[ta + 16 i][tb + 16 j]; the partials are
-  //    summed in block order, four blocks of loads in flight at a time
+  //    summed in block order
   double W[NB][NB];
-  double mytr = 0.0, mymax = 0.0;
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) W[i][j] = 0.0;
-  for (int b0 = 0; b0 < nblk; b0 += 4) {
-    double v[4][NB][NB];
+  for (int b0 = 0; b0 < nblk; b0 += PF) {
+    double v[PF][NB][NB];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < PF; ++q)
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -199,96 +235,186 @@ __global__ __launch_bounds__(256) void k_pass(const double* __restrict__ Qin, in
           v[q][i][j] = (b0 + q < nblk && a < l && b < l) ? part_in[(size_t)(b0 + q) * l * l + a * l + b] : 0.0;
         }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < PF; ++q)
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j) W[i][j] += v[q][i][j];
   }
+  __syncthreads();
+  bool mybad = false;
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j)
-      if (!isfinite(W[i][j])) bad = 1;
-  __syncthreads();
-  const bool anybad = bad != 0;
-  // trace (diagonal owners: ta == tb, i == j)
+    for (int j = 0; j < NB; ++j) mybad = mybad || !isfinite(W[i][j]);
+  if (mybad) flag_s = 1;
   if (ta == tb) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) mytr += W[i][i];
-    red[0][ta] = mytr;
-  }
-  __syncthreads();
-  double trace = 0.0;
-#pragma unroll
-  for (int t = 0; t < 16; ++t) trace += red[0][t];
-  const double shift = shifted ? 11.0 * ((double)n * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * trace : 0.0;
-  if (ta == tb) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      W[i][i] += shift;
-      mymax = fmax(mymax, W[i][i]);
-    }
-    red[1][ta] = mymax;
-  }
-  __syncthreads();
-  double maxdiag = 0.0;
-#pragma unroll
-  for (int t = 0; t < 16; ++t) maxdiag = fmax(maxdiag, red[1][t]);
-
-  // 2. right-looking Cholesky, W = R^T R, R upper
-  int ndef = 0;
-  for (int k = 0; k < l; ++k) {
-    const int kt = k & 15, ki = k >> 4;
-    if (ta == kt && tb == kt) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (i == ki) piv = W[i][i];
-    }
-    __syncthreads();
-    const double d = piv;
-    const bool dep = !(d > tau * maxdiag) || anybad;
-    const double inv = dep ? 0.0 : rsq_nr(d);  // 1 / sqrt(d)
-    const double rkk = d * inv;
-    if (ta == kt) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i)
-        if (i == ki) {
-#pragma unroll
-          for (int j = 0; j < NB; ++j) {
-            const int b = tb + 16 * j;
-            if (b < l) {
-              double v = 0.0;
-              if (!dep && b >= k) v = (b == k) ? rkk : W[i][j] * inv;
-              rrow[b] = v;
-              Rl[k][b] = v;
-            }
-          }
-        }
-    }
-    if (tid == 0) {
-      dfs[k] = dep ? 1 : 0;
-      inv_diag[k] = inv;
-    }
-    ndef += dep ? 1 : 0;
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int a = ta + 16 * i;
-      if (a > k && a < l) {
-        const double ra = rrow[a];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-          const int b = tb + 16 * j;
-          if (b > k && b < l) W[i][j] = fma(-ra, rrow[b], W[i][j]);
-        }
-      }
+      int e = 0;
+      if (role == 0 && a < l && W[i][i] > 0.0 && isfinite(W[i][i])) e = ilogb(W[i][i]) >> 1;
+      esc[a] = e;
     }
   }
   __syncthreads();
+  const bool anybad = flag_s != 0;
+  if (role == 0) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) W[i][j] = ldexp(W[i][j], -(esc[ta + 16 * i] + esc[tb + 16 * j]));
+  }
+  if (ta == tb) {
+    double tr = 0.0, mx = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      tr += W[i][i];
+      mx = fmax(mx, W[i][i]);
+    }
+    red[0][ta] = tr;
+    red[1][ta] = mx;
+  }
+  __syncthreads();
+  double trace = 0.0, maxdiag = 0.0;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    trace += red[0][t];
+    maxdiag = fmax(maxdiag, red[1][t]);
+  }
+  const double shift = role == 0 ? 11.0 * ((double)n * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * trace : 0.0;
+  maxdiag += shift;
+  if (ta == tb) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      if (ta + 16 * i < l) W[i][i] += shift;
+  }
+
+  // 2. blocked right-looking Cholesky W = R^T R (R upper), panels of 4 rows
+  //    and one barrier per panel: the panel's rows of the trailing matrix are
+  //    published by their owners before the previous barrier (double
+  //    buffered); every thread factors the 4 x 4 diagonal block itself (the
+  //    same arithmetic everywhere), forms the panel rows of R at the columns
+  //    it owns and applies the rank-4 update.
+  constexpr int PW = 4;
+  if (ta < PW) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) pbuf[0][ta][tb + 16 * j] = W[0][j];
+  }
+  // rows l .. LP-1 of R stay zero, so the solve can run all LP steps
+  for (int e = tid; e < (LP - l) * LP; e += 256) {
+    const int j = l + e / LP, b = e % LP;
+    Rp[j][b & 3][b >> 2] = 0.0;
+  }
+  if (tid >= l && tid < LP) inv_diag[tid] = 0.0;
+  __syncthreads();
+  uint64_t dmask = 0;
+  int ndef = 0;
+  const int npan = (l + PW - 1) / PW;
+  for (int pn = 0; pn < npan; ++pn) {
+    const int k0 = PW * pn;
+    const double (*buf)[LP] = pbuf[pn & 1];
+    // all loads of the panel first (one LDS round trip)
+    double xa[PW][NB], xb[PW][NB], dg[PW][PW], bv[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) xa[q][i] = buf[q][ta + 16 * i];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) xb[q][j] = buf[q][tb + 16 * j];
+#pragma unroll
+      for (int c = 0; c < PW; ++c) dg[q][c] = buf[q][k0 + c];
+      bv[q] = buf[q][tid < LP ? tid : 0];
+    }
+    // diagonal block: pivots, inverse square roots, R[k0+q][k0+c]
+    double inv[PW], piv[PW], rd[PW][PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      double pv = dg[q][q];
+#pragma unroll
+      for (int pp = 0; pp < q; ++pp) pv = fma(-rd[pp][q], rd[pp][q], pv);
+      const bool dep = !(pv > tau * maxdiag) || anybad;
+      inv[q] = dep ? 0.0 : rsq_nr(fmax(pv, 1e-300));
+      piv[q] = pv;
+      if (dep && k0 + q < l) {
+        dmask |= 1ull << (k0 + q);
+        ++ndef;
+      }
+#pragma unroll
+      for (int c = 0; c < PW; ++c) {
+        double v = dg[q][c];
+#pragma unroll
+        for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rd[pp][c], v);
+        rd[q][c] = c > q ? v * inv[q] : 0.0;
+      }
+    }
+    // panel rows of R at this thread's columns (zero at or left of the diagonal)
+    double ra[PW][NB], rb[PW][NB], rc[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+      const int k = k0 + q;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        double v = xa[q][i];
+#pragma unroll
+        for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], ra[pp][i], v);
+        ra[q][i] = v * (ta + 16 * i > k ? inv[q] : 0.0);
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        double v = xb[q][j];
+#pragma unroll
+        for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rb[pp][j], v);
+        rb[q][j] = v * (tb + 16 * j > k ? inv[q] : 0.0);
+      }
+      double v = bv[q];
+#pragma unroll
+      for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rc[pp], v);
+      rc[q] = v * (tid > k && tid < l ? inv[q] : 0.0);
+    }
+    if (tid < LP) {
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int k = k0 + q;
+        Rp[k][tid & 3][tid >> 2] = tid == k ? piv[q] * inv[q] : rc[q];  // inv = 0 when dep
+      }
+    }
+    if (tid < PW) {
+      double v = inv[0];
+#pragma unroll
+      for (int q = 1; q < PW; ++q) v = tid == q ? inv[q] : v;
+      inv_diag[k0 + tid] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        double w = W[i][j];
+#pragma unroll
+        for (int q = 0; q < PW; ++q) w = fma(-ra[q][i], rb[q][j], w);
+        W[i][j] = w;
+      }
+    // publish the next panel's rows
+    const int k1 = k0 + PW;
+    if (k1 < l && (ta >> 2) == ((k1 & 15) >> 2)) {
+      const int i1 = k1 >> 4, q = ta - (k1 & 15);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        double v = W[0][j];
+#pragma unroll
+        for (int i = 1; i < NB; ++i) v = i1 == i ? W[i][j] : v;
+        pbuf[(pn + 1) & 1][q][tb + 16 * j] = v;
+      }
+    }
+    __syncthreads();
+  }
   if (blockIdx.x == 0) {
-    for (int e = tid; e < l * l; e += 256) Rg[e] = Rl[e / l][e % l];
-    if (tid < l) defic_g[tid] = dfs[tid];
+    for (int e = tid; e < l * l; e += 256) {
+      const int a = e / l, b = e % l;
+      const double v = Rp[a][b & 3][b >> 2];
+      Rg[e] = role == 0 ? ldexp(v, esc[b]) : v;
+    }
+    if (tid < l) defic_g[tid] = (int)((dmask >> tid) & 1ull);
     if (tid == 0) {
       if (anybad) atomicOr(&status[0], TUCKER_INFO_NONFINITE);
       if (ndef) {
@@ -297,48 +423,72 @@ __global__ __launch_bounds__(256) void k_pass(const double* __restrict__ Qin, in
       }
     }
   }
-
-  // 3. forward substitution z R = y for the block's 64 rows: 4 lanes per row
-  //    (one quad), each summing a fixed quarter of the dot product, combined
-  //    by two DPP exchanges; the row lives in LDS.
-  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
-  for (int e = tid; e < OR_RB * LP; e += 256) {
-    const int r = e / LP, j = e % LP;
-    Zs[r][j] = (r0 + r < n && j < l) ? Qin[(r0 + r) * l + j] : 0.0;
-  }
-  __syncthreads();
-  {
-    const int r = tid >> 2, t = tid & 3;
-    const int64_t i = r0 + r;
-    const double inv_sqrt_n = rsqrt((double)n);
-    for (int j = 0; j < l; ++j) {
-      double z;
-      if (dfs[j]) {
-        z = (i < n) ? completion_entry(cseed, ctag, (uint64_t)i, (uint32_t)j) * inv_sqrt_n : 0.0;
-      } else {
-        double s = 0.0, s2 = 0.0;
-        int k = t;
-        for (; k + 4 < j; k += 8) {
-          s = fma(Zs[r][k], Rl[k][j], s);
-          s2 = fma(Zs[r][k + 4], Rl[k + 4][j], s2);
-        }
-        if (k < j) s = fma(Zs[r][k], Rl[k][j], s);
-        s += s2;
-        s += dpp_f64(s, 0);
-        s += dpp_f64(s, 1);
-        z = (Zs[r][j] - s) * inv_diag[j];
-      }
-      if (t == 0) Zs[r][j] = z;
+  // pass 2 decides pass 3 (the same answer in every block)
+  bool last = role == 2;
+  if (role == 1) {
+    if (tid == 0) flag_s = 0;
+    __syncthreads();
+    for (int e = tid; e < l * l; e += 256) {
+      const int a = e / l, b = e % l;
+      const double v = Rp[a][b & 3][b >> 2];
+      if (!(fabs(v - (a == b ? 1.0 : 0.0)) <= 1e-4)) flag_s = 1;
     }
+    __syncthreads();
+    last = flag_s == 0 && !anybad && ndef == 0;
+    if (blockIdx.x == 0 && tid == 0) status[2] = last ? 1 : 0;
+  }
+
+  // 3. solve z R = y for the block's 64 rows: 4 lanes per row (one quad), lane
+  //    t holds columns t + 4 m in registers; column j's value comes from its
+  //    owner lane by a quad broadcast and updates the rest right-looking.
+  const int r = tid >> 2, t = tid & 3;
+  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
+  const int64_t row = r0 + r;
+  double y[MW], z[MW];
+#pragma unroll
+  for (int m = 0; m < MW; ++m) {
+    const int b = t + 4 * m;
+    double v = (row < n && b < l) ? Qin[row * l + b] : 0.0;
+    if (role == 0) v = ldexp(v, -esc[b]);
+    y[m] = v;
+    z[m] = 0.0;
+  }
+  // A deficient column j has a zero row j in R (and inv_diag[j] = 0), so its
+  // value never reaches later columns: the loop carries zero for it and the
+  // completion direction is put in afterwards, off the dependency chain.
+#pragma unroll
+  for (int j = 0; j < LP; ++j) {
+    const int jt = j & 3, jm = j >> 2;
+    double zj = quad_bcast(y[jm] * inv_diag[j], jt);
+    z[jm] = t == jt ? zj : z[jm];
+#pragma unroll
+    for (int m = jm; m < MW; ++m) y[m] = fma(-zj, Rp[j][t][m], y[m]);
+  }
+#pragma unroll
+  for (int m = 0; m < MW; ++m) Zs[r][t + 4 * m] = z[m];
+  if (dmask != 0) {
+    const double inv_sqrt_n = rsqrt((double)n);
+    for (int j = t; j < l; j += 4)
+      if ((dmask >> j) & 1ull)
+        Zs[r][j] = row < n ? completion_entry(cseed, ctag, (uint64_t)row, (uint32_t)j) * inv_sqrt_n : 0.0;
   }
   __syncthreads();
   for (int e = tid; e < OR_RB * l; e += 256) {
-    const int r = e / l, j = e % l;
-    if (r0 + r < n) Qout[(r0 + r) * l + j] = Zs[r][j];
+    const int rr = e / l, j = e % l;
+    if (r0 + rr < n) Qout[(r0 + rr) * l + j] = Zs[rr][j];
   }
-  if (part_out == nullptr) return;
-  __syncthreads();
-  block_gram_store<LP>(Zs, l, part_out + (size_t)blockIdx.x * l * l);
+  if (last && qt != nullptr) {
+    for (int e = tid; e < OR_RB * l; e += 256) {
+      const int j = e / OR_RB, rr = e % OR_RB;
+      if (r0 + rr < n) {
+        if (qt_f64)
+          ((double*)qt)[(int64_t)j * n + r0 + rr] = Zs[rr][j];
+        else
+          ((float*)qt)[(int64_t)j * n + r0 + rr] = (float)Zs[rr][j];
+      }
+    }
+  }
+  if (part_out != nullptr && !(role == 1 && last)) block_gram_mfma<LP>(Zs, l, part_out + (size_t)blockIdx.x * l * l);
 }
 
 // C = A B for 64-wide LDS matrices (full product; the zero triangles add
@@ -366,17 +516,23 @@ __device__ __forceinline__ void tile_matmul(const double (*Am)[OR_LS], const dou
 }
 
 // Rotation (c, s) that orthogonalises two columns with squared norms al, be
-// and inner product ga: t = sign(d) g / (|d| + sqrt(d^2 + g^2)), d = be - al,
-// g = 2 ga. The angle is computed in FP32 on power-of-two-scaled inputs (any
-// angle is a valid rotation; this one annihilates ga to ~1e-7 relative), then
-// c = 1 / sqrt(1 + t^2) in FP64 by Newton, so c^2 + s^2 = 1 to rounding.
+// and inner product ga: t = tan(theta) is the root of smallest magnitude of
+// g t^2 + 2 d t - g = 0 (d = be - al, g = 2 ga). It is taken in FP32 on
+// power-of-two-scaled inputs, t = sign(d) g / (|d| + sqrt(d^2 + g^2)), then
+// refined by one FP64 Newton step (the FP32 start is within 1e-7, so one
+// step reaches FP64 accuracy); c = 1 / sqrt(1 + t^2) in FP64 by Newton and
+// s = c t, so c^2 + s^2 = 1 to rounding. Needs d or g nonzero.
 __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double& c, double& s) {
   const double d = be - al, g = 2.0 * ga;
   const int e = ilogb(fmax(fabs(d), fabs(g)));
-  const float df = (float)ldexp(d, -e), gf = (float)ldexp(g, -e);
-  const float h = sqrtf(fmaf(df, df, gf * gf));
+  const double ds = ldexp(d, -e), gs = ldexp(g, -e);
+  const float df = (float)ds, gf = (float)gs;
+  const float h = __builtin_amdgcn_sqrtf(fmaf(df, df, gf * gf));
   const float tf = copysignf(1.0f, df) * gf * __builtin_amdgcn_rcpf(fabsf(df) + h);
-  const double t = (double)tf;
+  double t = (double)tf;
+  const double f = fma(gs, fma(t, t, -1.0), 2.0 * ds * t);
+  const double fp = 2.0 * fma(gs, t, ds);
+  t -= f * (double)__builtin_amdgcn_rcpf((float)fp);
   const double x = fma(t, t, 1.0);
   double y = (double)__builtin_amdgcn_rsqf((float)x);
   y = y * fma(-0.5 * x * y, y, 1.5);
@@ -385,24 +541,31 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
   s = y * t;
 }
 
-// Racc = R3 R2 R1, one-sided Jacobi on Racc^T, sort, shift update, log.
-// Writes Wm (left singular vectors of R as columns, descending) and sigma.
+// Racc = R3 R2 R1 (R3 = I when pass 3 did not run), one-sided Jacobi on
+// Racc^T, sort, shift update, log. Writes Wm (left singular vectors of R as
+// columns, descending) and sigma.
+// Pairs follow the circle method (player 0 fixed, the others rotate); a pair
+// is left alone when its columns are orthogonal to tol relative to their
+// norms or when either column is below l u times the largest (rounding
+// noise of R, whose directions carry no information). The iteration stops
+// once a full cycle of rounds made no rotation.
 // RPT = rows per lane (8 lanes per column pair cover 8 * RPT >= l rows).
 template <int RPT>
-__global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg, int l, double* __restrict__ Wm,
-                                                   double* __restrict__ sigma, double* __restrict__ alpha,
-                                                   tucker_info* __restrict__ info, int mode, int step,
-                                                   int* __restrict__ status) {
+__global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg, int l,
+                                                   const int* __restrict__ status, double tol,
+                                                   double* __restrict__ Wm, double* __restrict__ sigma,
+                                                   double* __restrict__ alpha, tucker_info* __restrict__ info,
+                                                   int mode, int step) {
   __shared__ double A[kMaxL][OR_LS];  // A[a][x] = column a of R^T = row a of R
   __shared__ double J[kMaxL][OR_LS];  // J[a][x] = column a of the rotation
-  __shared__ unsigned char sched[kMaxL - 1][kMaxL];  // pairs per round
   __shared__ double sv[kMaxL];
   __shared__ int perm[kMaxL];
-  __shared__ int rotated;
+  __shared__ int rotf[3];
   const int tid = threadIdx.x;
   const int ta = tid >> 4, tb = tid & 15;
   const int lp = (l + 1) & ~1;
-  // R = R3 R2 R1 (upper triangular): J <- R1, A <- R2; c = A J; J <- c; A <- R3; c = A J
+  const bool three = status[2] == 0;
+  // J <- R1, A <- R2; c = A J; then (pass 3 ran) J <- c, A <- R3, c = A J
   for (int e = tid; e < kMaxL * kMaxL; e += 256) {
     const int r = e >> 6, x = e & 63;
     J[r][x] = (r < l && x < l) ? Rg[r * l + x] : 0.0;
@@ -411,17 +574,19 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
   __syncthreads();
   double c[4][4];
   tile_matmul(A, J, l, c);
-  __syncthreads();
+  if (three) {
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) J[ta + 16 * i][tb + 16 * j] = c[i][j];
-  for (int e = tid; e < kMaxL * kMaxL; e += 256) {
-    const int r = e >> 6, x = e & 63;
-    A[r][x] = (r < l && x < l) ? Rg[2 * kMaxL * kMaxL + r * l + x] : 0.0;
+      for (int j = 0; j < 4; ++j) J[ta + 16 * i][tb + 16 * j] = c[i][j];
+    for (int e = tid; e < kMaxL * kMaxL; e += 256) {
+      const int r = e >> 6, x = e & 63;
+      A[r][x] = (r < l && x < l) ? Rg[2 * kMaxL * kMaxL + r * l + x] : 0.0;
+    }
+    __syncthreads();
+    tile_matmul(A, J, l, c);
   }
-  __syncthreads();
-  tile_matmul(A, J, l, c);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -431,70 +596,80 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
       A[r][x] = c[i][j];
       J[r][x] = (r == x) ? 1.0 : 0.0;
     }
-  // round-robin schedule (circle method: player 0 fixed, the others rotate);
-  // for odd l the extra player is the zero column l, which never rotates
-  for (int e = tid; e < (lp - 1) * (lp / 2); e += 256) {
-    const int rnd = e / (lp / 2), pr = e % (lp / 2);
-    const int x0 = pr, x1 = lp - 1 - pr;
-    const int pa = (x0 == 0) ? 0 : 1 + (x0 - 1 + rnd) % (lp - 1);
-    const int pb = (x1 == 0) ? 0 : 1 + (x1 - 1 + rnd) % (lp - 1);
-    sched[rnd][2 * pr] = (unsigned char)pa;
-    sched[rnd][2 * pr + 1] = (unsigned char)pb;
+  if (tid < 3) rotf[tid] = 0;
+  __syncthreads();
+  for (int r = tid; r < l; r += 256) {
+    double s2 = 0.0;
+    for (int x = 0; x < l; ++x) s2 = fma(A[r][x], A[r][x], s2);
+    sv[r] = s2;
   }
   __syncthreads();
+  double big = 0.0;
+  for (int r = 0; r < l; ++r) big = fmax(big, sv[r]);
+  const double epl = 2.220446049250313e-16 * l;
+  const double nu2 = epl * epl * big;
+  const double tol2 = tol * tol;
 
   // 8 lanes per column pair, lane `sub` owns rows sub + 8 q, q < RPT (rows
   // at or beyond l are zero in A and in the first l columns of J)
   const int pair = tid >> 3, sub = tid & 7;
-  const double tol = 2.220446049250313e-16 * l;
-  const double tol2 = tol * tol;
-  int sweeps = 0;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    sweeps = sweep + 1;
-    if (tid == 0) rotated = 0;
-    __syncthreads();
-    for (int rnd = 0; rnd < lp - 1; ++rnd) {
-      if (pair < lp / 2) {
-        const int pa = sched[rnd][2 * pair], pb = sched[rnd][2 * pair + 1];
-        double u[RPT], v[RPT], ju[RPT], jv[RPT];
+  const int np = lp / 2, nr = lp - 1;
+  // players at positions x0 = pair, x1 = lp - 1 - pair; a moving player's
+  // column at round rnd is 1 + (x - 1 + rnd) mod nr (player 0 stays column 0)
+  int posa = pair == 0 ? 0 : pair - 1, posb = lp - 2 - pair;
+  const int maxr = 40 * nr;
+  int rnd = 0, quiet = 0, slot = 0;  // slot = rnd mod 3
+  for (;;) {
+    if (rnd > 0) {
+      quiet = rotf[slot == 0 ? 2 : slot - 1] ? 0 : quiet + 1;
+      if (quiet >= nr || rnd >= maxr) break;
+    }
+    if (tid == 0) rotf[slot == 2 ? 0 : slot + 1] = 0;
+    if (pair < np) {
+      const int pa = pair == 0 ? 0 : 1 + posa;
+      const int pb = 1 + posb;
+      double u[RPT], v[RPT], ju[RPT], jv[RPT];
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          u[q] = A[pa][sub + 8 * q];
-          v[q] = A[pb][sub + 8 * q];
-          ju[q] = J[pa][sub + 8 * q];
-          jv[q] = J[pb][sub + 8 * q];
-        }
-        double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
+      for (int q = 0; q < RPT; ++q) {
+        u[q] = A[pa][sub + 8 * q];
+        v[q] = A[pb][sub + 8 * q];
+        ju[q] = J[pa][sub + 8 * q];
+        jv[q] = J[pb][sub + 8 * q];
+      }
+      double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < RPT; q += 2) {
-          al0 = fma(u[q], u[q], al0);
-          be0 = fma(v[q], v[q], be0);
-          ga0 = fma(u[q], v[q], ga0);
-          if (q + 1 < RPT) {
-            al1 = fma(u[q + 1], u[q + 1], al1);
-            be1 = fma(v[q + 1], v[q + 1], be1);
-            ga1 = fma(u[q + 1], v[q + 1], ga1);
-          }
-        }
-        const double al = octet_sum(al0 + al1), be = octet_sum(be0 + be1), ga = octet_sum(ga0 + ga1);
-        if (ga * ga > tol2 * al * be) {
-          double cs, sn;
-          jacobi_rotation(al, be, ga, cs, sn);
-#pragma unroll
-          for (int q = 0; q < RPT; ++q) {
-            A[pa][sub + 8 * q] = cs * u[q] - sn * v[q];
-            A[pb][sub + 8 * q] = sn * u[q] + cs * v[q];
-            J[pa][sub + 8 * q] = cs * ju[q] - sn * jv[q];
-            J[pb][sub + 8 * q] = sn * ju[q] + cs * jv[q];
-          }
-          if (sub == 0) rotated = 1;
+      for (int q = 0; q < RPT; q += 2) {
+        al0 = fma(u[q], u[q], al0);
+        be0 = fma(v[q], v[q], be0);
+        ga0 = fma(u[q], v[q], ga0);
+        if (q + 1 < RPT) {
+          al1 = fma(u[q + 1], u[q + 1], al1);
+          be1 = fma(v[q + 1], v[q + 1], be1);
+          ga1 = fma(u[q + 1], v[q + 1], ga1);
         }
       }
-      __syncthreads();
+      const double al = octet_sum(al0 + al1), be = octet_sum(be0 + be1), ga = octet_sum(ga0 + ga1);
+      const bool rot = ga * ga > tol2 * al * be && fmin(al, be) > nu2;
+      if (rot) {  // the same decision in all 8 lanes of the pair
+        double cs, sn;
+        jacobi_rotation(al, be, ga, cs, sn);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          A[pa][sub + 8 * q] = cs * u[q] - sn * v[q];
+          A[pb][sub + 8 * q] = sn * u[q] + cs * v[q];
+          J[pa][sub + 8 * q] = cs * ju[q] - sn * jv[q];
+          J[pb][sub + 8 * q] = sn * ju[q] + cs * jv[q];
+        }
+        if (sub == 0) rotf[slot] = 1;
+      }
     }
-    if (!rotated) break;
+    posa = posa + 1 == nr ? 0 : posa + 1;
+    posb = posb + 1 == nr ? 0 : posb + 1;
+    slot = slot == 2 ? 0 : slot + 1;
+    ++rnd;
     __syncthreads();
   }
+  const int sweeps = (rnd + nr - 1) / nr;
   for (int r = tid; r < l; r += 256) {
     double s2 = 0.0;
     for (int x = 0; x < l; ++x) s2 = fma(A[r][x], A[r][x], s2);
@@ -557,7 +732,8 @@ __global__ void k_clear_status(int* status) {
 }
 
 template <int LP>
-static void orth_passes(int64_t n, int l, const double* Y, const OrthWs& ws, uint64_t cseed, int step, hipStream_t st) {
+static void orth_passes(int64_t n, int l, double* Y, const double* Wrot, const OrthWs& ws, void* qt, int qt_f64,
+                        uint64_t cseed, int step, hipStream_t st) {
   const int nblk = (int)((n + OR_RB - 1) / OR_RB);
   const size_t pstride = align_up((size_t)nblk * l * l * sizeof(double)) / sizeof(double);
   double* p0 = ws.part;
@@ -566,45 +742,75 @@ static void orth_passes(int64_t n, int l, const double* Y, const OrthWs& ws, uin
   // flag a column whose pivot is below the rounding level of an n-row Gram
   const double tau1 = 1e-15, tau = fmax(1e-14, 4.0 * (double)n * 2.220446049250313e-16);
   const uint32_t tag = 0x100u + 16u * (uint32_t)step;
-  hipLaunchKernelGGL((k_gram<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, p0);
-  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, p0, nblk, 1, tau1, cseed, tag + 1, ws.Qa, p1,
-                     ws.R, ws.defic, ws.status);
-  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, ws.Qa, n, l, p1, nblk, 0, tau, cseed, tag + 2, ws.Qb,
-                     p0, ws.R + kMaxL * kMaxL, ws.defic + kMaxL, ws.status);
-  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, ws.Qb, n, l, p0, nblk, 0, tau, cseed, tag + 3, ws.Qa,
-                     (double*)nullptr, ws.R + 2 * kMaxL * kMaxL, ws.defic + 2 * kMaxL, ws.status);
+  hipLaunchKernelGGL((k_gram<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, Wrot, p0);
+  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)Y, n, l, (const double*)p0, nblk, 0,
+                     tau1, cseed, tag + 1, ws.Qa, (void*)nullptr, 0, p1, ws.R, ws.defic, ws.status);
+  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)ws.Qa, n, l, (const double*)p1, nblk,
+                     1, tau, cseed, tag + 2, ws.Qa, qt, qt_f64, p0, ws.R + kMaxL * kMaxL, ws.defic + kMaxL,
+                     ws.status);
+  hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)ws.Qa, n, l, (const double*)p0, nblk,
+                     2, tau, cseed, tag + 3, ws.Qa, qt, qt_f64, (double*)nullptr, ws.R + 2 * kMaxL * kMaxL,
+                     ws.defic + 2 * kMaxL, ws.status);
 }
 
-hipError_t launch_orth(int64_t n, int l, const double* Y, tucker_precision prec, void* q_out, void* qt,
-                       double* q64, double* sigma, double* alpha, tucker_info* info, int mode, int step,
-                       const OrthWs& ws, uint64_t cseed, hipStream_t st) {
-  TimingScope ts(KC_ORTH, st, 8.0 * n * l * 8, 3.0 * 2.0 * n * l * l);
+hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucker_precision prec, void* qt,
+                          const OrthWs& ws, uint64_t cseed, int step, hipStream_t st) {
+  TimingScope ts(KC_ORTH, st, 8.0 * n * l * 8, 4.0 * 2.0 * n * l * l);
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, ws.status);
+  const int f64 = prec == TUCKER_FP64 ? 1 : 0;
   switch ((l + 15) / 16) {
-    case 1: orth_passes<16>(n, l, Y, ws, cseed, step, st); break;
-    case 2: orth_passes<32>(n, l, Y, ws, cseed, step, st); break;
-    case 3: orth_passes<48>(n, l, Y, ws, cseed, step, st); break;
-    case 4: orth_passes<64>(n, l, Y, ws, cseed, step, st); break;
+    case 1: orth_passes<16>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
+    case 2: orth_passes<32>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
+    case 3: orth_passes<48>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
+    case 4: orth_passes<64>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
     default: return hipErrorInvalidValue;
   }
-  switch ((l + 15) / 16) {
-    case 1: hipLaunchKernelGGL((k_small_svd<2>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
-                               step, ws.status); break;
-    case 2: hipLaunchKernelGGL((k_small_svd<4>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
-                               step, ws.status); break;
-    case 3: hipLaunchKernelGGL((k_small_svd<6>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
-                               step, ws.status); break;
-    default: hipLaunchKernelGGL((k_small_svd<8>), dim3(1), dim3(256), 0, st, ws.R, l, ws.Wm, sigma, alpha, info, mode,
-                                step, ws.status); break;
+  return hipGetLastError();
+}
+
+template <int RPT>
+static void svd_launch(int l, const OrthWs& ws, double* sigma, double* alpha, tucker_info* info, int mode, int step,
+                       hipStream_t st) {
+  const double tol = 2.220446049250313e-16 * l;
+  hipLaunchKernelGGL((k_small_svd<RPT>), dim3(1), dim3(256), 0, st, (const double*)ws.R, l, (const int*)ws.status,
+                     tol, ws.Wm, sigma, alpha, info, mode, step);
+}
+
+hipError_t launch_orth_svd(int l, const OrthWs& ws, double* sigma, double* alpha, tucker_info* info, int mode,
+                           int step, hipStream_t st) {
+  switch ((l + 7) / 8) {
+    case 1: svd_launch<1>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 2: svd_launch<2>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 3: svd_launch<3>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 4: svd_launch<4>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 5: svd_launch<5>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 6: svd_launch<6>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 7: svd_launch<7>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 8: svd_launch<8>(l, ws, sigma, alpha, info, mode, step, st); break;
+    default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_orth_rotate(int64_t n, int l, const OrthWs& ws, tucker_precision prec, void* q_out, void* qt,
+                              double* q64, hipStream_t st) {
   const unsigned rb = (unsigned)((n * l + 255) / 256);
   if (prec == TUCKER_FP64)
-    hipLaunchKernelGGL((k_rotate<double>), dim3(rb), dim3(256), 0, st, ws.Qa, n, l, ws.Wm, (double*)q_out,
-                       (double*)qt, q64);
+    hipLaunchKernelGGL((k_rotate<double>), dim3(rb), dim3(256), 0, st, (const double*)ws.Qa, n, l,
+                       (const double*)ws.Wm, (double*)q_out, (double*)qt, q64);
   else
-    hipLaunchKernelGGL((k_rotate<float>), dim3(rb), dim3(256), 0, st, ws.Qa, n, l, ws.Wm, (float*)q_out, (float*)qt,
-                       q64);
+    hipLaunchKernelGGL((k_rotate<float>), dim3(rb), dim3(256), 0, st, (const double*)ws.Qa, n, l,
+                       (const double*)ws.Wm, (float*)q_out, (float*)qt, q64);
   return hipGetLastError();
+}
+
+hipError_t launch_orth(int64_t n, int l, double* Y, tucker_precision prec, void* q_out, void* qt, double* q64,
+                       double* sigma, double* alpha, tucker_info* info, int mode, int step, const OrthWs& ws,
+                       uint64_t cseed, hipStream_t st) {
+  hipError_t e = launch_orth_qr(n, l, Y, nullptr, prec, nullptr, ws, cseed, step, st);
+  if (e == hipSuccess) e = launch_orth_svd(l, ws, sigma, alpha, info, mode, step, st);
+  if (e == hipSuccess) e = launch_orth_rotate(n, l, ws, prec, q_out, qt, q64, st);
+  return e;
 }
 
 // ---------------------------------------------------------------------------
