@@ -251,7 +251,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     e = hipEventRecord(side->qr_done, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->qr_done, 0);
     if (e == hipSuccess)
-      e = launch_orth_svd(l, ows, w.sigma, t == 1 ? nullptr : alpha_upd, info, k, t - 1, side->s);
+      e = launch_orth_svd(l, prec, ows, w.sigma, t == 1 ? nullptr : alpha_upd, info, k, t - 1, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->svd_done, side->s);
     // Z = X_(k)^T Q3 (j-major), Y' = X_(k) Z
     if (e == hipSuccess) e = launch_rowcontract(prec, v, X, w.qt, 1, n, l, w.omz, true, st);
@@ -263,7 +263,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, prec, w.qt, ows, cseed, t, st);
   }
   // last small SVD on the caller's stream, then Q = Q3 J
-  if (e == hipSuccess) e = launch_orth_svd(l, ows, w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q, st);
+  if (e == hipSuccess) e = launch_orth_svd(l, prec, ows, w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q, st);
   if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, nullptr, w.q64, st);
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch");
 }

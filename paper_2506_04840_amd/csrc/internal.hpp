@@ -90,8 +90,10 @@ hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucke
 // and, when alpha != nullptr, the midpoint shift update of *alpha. When
 // info != nullptr, Sigma(1,1), Sigma(l,l) and alpha are logged at
 // [mode][step], and status bits are or-ed into info->flags.
-hipError_t launch_orth_svd(int l, const OrthWs& ws, double* sigma, double* alpha, tucker_info* info, int mode,
-                           int step, hipStream_t st);
+// `prec` is the precision the iterate's products ran in (sets the rotation
+// thresholds).
+hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
+                           tucker_info* info, int mode, int step, hipStream_t st);
 // Q = Q3 Wm to q_out (n x l, `prec` storage), qt (j-major l x n, `prec`
 // storage) and q64 (n x l, FP64), each when not nullptr.
 hipError_t launch_orth_rotate(int64_t n, int l, const OrthWs& ws, tucker_precision prec, void* q_out, void* qt,

@@ -546,13 +546,14 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
 // columns, descending) and sigma.
 // Pairs follow the circle method (player 0 fixed, the others rotate); a pair
 // is left alone when its columns are orthogonal to tol relative to their
-// norms or when either column is below l u times the largest (rounding
-// noise of R, whose directions carry no information). The iteration stops
-// once a full cycle of rounds made no rotation.
+// norms or when either column is below negl times the largest (rounding
+// noise of the iterate, whose directions carry no information: l u for FP64
+// products, about the FP32 / BF16 rounding level otherwise). The iteration
+// stops once a full cycle of rounds made no rotation.
 // RPT = rows per lane (8 lanes per column pair cover 8 * RPT >= l rows).
 template <int RPT>
 __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg, int l,
-                                                   const int* __restrict__ status, double tol,
+                                                   const int* __restrict__ status, double tol, double negl,
                                                    double* __restrict__ Wm, double* __restrict__ sigma,
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
                                                    int mode, int step) {
@@ -561,6 +562,9 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
   __shared__ double sv[kMaxL];
   __shared__ int perm[kMaxL];
   __shared__ int rotf[3];
+  // issue priority over waves of other kernels sharing the CU: this one is a
+  // latency-bound chain that often runs beside a bandwidth-bound product
+  __builtin_amdgcn_s_setprio(3);
   const int tid = threadIdx.x;
   const int ta = tid >> 4, tb = tid & 15;
   const int lp = (l + 1) & ~1;
@@ -606,8 +610,7 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
   __syncthreads();
   double big = 0.0;
   for (int r = 0; r < l; ++r) big = fmax(big, sv[r]);
-  const double epl = 2.220446049250313e-16 * l;
-  const double nu2 = epl * epl * big;
+  const double nu2 = negl * negl * big;
   const double tol2 = tol * tol;
 
   // 8 lanes per column pair, lane `sub` owns rows sub + 8 q, q < RPT (rows
@@ -769,24 +772,30 @@ hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucke
 }
 
 template <int RPT>
-static void svd_launch(int l, const OrthWs& ws, double* sigma, double* alpha, tucker_info* info, int mode, int step,
-                       hipStream_t st) {
-  const double tol = 2.220446049250313e-16 * l;
+static void svd_launch(int l, const OrthWs& ws, double tol, double negl, double* sigma, double* alpha,
+                       tucker_info* info, int mode, int step, hipStream_t st) {
   hipLaunchKernelGGL((k_small_svd<RPT>), dim3(1), dim3(256), 0, st, (const double*)ws.R, l, (const int*)ws.status,
-                     tol, ws.Wm, sigma, alpha, info, mode, step);
+                     tol, negl, ws.Wm, sigma, alpha, info, mode, step);
 }
 
-hipError_t launch_orth_svd(int l, const OrthWs& ws, double* sigma, double* alpha, tucker_info* info, int mode,
-                           int step, hipStream_t st) {
+hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
+                           tucker_info* info, int mode, int step, hipStream_t st) {
+  // Rotation thresholds by the precision the iterate was formed in: FP64
+  // converges to l u; FP32 and BF16 iterates carry rounding noise near 1e-7
+  // and 1e-3 of their norm, which bounds what their singular values and
+  // vectors can resolve.
+  const double u = 2.220446049250313e-16;
+  const double tol = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-8 : 1e-7;
+  const double negl = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-6 : 1e-4;
   switch ((l + 7) / 8) {
-    case 1: svd_launch<1>(l, ws, sigma, alpha, info, mode, step, st); break;
-    case 2: svd_launch<2>(l, ws, sigma, alpha, info, mode, step, st); break;
-    case 3: svd_launch<3>(l, ws, sigma, alpha, info, mode, step, st); break;
-    case 4: svd_launch<4>(l, ws, sigma, alpha, info, mode, step, st); break;
-    case 5: svd_launch<5>(l, ws, sigma, alpha, info, mode, step, st); break;
-    case 6: svd_launch<6>(l, ws, sigma, alpha, info, mode, step, st); break;
-    case 7: svd_launch<7>(l, ws, sigma, alpha, info, mode, step, st); break;
-    case 8: svd_launch<8>(l, ws, sigma, alpha, info, mode, step, st); break;
+    case 1: svd_launch<1>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 2: svd_launch<2>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 3: svd_launch<3>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 4: svd_launch<4>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 5: svd_launch<5>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 6: svd_launch<6>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 7: svd_launch<7>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 8: svd_launch<8>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -808,7 +817,7 @@ hipError_t launch_orth(int64_t n, int l, double* Y, tucker_precision prec, void*
                        double* sigma, double* alpha, tucker_info* info, int mode, int step, const OrthWs& ws,
                        uint64_t cseed, hipStream_t st) {
   hipError_t e = launch_orth_qr(n, l, Y, nullptr, prec, nullptr, ws, cseed, step, st);
-  if (e == hipSuccess) e = launch_orth_svd(l, ws, sigma, alpha, info, mode, step, st);
+  if (e == hipSuccess) e = launch_orth_svd(l, prec, ws, sigma, alpha, info, mode, step, st);
   if (e == hipSuccess) e = launch_orth_rotate(n, l, ws, prec, q_out, qt, q64, st);
   return e;
 }

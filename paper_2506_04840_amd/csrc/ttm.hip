@@ -193,6 +193,167 @@ __global__ __launch_bounds__(256) void k_cr_rows(const typename Pol<MK>::T* __re
 }
 
 // ---------------------------------------------------------------------------
+// Column reduction, S > 1, staged through LDS: part[split][i][j] = sum over
+// the split's columns c of X_(k)[i, c] Bt[j, c]. A workgroup owns 64 rows
+// (16 per wave) and one split; a stage is KT consecutive columns of one p
+// (256 bytes of every row). The stage's X and Bt tiles are read from HBM
+// with whole-row 16-byte vector loads (a wave covers 4 rows x 256 B per
+// instruction), kept two stages ahead in registers, written to a double
+// buffered LDS tile (BF16: converted once here) and read back by the matrix
+// cores as 16-byte fragments. LDS rows are padded by 16 bytes so the 16
+// lanes of each fragment read hit distinct banks. One barrier per stage.
+// ---------------------------------------------------------------------------
+template <int MK>
+struct LdsPol;
+template <>
+struct LdsPol<MF_F32> {
+  using LT = float;
+  static constexpr int KT = 64, RV = 4;  // stage width (elements), elements per 16-byte fragment
+};
+template <>
+struct LdsPol<MF_F64> {
+  using LT = double;
+  static constexpr int KT = 32, RV = 2;
+};
+template <>
+struct LdsPol<MF_BF16> {
+  using LT = __bf16;
+  static constexpr int KT = 64, RV = 8;
+};
+
+template <int MK, int NJ, bool VEC>
+__global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __restrict__ X,
+                                                const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
+                                                int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
+                                                int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
+  using Po = Pol<MK>;
+  using T = typename Po::T;
+  using LT = typename LdsPol<MK>::LT;
+  constexpr int KT = LdsPol<MK>::KT, RV = LdsPol<MK>::RV, KL = Po::KL;
+  constexpr int VE = 16 / (int)sizeof(T);          // elements of T per 16-byte global load
+  constexpr int UPR = KT / VE;                     // 16-byte units per row per stage (16)
+  constexpr int LS = KT + 16 / (int)sizeof(LT);    // padded LDS row (elements)
+  constexpr int XU = 64 * UPR / 256, BU = 16 * NJ * UPR / 256;  // units per thread: X tile, Bt tile
+  __shared__ __align__(16) LT xs[2][64][LS];
+  __shared__ __align__(16) LT bs[2][16 * NJ][LS];
+
+  int split, rb;
+  if (!xcd_decode(blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mm = lane & 15, g = lane >> 4;
+  const int64_t r0 = (int64_t)rb * 64;
+  const int64_t t0 = nsteps * split / nsplit, t1 = nsteps * (split + 1) / nsplit;
+
+  using V4 = float4;  // 16 raw bytes
+  auto gload = [&](int64_t t, V4 (&xr)[XU], V4 (&br)[BU]) {
+    const int64_t p = t / spp;
+    const int64_t s0 = (t - p * spp) * KT;
+    const bool live = t < t1;
+#pragma unroll
+    for (int q = 0; q < XU; ++q) {
+      const int L = q * 256 + tid, row = L / UPR, u = L % UPR;
+      const int64_t i = r0 + row, s = s0 + (int64_t)u * VE;
+      const T* src = X + (p * n + i) * S + s;
+      if (VEC) {
+        xr[q] = (live && i < n && s < S) ? *reinterpret_cast<const V4*>(src) : V4{0.f, 0.f, 0.f, 0.f};
+      } else {
+        T v[VE];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) v[e] = (live && i < n && s + e < S) ? src[e] : T(0);
+        xr[q] = *reinterpret_cast<const V4*>(v);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BU; ++q) {
+      const int L = q * 256 + tid, j = L / UPR, u = L % UPR;
+      const int64_t s = s0 + (int64_t)u * VE;
+      const T* src = Bt + (int64_t)j * m + p * S + s;
+      if (VEC) {
+        br[q] = (live && j < l && s < S) ? *reinterpret_cast<const V4*>(src) : V4{0.f, 0.f, 0.f, 0.f};
+      } else {
+        T v[VE];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) v[e] = (live && j < l && s + e < S) ? src[e] : T(0);
+        br[q] = *reinterpret_cast<const V4*>(v);
+      }
+    }
+  };
+  auto sput = [&](LT* dst, const V4& v) {
+    if constexpr (MK == MF_BF16) {
+      const float* f = reinterpret_cast<const float*>(&v);
+      typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+      const bf16x4 b = {(__bf16)f[0], (__bf16)f[1], (__bf16)f[2], (__bf16)f[3]};
+      *reinterpret_cast<bf16x4*>(dst) = b;
+    } else {
+      *reinterpret_cast<V4*>(dst) = v;
+    }
+  };
+  auto lstore = [&](int buf, const V4 (&xr)[XU], const V4 (&br)[BU]) {
+#pragma unroll
+    for (int q = 0; q < XU; ++q) {
+      const int L = q * 256 + tid, row = L / UPR, u = L % UPR;
+      sput(&xs[buf][row][u * VE], xr[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < BU; ++q) {
+      const int L = q * 256 + tid, j = L / UPR, u = L % UPR;
+      sput(&bs[buf][j][u * VE], br[q]);
+    }
+  };
+
+  typename Po::acc_t acc[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) acc[u] = typename Po::acc_t{0, 0, 0, 0};
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 4 * RV) {
+      LT a[RV];
+      *reinterpret_cast<V4*>(a) = *reinterpret_cast<const V4*>(&xs[buf][16 * wave + mm][kk + RV * g]);
+      LT b[NJ][RV];
+#pragma unroll
+      for (int u = 0; u < NJ; ++u)
+        *reinterpret_cast<V4*>(b[u]) = *reinterpret_cast<const V4*>(&bs[buf][16 * u + mm][kk + RV * g]);
+      if constexpr (MK == MF_BF16) {
+#pragma unroll
+        for (int u = 0; u < NJ; ++u)
+          acc[u] = mfma_bf16(*reinterpret_cast<const bf16x8*>(a), *reinterpret_cast<const bf16x8*>(b[u]), acc[u]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < RV; e += KL)
+#pragma unroll
+          for (int u = 0; u < NJ; ++u) acc[u] = mma<MK>(&a[e], &b[u][e], acc[u]);
+      }
+    }
+  };
+
+  V4 xa[XU], ba[BU], xb[XU], bb[BU];
+  gload(t0, xa, ba);
+  gload(t0 + 1, xb, bb);
+  lstore(0, xa, ba);
+  __syncthreads();
+  for (int64_t t = t0; t < t1; t += 2) {
+    // stage t in buffer 0, stage t + 1 in registers xb/bb
+    gload(t + 2, xa, ba);
+    compute(0);
+    lstore(1, xb, bb);
+    __syncthreads();
+    if (t + 1 >= t1) break;
+    gload(t + 3, xb, bb);
+    compute(1);
+    lstore(0, xa, ba);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < NJ; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + 16 * wave + mfma_drow<MK>(lane, v);
+      const int col = 16 * u + mm;
+      if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[u][v];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Column reduction, S == 1: X is [P, n] with rows p contiguous along i (the
 // output row index). A batch covers 4 * KB consecutive p; k-slot g of the
 // MFMA takes p = pbase + KB g + q, q < KB, for both operands.
@@ -273,27 +434,34 @@ __global__ __launch_bounds__(256) void k_cr_cols(const typename Pol<MK>::T* __re
 }
 
 static void cr_geom(tucker_precision prec, const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
-  const int kc = prec == TUCKER_FP64 ? 4 : 8;  // 32 contiguous bytes per lane in k_cr_rows
-  const int kb = prec == TUCKER_BF16 ? 8 : 4;
   if (v.S == 1) {
+    const int kb = prec == TUCKER_BF16 ? 8 : 4;
     *spp = 0;
     *nsteps = (v.P + 4 * kb - 1) / (4 * kb);
+    *nrblocks = (int)((v.n + 255) / 256);
   } else {
-    *spp = (v.S + 4 * kc - 1) / (4 * kc);
+    const int kt = prec == TUCKER_FP64 ? 32 : 64;  // stage width of k_cr_lds
+    *spp = (v.S + kt - 1) / kt;
     *nsteps = v.P * *spp;
+    *nrblocks = (int)((v.n + 63) / 64);
   }
-  *nrblocks = (int)((v.n + 255) / 256);
 }
 
 int colreduce_splits_prec(const View3& v, tucker_precision prec) {
   int64_t nsteps, spp;
   int nrb;
   cr_geom(prec, v, &nsteps, &spp, &nrb);
-  const int64_t waves_per_split = std::min<int64_t>((v.n + 63) / 64, 4 * (int64_t)nrb);
-  // about 2048 waves (2 per SIMD), each wave at least 8 steps; a multiple of 8
-  // so the XCD mapping has no holes
-  int64_t ns = (2048 + waves_per_split - 1) / waves_per_split;
+  // S == 1: about 2048 waves (2 per SIMD), each wave at least 8 steps.
+  // S > 1: about 1536 workgroups (two resident per CU), each at least 8 stages.
+  int64_t ns;
+  if (v.S == 1) {
+    const int64_t waves_per_split = std::min<int64_t>((v.n + 63) / 64, 4 * (int64_t)nrb);
+    ns = (2048 + waves_per_split - 1) / waves_per_split;
+  } else {
+    ns = (1536 + nrb - 1) / nrb;
+  }
   ns = std::min<int64_t>(ns, std::max<int64_t>(1, nsteps / 8));
+  // a multiple of 8 so the XCD mapping has no holes
   if (ns > 8) ns = ns / 8 * 8;
   return (int)std::max<int64_t>(1, ns);
 }
@@ -336,10 +504,10 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
   } else {
     const bool vec = (v.S % VE == 0) && (xa % 16 == 0) && (ba % 16 == 0);
     if (vec)
-      hipLaunchKernelGGL((k_cr_rows<MK, NJ, true>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
+      hipLaunchKernelGGL((k_cr_lds<MK, NJ, true>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
                          v.S, l, m, spp, nsteps, nsplit, nrb, (PT*)part);
     else
-      hipLaunchKernelGGL((k_cr_rows<MK, NJ, false>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
+      hipLaunchKernelGGL((k_cr_lds<MK, NJ, false>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
                          v.S, l, m, spp, nsteps, nsplit, nrb, (PT*)part);
   }
   return hipGetLastError();
