@@ -4,19 +4,20 @@
 //
 // Route, all in FP64:
 //   pass 1  D = 2^floor(log4 diag(Y^T Y)) (exact column scaling),
-//           W = D^-1 Y^T Y D^-1 + s I, R~ = chol(W), Q1 = (Y D^-1) R~^-1, R1 = R~ D
-//           (shifted CholeskyQR on Y D^-1, s = 11 (n l + l (l+1)) u ||Y D^-1||_F^2,
-//           Fukaya et al. 2020)
+//           W = D^-1 Y^T Y D^-1 (+ s I), R~ = chol(W), Q1 = (Y D^-1) R~^-1, R1 = R~ D.
+//           For an iterate formed by FP64 products this is shifted
+//           CholeskyQR on Y D^-1 (s = 11 (n l + l (l+1)) u ||Y D^-1||_F^2,
+//           Fukaya et al. 2020). For FP32 / BF16 products there is no shift;
+//           a pivot below their rounding level marks the column dependent.
 //   pass 2  R2 = chol(Q1^T Q1), Q2 = Q1 R2^-1
-//   pass 3  R3 = chol(Q2^T Q2), Q3 = Q2 R3^-1, run only when R2 is not within
-//           1e-4 of I (otherwise Q1 was already well conditioned and Q2 is
-//           orthonormal to rounding, the CholeskyQR2 regime)
+//   pass 3  R3 = chol(Q2^T Q2), Q3 = Q2 R3^-1, skipped (R3 = I) when Q2^T Q2
+//           is already I to 1e-13 (FP64) / 1e-10 (FP32, BF16)
 //   R = R3 R2 R1 (so Y = Q3 R); one-sided Jacobi on R^T: R^T J = B with
 //   orthogonal columns, hence R = J diag(|B_j|) (B/|B|)^T and the left
 //   singular vectors of Y are Q3 J. Columns sorted by descending Sigma.
-// The scaling makes the shifted pass insensitive to graded column norms: the
-// iterates of the power steps have nearly orthogonal columns of very
-// different lengths, and for them two passes suffice.
+// The scaling makes pass 1 insensitive to graded column norms: the iterates
+// of the power steps have nearly orthogonal columns of very different
+// lengths, and for them two passes suffice.
 // A Cholesky pivot below tau * max(diag) marks the column numerically
 // dependent on the previous ones: its row of R is zero and the solve puts a
 // random direction in that column, which the next pass orthonormalises.
@@ -144,11 +145,13 @@ __device__ __forceinline__ void block_gram_mfma(const double (*Zs)[OR_LS], int l
 // step run on an unrotated basis into the iterate of the rotated one).
 template <int LP>
 __global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n, int l,
-                                              const double* __restrict__ Wm, double* __restrict__ part) {
+                                              const double* __restrict__ Wm, double* __restrict__ part,
+                                              int* __restrict__ status) {
   constexpr int NB = LP / 16;
   __shared__ double Zs[OR_RB][OR_LS];
   __shared__ double Ws[kMaxL][OR_LS];
   const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid < 4) status[tid] = 0;  // flags of this factorisation
   const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
   for (int e = tid; e < OR_RB * LP; e += 256) {
     const int r = e / LP, j = e % LP;
@@ -186,19 +189,21 @@ __global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n,
   block_gram_mfma<LP>(Zs, l, part + (size_t)blockIdx.x * l * l);
 }
 
-// One CholeskyQR pass over 64 rows per block (role 0: pass 1, shifted and
-// scaled; role 1: pass 2, decides whether pass 3 runs; role 2: pass 3).
+// One CholeskyQR pass over 64 rows per block (role 0: pass 1, scaled and
+// shifted by shift_scale * trace; role 1: pass 2; role 2: pass 3, which
+// leaves at once when W is I to eps3).
 //   W = sum_b part_in[b] (scaled and shifted for role 0); R = chol(W) with
 //   deficiency flags; Qout rows = Qin rows R^-1 (deficient columns: random
 //   direction / sqrt(n)); part_out[blk] = Gram of this block's Qout rows.
 // Qout may alias Qin (each block reads its rows before writing them).
 // Block 0 writes R (role 0: R~ D) and the flags for the small SVD.
-// The last pass that runs also writes Q j-major in the storage precision to
-// qt (when not null).
+// Passes 2 and 3 also write Q j-major in the storage precision to qt (when
+// not null).
 template <int LP>
 __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int l, const double* __restrict__ part_in,
-                                              int nblk, int role, double tau, uint64_t cseed, uint32_t ctag,
-                                              double* Qout, void* __restrict__ qt, int qt_f64,
+                                              int nblk, int role, double tau, double shift_scale, double eps3,
+                                              uint64_t cseed, uint32_t ctag, double* Qout, void* __restrict__ qt,
+                                              int qt_f64,
                                               double* __restrict__ part_out, double* __restrict__ Rg,
                                               int* __restrict__ defic_g, int* __restrict__ status) {
   constexpr int NB = LP / 16, MW = LP / 4;
@@ -209,12 +214,14 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
   __shared__ double inv_diag[LP];
   __shared__ double red[2][16];
   __shared__ int esc[LP];
-  __shared__ int flag_s;
+  __shared__ int flag_s, far_s;
 
-  if (role == 2 && status[2] != 0) return;  // pass 3 not needed (same value in every block)
   const int tid = threadIdx.x;
   const int ta = tid >> 4, tb = tid & 15;
-  if (tid == 0) flag_s = 0;
+  if (tid == 0) {
+    flag_s = 0;
+    far_s = 0;
+  }
 
   // 1. W in registers: thread owns W[ta + 16 i][tb + 16 j]; the partials are
   //    summed in block order
@@ -242,12 +249,17 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
         for (int j = 0; j < NB; ++j) W[i][j] += v[q][i][j];
   }
   __syncthreads();
-  bool mybad = false;
+  bool mybad = false, myfar = false;
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) mybad = mybad || !isfinite(W[i][j]);
+    for (int j = 0; j < NB; ++j) {
+      const int a = ta + 16 * i, b = tb + 16 * j;
+      mybad = mybad || !isfinite(W[i][j]);
+      myfar = myfar || (a < l && b < l && !(fabs(W[i][j] - (a == b ? 1.0 : 0.0)) <= eps3));
+    }
   if (mybad) flag_s = 1;
+  if (myfar) far_s = 1;
   if (ta == tb) {
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -259,6 +271,12 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
   }
   __syncthreads();
   const bool anybad = flag_s != 0;
+  // pass 3: when Q2^T Q2 is already I to eps3, Q2 is the result (R3 = I);
+  // every block sees the same sums and leaves together
+  if (role == 2 && far_s == 0 && !anybad) {
+    if (blockIdx.x == 0 && tid == 0) status[2] = 1;
+    return;
+  }
   if (role == 0) {
 #pragma unroll
     for (int i = 0; i < NB; ++i)
@@ -282,7 +300,7 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
     trace += red[0][t];
     maxdiag = fmax(maxdiag, red[1][t]);
   }
-  const double shift = role == 0 ? 11.0 * ((double)n * l + (double)l * (l + 1)) * 1.1102230246251565e-16 * trace : 0.0;
+  const double shift = role == 0 ? shift_scale * trace : 0.0;
   maxdiag += shift;
   if (ta == tb) {
 #pragma unroll
@@ -423,20 +441,9 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
       }
     }
   }
-  // pass 2 decides pass 3 (the same answer in every block)
-  bool last = role == 2;
-  if (role == 1) {
-    if (tid == 0) flag_s = 0;
-    __syncthreads();
-    for (int e = tid; e < l * l; e += 256) {
-      const int a = e / l, b = e % l;
-      const double v = Rp[a][b & 3][b >> 2];
-      if (!(fabs(v - (a == b ? 1.0 : 0.0)) <= 1e-4)) flag_s = 1;
-    }
-    __syncthreads();
-    last = flag_s == 0 && !anybad && ndef == 0;
-    if (blockIdx.x == 0 && tid == 0) status[2] = last ? 1 : 0;
-  }
+  // passes 2 and 3 write Q in the storage precision (pass 3, when it runs,
+  // overwrites what pass 2 wrote)
+  const bool emit = role >= 1;
 
   // 3. solve z R = y for the block's 64 rows: 4 lanes per row (one quad), lane
   //    t holds columns t + 4 m in registers; column j's value comes from its
@@ -477,7 +484,7 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
     const int rr = e / l, j = e % l;
     if (r0 + rr < n) Qout[(r0 + rr) * l + j] = Zs[rr][j];
   }
-  if (last && qt != nullptr) {
+  if (emit && qt != nullptr) {
     for (int e = tid; e < OR_RB * l; e += 256) {
       const int j = e / OR_RB, rr = e % OR_RB;
       if (r0 + rr < n) {
@@ -488,7 +495,7 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
       }
     }
   }
-  if (part_out != nullptr && !(role == 1 && last)) block_gram_mfma<LP>(Zs, l, part_out + (size_t)blockIdx.x * l * l);
+  if (part_out != nullptr) block_gram_mfma<LP>(Zs, l, part_out + (size_t)blockIdx.x * l * l);
 }
 
 // C = A B for 64-wide LDS matrices (full product; the zero triangles add
@@ -730,42 +737,47 @@ __global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ Q3, i
   if (q64 != nullptr) q64[e] = s;
 }
 
-__global__ void k_clear_status(int* status) {
-  if (threadIdx.x < 4) status[threadIdx.x] = 0;
-}
-
 template <int LP>
-static void orth_passes(int64_t n, int l, double* Y, const double* Wrot, const OrthWs& ws, void* qt, int qt_f64,
-                        uint64_t cseed, int step, hipStream_t st) {
+static void orth_passes(int64_t n, int l, double* Y, const double* Wrot, tucker_precision prec, const OrthWs& ws,
+                        void* qt, int qt_f64, uint64_t cseed, int step, hipStream_t st) {
   const int nblk = (int)((n + OR_RB - 1) / OR_RB);
   const size_t pstride = align_up((size_t)nblk * l * l * sizeof(double)) / sizeof(double);
   double* p0 = ws.part;
   double* p1 = ws.part + pstride;
-  // pass 1 carries the shift, so its pivots sit far above tau1; passes 2 and 3
-  // flag a column whose pivot is below the rounding level of an n-row Gram
-  const double tau1 = 1e-15, tau = fmax(1e-14, 4.0 * (double)n * 2.220446049250313e-16);
+  // Pass 1 works on unit-scaled columns: a pivot below tau1 says the column
+  // lies within sqrt(tau1) of the span of the previous ones, below what the
+  // products that formed Y resolve (FP64: the shift keeps every pivot above
+  // 1e-15; FP32 and BF16: their rounding level), so it is treated as
+  // dependent. Passes 2 and 3 flag a column whose pivot is below the rounding
+  // level of an n-row Gram.
+  const double tau1 = prec == TUCKER_FP64 ? 1e-15 : prec == TUCKER_FP32 ? 1e-12 : 1e-6;
+  const double tau = fmax(1e-14, 4.0 * (double)n * 2.220446049250313e-16);
+  // the shift of pass 1 (FP64 only; the FP32 / BF16 threshold already keeps
+  // every accepted pivot far above rounding)
+  const double shift1 = prec == TUCKER_FP64 ? 11.0 * ((double)n * l + (double)l * (l + 1)) * 1.1102230246251565e-16 : 0.0;
+  // pass 3 is skipped when Q2 is orthonormal to this (it only re-orthogonalises)
+  const double eps3 = prec == TUCKER_FP64 ? 1e-13 : 1e-10;
   const uint32_t tag = 0x100u + 16u * (uint32_t)step;
-  hipLaunchKernelGGL((k_gram<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, Wrot, p0);
+  hipLaunchKernelGGL((k_gram<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, Wrot, p0, ws.status);
   hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)Y, n, l, (const double*)p0, nblk, 0,
-                     tau1, cseed, tag + 1, ws.Qa, (void*)nullptr, 0, p1, ws.R, ws.defic, ws.status);
+                     tau1, shift1, 0.0, cseed, tag + 1, ws.Qa, (void*)nullptr, 0, p1, ws.R, ws.defic, ws.status);
   hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)ws.Qa, n, l, (const double*)p1, nblk,
-                     1, tau, cseed, tag + 2, ws.Qa, qt, qt_f64, p0, ws.R + kMaxL * kMaxL, ws.defic + kMaxL,
+                     1, tau, 0.0, 0.0, cseed, tag + 2, ws.Qa, qt, qt_f64, p0, ws.R + kMaxL * kMaxL, ws.defic + kMaxL,
                      ws.status);
   hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)ws.Qa, n, l, (const double*)p0, nblk,
-                     2, tau, cseed, tag + 3, ws.Qa, qt, qt_f64, (double*)nullptr, ws.R + 2 * kMaxL * kMaxL,
+                     2, tau, 0.0, eps3, cseed, tag + 3, ws.Qa, qt, qt_f64, (double*)nullptr, ws.R + 2 * kMaxL * kMaxL,
                      ws.defic + 2 * kMaxL, ws.status);
 }
 
 hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucker_precision prec, void* qt,
                           const OrthWs& ws, uint64_t cseed, int step, hipStream_t st) {
   TimingScope ts(KC_ORTH, st, 8.0 * n * l * 8, 4.0 * 2.0 * n * l * l);
-  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(64), 0, st, ws.status);
   const int f64 = prec == TUCKER_FP64 ? 1 : 0;
   switch ((l + 15) / 16) {
-    case 1: orth_passes<16>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
-    case 2: orth_passes<32>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
-    case 3: orth_passes<48>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
-    case 4: orth_passes<64>(n, l, Y, Wrot, ws, qt, f64, cseed, step, st); break;
+    case 1: orth_passes<16>(n, l, Y, Wrot, prec, ws, qt, f64, cseed, step, st); break;
+    case 2: orth_passes<32>(n, l, Y, Wrot, prec, ws, qt, f64, cseed, step, st); break;
+    case 3: orth_passes<48>(n, l, Y, Wrot, prec, ws, qt, f64, cseed, step, st); break;
+    case 4: orth_passes<64>(n, l, Y, Wrot, prec, ws, qt, f64, cseed, step, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -460,7 +460,7 @@ int colreduce_splits_prec(const View3& v, tucker_precision prec) {
   } else {
     ns = (1536 + nrb - 1) / nrb;
   }
-  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nsteps / 8));
+  ns = std::min<int64_t>(ns, std::max<int64_t>(1, nsteps / (v.S == 1 ? 2 : 8)));
   // a multiple of 8 so the XCD mapping has no holes
   if (ns > 8) ns = ns / 8 * 8;
   return (int)std::max<int64_t>(1, ns);
@@ -596,19 +596,26 @@ template <int MK, int NJ, bool VEC, bool WVEC>
 __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
                                                  int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
-                                                 int64_t ntiles, typename Pol<MK>::T* __restrict__ out, int64_t osp,
-                                                 int64_t osj) {
+                                                 int64_t ntiles, int ksplit, typename Pol<MK>::T* __restrict__ out,
+                                                 int64_t osp, int64_t osj) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
   constexpr int KB = (KL == 1) ? 4 : KL, ROWS = 4 * KB;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mm = lane & 15, g = lane >> 4;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-  if (tile >= ntiles) return;
-  const int64_t p = tile / tiles_per_p;
+  // ksplit: the 4 waves of a workgroup share one tile and split the n rows
+  // (in whole batches), adding their partial tiles in wave order at the end
+  // (few tiles); otherwise each wave owns a tile and all n rows.
+  const int64_t tile = ksplit ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
+  if (ksplit ? tile >= ntiles : (int64_t)blockIdx.x * 4 >= ntiles) return;
+  const bool live = tile < ntiles;
+  const int64_t p = live ? tile / tiles_per_p : 0;
   const int64_t s0 = (tile - p * tiles_per_p) * 64;
   const T* xp = X + p * n * S;
+  const int64_t nbat = (n + ROWS - 1) / ROWS;
+  const int64_t iw0 = ksplit ? nbat * wave / 4 * ROWS : 0;
+  const int64_t iw1 = !live ? 0 : ksplit ? min<int64_t>(n, nbat * (wave + 1) / 4 * ROWS) : n;
 
   typename Po::acc_t acc[4][NJ];
 #pragma unroll
@@ -618,7 +625,7 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
 
   auto fetch = [&](int64_t i0, T (&fa)[4][KB], T (&fb)[NJ][KB]) {
     const int64_t iq = i0 + KB * g;
-    const int icnt = (int)min<int64_t>(KB, n - iq);
+    const int icnt = (int)max<int64_t>(-1, min<int64_t>(KB, iw1 - iq));
 #pragma unroll
     for (int q = 0; q < KB; ++q) {
       const int64_t i = iq + q;
@@ -651,13 +658,37 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
         for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][q], &fb[u][q], acc[tm][u]);
   };
   T a0[4][KB], b0[NJ][KB], a1[4][KB], b1[NJ][KB];
-  fetch(0, a0, b0);
-  fetch(ROWS, a1, b1);
-  for (int64_t i0 = 0; i0 < n; i0 += 2 * ROWS) {
+  fetch(iw0, a0, b0);
+  fetch(iw0 + ROWS, a1, b1);
+  for (int64_t i0 = iw0; i0 < iw1; i0 += 2 * ROWS) {
     compute(a0, b0);
-    fetch(i0 + 2 * ROWS, a0, b0);  // zero-filled past row n
+    fetch(i0 + 2 * ROWS, a0, b0);  // zero-filled past the wave's last row
     compute(a1, b1);
     fetch(i0 + 3 * ROWS, a1, b1);
+  }
+  if (ksplit) {
+    using AE = typename Po::part_t;
+    __shared__ AE red[3][16 * NJ][64];
+    if (wave > 0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NJ; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) red[wave - 1][(a * NJ + b) * 4 + v][lane] = acc[a][b][v];
+    }
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < NJ; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[a][b][v] += red[w][(a * NJ + b) * 4 + v][lane];
+  } else if (!live) {
+    return;
   }
   // tile tm = h * MV + vv, result row dr -> column s0 + h*16*MV + MV*dr + vv
   T* op = out + p * osp;
@@ -702,8 +733,12 @@ __global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __re
   constexpr int KC = Po::KC;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mm = lane & 15, g = lane >> 4;
-  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
   if (p0 >= P) return;
+  // the 4 waves split the n reduction rows (in whole batches of 4 KC) and add
+  // their partial tiles in wave order at the end
+  const int64_t nbat = (n + 4 * KC - 1) / (4 * KC);
+  const int64_t iw0 = nbat * wave / 4 * 4 * KC, iw1 = min<int64_t>(n, nbat * (wave + 1) / 4 * 4 * KC);
 
   typename Po::acc_t acc[4][NJ];
 #pragma unroll
@@ -713,7 +748,7 @@ __global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __re
 
   auto fetch = [&](int64_t i0, T (&fa)[4][KC], T (&fb)[NJ][KC]) {
     const int64_t ib = i0 + KC * g;
-    const int cnt = (int)min<int64_t>(KC, n - ib);
+    const int cnt = (int)max<int64_t>(-1, min<int64_t>(KC, iw1 - ib));
 #pragma unroll
     for (int tm = 0; tm < 4; ++tm) {
       const int64_t p = p0 + 16 * tm + mm;
@@ -739,14 +774,34 @@ __global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __re
         for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][e], &fb[u][e], acc[tm][u]);
   };
   T a0[4][KC], b0[NJ][KC], a1[4][KC], b1[NJ][KC];
-  fetch(0, a0, b0);
-  fetch(4 * KC, a1, b1);
-  for (int64_t i0 = 0; i0 < n; i0 += 8 * KC) {
+  fetch(iw0, a0, b0);
+  fetch(iw0 + 4 * KC, a1, b1);
+  for (int64_t i0 = iw0; i0 < iw1; i0 += 8 * KC) {
     compute(a0, b0);
-    fetch(i0 + 8 * KC, a0, b0);  // zero-filled past row n
+    fetch(i0 + 8 * KC, a0, b0);  // zero-filled past the wave's last row
     compute(a1, b1);
     fetch(i0 + 12 * KC, a1, b1);
   }
+  using AE = typename Po::part_t;
+  __shared__ AE red[3][16 * NJ][64];
+  if (wave > 0) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < NJ; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[wave - 1][(a * NJ + b) * 4 + v][lane] = acc[a][b][v];
+  }
+  __syncthreads();
+  if (wave != 0) return;
+#pragma unroll
+  for (int w = 0; w < 3; ++w)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < NJ; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[a][b][v] += red[w][(a * NJ + b) * 4 + v][lane];
 #pragma unroll
   for (int tm = 0; tm < 4; ++tm)
 #pragma unroll
@@ -770,8 +825,7 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
   const bool wvec = (wsi == 1) && (wsj % VE == 0) && (wa % 16 == 0);
   if (v.S == 1) {
     const int64_t osp = out_jmajor ? 1 : lw, osj = out_jmajor ? m : 1;
-    const int64_t waves = (v.P + 63) / 64;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
+    const unsigned blocks = (unsigned)((v.P + 63) / 64);
     const bool vec = (v.n % Po::KC == 0) && (xa % 16 == 0);
 #define TK_RC_COLS(V, WV)                                                                                    \
   hipLaunchKernelGGL((k_rc_cols<MK, NJ, V, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.P, \
@@ -785,11 +839,12 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     const int64_t osp = out_jmajor ? v.S : (int64_t)lw * v.S, osj = out_jmajor ? m : v.S;
     const int64_t tpp = (v.S + 63) / 64;
     const int64_t ntiles = v.P * tpp;
-    const unsigned blocks = (unsigned)((ntiles + 3) / 4);
+    const int ksplit = ntiles < 2048 ? 1 : 0;  // split the rows when tiles alone cannot fill the chip
+    const unsigned blocks = (unsigned)(ksplit ? ntiles : (ntiles + 3) / 4);
     const bool vec = (v.S % Po::MV == 0) && (xa % 16 == 0) && (oa % 16 == 0) && (osj % VE == 0) && (osp % VE == 0);
 #define TK_RC_ROWS(V, WV)                                                                                        \
   hipLaunchKernelGGL((k_rc_rows<MK, NJ, V, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
-                     lw, wsi, wsj, tpp, ntiles, (T*)out, osp, osj)
+                     lw, wsi, wsj, tpp, ntiles, ksplit, (T*)out, osp, osj)
     if (vec && wvec) TK_RC_ROWS(true, true);
     else if (vec) TK_RC_ROWS(true, false);
     else if (wvec) TK_RC_ROWS(false, true);
