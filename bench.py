@@ -54,6 +54,21 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of a kernel class from the committed counter summary
+    (profiles/<kernel>_<workload>_traffic.json), or None when there is none or
+    the kernel source has changed since the counters were taken."""
+    from paper_2506_04840_amd.pmc_traffic import source_digest
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != source_digest():
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def reconstruct_torch(G, U):
     import torch
     t = G
@@ -163,6 +178,10 @@ def main():
             achieved = tk["bytes"] / sec / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+        traffic = measured_traffic(args.kernel, args.workload) if prec == CONFIGS[args.workload]["precision"] else None
+        roof["traffic"] = traffic
+        if traffic is not None:
+            roof["traffic_unit"] = "bytes/launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         roof.update({"kernel": args.kernel, "launches": tk["launches"],
                      "avg_launch_us": round(1e3 * tk["ms"] / max(tk["launches"], 1), 3),
                      "alg_bytes_per_launch": tk["bytes"] / max(tk["launches"], 1),
