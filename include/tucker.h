@@ -218,6 +218,52 @@ int tucker_timing_reset(void);
 /* Disable and free the events. */
 int tucker_timing_disable(void);
 
+/* ---- Batched solves: many small shifted randomized ST-HOSVDs at once ------
+ * Algorithm 3 for a set of requests of one order d and one power count q,
+ * FP32 storage (Section 3.1; the same arithmetic as tucker_rsthosvd with FP32,
+ * shift as given). Every phase of the method runs as one persistent launch
+ * over all requests of the batch (a fixed grid looping over a table of work
+ * items), so a batch costs the same number of launches as one request.
+ *
+ * The launch sequence of tucker_batch_step depends only on (capacity, d, q,
+ * lclass) and on the plan buffer and workspace addresses: a step captured into
+ * a graph replays correctly for any later plan made with the same
+ * (capacity, d, q, lclass) into the same plan buffer and workspace.
+ *
+ * Limits: 1 <= d <= 8, every l_k <= lclass (16, 32, 48 or 64), nitems <=
+ * capacity <= 4096. info->normG2 is not computed by the batch path (0).
+ * Ownership: every pointer in an item is the caller's device memory; the plan
+ * is caller host memory (pinned, e.g. hipHostMalloc, so the step's upload is
+ * asynchronous and capturable); the workspace is caller device memory. */
+typedef struct {
+  tucker_shape shape;                 /* dims of A */
+  int64_t ranks[TUCKER_MAX_ORDER];
+  uint64_t seed;                      /* Omega_k as in tucker_fill_gaussian */
+  const void* A;                      /* FP32 tensor, row-major */
+  void* G;                            /* FP32 core r_1 x ... x r_d */
+  void* U[TUCKER_MAX_ORDER];          /* FP32 n_k x r_k */
+  tucker_info* info;                  /* device, or NULL */
+} tucker_batch_item;
+
+/* Host plan buffer bytes and the device table bytes (the start of the batch
+ * workspace) for a capacity. 0 on bad arguments. */
+size_t tucker_batch_plan_bytes(int32_t capacity, int32_t order, int32_t q);
+size_t tucker_batch_table_bytes(int32_t capacity, int32_t order, int32_t q);
+/* Device workspace one item needs (0 on bad arguments); a batch workspace is
+ * tucker_batch_table_bytes + the sum over its items (each rounded up to 256). */
+size_t tucker_batch_item_bytes(const tucker_batch_item* item, int32_t p, int32_t q);
+/* Host-only: validates the items, carves ws and writes the plan (nitems may
+ * be 0). EINVAL for a bad item (same checks as tucker_rsthosvd) or an item
+ * whose order is not `order`, EUNSUPPORTED
+ * when some l_k > lclass, EWORKSPACE when ws or the plan is too small. */
+int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t nitems, const tucker_batch_item* items,
+                      int32_t p, int32_t q, tucker_shift shift, void* ws, size_t ws_bytes, void* plan,
+                      size_t plan_bytes);
+/* Enqueues the batch on `stream`: one upload of the plan's tables into the
+ * workspace, then the persistent launches. Results land in each item's G, U
+ * and info when the stream reaches this point. */
+int tucker_batch_step(const void* plan, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

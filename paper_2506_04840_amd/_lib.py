@@ -51,6 +51,18 @@ class Info(ctypes.Structure):
 
 INFO_BYTES = ctypes.sizeof(Info)
 
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("shape", Shape),
+        ("ranks", ctypes.c_int64 * MAX_ORDER),
+        ("seed", ctypes.c_uint64),
+        ("A", ctypes.c_void_p),
+        ("G", ctypes.c_void_p),
+        ("U", ctypes.c_void_p * MAX_ORDER),
+        ("info", ctypes.c_void_p),
+    ]
+
 # Every symbol of include/tucker.h with its ctypes signature.
 _P, _I32, _I64, _U64, _SZ, _D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64,
                                  ctypes.c_size_t, ctypes.c_double)
@@ -75,6 +87,12 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "tucker_timing_reset": (ctypes.c_int, []),
     "tucker_timing_disable": (ctypes.c_int, []),
+    "tucker_batch_plan_bytes": (_SZ, [_I32, _I32, _I32]),
+    "tucker_batch_table_bytes": (_SZ, [_I32, _I32, _I32]),
+    "tucker_batch_item_bytes": (_SZ, [ctypes.POINTER(BatchItem), _I32, _I32]),
+    "tucker_batch_plan": (ctypes.c_int, [_I32, _I32, _I32, _I32, ctypes.POINTER(BatchItem), _I32, _I32, ctypes.c_int,
+                                         _P, _SZ, _P, _SZ]),
+    "tucker_batch_step": (ctypes.c_int, [_P, _P]),
 }
 
 KC = {"colreduce": 0, "rowcontract": 1, "orth": 2, "fill": 3, "reduce": 4}
@@ -335,3 +353,60 @@ def timing_reset() -> None:
 
 def timing_disable() -> None:
     _check(lib.tucker_timing_disable())
+
+
+# --------------------------------------------------------------------------- batched solves
+class BatchSolver:
+    """Many small shifted randomized ST-HOSVDs (FP32, one order d, one q) per
+    launch sequence. plan(items) writes the pinned plan for a batch (host
+    only); step() enqueues the whole batch on the current stream. A step
+    captured in a graph replays for later plans (same capacity, d, q, lclass)."""
+
+    def __init__(self, capacity: int, order: int, q: int, p: int, lclass: int, ws_bytes: int,
+                 shift: str = "adaptive", device="cuda"):
+        self.capacity, self.order, self.q, self.p, self.lclass = int(capacity), int(order), int(q), int(p), int(lclass)
+        self.shift = _SHIFT[shift]
+        self.device = torch.device(device)
+        nb = lib.tucker_batch_plan_bytes(self.capacity, self.order, self.q)
+        if nb == 0:
+            raise ValueError("bad batch capacity, order or q")
+        self.table_bytes = int(lib.tucker_batch_table_bytes(self.capacity, self.order, self.q))
+        self.plan_buf = torch.empty(int(nb), dtype=torch.uint8, pin_memory=True)
+        self.ws = torch.empty(int(ws_bytes), dtype=torch.uint8, device=self.device)
+        self._items = (BatchItem * self.capacity)()
+
+    @staticmethod
+    def item(A: torch.Tensor, G: torch.Tensor, U: Sequence[torch.Tensor], ranks, seed: int,
+             info: Optional[torch.Tensor] = None) -> BatchItem:
+        it = BatchItem()
+        it.shape = _shape(A.shape)
+        for k, r in enumerate(ranks):
+            it.ranks[k] = int(r)
+        it.seed = int(seed)
+        it.A = _dev(A, "A")
+        it.G = _dev(G, "G")
+        for k, u in enumerate(U):
+            it.U[k] = _dev(u, "U")
+        it.info = info.data_ptr() if info is not None else None
+        return it
+
+    def item_bytes(self, it: BatchItem) -> int:
+        nb = lib.tucker_batch_item_bytes(ctypes.byref(it), self.p, self.q)
+        if nb == 0:
+            raise ValueError("invalid batch item")
+        return int(nb)
+
+    def plan(self, items: Sequence[BatchItem]) -> None:
+        if len(items) > self.capacity:
+            raise ValueError("more items than the batch capacity")
+        for i, it in enumerate(items):
+            self._items[i] = it
+        _check(lib.tucker_batch_plan(self.capacity, self.order, self.lclass, len(items), self._items, self.p, self.q,
+                                     self.shift,
+                                     ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws.numel()),
+                                     ctypes.c_void_p(self.plan_buf.data_ptr()),
+                                     ctypes.c_size_t(self.plan_buf.numel())))
+
+    def step(self) -> None:
+        _check(lib.tucker_batch_step(ctypes.c_void_p(self.plan_buf.data_ptr()), _stream(self.device)))
+

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 #include "tucker.h"
@@ -363,6 +364,257 @@ size_t op_ws_layout(const View3& v, int64_t m, int l, tucker_precision prec, cha
   return off;
 }
 
+
+// ---- batched solves --------------------------------------------------------
+constexpr uint32_t kBatchMagic = 0x54424154u;  // plan header tag
+
+struct BatchHeader {
+  uint32_t magic;
+  int32_t capacity, order, q, lclass, nphases;
+  size_t table_bytes;
+  char* ws;
+};
+struct PhaseRec {
+  int32_t kind;
+  int32_t pad;
+  size_t hdr_off, desc_off;  // within the table image
+};
+
+// The fixed phase sequence for (order, q).
+std::vector<BatchKind> batch_phases(int d, int q) {
+  std::vector<BatchKind> ph{BK_INIT};
+  const BatchKind orth[] = {BK_GRAM, BK_PASS, BK_PASS, BK_PASS, BK_SVD};
+  for (int k = 0; k < d; ++k) {
+    for (BatchKind b : {BK_FILL, BK_CR_LDS, BK_CR_COLS, BK_REDUCE}) ph.push_back(b);
+    for (BatchKind b : orth) ph.push_back(b);
+    for (int t = 1; t <= q; ++t) {
+      for (BatchKind b : {BK_RC_ROWS, BK_RC_COLS, BK_CR_LDS, BK_CR_COLS, BK_REDUCE}) ph.push_back(b);
+      for (BatchKind b : orth) ph.push_back(b);
+    }
+    for (BatchKind b : {BK_ROTATE, BK_SIGNFIX, BK_RC_ROWS, BK_RC_COLS}) ph.push_back(b);
+  }
+  return ph;
+}
+
+size_t batch_table_layout(int cap, int d, int q, std::vector<PhaseRec>* recs) {
+  const std::vector<BatchKind> ph = batch_phases(d, q);
+  size_t off = 0;
+  if (recs) recs->clear();
+  for (BatchKind k : ph) {
+    PhaseRec r;
+    r.kind = (int32_t)k;
+    r.pad = 0;
+    r.hdr_off = off;
+    off += align_up((size_t)(cap + 2) * sizeof(int));
+    r.desc_off = off;
+    off += align_up((size_t)cap * batch_desc_bytes(k));
+    if (recs) recs->push_back(r);
+  }
+  return off;
+}
+
+size_t batch_plan_bytes(int cap, int d, int q) {
+  return align_up(sizeof(BatchHeader)) + align_up(batch_phases(d, q).size() * sizeof(PhaseRec)) +
+         batch_table_layout(cap, d, q, nullptr);
+}
+
+int batch_item_plan(const tucker_batch_item* it, int32_t p, int32_t q, Plan* pl) {
+  if (it == nullptr) return fail(TUCKER_EINVAL, "null item");
+  int rc = make_plan(&it->shape, it->ranks, p, q, TUCKER_FP32, true, pl);
+  if (rc) return rc;
+  if (it->A == nullptr || it->G == nullptr) return fail(TUCKER_EINVAL, "item with null tensor or core");
+  for (int k = 0; k < pl->d; ++k)
+    if (it->U[k] == nullptr) return fail(TUCKER_EINVAL, "item with null U[%d]", k);
+  return TUCKER_OK;
+}
+
+// Fills one phase's descriptor for item b (returns its work items).
+int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const SolveWs& w,
+                   const tucker_batch_item& it, tucker_shift shift, int d, void* dst) {
+  const View3 v = pl.v[k];
+  const int l = pl.l[k], r = (int)pl.r[k];
+  const int64_t n = v.n, m = pl.m[k];
+  const OrthWs ows = carve_orth(w.orth, n, l);
+  const void* X = k == 0 ? it.A : w.xbuf[(k - 1) & 1];
+  const int nsplit = colreduce_splits(v, l);
+  const int nblk = (int)((n + 63) / 64);
+  double* alpha = w.alpha + k;
+  switch (kind) {
+    case BK_INIT: {
+      BInit* b = (BInit*)dst;
+      b->info = it.info;
+      b->alpha = w.alpha;
+      for (int j = 0; j < TUCKER_MAX_ORDER; ++j) b->l[j] = j < d ? pl.l[j] : 0;
+      b->d = d;
+      b->flags = pl.flags;
+      return 1;
+    }
+    case BK_FILL: {
+      BFill* b = (BFill*)dst;
+      b->out = (float*)w.omz;
+      b->seed = it.seed;
+      b->rows = m;
+      b->ld = m;
+      b->mode = (uint32_t)k;
+      b->cols = l;
+      return (m * ((l + 3) / 4) + 255) / 256;
+    }
+    case BK_CR_LDS:
+    case BK_CR_COLS: {
+      int64_t nsteps, spp;
+      int nrb;
+      cr_geometry(v, &nsteps, &spp, &nrb);
+      if (kind == BK_CR_LDS) {
+        BCrLds* b = (BCrLds*)dst;
+        b->X = (const float*)X;
+        b->Bt = (const float*)w.omz;
+        b->part = (float*)w.part;
+        b->n = n;
+        b->S = v.S;
+        b->m = m;
+        b->spp = spp;
+        b->nsteps = nsteps;
+        b->l = l;
+        b->nsplit = nsplit;
+        b->nrb = nrb;
+        return v.S > 1 ? cr_lds_items(n, nsplit) : 0;
+      }
+      BCrCols* b = (BCrCols*)dst;
+      b->X = (const float*)X;
+      b->Bt = (const float*)w.omz;
+      b->part = (float*)w.part;
+      b->P = v.P;
+      b->n = n;
+      b->nsteps = nsteps;
+      b->l = l;
+      b->nsplit = nsplit;
+      b->nrb = nrb;
+      return v.S == 1 ? cr_cols_items(n, nsplit) : 0;
+    }
+    case BK_REDUCE: {
+      BReduce* b = (BReduce*)dst;
+      b->part = (const float*)w.part;
+      b->qsub = t == 0 ? nullptr : ows.Qa;
+      b->alpha = alpha;
+      b->Y = w.y64;
+      b->nl = n * l;
+      b->nsplit = nsplit;
+      return (n * l + 31) / 32;
+    }
+    case BK_RC_ROWS:
+    case BK_RC_COLS: {
+      // power step (role 0): Z = X_(k)^T Q3, j-major; core (role 1): X x_k U_k^T
+      const bool core = role == 1;
+      const int lw = core ? r : l;
+      const void* W = core ? w.ut : w.qt;
+      void* out = core ? (k == d - 1 ? it.G : w.xbuf[k & 1]) : w.omz;
+      if (kind == BK_RC_ROWS) {
+        BRcRows* b = (BRcRows*)dst;
+        int ksplit;
+        int64_t tpp;
+        const int64_t ntiles = rc_rows_tiles(v, &ksplit, &tpp);
+        b->X = (const float*)X;
+        b->W = (const float*)W;
+        b->out = (float*)out;
+        b->n = n;
+        b->S = v.S;
+        b->wsi = 1;
+        b->wsj = n;
+        b->tpp = tpp;
+        b->ntiles = ntiles;
+        b->osp = core ? (int64_t)lw * v.S : v.S;
+        b->osj = core ? v.S : m;
+        b->lw = lw;
+        b->ksplit = ksplit;
+        return v.S > 1 ? (ksplit ? ntiles : (ntiles + 3) / 4) : 0;
+      }
+      BRcCols* b = (BRcCols*)dst;
+      b->X = (const float*)X;
+      b->W = (const float*)W;
+      b->out = (float*)out;
+      b->P = v.P;
+      b->n = n;
+      b->wsi = 1;
+      b->wsj = n;
+      b->osp = core ? lw : 1;
+      b->osj = core ? 1 : m;
+      b->lw = lw;
+      return v.S == 1 ? (v.P + 63) / 64 : 0;
+    }
+    case BK_GRAM: {
+      BGram* b = (BGram*)dst;
+      b->Y = w.y64;
+      b->Wm = t == 0 ? nullptr : ows.Wm;
+      b->part = ows.part;
+      b->status = ows.status;
+      b->n = n;
+      b->l = l;
+      return nblk;
+    }
+    case BK_PASS: {
+      BPass* b = (BPass*)dst;
+      const size_t pstride = align_up((size_t)nblk * l * l * sizeof(double)) / sizeof(double);
+      double* p0 = ows.part;
+      double* p1 = ows.part + pstride;
+      const uint32_t tag = 0x100u + 16u * (uint32_t)t;
+      b->Qin = role == 0 ? w.y64 : ows.Qa;
+      b->part_in = role == 1 ? p1 : p0;
+      b->Qout = ows.Qa;
+      b->qt = role == 0 ? nullptr : w.qt;
+      b->part_out = role == 0 ? p1 : (role == 1 ? p0 : nullptr);
+      b->Rg = ows.R + (size_t)role * TUCKER_MAX_L * TUCKER_MAX_L;
+      b->defic = ows.defic + role * TUCKER_MAX_L;
+      b->status = ows.status;
+      b->cseed = completion_seed(it.seed, k);
+      b->tau = role == 0 ? 1e-12 : std::max(1e-14, 4.0 * (double)n * 2.220446049250313e-16);
+      b->shift_scale = 0.0;
+      b->eps3 = 1e-10;
+      b->n = n;
+      b->l = l;
+      b->nblk = nblk;
+      b->role = role;
+      b->ctag = tag + 1 + (uint32_t)role;
+      return nblk;
+    }
+    case BK_SVD: {
+      BSvd* b = (BSvd*)dst;
+      b->Rg = ows.R;
+      b->status = ows.status;
+      b->Wm = ows.Wm;
+      b->sigma = w.sigma;
+      b->alpha = (t == 0 || shift != TUCKER_SHIFT_ADAPTIVE) ? nullptr : alpha;
+      b->info = it.info;
+      b->tol = 1e-8;
+      b->negl = 1e-6;
+      b->l = l;
+      b->mode = k;
+      b->step = t;
+      return 1;
+    }
+    case BK_ROTATE: {
+      BRotate* b = (BRotate*)dst;
+      b->Q3 = ows.Qa;
+      b->Wm = ows.Wm;
+      b->q64 = w.q64;
+      b->n = n;
+      b->l = l;
+      return (n * l + 255) / 256;
+    }
+    case BK_SIGNFIX: {
+      BSignfix* b = (BSignfix*)dst;
+      b->Q = w.q64;
+      b->U = (float*)it.U[k];
+      b->Ut = (float*)w.ut;
+      b->n = n;
+      b->l = l;
+      b->r = r;
+      return r;
+    }
+    default:
+      return 0;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -504,6 +756,128 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
                     tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                     tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
   return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream);
+}
+
+size_t tucker_batch_plan_bytes(int32_t capacity, int32_t order, int32_t q) {
+  if (capacity < 1 || capacity > 4096 || order < 1 || order > TUCKER_MAX_ORDER || q < 0 || q > TUCKER_MAX_Q) return 0;
+  return batch_plan_bytes(capacity, order, q);
+}
+
+size_t tucker_batch_table_bytes(int32_t capacity, int32_t order, int32_t q) {
+  if (capacity < 1 || capacity > 4096 || order < 1 || order > TUCKER_MAX_ORDER || q < 0 || q > TUCKER_MAX_Q) return 0;
+  return align_up(batch_table_layout(capacity, order, q, nullptr));
+}
+
+size_t tucker_batch_item_bytes(const tucker_batch_item* item, int32_t p, int32_t q) {
+  Plan pl;
+  if (batch_item_plan(item, p, q, &pl)) return 0;
+  SolveWs w;
+  return align_up(solve_ws_layout(pl, TUCKER_FP32, nullptr, &w));
+}
+
+int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t nitems, const tucker_batch_item* items,
+                      int32_t p, int32_t q, tucker_shift shift, void* ws, size_t ws_bytes, void* plan,
+                      size_t plan_bytes) {
+  if (capacity < 1 || capacity > 4096) return fail(TUCKER_EINVAL, "capacity %d outside 1..4096", capacity);
+  if (lclass != 16 && lclass != 32 && lclass != 48 && lclass != 64)
+    return fail(TUCKER_EINVAL, "lclass %d is not 16, 32, 48 or 64", lclass);
+  if (nitems < 0 || nitems > capacity) return fail(TUCKER_EINVAL, "nitems %d outside 0..capacity", nitems);
+  if (nitems > 0 && items == nullptr) return fail(TUCKER_EINVAL, "items is null");
+  if (shift != TUCKER_SHIFT_ADAPTIVE && shift != TUCKER_SHIFT_NONE) return fail(TUCKER_EINVAL, "bad shift mode");
+  if (q < 0 || q > TUCKER_MAX_Q) return fail(TUCKER_EINVAL, "power count q = %d outside 0..%d", q, TUCKER_MAX_Q);
+  if (ws == nullptr || plan == nullptr) return fail(TUCKER_EINVAL, "null workspace or plan");
+  const int d = order;
+  if (d < 1 || d > TUCKER_MAX_ORDER) return fail(TUCKER_EINVAL, "order %d outside 1..%d", d, TUCKER_MAX_ORDER);
+  const size_t need_plan = batch_plan_bytes(capacity, d, q);
+  if (plan_bytes < need_plan) return fail(TUCKER_EWORKSPACE, "plan buffer %zu < %zu", plan_bytes, need_plan);
+  std::vector<PhaseRec> recs;
+  const size_t tb = batch_table_layout(capacity, d, q, &recs);
+  // per item plans and workspace carve
+  std::vector<Plan> pls((size_t)nitems);
+  std::vector<SolveWs> wss((size_t)nitems);
+  size_t off = align_up(tb);
+  for (int b = 0; b < nitems; ++b) {
+    if (items[b].shape.order != d) return fail(TUCKER_EINVAL, "item %d has order %d, batch order %d", b,
+                                               items[b].shape.order, d);
+    int rc = batch_item_plan(&items[b], p, q, &pls[b]);
+    if (rc) return rc;
+    for (int k = 0; k < d; ++k)
+      if (pls[b].l[k] > lclass)
+        return fail(TUCKER_EUNSUPPORTED, "item %d: l[%d] = %d exceeds lclass %d", b, k, pls[b].l[k], lclass);
+    const size_t need = align_up(solve_ws_layout(pls[b], TUCKER_FP32, nullptr, &wss[b]));
+    if (off + need > ws_bytes) return fail(TUCKER_EWORKSPACE, "batch workspace %zu too small (item %d)", ws_bytes, b);
+    solve_ws_layout(pls[b], TUCKER_FP32, (char*)ws + off, &wss[b]);
+    off += need;
+  }
+  // header and phase records
+  char* pb = (char*)plan;
+  BatchHeader* h = (BatchHeader*)pb;
+  h->magic = kBatchMagic;
+  h->capacity = capacity;
+  h->order = d;
+  h->q = q;
+  h->lclass = lclass;
+  h->nphases = (int32_t)recs.size();
+  h->table_bytes = tb;
+  h->ws = (char*)ws;
+  PhaseRec* pr = (PhaseRec*)(pb + align_up(sizeof(BatchHeader)));
+  char* img = pb + align_up(sizeof(BatchHeader)) + align_up(recs.size() * sizeof(PhaseRec));
+  for (size_t i = 0; i < recs.size(); ++i) pr[i] = recs[i];
+  // tables: walk the phase sequence with the same (mode, step, role) bookkeeping
+  size_t ip = 0;
+  auto fill_phase = [&](int k, int t, int role) {
+    const PhaseRec& r = recs[ip++];
+    int* hdr = (int*)(img + r.hdr_off);
+    char* desc = img + r.desc_off;
+    const size_t dsz = batch_desc_bytes((BatchKind)r.kind);
+    hdr[0] = nitems;
+    int64_t acc = 0;
+    for (int b = 0; b < nitems; ++b) {
+      hdr[1 + b] = (int)acc;
+      acc += batch_desc((BatchKind)r.kind, k, t, role, pls[b], wss[b], items[b], shift, d, desc + (size_t)b * dsz);
+    }
+    hdr[1 + nitems] = (int)acc;
+    return acc < (1ll << 31);
+  };
+  bool ok = fill_phase(0, 0, 0);  // init
+  for (int k = 0; k < d && ok; ++k) {
+    for (int i = 0; i < 4; ++i) ok = ok && fill_phase(k, 0, 0);  // fill, cr, cr, reduce
+    ok = ok && fill_phase(k, 0, 0);                                // gram
+    for (int role = 0; role < 3; ++role) ok = ok && fill_phase(k, 0, role);
+    ok = ok && fill_phase(k, 0, 0);                                // svd
+    for (int t = 1; t <= q; ++t) {
+      for (int i = 0; i < 5; ++i) ok = ok && fill_phase(k, t, 0);  // rc, rc, cr, cr, reduce
+      ok = ok && fill_phase(k, t, 0);                              // gram
+      for (int role = 0; role < 3; ++role) ok = ok && fill_phase(k, t, role);
+      ok = ok && fill_phase(k, t, 0);                              // svd
+    }
+    ok = ok && fill_phase(k, q, 0);  // rotate
+    ok = ok && fill_phase(k, q, 0);  // signfix
+    ok = ok && fill_phase(k, q, 1);  // core (rows)
+    ok = ok && fill_phase(k, q, 1);  // core (cols)
+  }
+  if (!ok) return fail(TUCKER_EUNSUPPORTED, "batch has more than 2^31 work items in a phase");
+  if (ip != recs.size()) return fail(TUCKER_EINVAL, "internal: phase bookkeeping mismatch");
+  return TUCKER_OK;
+}
+
+int tucker_batch_step(const void* plan, hipStream_t stream) {
+  if (plan == nullptr) return fail(TUCKER_EINVAL, "plan is null");
+  const char* pb = (const char*)plan;
+  const BatchHeader* h = (const BatchHeader*)pb;
+  if (h->magic != kBatchMagic) return fail(TUCKER_EINVAL, "not a batch plan");
+  const PhaseRec* pr = (const PhaseRec*)(pb + align_up(sizeof(BatchHeader)));
+  const char* img = pb + align_up(sizeof(BatchHeader)) + align_up((size_t)h->nphases * sizeof(PhaseRec));
+  hipError_t e = hipMemcpyAsync(h->ws, img, h->table_bytes, hipMemcpyHostToDevice, stream);
+  for (int i = 0; i < h->nphases && e == hipSuccess; ++i) {
+    const BatchKind kind = (BatchKind)pr[i].kind;
+    const int* hdr = (const int*)(h->ws + pr[i].hdr_off);
+    const void* desc = h->ws + pr[i].desc_off;
+    const bool orth = kind == BK_INIT || kind == BK_GRAM || kind == BK_PASS || kind == BK_SVD || kind == BK_ROTATE ||
+                      kind == BK_SIGNFIX;
+    e = orth ? launch_batch_orth(kind, h->lclass, hdr, desc, stream) : launch_batch_ttm(kind, h->lclass, hdr, desc, stream);
+  }
+  return dev_check(e, "batch step");
 }
 
 }  // extern "C"

@@ -108,4 +108,27 @@ __device__ __forceinline__ void gaussian4_f32(uint64_t seed, uint32_t mode, uint
   out[3] = r * sn;
 }
 
+// Persistent batched launch: the grid's workgroups loop over the work items
+// of all requests in the table (hdr[0] = requests, hdr[1 + b] = first item of
+// request b, hdr[1 + nreq] = total) and run the request's workgroup body F
+// with the request-local block index. A barrier separates consecutive items
+// so a body may leave some waves early and reuse LDS freely.
+template <typename D, void (*F)(const D&, int)>
+__global__ __launch_bounds__(256) void k_persist(const int* __restrict__ hdr, const D* __restrict__ desc) {
+  const int nreq = hdr[0];
+  const int total = hdr[1 + nreq];
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (hdr[1 + mid] <= w)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    F(desc[lo], w - hdr[1 + lo]);
+    __syncthreads();
+  }
+}
+
 }  // namespace tk

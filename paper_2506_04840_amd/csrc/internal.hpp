@@ -115,4 +115,122 @@ hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t
 hipError_t launch_info_init(tucker_info* info, const int32_t* l, int d, int32_t flags, hipStream_t st);
 hipError_t launch_set_double(double* dst, double v, hipStream_t st);
 
+// ---- batched persistent launches (many small solves at once) --------------
+// A batched phase is one launch of a fixed grid whose workgroups loop over
+// the phase's work items: hdr[0] = number of requests, hdr[1 + b] = first
+// work item of request b (prefix sums, hdr[1 + nreq] = total), desc[b] = the
+// arguments of request b. Work item w of request b runs the same workgroup
+// body as a single-request launch with block index w - hdr[1 + b]. All FP32
+// storage; lclass (16, 32, 48 or 64) fixes the tile templates for l <= lclass.
+struct BInit {
+  tucker_info* info;
+  double* alpha;  // d shifts, set to 0
+  int32_t l[TUCKER_MAX_ORDER];
+  int32_t d, flags;
+};
+struct BFill {
+  float* out;
+  uint64_t seed;
+  int64_t rows, ld;
+  uint32_t mode;
+  int32_t cols;
+};
+struct BCrLds {
+  const float* X;
+  const float* Bt;
+  float* part;
+  int64_t n, S, m, spp, nsteps;
+  int32_t l, nsplit, nrb;
+};
+struct BCrCols {
+  const float* X;
+  const float* Bt;
+  float* part;
+  int64_t P, n, nsteps;
+  int32_t l, nsplit, nrb;
+};
+struct BReduce {
+  const float* part;
+  const double* qsub;
+  const double* alpha;
+  double* Y;
+  int64_t nl;
+  int32_t nsplit;
+};
+struct BRcRows {
+  const float* X;
+  const float* W;
+  float* out;
+  int64_t n, S, wsi, wsj, tpp, ntiles, osp, osj;
+  int32_t lw, ksplit;
+};
+struct BRcCols {
+  const float* X;
+  const float* W;
+  float* out;
+  int64_t P, n, wsi, wsj, osp, osj;
+  int32_t lw;
+};
+struct BGram {
+  double* Y;
+  const double* Wm;
+  double* part;
+  int* status;
+  int64_t n;
+  int32_t l;
+};
+struct BPass {
+  const double* Qin;
+  const double* part_in;
+  double* Qout;
+  void* qt;
+  double* part_out;
+  double* Rg;
+  int* defic;
+  int* status;
+  uint64_t cseed;
+  double tau, shift_scale, eps3;
+  int64_t n;
+  int32_t l, nblk, role;
+  uint32_t ctag;
+};
+struct BSvd {
+  const double* Rg;
+  const int* status;
+  double* Wm;
+  double* sigma;
+  double* alpha;
+  tucker_info* info;
+  double tol, negl;
+  int32_t l, mode, step;
+};
+struct BRotate {
+  const double* Q3;
+  const double* Wm;
+  double* q64;
+  int64_t n;
+  int32_t l;
+};
+struct BSignfix {
+  const double* Q;
+  float* U;
+  float* Ut;
+  int64_t n;
+  int32_t l, r;
+};
+enum BatchKind {
+  BK_INIT = 0, BK_FILL, BK_CR_LDS, BK_CR_COLS, BK_REDUCE, BK_RC_ROWS, BK_RC_COLS,
+  BK_GRAM, BK_PASS, BK_SVD, BK_ROTATE, BK_SIGNFIX, BK_COUNT
+};
+size_t batch_desc_bytes(BatchKind kind);
+// Persistent grid of each kind (workgroups; a multiple of 8).
+int batch_grid(BatchKind kind);
+hipError_t launch_batch_ttm(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
+hipError_t launch_batch_orth(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
+// Work items (workgroups) of one request for the geometry-driven kinds.
+int64_t cr_lds_items(int64_t n, int nsplit);
+int64_t cr_cols_items(int64_t n, int nsplit);
+void cr_geometry(const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks);
+int64_t rc_rows_tiles(const View3& v, int* ksplit, int64_t* tpp);
+
 }  // namespace tk

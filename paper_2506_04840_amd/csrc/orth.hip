@@ -144,15 +144,15 @@ __device__ __forceinline__ void block_gram_mfma(const double (*Zs)[OR_LS], int l
 // in place, Y <- Y Wm (the basis change that turns the iterate of a power
 // step run on an unrotated basis into the iterate of the rotated one).
 template <int LP>
-__global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n, int l,
+__device__ __forceinline__ void gram_body(double* __restrict__ Y, int64_t n, int l,
                                               const double* __restrict__ Wm, double* __restrict__ part,
-                                              int* __restrict__ status) {
+                                              int* __restrict__ status, int bid) {
   constexpr int NB = LP / 16;
   __shared__ double Zs[OR_RB][OR_LS];
   __shared__ double Ws[kMaxL][OR_LS];
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid < 4) status[tid] = 0;  // flags of this factorisation
-  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
+  if (bid == 0 && tid < 4) status[tid] = 0;  // flags of this factorisation
+  const int64_t r0 = (int64_t)bid * OR_RB;
   for (int e = tid; e < OR_RB * LP; e += 256) {
     const int r = e / LP, j = e % LP;
     Zs[r][j] = (r0 + r < n && j < l) ? Y[(r0 + r) * l + j] : 0.0;
@@ -186,7 +186,14 @@ __global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n,
       if (r0 + r < n) Y[(r0 + r) * l + j] = Zs[r][j];
     }
   }
-  block_gram_mfma<LP>(Zs, l, part + (size_t)blockIdx.x * l * l);
+  block_gram_mfma<LP>(Zs, l, part + (size_t)bid * l * l);
+}
+
+template <int LP>
+__global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n, int l,
+                                              const double* __restrict__ Wm, double* __restrict__ part,
+                                              int* __restrict__ status) {
+  gram_body<LP>(Y, n, l, Wm, part, status, (int)blockIdx.x);
 }
 
 // One CholeskyQR pass over 64 rows per block (role 0: pass 1, scaled and
@@ -200,12 +207,12 @@ __global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n,
 // Passes 2 and 3 also write Q j-major in the storage precision to qt (when
 // not null).
 template <int LP>
-__global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int l, const double* __restrict__ part_in,
+__device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, const double* __restrict__ part_in,
                                               int nblk, int role, double tau, double shift_scale, double eps3,
                                               uint64_t cseed, uint32_t ctag, double* Qout, void* __restrict__ qt,
                                               int qt_f64,
                                               double* __restrict__ part_out, double* __restrict__ Rg,
-                                              int* __restrict__ defic_g, int* __restrict__ status) {
+                                              int* __restrict__ defic_g, int* __restrict__ status, int bid) {
   constexpr int NB = LP / 16, MW = LP / 4;
   constexpr int PF = NB <= 3 ? 8 : 4;  // Gram partials in flight per thread
   __shared__ double Zs[OR_RB][OR_LS];
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
   // pass 3: when Q2^T Q2 is already I to eps3, Q2 is the result (R3 = I);
   // every block sees the same sums and leaves together
   if (role == 2 && far_s == 0 && !anybad) {
-    if (blockIdx.x == 0 && tid == 0) status[2] = 1;
+    if (bid == 0 && tid == 0) status[2] = 1;
     return;
   }
   if (role == 0) {
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
     }
     __syncthreads();
   }
-  if (blockIdx.x == 0) {
+  if (bid == 0) {
     for (int e = tid; e < l * l; e += 256) {
       const int a = e / l, b = e % l;
       const double v = Rp[a][b & 3][b >> 2];
@@ -449,7 +456,7 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
   //    t holds columns t + 4 m in registers; column j's value comes from its
   //    owner lane by a quad broadcast and updates the rest right-looking.
   const int r = tid >> 2, t = tid & 3;
-  const int64_t r0 = (int64_t)blockIdx.x * OR_RB;
+  const int64_t r0 = (int64_t)bid * OR_RB;
   const int64_t row = r0 + r;
   double y[MW], z[MW];
 #pragma unroll
@@ -495,7 +502,17 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
       }
     }
   }
-  if (part_out != nullptr) block_gram_mfma<LP>(Zs, l, part_out + (size_t)blockIdx.x * l * l);
+  if (part_out != nullptr) block_gram_mfma<LP>(Zs, l, part_out + (size_t)bid * l * l);
+}
+
+template <int LP>
+__global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int l, const double* __restrict__ part_in,
+                                              int nblk, int role, double tau, double shift_scale, double eps3,
+                                              uint64_t cseed, uint32_t ctag, double* Qout, void* __restrict__ qt,
+                                              int qt_f64,
+                                              double* __restrict__ part_out, double* __restrict__ Rg,
+                                              int* __restrict__ defic_g, int* __restrict__ status) {
+  pass_body<LP>(Qin, n, l, part_in, nblk, role, tau, shift_scale, eps3, cseed, ctag, Qout, qt, qt_f64, part_out, Rg, defic_g, status, (int)blockIdx.x);
 }
 
 // C = A B for 64-wide LDS matrices (full product; the zero triangles add
@@ -559,11 +576,11 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
 // stops once a full cycle of rounds made no rotation.
 // RPT = rows per lane (8 lanes per column pair cover 8 * RPT >= l rows).
 template <int RPT>
-__global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg, int l,
+__device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, int l,
                                                    const int* __restrict__ status, double tol, double negl,
                                                    double* __restrict__ Wm, double* __restrict__ sigma,
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
-                                                   int mode, int step) {
+                                                   int mode, int step, int bid) {
   __shared__ double A[kMaxL][OR_LS];  // A[a][x] = column a of R^T = row a of R
   __shared__ double J[kMaxL][OR_LS];  // J[a][x] = column a of the rotation
   __shared__ double sv[kMaxL];
@@ -717,15 +734,24 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
   }
 }
 
+template <int RPT>
+__global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg, int l,
+                                                   const int* __restrict__ status, double tol, double negl,
+                                                   double* __restrict__ Wm, double* __restrict__ sigma,
+                                                   double* __restrict__ alpha, tucker_info* __restrict__ info,
+                                                   int mode, int step) {
+  small_svd_body<RPT>(Rg, l, status, tol, negl, Wm, sigma, alpha, info, mode, step, (int)blockIdx.x);
+}
+
 // Q = Q3 Wm, written in the storage precision (and optionally in FP64).
 template <typename T>
-__global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ Q3, int64_t n, int l,
+__device__ __forceinline__ void rotate_body(const double* __restrict__ Q3, int64_t n, int l,
                                                 const double* __restrict__ Wm, T* __restrict__ qout,
-                                                T* __restrict__ qt, double* __restrict__ q64) {
+                                                T* __restrict__ qt, double* __restrict__ q64, int bid) {
   __shared__ double Ws[kMaxL][OR_LS];
   for (int e = threadIdx.x; e < l * l; e += 256) Ws[e / l][e % l] = Wm[e];
   __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = (int64_t)bid * 256 + threadIdx.x;
   if (e >= n * l) return;
   const int64_t i = e / l;
   const int j = (int)(e - i * l);
@@ -735,6 +761,13 @@ __global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ Q3, i
   if (qout != nullptr) qout[e] = (T)s;
   if (qt != nullptr) qt[(int64_t)j * n + i] = (T)s;
   if (q64 != nullptr) q64[e] = s;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_rotate(const double* __restrict__ Q3, int64_t n, int l,
+                                                const double* __restrict__ Wm, T* __restrict__ qout,
+                                                T* __restrict__ qt, double* __restrict__ q64) {
+  rotate_body<T>(Q3, n, l, Wm, qout, qt, q64, (int)blockIdx.x);
 }
 
 template <int LP>
@@ -838,11 +871,11 @@ hipError_t launch_orth(int64_t n, int l, double* Y, tucker_precision prec, void*
 // Sign rule and truncation: one workgroup per kept column.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_signfix(const double* __restrict__ Q, int64_t n, int l, int r,
-                                                 T* __restrict__ U, T* __restrict__ Ut) {
+__device__ __forceinline__ void signfix_body(const double* __restrict__ Q, int64_t n, int l, int r,
+                                                 T* __restrict__ U, T* __restrict__ Ut, int bid) {
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
-  const int j = blockIdx.x;
+  const int j = bid;
   double best = -1.0;
   int64_t bidx = 0;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
@@ -872,6 +905,12 @@ __global__ __launch_bounds__(256) void k_signfix(const double* __restrict__ Q, i
     U[i * r + j] = v;
     if (Ut != nullptr) Ut[(int64_t)j * n + i] = v;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_signfix(const double* __restrict__ Q, int64_t n, int l, int r,
+                                                 T* __restrict__ U, T* __restrict__ Ut) {
+  signfix_body<T>(Q, n, l, r, U, Ut, (int)blockIdx.x);
 }
 
 hipError_t launch_signfix(tucker_precision prec, const double* Q, int64_t n, int l, int r, void* U, void* Ut,
@@ -910,6 +949,108 @@ __global__ void k_set_double(double* dst, double v) {
 hipError_t launch_set_double(double* dst, double v, hipStream_t st) {
   hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, dst, v);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent launches of the orthonormalisation kernels.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void b_init(const BInit& d, int bid) {
+  if (bid != 0) return;
+  if (d.info != nullptr) {
+    char* p = (char*)d.info;
+    for (size_t e = threadIdx.x; e < sizeof(tucker_info); e += blockDim.x) p[e] = 0;
+  }
+  if ((int)threadIdx.x < d.d) d.alpha[threadIdx.x] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0 && d.info != nullptr) {
+    for (int k = 0; k < TUCKER_MAX_ORDER; ++k) d.info->l[k] = k < d.d ? d.l[k] : 0;
+    d.info->flags = d.flags;
+  }
+}
+template <int LP>
+__device__ __forceinline__ void b_gram(const BGram& d, int bid) {
+  gram_body<LP>(d.Y, d.n, d.l, d.Wm, d.part, d.status, bid);
+}
+template <int LP>
+__device__ __forceinline__ void b_pass(const BPass& d, int bid) {
+  pass_body<LP>(d.Qin, d.n, d.l, d.part_in, d.nblk, d.role, d.tau, d.shift_scale, d.eps3, d.cseed, d.ctag, d.Qout,
+                d.qt, 0, d.part_out, d.Rg, d.defic, d.status, bid);
+}
+template <int RPT>
+__device__ __forceinline__ void b_svd(const BSvd& d, int bid) {
+  small_svd_body<RPT>(d.Rg, d.l, d.status, d.tol, d.negl, d.Wm, d.sigma, d.alpha, d.info, d.mode, d.step, bid);
+}
+__device__ __forceinline__ void b_rotate(const BRotate& d, int bid) {
+  rotate_body<float>(d.Q3, d.n, d.l, d.Wm, (float*)nullptr, (float*)nullptr, d.q64, bid);
+}
+__device__ __forceinline__ void b_signfix(const BSignfix& d, int bid) {
+  signfix_body<float>(d.Q, d.n, d.l, d.r, d.U, d.Ut, bid);
+}
+
+size_t batch_desc_bytes(BatchKind kind) {
+  switch (kind) {
+    case BK_INIT: return sizeof(BInit);
+    case BK_FILL: return sizeof(BFill);
+    case BK_CR_LDS: return sizeof(BCrLds);
+    case BK_CR_COLS: return sizeof(BCrCols);
+    case BK_REDUCE: return sizeof(BReduce);
+    case BK_RC_ROWS: return sizeof(BRcRows);
+    case BK_RC_COLS: return sizeof(BRcCols);
+    case BK_GRAM: return sizeof(BGram);
+    case BK_PASS: return sizeof(BPass);
+    case BK_SVD: return sizeof(BSvd);
+    case BK_ROTATE: return sizeof(BRotate);
+    case BK_SIGNFIX: return sizeof(BSignfix);
+    default: return 0;
+  }
+}
+
+int batch_grid(BatchKind kind) {
+  switch (kind) {
+    case BK_INIT: return 8;
+    case BK_SVD: return 256;        // one workgroup per request
+    case BK_GRAM:
+    case BK_PASS: return 512;       // 64-row blocks, 66 KB / 56 KB of LDS
+    default: return 1024;
+  }
+}
+
+template <int LP, int RPT>
+static hipError_t batch_orth_lp(BatchKind kind, const int* hdr, const void* desc, hipStream_t st) {
+  const dim3 grid(batch_grid(kind)), blk(256);
+  switch (kind) {
+    case BK_INIT:
+      hipLaunchKernelGGL((k_persist<BInit, b_init>), grid, blk, 0, st, hdr, (const BInit*)desc);
+      break;
+    case BK_GRAM:
+      hipLaunchKernelGGL((k_persist<BGram, b_gram<LP>>), grid, blk, 0, st, hdr, (const BGram*)desc);
+      break;
+    case BK_PASS:
+      hipLaunchKernelGGL((k_persist<BPass, b_pass<LP>>), grid, blk, 0, st, hdr, (const BPass*)desc);
+      break;
+    case BK_SVD:
+      hipLaunchKernelGGL((k_persist<BSvd, b_svd<RPT>>), grid, blk, 0, st, hdr, (const BSvd*)desc);
+      break;
+    case BK_ROTATE:
+      hipLaunchKernelGGL((k_persist<BRotate, b_rotate>), grid, blk, 0, st, hdr, (const BRotate*)desc);
+      break;
+    case BK_SIGNFIX:
+      hipLaunchKernelGGL((k_persist<BSignfix, b_signfix>), grid, blk, 0, st, hdr, (const BSignfix*)desc);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_orth(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st) {
+  switch (lclass) {
+    case 16: return batch_orth_lp<16, 2>(kind, hdr, desc, st);
+    case 32: return batch_orth_lp<32, 4>(kind, hdr, desc, st);
+    case 48: return batch_orth_lp<48, 6>(kind, hdr, desc, st);
+    case 64: return batch_orth_lp<64, 8>(kind, hdr, desc, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace tk

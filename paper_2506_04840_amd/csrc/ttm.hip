@@ -117,82 +117,6 @@ __device__ __forceinline__ void copy_frag(T* dst, const T* src) {
 }
 
 // ---------------------------------------------------------------------------
-// Column reduction, S > 1: part[split][i][j] = sum over the split's columns c
-// of X_(k)[i, c] Bt[j, c]; the reduction runs along s (contiguous). A
-// workgroup is 4 waves on 4 consecutive groups of 64 rows and one split of
-// the column steps (each step 4 * KC columns of one p), so the 4 waves read
-// the same Bt slice close together (L1 reuse). Each wave writes its rows'
-// partials directly.
-// ---------------------------------------------------------------------------
-template <int MK, int NJ, bool VEC>
-__global__ __launch_bounds__(256) void k_cr_rows(const typename Pol<MK>::T* __restrict__ X,
-                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
-                                                 int l, int64_t m, int64_t steps_per_p, int64_t nsteps, int nsplit,
-                                                 int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
-  using Po = Pol<MK>;
-  using T = typename Po::T;
-  // 32 contiguous bytes per lane and row: four lanes cover a 128-byte line
-  constexpr int KC = 32 / (int)sizeof(T), STEP = 4 * KC;
-  int split, rb;
-  if (!xcd_decode(blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int mm = lane & 15, g = lane >> 4;
-  const int64_t r0 = ((int64_t)rb * 4 + wave) * 64;
-  if (r0 >= n) return;
-  const int64_t t0 = nsteps * split / nsplit, t1 = nsteps * (split + 1) / nsplit;
-
-  typename Po::acc_t acc[4][NJ];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < NJ; ++b) acc[a][b] = typename Po::acc_t{0, 0, 0, 0};
-
-  auto fetch = [&](int64_t t, T (&fa)[4][KC], T (&fb)[NJ][KC]) {
-    const int64_t p = t / steps_per_p;
-    const int64_t c0 = (t - p * steps_per_p) * STEP + KC * g;
-    const int cnt = t < t1 ? (int)min<int64_t>(KC, S - c0) : 0;
-#pragma unroll
-    for (int tm = 0; tm < 4; ++tm) {
-      const int64_t row = r0 + 16 * tm + mm;
-      load_n<T, KC, VEC>(X + (p * n + row) * S + c0, row < n ? cnt : 0, fa[tm]);
-    }
-#pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      const int j = 16 * u + mm;
-      load_n<T, KC, VEC>(Bt + (int64_t)j * m + p * S + c0, j < l ? cnt : 0, fb[u]);
-    }
-  };
-  auto compute = [&](T (&fa)[4][KC], T (&fb)[NJ][KC]) {
-#pragma unroll
-    for (int e = 0; e < KC; e += Po::KL)
-#pragma unroll
-      for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-        for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][e], &fb[u][e], acc[tm][u]);
-  };
-  // two register stages: step t computes while t + 1 and t + 2 are in flight
-  T xa0[4][KC], xb0[NJ][KC], xa1[4][KC], xb1[NJ][KC];
-  fetch(t0, xa0, xb0);
-  fetch(t0 + 1, xa1, xb1);
-  for (int64_t t = t0; t < t1; t += 2) {
-    compute(xa0, xb0);
-    fetch(t + 2, xa0, xb0);  // zero-filled past the end of the split
-    compute(xa1, xb1);       // zeros when t + 1 is past the end
-    fetch(t + 3, xa1, xb1);
-  }
-#pragma unroll
-  for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-    for (int u = 0; u < NJ; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = r0 + 16 * tm + mfma_drow<MK>(lane, v);
-        const int col = 16 * u + mm;
-        if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[tm][u][v];
-      }
-}
-
-// ---------------------------------------------------------------------------
 // Column reduction, S > 1, staged through LDS: part[split][i][j] = sum over
 // the split's columns c of X_(k)[i, c] Bt[j, c]. A workgroup owns 64 rows
 // (16 per wave) and one split; a stage is KT consecutive columns of one p
@@ -222,10 +146,10 @@ struct LdsPol<MF_BF16> {
 };
 
 template <int MK, int NJ, bool VEC>
-__global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __restrict__ X,
+__device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restrict__ X,
                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
                                                 int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
-                                                int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
+                                                int nrblocks, typename Pol<MK>::part_t* __restrict__ part, int bid) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   using LT = typename LdsPol<MK>::LT;
@@ -238,7 +162,7 @@ __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __res
   __shared__ __align__(16) LT bs[2][16 * NJ][LS];
 
   int split, rb;
-  if (!xcd_decode(blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  if (!xcd_decode(bid, nsplit, nrblocks, &split, &rb)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mm = lane & 15, g = lane >> 4;
   const int64_t r0 = (int64_t)rb * 64;
@@ -353,22 +277,30 @@ __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __res
     }
 }
 
+template <int MK, int NJ, bool VEC>
+__global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __restrict__ X,
+                                                const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
+                                                int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
+                                                int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
+  cr_lds_body<MK, NJ, VEC>(X, Bt, n, S, l, m, spp, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Column reduction, S == 1: X is [P, n] with rows p contiguous along i (the
 // output row index). A batch covers 4 * KB consecutive p; k-slot g of the
 // MFMA takes p = pbase + KB g + q, q < KB, for both operands.
 // ---------------------------------------------------------------------------
 template <int MK, int NJ, bool VEC, bool BVEC>
-__global__ __launch_bounds__(256) void k_cr_cols(const typename Pol<MK>::T* __restrict__ X,
+__device__ __forceinline__ void cr_cols_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ Bt, int64_t P, int64_t n,
                                                  int l, int64_t nsteps, int nsplit, int nrblocks,
-                                                 typename Pol<MK>::part_t* __restrict__ part) {
+                                                 typename Pol<MK>::part_t* __restrict__ part, int bid) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
   constexpr int KB = (KL == 1) ? 4 : KL;
   int split, rb;
-  if (!xcd_decode(blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  if (!xcd_decode(bid, nsplit, nrblocks, &split, &rb)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mm = lane & 15, g = lane >> 4;
   const int64_t r0 = ((int64_t)rb * 4 + wave) * 64;
@@ -431,6 +363,14 @@ __global__ __launch_bounds__(256) void k_cr_cols(const typename Pol<MK>::T* __re
         const int col = 16 * u + mm;
         if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[tm][u][v];
       }
+}
+
+template <int MK, int NJ, bool VEC, bool BVEC>
+__global__ __launch_bounds__(256) void k_cr_cols(const typename Pol<MK>::T* __restrict__ X,
+                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t P, int64_t n,
+                                                 int l, int64_t nsteps, int nsplit, int nrblocks,
+                                                 typename Pol<MK>::part_t* __restrict__ part) {
+  cr_cols_body<MK, NJ, VEC, BVEC>(X, Bt, P, n, l, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
 }
 
 static void cr_geom(tucker_precision prec, const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
@@ -544,11 +484,11 @@ hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X
 // scheduling.
 // ---------------------------------------------------------------------------
 template <typename PT, typename QT>
-__global__ __launch_bounds__(256) void k_reduce_splits(const PT* __restrict__ part, int nsplit, int64_t nl,
+__device__ __forceinline__ void reduce_splits_body(const PT* __restrict__ part, int nsplit, int64_t nl,
                                                        const QT* __restrict__ qsub,
-                                                       const double* __restrict__ alpha, double* __restrict__ Y) {
+                                                       const double* __restrict__ alpha, double* __restrict__ Y, int bid) {
   const int sub = threadIdx.x & 7;
-  const int64_t e = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  const int64_t e = (int64_t)bid * 32 + (threadIdx.x >> 3);
   double s = 0.0;
   if (e < nl) {
     const int s0 = (int)((int64_t)nsplit * sub / 8), s1 = (int)((int64_t)nsplit * (sub + 1) / 8);
@@ -561,6 +501,13 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const PT* __restrict__ pa
   double y = ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
   if (qsub != nullptr) y -= (*alpha) * (double)qsub[e];
   Y[e] = y;
+}
+
+template <typename PT, typename QT>
+__global__ __launch_bounds__(256) void k_reduce_splits(const PT* __restrict__ part, int nsplit, int64_t nl,
+                                                       const QT* __restrict__ qsub,
+                                                       const double* __restrict__ alpha, double* __restrict__ Y) {
+  reduce_splits_body<PT, QT>(part, nsplit, nl, qsub, alpha, Y, (int)blockIdx.x);
 }
 
 hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, int nsplit, int64_t nl,
@@ -593,11 +540,11 @@ hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, in
 // wave, in batches of 4 * KB rows: k-slot g takes i = i0 + KB g + q, q < KB.
 // ---------------------------------------------------------------------------
 template <int MK, int NJ, bool VEC, bool WVEC>
-__global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __restrict__ X,
+__device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
                                                  int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
                                                  int64_t ntiles, int ksplit, typename Pol<MK>::T* __restrict__ out,
-                                                 int64_t osp, int64_t osj) {
+                                                 int64_t osp, int64_t osj, int bid) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
@@ -607,8 +554,8 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
   // ksplit: the 4 waves of a workgroup share one tile and split the n rows
   // (in whole batches), adding their partial tiles in wave order at the end
   // (few tiles); otherwise each wave owns a tile and all n rows.
-  const int64_t tile = ksplit ? (int64_t)blockIdx.x : (int64_t)blockIdx.x * 4 + wave;
-  if (ksplit ? tile >= ntiles : (int64_t)blockIdx.x * 4 >= ntiles) return;
+  const int64_t tile = ksplit ? (int64_t)bid : (int64_t)bid * 4 + wave;
+  if (ksplit ? tile >= ntiles : (int64_t)bid * 4 >= ntiles) return;
   const bool live = tile < ntiles;
   const int64_t p = live ? tile / tiles_per_p : 0;
   const int64_t s0 = (tile - p * tiles_per_p) * 64;
@@ -718,22 +665,31 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
   }
 }
 
+template <int MK, int NJ, bool VEC, bool WVEC>
+__global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __restrict__ X,
+                                                 const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
+                                                 int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
+                                                 int64_t ntiles, int ksplit, typename Pol<MK>::T* __restrict__ out,
+                                                 int64_t osp, int64_t osj) {
+  rc_rows_body<MK, NJ, VEC, WVEC>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, ksplit, out, osp, osj, (int)blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Row contraction, S == 1: X is [P, n] (rows p contiguous along i, the
 // reduction index); out(p, j) = out[p * osp + j * osj]; each wave owns 64
 // rows p, 4 waves per workgroup.
 // ---------------------------------------------------------------------------
 template <int MK, int NJ, bool VEC, bool WVEC>
-__global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __restrict__ X,
+__device__ __forceinline__ void rc_cols_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t P, int64_t n,
                                                  int lw, int64_t wsi, int64_t wsj, typename Pol<MK>::T* __restrict__ out,
-                                                 int64_t osp, int64_t osj) {
+                                                 int64_t osp, int64_t osj, int bid) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   constexpr int KC = Po::KC;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mm = lane & 15, g = lane >> 4;
-  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int64_t p0 = (int64_t)bid * 64;
   if (p0 >= P) return;
   // the 4 waves split the n reduction rows (in whole batches of 4 KC) and add
   // their partial tiles in wave order at the end
@@ -814,6 +770,14 @@ __global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __re
       }
 }
 
+template <int MK, int NJ, bool VEC, bool WVEC>
+__global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __restrict__ X,
+                                                 const typename Pol<MK>::T* __restrict__ W, int64_t P, int64_t n,
+                                                 int lw, int64_t wsi, int64_t wsj, typename Pol<MK>::T* __restrict__ out,
+                                                 int64_t osp, int64_t osj) {
+  rc_cols_body<MK, NJ, VEC, WVEC>(X, W, P, n, lw, wsi, wsj, out, osp, osj, (int)blockIdx.x);
+}
+
 template <int MK, int NJ>
 static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_t wsi, int64_t wsj, int lw, void* out,
                             bool out_jmajor, hipStream_t st) {
@@ -882,10 +846,10 @@ hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X
 // Gaussian fill.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_fill_gaussian(uint64_t seed, uint32_t mode, int64_t row0, int64_t rows,
-                                                       int cols, int64_t ld, int jmajor, T* __restrict__ out) {
+__device__ __forceinline__ void fill_gaussian_body(uint64_t seed, uint32_t mode, int64_t row0, int64_t rows,
+                                                       int cols, int64_t ld, int jmajor, T* __restrict__ out, int bid) {
   const int groups = (cols + 3) / 4;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = (int64_t)bid * 256 + threadIdx.x;
   if (e >= rows * groups) return;
   const int g = (int)(e / rows);
   const int64_t c = e - (int64_t)g * rows;
@@ -900,6 +864,12 @@ __global__ __launch_bounds__(256) void k_fill_gaussian(uint64_t seed, uint32_t m
     const int j = 4 * g + q;
     if (j < cols) out[jmajor ? (int64_t)j * ld + c : c * cols + j] = v[q];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_gaussian(uint64_t seed, uint32_t mode, int64_t row0, int64_t rows,
+                                                       int cols, int64_t ld, int jmajor, T* __restrict__ out) {
+  fill_gaussian_body<T>(seed, mode, row0, rows, cols, ld, jmajor, out, (int)blockIdx.x);
 }
 
 hipError_t launch_fill_gaussian(tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0, int64_t rows,
@@ -978,6 +948,84 @@ hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t
   else
     hipLaunchKernelGGL((k_to_f64<float>), dim3(blocks), dim3(256), 0, st, (const float*)src, count, dst);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched persistent launches of the product kernels (FP32 storage, scalar
+// loads so any shape and alignment fits one instantiation).
+// ---------------------------------------------------------------------------
+void cr_geometry(const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
+  cr_geom(TUCKER_FP32, v, nsteps, spp, nrblocks);
+}
+int64_t cr_lds_items(int64_t n, int nsplit) { return (int64_t)((nsplit + 7) / 8) * 8 * ((n + 63) / 64); }
+int64_t cr_cols_items(int64_t n, int nsplit) { return (int64_t)((nsplit + 7) / 8) * 8 * ((n + 255) / 256); }
+int64_t rc_rows_tiles(const View3& v, int* ksplit, int64_t* tpp) {
+  *tpp = (v.S + 63) / 64;
+  const int64_t ntiles = v.P * *tpp;
+  *ksplit = ntiles < 2048 ? 1 : 0;
+  return ntiles;
+}
+
+__device__ __forceinline__ void b_fill(const BFill& d, int bid) {
+  fill_gaussian_body<float>(d.seed, d.mode, 0, d.rows, d.cols, d.ld, 1, d.out, bid);
+}
+template <int NJ>
+__device__ __forceinline__ void b_cr_lds(const BCrLds& d, int bid) {
+  cr_lds_body<MF_F32, NJ, false>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.nrb, d.part, bid);
+}
+template <int NJ>
+__device__ __forceinline__ void b_cr_cols(const BCrCols& d, int bid) {
+  cr_cols_body<MF_F32, NJ, false, false>(d.X, d.Bt, d.P, d.n, d.l, d.nsteps, d.nsplit, d.nrb, d.part, bid);
+}
+__device__ __forceinline__ void b_reduce(const BReduce& d, int bid) {
+  reduce_splits_body<float, double>(d.part, d.nsplit, d.nl, d.qsub, d.alpha, d.Y, bid);
+}
+template <int NJ>
+__device__ __forceinline__ void b_rc_rows(const BRcRows& d, int bid) {
+  rc_rows_body<MF_F32, NJ, false, false>(d.X, d.W, d.n, d.S, d.lw, d.wsi, d.wsj, d.tpp, d.ntiles, d.ksplit, d.out,
+                                         d.osp, d.osj, bid);
+}
+template <int NJ>
+__device__ __forceinline__ void b_rc_cols(const BRcCols& d, int bid) {
+  rc_cols_body<MF_F32, NJ, false, false>(d.X, d.W, d.P, d.n, d.lw, d.wsi, d.wsj, d.out, d.osp, d.osj, bid);
+}
+
+template <int NJ>
+static hipError_t batch_ttm_nj(BatchKind kind, const int* hdr, const void* desc, hipStream_t st) {
+  const dim3 grid(batch_grid(kind)), blk(256);
+  switch (kind) {
+    case BK_FILL:
+      hipLaunchKernelGGL((k_persist<BFill, b_fill>), grid, blk, 0, st, hdr, (const BFill*)desc);
+      break;
+    case BK_CR_LDS:
+      hipLaunchKernelGGL((k_persist<BCrLds, b_cr_lds<NJ>>), grid, blk, 0, st, hdr, (const BCrLds*)desc);
+      break;
+    case BK_CR_COLS:
+      hipLaunchKernelGGL((k_persist<BCrCols, b_cr_cols<NJ>>), grid, blk, 0, st, hdr, (const BCrCols*)desc);
+      break;
+    case BK_REDUCE:
+      hipLaunchKernelGGL((k_persist<BReduce, b_reduce>), grid, blk, 0, st, hdr, (const BReduce*)desc);
+      break;
+    case BK_RC_ROWS:
+      hipLaunchKernelGGL((k_persist<BRcRows, b_rc_rows<NJ>>), grid, blk, 0, st, hdr, (const BRcRows*)desc);
+      break;
+    case BK_RC_COLS:
+      hipLaunchKernelGGL((k_persist<BRcCols, b_rc_cols<NJ>>), grid, blk, 0, st, hdr, (const BRcCols*)desc);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_ttm(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st) {
+  switch (lclass) {
+    case 16: return batch_ttm_nj<1>(kind, hdr, desc, st);
+    case 32: return batch_ttm_nj<2>(kind, hdr, desc, st);
+    case 48: return batch_ttm_nj<3>(kind, hdr, desc, st);
+    case 64: return batch_ttm_nj<4>(kind, hdr, desc, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace tk

@@ -88,3 +88,49 @@ def test_python_binding_rejects_host_tensors():
     from paper_2506_04840_amd import _lib
     with pytest.raises(ValueError):
         _lib._dev(torch.zeros(3), "X")
+
+
+def _fake_item(dims, ranks, seed=1):
+    from paper_2506_04840_amd import _lib
+    it = _lib.BatchItem()
+    it.shape = _lib._shape(dims)
+    for k, r in enumerate(ranks):
+        it.ranks[k] = r
+    it.seed = seed
+    it.A, it.G = 4096, 8192
+    for k in range(len(dims)):
+        it.U[k] = 12288 + 4096 * k
+    it.info = None
+    return it
+
+
+def test_batch_plan_on_the_host():
+    """tucker_batch_plan is host-only: it validates, carves the workspace and
+    writes the plan without touching device memory (fake addresses here)."""
+    from paper_2506_04840_amd import _lib
+    L = _lib.lib
+    cap, d, q, p = 8, 3, 1, 8
+    nplan = L.tucker_batch_plan_bytes(cap, d, q)
+    ntab = L.tucker_batch_table_bytes(cap, d, q)
+    assert nplan > ntab > 0
+    assert L.tucker_batch_plan_bytes(0, d, q) == 0 and L.tucker_batch_plan_bytes(cap, 9, q) == 0
+    items = (_lib.BatchItem * cap)(*[_fake_item((40 + i, 50, 33 + 2 * i), (10 - i, 6, 4 + i)) for i in range(3)])
+    need = ntab + sum(L.tucker_batch_item_bytes(ctypes.byref(items[i]), p, q) for i in range(3))
+    plan = ctypes.create_string_buffer(nplan)
+    ws = ctypes.c_void_p(1 << 40)
+    ok = L.tucker_batch_plan(cap, d, 48, 3, items, p, q, 0, ws, need, plan, nplan)
+    assert ok == 0, L.tucker_status_string(ok)
+    # an empty batch plans too (the launch sequence is the same)
+    assert L.tucker_batch_plan(cap, d, 48, 0, items, p, q, 0, ws, need, plan, nplan) == 0
+    # workspace one byte short, plan buffer short, lclass too narrow, bad lclass, order mismatch
+    assert L.tucker_batch_plan(cap, d, 48, 3, items, p, q, 0, ws, need - 1, plan, nplan) == -2
+    assert L.tucker_batch_plan(cap, d, 48, 3, items, p, q, 0, ws, need, plan, nplan - 1) == -2
+    assert L.tucker_batch_plan(cap, d, 16, 3, items, p, q, 0, ws, need, plan, nplan) == -4
+    assert L.tucker_batch_plan(cap, d, 40, 3, items, p, q, 0, ws, need, plan, nplan) == -1
+    n4 = L.tucker_batch_plan_bytes(cap, 4, q)
+    plan4 = ctypes.create_string_buffer(n4)
+    assert L.tucker_batch_plan(cap, 4, 48, 3, items, p, q, 0, ws, 1 << 30, plan4, n4) == -1
+    assert L.tucker_batch_plan(cap, d, 48, cap + 1, items, p, q, 0, ws, need, plan, nplan) == -1
+    # infeasible rank inside a batch is rejected like in tucker_rsthosvd
+    bad = (_lib.BatchItem * 1)(_fake_item((40, 40, 40), (4, 4, 32)))
+    assert L.tucker_batch_plan(cap, d, 48, 1, bad, p, q, 0, ws, 1 << 30, plan, nplan) == -1

@@ -245,3 +245,31 @@ def request_stream(count: int, rate_per_s: float, seed: int = 0, n_lo: int = 32,
 def request_tensor(req: Request, eta: float = 1e-3) -> np.ndarray:
     a, _, _ = random_tucker(req.dims, req.ranks, eta, req.seed)
     return a
+
+
+def poisson_arrivals(count: int, rate_per_s: float, seed: int = 0) -> List[float]:
+    """Arrival times (s) of a Poisson stream; rate 0 or inf: all at t = 0."""
+    if not rate_per_s or not math.isfinite(rate_per_s):
+        return [0.0] * count
+    gen = rng(seed + 7)
+    return [float(x) for x in np.cumsum(gen.exponential(1.0 / rate_per_s, size=count))]
+
+
+def request_tensor_device(req: Request, device, eta: float = 1e-3):
+    """The request's tensor (Gaussian core x Haar factors + eta noise), FP32 on
+    `device`: core and factors from the request's host stream (as
+    request_tensor), the expansion and the noise on the device."""
+    import torch
+
+    gen = rng(req.seed)
+    core = gen.standard_normal(req.ranks)
+    factors = [haar(n, r, gen) for n, r in zip(req.dims, req.ranks)]
+    t = torch.from_numpy(core).to(device)
+    for k, u in enumerate(factors):
+        t = torch.movedim(torch.tensordot(torch.from_numpy(u).to(device), t, dims=([1], [k])), 0, k)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(req.seed) + 104729)
+    e = torch.randn(req.dims, generator=g, device=device, dtype=torch.float64)
+    out = t + (eta * torch.linalg.vector_norm(t) / torch.linalg.vector_norm(e)) * e
+    return out.float().contiguous()
+
