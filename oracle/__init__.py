@@ -13,6 +13,6 @@ Contents:
              unshifted model, the deterministic HOSVD) step by step in FP64.
 
 Parity status: every function is pinned by tests under tests/ against values
-the paper prints, closed forms, invariants or brute force (see the pin list in
-DESIGN.md). No function here is "parity unpinned".
+the paper prints, closed forms, invariants or brute force (test_oracle_*.py
+name the pin of each function). No function here is "parity unpinned".
 """

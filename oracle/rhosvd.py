@@ -20,7 +20,7 @@ Per mode k, on X = A (variant t) or X = the partially contracted core
       else alpha_t = alpha_{t-1}
   U_k = Q(:, 1:r_k) ;  G <- G x_k U_k^T
 
-Readings where the paper is silent or loose (each also listed in the design doc):
+Readings where the paper is silent or loose:
   * Algorithm 3 writes the shift in the power step without its subscript; it
     is alpha_{t-1}, as in Algorithm 2.
   * The else-branch of the shift update is not written: alpha_t = alpha_{t-1}.

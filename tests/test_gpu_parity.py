@@ -1,6 +1,9 @@
 """GPU parity: each C-ABI call against the FP64 oracle on the same seeded inputs.
 
-Tolerances (written here, derived in the design doc): FP64 1e-10 and FP32 1e-5,
+Tolerances: FP64 1e-10 (about 1e6 unit roundoffs: summation error over
+contractions of up to 1e6 terms, times the conditioning of the
+orthonormalisation) and FP32 1e-5 (about 170 FP32 unit roundoffs; FP32
+sums are blocked, so their error grows with the log of the length),
 relative to the natural scale of each quantity (Cauchy-Schwarz scale for a
 product entry, ||A|| for a reconstruction, Sigma_1 for a shift); subspace
 sine distance <= 1e-4 where the oracle's spectral gap is at least 1e-2

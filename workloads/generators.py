@@ -10,7 +10,7 @@ tensor is reproducible bit for bit on any host. The large-tensor builders in
 ``build_on_device`` use torch on the GPU only to assemble inputs quickly; they
 are not part of the method either.
 
-Constructions (paper section 5.1 and the workload list in the design doc):
+Constructions (paper section 5.1):
 
 * ``haar``: an n x r matrix with orthonormal columns, the Q factor of a
   Gaussian matrix with the signs of diag(R) folded in (Mezzadri 2007), which
@@ -117,8 +117,9 @@ def tensor_c(kind: str, n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
 
 
 # --------------------------------------------------------------------------
-# Named workloads. Sizes and structure follow the five configurations listed
-# in the design doc (workload recipe). Seeds: data seed 0, sketch seed 1.
+# Named workloads: the paper's section 5 test tensors at the sizes measured
+# here (Hilbert, Tucker-plus-noise, tensor C, an order-4 Tucker tensor).
+# Seeds: data seed 0, sketch seed 1.
 # --------------------------------------------------------------------------
 
 @dataclasses.dataclass(frozen=True)
