@@ -7,7 +7,17 @@ contraction) of a tensor already resident in HBM.
 
 Default workload: the 400^3 smooth-function tensor a_ijk = 1/(i+j+k-2) in
 FP32, ST-HOSVD, ranks (30,30,30), p = 10, q = 3, adaptive shift.
-Other workloads: --workload tucker3_60_fp64 | tucker4_120 | tucker3_1000.
+Other workloads: --workload tucker3_60_fp64 | tucker4_120 | tucker3_1000 |
+serving_stream_4096.
+
+serving_stream_4096: 4096 order-3 FP32 requests (mode sizes U{32..256},
+Tucker ranks U{4..32}, Gaussian core x Haar factors + 1e-3 noise, p = 8,
+q = 1, adaptive shift). A step is one burst of all 4096 requests through the
+continuous-batching server (persistent batched kernels, graph replay); value
+is approximations/s over the timed bursts. Beside it: the same burst one
+request at a time (tucker_rsthosvd per request), the relative error of every
+request on both paths, and p50/p99 latency at Poisson arrival rates of 0.5
+and 0.9 x the measured batched capacity.
 
 The dominant kernel's roofline figure comes from HIP events the library
 records around each launch of that kernel class (tucker_timing_*) during a
@@ -37,6 +47,9 @@ CONFIGS = {
     "tucker4_120": dict(precision="bf16", variant="st", ranks=(20, 20, 20, 20), p=10, q=2),
     "tucker3_1000": dict(precision="fp32", variant="st", ranks=(50, 50, 50), p=10, q=3),
 }
+SERVING = "serving_stream_4096"
+SERVING_CFG = dict(count=4096, n_lo=32, n_hi=256, r_lo=4, r_hi=32, eta=1e-3, p=8, q=1, capacity=256, lclass=48,
+                   ws_bytes=4 << 30, data_seed=0)
 
 
 def parse():
@@ -44,7 +57,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="hilbert3_400", choices=sorted(CONFIGS))
+    ap.add_argument("--workload", default="hilbert3_400", choices=sorted(CONFIGS) + [SERVING])
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "bf16"])
     ap.add_argument("--q", type=int, default=None)
     ap.add_argument("--shift", default="adaptive", choices=["adaptive", "none"])
@@ -112,6 +125,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == SERVING:
+        serving_main(args)
+        return
 
     import numpy as np
     import torch
@@ -210,6 +227,182 @@ def main():
         "config": {"workload": args.workload, "dims": list(A.shape), "ranks": list(cfg["ranks"]), "p": cfg["p"],
                    "q": q, "shift": args.shift, "variant": cfg["variant"], "precision": prec,
                    "rel_error": re},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def _roof_from_timing(tk, prec="fp32"):
+    sec = tk["ms"] * 1e-3
+    t_mem = tk["bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_flop = tk["flops"] / (PEAK_TFLOPS[prec] * 1e12)
+    if t_flop > t_mem:
+        achieved = tk["flops"] / sec / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_TFLOPS[prec], 4)}
+    else:
+        achieved = tk["bytes"] / sec / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roof.update({"traffic": None, "launches": tk["launches"],
+                 "avg_launch_us": round(1e3 * tk["ms"] / max(tk["launches"], 1), 3),
+                 "alg_bytes_per_launch": tk["bytes"] / max(tk["launches"], 1),
+                 "alg_flops_per_launch": tk["flops"] / max(tk["launches"], 1), "total_ms": tk["ms"]})
+    return roof
+
+
+def serving_main(args):
+    """Continuous-batching burst throughput, one-at-a-time reference, RE parity and Poisson latency."""
+    import numpy as np
+    import torch
+
+    from paper_2506_04840_amd import _lib as T
+    from paper_2506_04840_amd import serve
+    from workloads import generators as gen
+
+    c = SERVING_CFG
+    dev = torch.device("cuda:0")
+    reqs = gen.request_stream(c["count"], 0.0, seed=c["data_seed"], n_lo=c["n_lo"], n_hi=c["n_hi"], r_lo=c["r_lo"],
+                              r_hi=c["r_hi"])
+    tensors = []
+    for i, r in enumerate(reqs):
+        tensors.append(gen.request_tensor_device(r, dev, c["eta"]))
+        if (i + 1) % 1024 == 0:
+            _log("built %d request tensors" % (i + 1))
+    torch.cuda.synchronize()
+
+    def jobs(arrivals=None):
+        out = []
+        for i, r in enumerate(reqs):
+            out.append(serve.Job(r.rid, tensors[i], r.ranks, r.seed, 0.0 if arrivals is None else arrivals[i])
+                       .prepare(c["p"], c["q"]))
+        return out
+
+    srv = serve.BatchServer(capacity=c["capacity"], q=c["q"], p=c["p"], lclass=c["lclass"], ws_bytes=c["ws_bytes"],
+                            device=dev)
+    jb = jobs()
+    for _ in range(args.warmup):
+        srv.run(jb[:2 * c["capacity"]])
+    torch.cuda.synchronize()
+    _log("warm")
+
+    # timed region: K bursts of every request through the batching server
+    srv.batch_sizes = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        srv.run(jb, t0=time.perf_counter())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cap = args.steps * len(jb) / elapsed
+    mean_batch = float(np.mean(srv.batch_sizes))
+    _log("batched burst: %.1f approximations/s" % cap)
+
+    # one request at a time, same requests, same burst
+    single = serve.SingleServer(p=c["p"], q=c["q"], ws_bytes=64 << 20, device=dev)
+    js = jobs()
+    single.run(js[:64])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    single.run(js, t0=t1)
+    torch.cuda.synchronize()
+    single_rate = len(js) / (time.perf_counter() - t1)
+    _log("one-at-a-time burst: %.1f approximations/s" % single_rate)
+
+    # relative error of every request on both paths (FP64 reconstruction, outside the timed regions)
+    re_b, re_s = [], []
+    for a, x, y in zip(tensors, jb, js):
+        ad = a.double()
+        na = torch.linalg.vector_norm(ad)
+        re_b.append(float(torch.linalg.vector_norm(ad - reconstruct_torch(x.G.double(), [u.double() for u in x.U])) / na))
+        re_s.append(float(torch.linalg.vector_norm(ad - reconstruct_torch(y.G.double(), [u.double() for u in y.U])) / na))
+    re_b, re_s = np.array(re_b), np.array(re_s)
+    _log("relative errors done")
+
+    # Poisson arrivals at 0.5 and 0.9 x the measured batched capacity
+    poisson = []
+    for frac in (0.5, 0.9):
+        rate = frac * cap
+        arr = gen.poisson_arrivals(len(reqs), rate, seed=c["data_seed"])
+        jp = jobs(arr)
+        srv.batch_sizes = []
+        torch.cuda.synchronize()
+        out = srv.run(jp, t0=time.perf_counter())
+        st = serve.latency_stats(out)
+        st.update({"rate_per_s": round(rate, 1), "load": frac, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
+                   "batches": len(srv.batch_sizes)})
+        poisson.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
+        _log("poisson %.1f/s: p50 %.2f ms p99 %.2f ms" % (rate, st["p50_ms"], st["p99_ms"]))
+
+    # dominant product kernel of the batched path: HIP events around each batched phase (direct steps)
+    roof = None
+    if not args.no_kernel_timing:
+        timed = {}
+        srv_t = serve.BatchServer(capacity=c["capacity"], q=c["q"], p=c["p"], lclass=c["lclass"],
+                                  ws_bytes=c["ws_bytes"], device=dev, use_graphs=False)
+        for kern in ("colreduce", "rowcontract"):
+            T.timing_enable(kern, capacity=65536)
+            torch.cuda.synchronize()
+            srv_t.run(jb, t0=time.perf_counter())
+            torch.cuda.synchronize()
+            timed[kern] = T.timing_read(kern)
+            T.timing_disable()
+        kern = max(timed, key=lambda k: timed[k]["ms"])
+        roof = _roof_from_timing(timed[kern])
+        roof["kernel"] = "batched " + kern
+        roof["burst_share"] = round(timed[kern]["ms"] * 1e-3 / (len(jb) / cap), 4)
+        del srv_t
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import rhosvd as orc
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        done, tsum = 0, 0.0
+        for i, r in enumerate(reqs):
+            a64 = tensors[i].double().cpu().numpy()
+            t2 = time.perf_counter()
+            orc.randomized_hosvd(a64, r.ranks, c["p"], c["q"], shift="adaptive", variant="st", seed=r.seed)
+            tsum += time.perf_counter() - t2
+            done += 1
+            if tsum > 15.0:
+                break
+        cpu = {"value": round(done / tsum, 3), "unit": "approximations/s", "cores": int(threads), "kind": "oracle",
+               "sample": "the first %d requests of the stream, one after another (FP64 oracle)" % done}
+
+    line = {
+        "metric": METRIC,
+        "value": round(cap, 2),
+        "unit": "approximations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": SERVING, "requests": c["count"], "dims": "U{%d..%d} per mode" % (c["n_lo"], c["n_hi"]),
+                   "ranks": "U{%d..%d}" % (c["r_lo"], c["r_hi"]), "noise": c["eta"], "p": c["p"], "q": c["q"],
+                   "shift": "adaptive", "variant": "st", "precision": "fp32", "capacity": c["capacity"],
+                   "lclass": c["lclass"], "ws_bytes_per_slot": c["ws_bytes"]},
+        "serving": {
+            "batched_approx_per_s": round(cap, 2),
+            "single_approx_per_s": round(single_rate, 2),
+            "speedup": round(cap / single_rate, 3),
+            "burst_mean_batch": round(mean_batch, 2),
+            "rel_error_batched": {"mean": float(re_b.mean()), "max": float(re_b.max())},
+            "rel_error_single": {"mean": float(re_s.mean()), "max": float(re_s.max())},
+            "rel_error_max_abs_diff": float(np.max(np.abs(re_b - re_s))),
+            "poisson": poisson,
+        },
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -255,13 +255,17 @@ size_t tucker_batch_item_bytes(const tucker_batch_item* item, int32_t p, int32_t
 /* Host-only: validates the items, carves ws and writes the plan (nitems may
  * be 0). EINVAL for a bad item (same checks as tucker_rsthosvd) or an item
  * whose order is not `order`, EUNSUPPORTED
- * when some l_k > lclass, EWORKSPACE when ws or the plan is too small. */
+ * when some l_k > lclass, EWORKSPACE when ws or the plan is too small. On
+ * any error the plan is left invalid (tucker_batch_step rejects it). */
 int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t nitems, const tucker_batch_item* items,
                       int32_t p, int32_t q, tucker_shift shift, void* ws, size_t ws_bytes, void* plan,
                       size_t plan_bytes);
 /* Enqueues the batch on `stream`: one upload of the plan's tables into the
  * workspace, then the persistent launches. Results land in each item's G, U
- * and info when the stream reaches this point. */
+ * and info when the stream reaches this point. With launch timing enabled,
+ * the product phases are recorded under TUCKER_KC_COLREDUCE / ROWCONTRACT /
+ * REDUCE / FILL with the batch's summed algorithmic bytes and flops (do not
+ * capture a step into a graph while timing is enabled). */
 int tucker_batch_step(const void* plan, hipStream_t stream);
 
 #ifdef __cplusplus

@@ -378,6 +378,9 @@ class BatchSolver:
     @staticmethod
     def item(A: torch.Tensor, G: torch.Tensor, U: Sequence[torch.Tensor], ranks, seed: int,
              info: Optional[torch.Tensor] = None) -> BatchItem:
+        for t, name in [(A, "A"), (G, "G")] + [(u, "U") for u in U]:
+            if t.dtype != torch.float32:
+                raise ValueError("batched solves are FP32: %s is %s" % (name, t.dtype))
         it = BatchItem()
         it.shape = _shape(A.shape)
         for k, r in enumerate(ranks):

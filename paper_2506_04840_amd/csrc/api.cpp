@@ -378,6 +378,7 @@ struct PhaseRec {
   int32_t kind;
   int32_t pad;
   size_t hdr_off, desc_off;  // within the table image
+  double bytes, flops;       // algorithmic traffic and work of the phase (launch timing)
 };
 
 // The fixed phase sequence for (order, q).
@@ -404,6 +405,7 @@ size_t batch_table_layout(int cap, int d, int q, std::vector<PhaseRec>* recs) {
     PhaseRec r;
     r.kind = (int32_t)k;
     r.pad = 0;
+    r.bytes = r.flops = 0.0;
     r.hdr_off = off;
     off += align_up((size_t)(cap + 2) * sizeof(int));
     r.desc_off = off;
@@ -426,6 +428,19 @@ int batch_item_plan(const tucker_batch_item* it, int32_t p, int32_t q, Plan* pl)
   for (int k = 0; k < pl->d; ++k)
     if (it->U[k] == nullptr) return fail(TUCKER_EINVAL, "item with null U[%d]", k);
   return TUCKER_OK;
+}
+
+// Algorithmic HBM bytes and flops of one item's mode product in a phase (the
+// unfolding read once, the small operand read once; FP32 storage).
+void batch_phase_work(BatchKind kind, int k, int role, const Plan& pl, double* bytes, double* flops) {
+  const View3 v = pl.v[k];
+  const double N = (double)v.P * v.n * v.S, m = (double)pl.m[k];
+  const bool cr = (kind == BK_CR_LDS && v.S > 1) || (kind == BK_CR_COLS && v.S == 1);
+  const bool rc = (kind == BK_RC_ROWS && v.S > 1) || (kind == BK_RC_COLS && v.S == 1);
+  if (!cr && !rc) return;
+  const double w = rc && role == 1 ? (double)pl.r[k] : (double)pl.l[k];
+  *bytes += 4.0 * (N + m * w);
+  *flops += 2.0 * N * w;
 }
 
 // Fills one phase's descriptor for item b (returns its work items).
@@ -812,7 +827,7 @@ int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t n
   // header and phase records
   char* pb = (char*)plan;
   BatchHeader* h = (BatchHeader*)pb;
-  h->magic = kBatchMagic;
+  h->magic = 0;  // valid only once every table is written
   h->capacity = capacity;
   h->order = d;
   h->q = q;
@@ -822,11 +837,10 @@ int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t n
   h->ws = (char*)ws;
   PhaseRec* pr = (PhaseRec*)(pb + align_up(sizeof(BatchHeader)));
   char* img = pb + align_up(sizeof(BatchHeader)) + align_up(recs.size() * sizeof(PhaseRec));
-  for (size_t i = 0; i < recs.size(); ++i) pr[i] = recs[i];
   // tables: walk the phase sequence with the same (mode, step, role) bookkeeping
   size_t ip = 0;
   auto fill_phase = [&](int k, int t, int role) {
-    const PhaseRec& r = recs[ip++];
+    PhaseRec& r = recs[ip++];
     int* hdr = (int*)(img + r.hdr_off);
     char* desc = img + r.desc_off;
     const size_t dsz = batch_desc_bytes((BatchKind)r.kind);
@@ -835,6 +849,7 @@ int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t n
     for (int b = 0; b < nitems; ++b) {
       hdr[1 + b] = (int)acc;
       acc += batch_desc((BatchKind)r.kind, k, t, role, pls[b], wss[b], items[b], shift, d, desc + (size_t)b * dsz);
+      batch_phase_work((BatchKind)r.kind, k, role, pls[b], &r.bytes, &r.flops);
     }
     hdr[1 + nitems] = (int)acc;
     return acc < (1ll << 31);
@@ -858,6 +873,8 @@ int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t n
   }
   if (!ok) return fail(TUCKER_EUNSUPPORTED, "batch has more than 2^31 work items in a phase");
   if (ip != recs.size()) return fail(TUCKER_EINVAL, "internal: phase bookkeeping mismatch");
+  for (size_t i = 0; i < recs.size(); ++i) pr[i] = recs[i];
+  h->magic = kBatchMagic;
   return TUCKER_OK;
 }
 
@@ -875,7 +892,15 @@ int tucker_batch_step(const void* plan, hipStream_t stream) {
     const void* desc = h->ws + pr[i].desc_off;
     const bool orth = kind == BK_INIT || kind == BK_GRAM || kind == BK_PASS || kind == BK_SVD || kind == BK_ROTATE ||
                       kind == BK_SIGNFIX;
-    e = orth ? launch_batch_orth(kind, h->lclass, hdr, desc, stream) : launch_batch_ttm(kind, h->lclass, hdr, desc, stream);
+    if (orth) {
+      e = launch_batch_orth(kind, h->lclass, hdr, desc, stream);
+      continue;
+    }
+    const int cls = (kind == BK_CR_LDS || kind == BK_CR_COLS) ? KC_COLREDUCE
+                    : (kind == BK_RC_ROWS || kind == BK_RC_COLS) ? KC_ROWCONTRACT
+                    : kind == BK_REDUCE ? KC_REDUCE : KC_FILL;
+    TimingScope ts(cls, stream, pr[i].bytes, pr[i].flops);
+    e = launch_batch_ttm(kind, h->lclass, hdr, desc, stream);
   }
   return dev_check(e, "batch step");
 }

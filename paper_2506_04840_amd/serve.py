@@ -1,16 +1,23 @@
 """Serving loop: continuous batching of small shifted randomized ST-HOSVDs.
 
-Requests (an FP32 order-3 tensor resident on the device, its ranks and seed)
+Requests (an FP32 tensor resident on the device, its Tucker ranks and seed)
 arrive over time. The loop admits waiting requests into the next batch while
 the batch fits the capacity and the workspace budget, writes the batch plan
 (host only) and replays a graph captured once per slot: the library's
-persistent batched kernels run every phase of Algorithm 3 for all requests
-of the batch in one launch each. Two slots alternate, so the next batch is
-planned while the previous one runs; a request's latency runs from its
-arrival to the moment its batch's completion event is seen.
+persistent batched kernels run every phase of Algorithm 3 for all requests of
+the batch in one launch each. Requests of different orders go to different
+slot pairs (a plan holds one order). Two slots per order alternate, so the
+next batch is admitted and planned while the previous one runs; a request's
+latency runs from its arrival to the moment its batch's completion event is
+seen by the loop.
+
+A request's descriptor (shape, ranks, seed and device pointers of A, G and the
+U_k) is built once when the request is made (Job.prepare), as a client would
+hand over its buffers; admission reads only its workspace size.
 
 The one-at-a-time reference solves the same requests in arrival order with
-one tucker_rsthosvd call each on a preallocated workspace.
+one tucker_rsthosvd call each (FP32, same p, q, shift and seed) on a
+preallocated workspace.
 """
 from __future__ import annotations
 
@@ -18,7 +25,7 @@ import collections
 import ctypes
 import dataclasses
 import time
-from typing import List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence
 
 import torch
 
@@ -34,54 +41,78 @@ class Job:
     arrival: float
     G: Optional[torch.Tensor] = None
     U: Optional[List[torch.Tensor]] = None
+    item: Optional[T.BatchItem] = None
+    ws_bytes: int = 0
     done: float = -1.0
 
-
-def _alloc_outputs(job: Job, device) -> None:
-    job.G = torch.empty(job.ranks, dtype=torch.float32, device=device)
-    job.U = [torch.empty((n, r), dtype=torch.float32, device=device) for n, r in zip(job.A.shape, job.ranks)]
+    def prepare(self, p: int, q: int) -> "Job":
+        """Allocate G and the U_k on A's device and build the request's descriptor."""
+        if self.A.dtype != torch.float32:
+            raise ValueError("served requests are FP32")
+        dev = self.A.device
+        self.G = torch.empty(self.ranks, dtype=torch.float32, device=dev)
+        self.U = [torch.empty((n, r), dtype=torch.float32, device=dev) for n, r in zip(self.A.shape, self.ranks)]
+        self.item = T.BatchSolver.item(self.A, self.G, self.U, self.ranks, self.seed)
+        nb = T.lib.tucker_batch_item_bytes(ctypes.byref(self.item), p, q)
+        if nb == 0:
+            raise ValueError("request %d: invalid shape or ranks" % self.rid)
+        self.ws_bytes = int(nb)
+        return self
 
 
 class _Slot:
-    def __init__(self, capacity, q, p, lclass, ws_bytes, shift, device):
-        self.solver = T.BatchSolver(capacity, 3, q, p, lclass, ws_bytes, shift, device)
+    def __init__(self, capacity, order, q, p, lclass, ws_bytes, shift, device):
+        self.solver = T.BatchSolver(capacity, order, q, p, lclass, ws_bytes, shift, device)
         self.graph = None
         self.event = None
         self.jobs: List[Job] = []
 
     def capture(self):
         """Capture one step (on an empty plan) into a graph; replays run later plans."""
+        dev = self.solver.device
         self.solver.plan([])
-        s = torch.cuda.Stream(device=self.solver.device)
-        s.wait_stream(torch.cuda.current_stream(self.solver.device))
+        s = torch.cuda.Stream(device=dev)
+        s.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(s):
             self.solver.step()  # warm the launch path outside capture
-        torch.cuda.current_stream(self.solver.device).wait_stream(s)
-        torch.cuda.synchronize(self.solver.device)
+        torch.cuda.current_stream(dev).wait_stream(s)
+        torch.cuda.synchronize(dev)
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
             self.solver.step()
-        torch.cuda.synchronize(self.solver.device)
+        torch.cuda.synchronize(dev)
 
 
 class BatchServer:
-    """Continuous batching over two graph-replayed slots."""
+    """Continuous batching over two graph-replayed slots per tensor order."""
 
     def __init__(self, capacity=256, q=1, p=8, lclass=48, ws_bytes=8 << 30, shift="adaptive", device="cuda",
-                 use_graphs=True):
+                 use_graphs=True, orders=(3,)):
         self.device = torch.device(device)
-        self.p, self.q = p, q
-        self.slots = [_Slot(capacity, q, p, lclass, ws_bytes, shift, self.device) for _ in range(2)]
-        self.capacity = capacity
+        self.p, self.q, self.lclass, self.shift = p, q, lclass, shift
+        self.capacity, self.ws_bytes = capacity, ws_bytes
         self.use_graphs = use_graphs
-        if use_graphs:
-            for s in self.slots:
-                s.capture()
-        self.budget = self.slots[0].solver.ws.numel() - self.slots[0].solver.table_bytes
+        self.slots: Dict[int, List[_Slot]] = {}
+        for d in orders:
+            self._slots_for(d)
+        self.batch_sizes: List[int] = []
+
+    def _slots_for(self, d: int) -> List[_Slot]:
+        if d not in self.slots:
+            pair = [_Slot(self.capacity, d, self.q, self.p, self.lclass, self.ws_bytes, self.shift, self.device)
+                    for _ in range(2)]
+            if self.use_graphs:
+                for s in pair:
+                    s.capture()
+            self.slots[d] = pair
+        return self.slots[d]
+
+    def budget(self, d: int) -> int:
+        s = self._slots_for(d)[0].solver
+        return s.ws.numel() - s.table_bytes
 
     def _launch(self, slot: _Slot, jobs: List[Job]):
-        items = [T.BatchSolver.item(j.A, j.G, j.U, j.ranks, j.seed) for j in jobs]
-        slot.solver.plan(items)
+        slot.solver.plan([j.item for j in jobs])
         if self.use_graphs:
             slot.graph.replay()
         else:
@@ -89,43 +120,63 @@ class BatchServer:
         slot.event = torch.cuda.Event()
         slot.event.record()
         slot.jobs = jobs
+        self.batch_sizes.append(len(jobs))
+
+    def _admit(self, waiting: collections.deque, d: int) -> List[Job]:
+        """FIFO among waiting requests of order d, while capacity and budget allow."""
+        batch, used, keep = [], 0, collections.deque()
+        budget = self.budget(d)
+        while waiting and len(batch) < self.capacity:
+            j = waiting.popleft()
+            if j.A.dim() != d:
+                keep.append(j)
+                continue
+            if j.ws_bytes > budget:
+                raise ValueError("request %d needs %d workspace bytes, budget %d" % (j.rid, j.ws_bytes, budget))
+            if used + j.ws_bytes > budget:
+                keep.append(j)
+                break
+            batch.append(j)
+            used += j.ws_bytes
+        keep.extend(waiting)
+        waiting.clear()
+        waiting.extend(keep)
+        return batch
 
     def run(self, jobs: Sequence[Job], t0: Optional[float] = None) -> List[Job]:
-        """Serve `jobs` (arrival seconds relative to t0); returns them with .done set."""
+        """Serve prepared `jobs` (arrival seconds relative to t0); returns them with .done set."""
+        for j in jobs:
+            if j.item is None:
+                j.prepare(self.p, self.q)
+        for d in sorted({j.A.dim() for j in jobs}):
+            self._slots_for(d)
         pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
         waiting: collections.deque = collections.deque()
+        busy: List[_Slot] = []
         t0 = time.perf_counter() if t0 is None else t0
-        sizer = self.slots[0].solver
-        while pending or waiting or any(s.jobs for s in self.slots):
+        while pending or waiting or busy:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
-            for s in self.slots:
-                if s.jobs and s.event.query():
+            for s in list(busy):
+                if s.event.query():
                     t = time.perf_counter() - t0
                     for j in s.jobs:
                         j.done = t
                     s.jobs = []
-            free = [s for s in self.slots if not s.jobs]
-            if free and waiting:
-                batch, used = [], 0
-                while waiting and len(batch) < self.capacity:
-                    j = waiting[0]
-                    if j.G is None:
-                        _alloc_outputs(j, self.device)
-                    need = sizer.item_bytes(T.BatchSolver.item(j.A, j.G, j.U, j.ranks, j.seed))
-                    if batch and used + need > self.budget:
-                        break
-                    batch.append(waiting.popleft())
-                    used += need
-                self._launch(free[0], batch)
-                continue
-            if not pending and not waiting:
-                time.sleep(20e-6)
-            elif pending and not waiting:
+                    busy.remove(s)
+            if waiting:
+                d = waiting[0].A.dim()
+                free = [s for s in self.slots[d] if not s.jobs]
+                if free:
+                    batch = self._admit(waiting, d)
+                    self._launch(free[0], batch)
+                    busy.append(free[0])
+                    continue
+            if pending and not waiting and not busy:
                 time.sleep(min(200e-6, max(0.0, pending[0].arrival - now)))
             else:
-                time.sleep(20e-6)
+                time.sleep(10e-6)
         return list(jobs)
 
 
@@ -137,35 +188,36 @@ class SingleServer:
         self.p, self.q, self.shift = p, q, T._SHIFT[shift]
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
 
-    def _solve(self, j: Job):
-        s = T._shape(j.A.shape)
-        r = (ctypes.c_int64 * 3)(*j.ranks)
-        u = (ctypes.c_void_p * 3)(*[x.data_ptr() for x in j.U])
-        T._check(T.lib.tucker_rsthosvd(ctypes.byref(s), ctypes.c_void_p(j.A.data_ptr()), r, self.p, self.q,
-                                       self.shift, ctypes.c_uint64(j.seed), T.FP32,
-                                       ctypes.c_void_p(j.G.data_ptr()), u, None,
+    def _solve(self, j: Job, stream):
+        it = j.item
+        T._check(T.lib.tucker_rsthosvd(ctypes.byref(it.shape), it.A, it.ranks, self.p, self.q, self.shift,
+                                       ctypes.c_uint64(it.seed), T.FP32, it.G, it.U, None,
                                        ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws.numel()),
-                                       T._stream(self.device)))
+                                       stream))
 
     def run(self, jobs: Sequence[Job], t0: Optional[float] = None) -> List[Job]:
+        for j in jobs:
+            if j.item is None:
+                j.prepare(self.p, self.q)
         order = sorted(jobs, key=lambda j: j.arrival)
+        stream = T._stream(self.device)
         t0 = time.perf_counter() if t0 is None else t0
         inflight = collections.deque()
-        for j in order:
-            while time.perf_counter() - t0 < j.arrival:
-                while inflight and inflight[0][1].query():
-                    jj, _ = inflight.popleft()
-                    jj.done = time.perf_counter() - t0
-                time.sleep(20e-6)
-            if j.G is None:
-                _alloc_outputs(j, self.device)
-            self._solve(j)
-            ev = torch.cuda.Event()
-            ev.record()
-            inflight.append((j, ev))
+
+        def retire():
             while inflight and inflight[0][1].query():
                 jj, _ = inflight.popleft()
                 jj.done = time.perf_counter() - t0
+
+        for j in order:
+            while time.perf_counter() - t0 < j.arrival:
+                retire()
+                time.sleep(10e-6)
+            self._solve(j, stream)
+            ev = torch.cuda.Event()
+            ev.record()
+            inflight.append((j, ev))
+            retire()
         while inflight:
             jj, ev = inflight.popleft()
             ev.synchronize()
@@ -174,6 +226,7 @@ class SingleServer:
 
 
 def latency_stats(jobs: Sequence[Job]) -> dict:
+    """p50 / p99 / max latency (arrival to completion seen), span and throughput."""
     lat = sorted(j.done - j.arrival for j in jobs)
     if not lat:
         return {}
