@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--kernel", default="colreduce", help="kernel class reported in the roofline object")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--burst-only", action="store_true",
+                    help="serving workload: time the batched bursts only (for profiler runs)")
     return ap.parse_args()
 
 
@@ -302,6 +304,11 @@ def serving_main(args):
     cap = args.steps * len(jb) / elapsed
     mean_batch = float(np.mean(srv.batch_sizes))
     _log("batched burst: %.1f approximations/s" % cap)
+    if args.burst_only:
+        print(json.dumps({"metric": METRIC, "value": round(cap, 2), "unit": "approximations/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+                          "config": {"workload": SERVING, "burst_only": True}}), flush=True)
+        return
 
     # one request at a time, same requests, same burst
     single = serve.SingleServer(p=c["p"], q=c["q"], ws_bytes=64 << 20, device=dev)

@@ -82,21 +82,34 @@ __device__ __forceinline__ typename Pol<MK>::acc_t mma(const typename Pol<MK>::T
   }
 }
 
-// N consecutive elements at p; `cnt` of them exist (<= 0: none). With VEC
-// the caller guarantees 16-byte alignment of p whenever cnt >= N.
-template <typename T, int N, bool VEC>
+// 16 raw bytes with only 4-byte alignment: global loads and stores of this
+// type are single dwordx4 accesses at any element address, so rows of any
+// length (odd unfolding widths, sub-tensors at odd offsets) take the wide path.
+typedef float f4u_t __attribute__((ext_vector_type(4), aligned(4)));
+
+// N consecutive elements at p; `cnt` of them exist (<= 0: none). A whole
+// group is read with 16-byte loads; a short group with guarded element loads.
+template <typename T, int N>
 __device__ __forceinline__ void load_n(const T* __restrict__ p, int cnt, T* out) {
-  if (VEC && cnt >= N) {
-    static_assert((sizeof(T) * N) % 16 == 0, "vector width");
+  static_assert((sizeof(T) * N) % 16 == 0, "vector width");
+  if (cnt >= N) {
 #pragma unroll
     for (int q = 0; q < (int)(sizeof(T) * N / 16); ++q) {
-      const float4 v = *reinterpret_cast<const float4*>(reinterpret_cast<const char*>(p) + 16 * q);
-      *reinterpret_cast<float4*>(reinterpret_cast<char*>(out) + 16 * q) = v;
+      const f4u_t v = *reinterpret_cast<const f4u_t*>(reinterpret_cast<const char*>(p) + 16 * q);
+      *reinterpret_cast<f4u_t*>(reinterpret_cast<char*>(out) + 16 * q) = v;
     }
   } else {
 #pragma unroll
     for (int e = 0; e < N; ++e) out[e] = (e < cnt) ? p[e] : T(0);
   }
+}
+
+// The 16 bytes of VE elements at p as raw float4, `cnt` of them present.
+template <typename T, int VE>
+__device__ __forceinline__ float4 load16(const T* __restrict__ p, int cnt) {
+  T v[VE];
+  load_n<T, VE>(p, cnt, v);
+  return *reinterpret_cast<const float4*>(v);
 }
 
 // Workgroup -> (split, row block) so that the workgroups of one split, which
@@ -145,7 +158,7 @@ struct LdsPol<MF_BF16> {
   static constexpr int KT = 64, RV = 8;
 };
 
-template <int MK, int NJ, bool VEC>
+template <int MK, int NJ>
 __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restrict__ X,
                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
                                                 int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
@@ -177,29 +190,15 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
     for (int q = 0; q < XU; ++q) {
       const int L = q * 256 + tid, row = L / UPR, u = L % UPR;
       const int64_t i = r0 + row, s = s0 + (int64_t)u * VE;
-      const T* src = X + (p * n + i) * S + s;
-      if (VEC) {
-        xr[q] = (live && i < n && s < S) ? *reinterpret_cast<const V4*>(src) : V4{0.f, 0.f, 0.f, 0.f};
-      } else {
-        T v[VE];
-#pragma unroll
-        for (int e = 0; e < VE; ++e) v[e] = (live && i < n && s + e < S) ? src[e] : T(0);
-        xr[q] = *reinterpret_cast<const V4*>(v);
-      }
+      const int cnt = (live && i < n) ? (int)max<int64_t>(0, min<int64_t>(VE, S - s)) : 0;
+      xr[q] = load16<T, VE>(X + (p * n + i) * S + s, cnt);
     }
 #pragma unroll
     for (int q = 0; q < BU; ++q) {
       const int L = q * 256 + tid, j = L / UPR, u = L % UPR;
       const int64_t s = s0 + (int64_t)u * VE;
-      const T* src = Bt + (int64_t)j * m + p * S + s;
-      if (VEC) {
-        br[q] = (live && j < l && s < S) ? *reinterpret_cast<const V4*>(src) : V4{0.f, 0.f, 0.f, 0.f};
-      } else {
-        T v[VE];
-#pragma unroll
-        for (int e = 0; e < VE; ++e) v[e] = (live && j < l && s + e < S) ? src[e] : T(0);
-        br[q] = *reinterpret_cast<const V4*>(v);
-      }
+      const int cnt = (live && j < l) ? (int)max<int64_t>(0, min<int64_t>(VE, S - s)) : 0;
+      br[q] = load16<T, VE>(Bt + (int64_t)j * m + p * S + s, cnt);
     }
   };
   auto sput = [&](LT* dst, const V4& v) {
@@ -277,12 +276,12 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
     }
 }
 
-template <int MK, int NJ, bool VEC>
+template <int MK, int NJ>
 __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __restrict__ X,
                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
                                                 int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
                                                 int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
-  cr_lds_body<MK, NJ, VEC>(X, Bt, n, S, l, m, spp, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
+  cr_lds_body<MK, NJ>(X, Bt, n, S, l, m, spp, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -290,7 +289,7 @@ __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __res
 // output row index). A batch covers 4 * KB consecutive p; k-slot g of the
 // MFMA takes p = pbase + KB g + q, q < KB, for both operands.
 // ---------------------------------------------------------------------------
-template <int MK, int NJ, bool VEC, bool BVEC>
+template <int MK, int NJ>
 __device__ __forceinline__ void cr_cols_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ Bt, int64_t P, int64_t n,
                                                  int l, int64_t nsteps, int nsplit, int nrblocks,
@@ -323,7 +322,7 @@ __device__ __forceinline__ void cr_cols_body(const typename Pol<MK>::T* __restri
       for (int h = 0; h < NH; ++h) {
         const int64_t base = r0 + h * 16 * MV + MV * mm;
         T v[MV];
-        load_n<T, MV, VEC>(X + p * n + base, q < pcnt ? (int)min<int64_t>(MV, n - base) : 0, v);
+        load_n<T, MV>(X + p * n + base, q < pcnt ? (int)min<int64_t>(MV, n - base) : 0, v);
 #pragma unroll
         for (int vv = 0; vv < MV; ++vv) fa[h * MV + vv][q] = v[vv];
       }
@@ -331,7 +330,7 @@ __device__ __forceinline__ void cr_cols_body(const typename Pol<MK>::T* __restri
 #pragma unroll
     for (int u = 0; u < NJ; ++u) {
       const int j = 16 * u + mm;
-      load_n<T, KB, BVEC>(Bt + (int64_t)j * P + pq, j < l ? pcnt : 0, fb[u]);
+      load_n<T, KB>(Bt + (int64_t)j * P + pq, j < l ? pcnt : 0, fb[u]);
     }
   };
   auto compute = [&](T (&fa)[4][KB], T (&fb)[NJ][KB]) {
@@ -365,12 +364,12 @@ __device__ __forceinline__ void cr_cols_body(const typename Pol<MK>::T* __restri
       }
 }
 
-template <int MK, int NJ, bool VEC, bool BVEC>
+template <int MK, int NJ>
 __global__ __launch_bounds__(256) void k_cr_cols(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ Bt, int64_t P, int64_t n,
                                                  int l, int64_t nsteps, int nsplit, int nrblocks,
                                                  typename Pol<MK>::part_t* __restrict__ part) {
-  cr_cols_body<MK, NJ, VEC, BVEC>(X, Bt, P, n, l, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
+  cr_cols_body<MK, NJ>(X, Bt, P, n, l, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
 }
 
 static void cr_geom(tucker_precision prec, const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
@@ -427,29 +426,13 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
   int nrb;
   cr_geom(prec, v, &nsteps, &spp, &nrb);
   const unsigned blocks = (unsigned)(((nsplit + 7) / 8) * 8 * nrb);
-  const uintptr_t xa = (uintptr_t)X, ba = (uintptr_t)Bt;
   const int64_t m = v.P * v.S;
-  constexpr int VE = 16 / (int)sizeof(T);  // elements per 16-byte vector
-  if (v.S == 1) {
-    const bool vec = (v.n % Po::MV == 0) && (xa % 16 == 0);
-    const bool bvec = (v.P % VE == 0) && (ba % 16 == 0);
-#define TK_CR_COLS(V, BV)                                                                                     \
-  hipLaunchKernelGGL((k_cr_cols<MK, NJ, V, BV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, \
-                     v.n, l, nsteps, nsplit, nrb, (PT*)part)
-    if (vec && bvec) TK_CR_COLS(true, true);
-    else if (vec) TK_CR_COLS(true, false);
-    else if (bvec) TK_CR_COLS(false, true);
-    else TK_CR_COLS(false, false);
-#undef TK_CR_COLS
-  } else {
-    const bool vec = (v.S % VE == 0) && (xa % 16 == 0) && (ba % 16 == 0);
-    if (vec)
-      hipLaunchKernelGGL((k_cr_lds<MK, NJ, true>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
-                         v.S, l, m, spp, nsteps, nsplit, nrb, (PT*)part);
-    else
-      hipLaunchKernelGGL((k_cr_lds<MK, NJ, false>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n,
-                         v.S, l, m, spp, nsteps, nsplit, nrb, (PT*)part);
-  }
+  if (v.S == 1)
+    hipLaunchKernelGGL((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l,
+                       nsteps, nsplit, nrb, (PT*)part);
+  else
+    hipLaunchKernelGGL((k_cr_lds<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n, v.S, l, m,
+                       spp, nsteps, nsplit, nrb, (PT*)part);
   return hipGetLastError();
 }
 
@@ -539,7 +522,7 @@ hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, in
 // (4 interleaved 16-row MFMA tiles), 4 waves per workgroup, all n rows per
 // wave, in batches of 4 * KB rows: k-slot g takes i = i0 + KB g + q, q < KB.
 // ---------------------------------------------------------------------------
-template <int MK, int NJ, bool VEC, bool WVEC>
+template <int MK, int NJ, bool WVEC>
 __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
                                                  int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
@@ -580,7 +563,7 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
       for (int h = 0; h < NH; ++h) {
         const int64_t base = s0 + h * 16 * MV + MV * mm;
         T v[MV];
-        load_n<T, MV, VEC>(xp + i * S + base, q < icnt ? (int)min<int64_t>(MV, S - base) : 0, v);
+        load_n<T, MV>(xp + i * S + base, q < icnt ? (int)min<int64_t>(MV, S - base) : 0, v);
 #pragma unroll
         for (int vv = 0; vv < MV; ++vv) fa[h * MV + vv][q] = v[vv];
       }
@@ -589,7 +572,7 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
     for (int u = 0; u < NJ; ++u) {
       const int j = 16 * u + mm;
       if constexpr (WVEC) {
-        load_n<T, KB, true>(W + (int64_t)j * wsj + iq, j < lw ? icnt : 0, fb[u]);
+        load_n<T, KB>(W + (int64_t)j * wsj + iq, j < lw ? icnt : 0, fb[u]);
       } else {
 #pragma unroll
         for (int q = 0; q < KB; ++q) fb[u][q] = (q < icnt && j < lw) ? W[(iq + q) * wsi + (int64_t)j * wsj] : T(0);
@@ -650,9 +633,9 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
       for (int h = 0; h < NH; ++h) {
         const int64_t c = s0 + h * 16 * MV + MV * dr;
         T* dst = op + (int64_t)j * osj + c;
-        if constexpr (VEC && MV == 4) {
+        if constexpr (MV == 4) {
           if (c + 3 < S) {
-            *reinterpret_cast<float4*>(dst) = make_float4((float)acc[h * MV + 0][u][v], (float)acc[h * MV + 1][u][v],
+            *reinterpret_cast<f4u_t*>(dst) = f4u_t((float)acc[h * MV + 0][u][v], (float)acc[h * MV + 1][u][v],
                                                           (float)acc[h * MV + 2][u][v], (float)acc[h * MV + 3][u][v]);
             continue;
           }
@@ -665,13 +648,13 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
   }
 }
 
-template <int MK, int NJ, bool VEC, bool WVEC>
+template <int MK, int NJ, bool WVEC>
 __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
                                                  int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
                                                  int64_t ntiles, int ksplit, typename Pol<MK>::T* __restrict__ out,
                                                  int64_t osp, int64_t osj) {
-  rc_rows_body<MK, NJ, VEC, WVEC>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, ksplit, out, osp, osj, (int)blockIdx.x);
+  rc_rows_body<MK, NJ, WVEC>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, ksplit, out, osp, osj, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -679,7 +662,7 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
 // reduction index); out(p, j) = out[p * osp + j * osj]; each wave owns 64
 // rows p, 4 waves per workgroup.
 // ---------------------------------------------------------------------------
-template <int MK, int NJ, bool VEC, bool WVEC>
+template <int MK, int NJ, bool WVEC>
 __device__ __forceinline__ void rc_cols_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t P, int64_t n,
                                                  int lw, int64_t wsi, int64_t wsj, typename Pol<MK>::T* __restrict__ out,
@@ -708,13 +691,13 @@ __device__ __forceinline__ void rc_cols_body(const typename Pol<MK>::T* __restri
 #pragma unroll
     for (int tm = 0; tm < 4; ++tm) {
       const int64_t p = p0 + 16 * tm + mm;
-      load_n<T, KC, VEC>(X + p * n + ib, p < P ? cnt : 0, fa[tm]);
+      load_n<T, KC>(X + p * n + ib, p < P ? cnt : 0, fa[tm]);
     }
 #pragma unroll
     for (int u = 0; u < NJ; ++u) {
       const int j = 16 * u + mm;
       if constexpr (WVEC) {
-        load_n<T, KC, true>(W + (int64_t)j * wsj + ib, j < lw ? cnt : 0, fb[u]);
+        load_n<T, KC>(W + (int64_t)j * wsj + ib, j < lw ? cnt : 0, fb[u]);
       } else {
 #pragma unroll
         for (int e = 0; e < KC; ++e) fb[u][e] = (e < cnt && j < lw) ? W[(ib + e) * wsi + (int64_t)j * wsj] : T(0);
@@ -770,34 +753,28 @@ __device__ __forceinline__ void rc_cols_body(const typename Pol<MK>::T* __restri
       }
 }
 
-template <int MK, int NJ, bool VEC, bool WVEC>
+template <int MK, int NJ, bool WVEC>
 __global__ __launch_bounds__(256) void k_rc_cols(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t P, int64_t n,
                                                  int lw, int64_t wsi, int64_t wsj, typename Pol<MK>::T* __restrict__ out,
                                                  int64_t osp, int64_t osj) {
-  rc_cols_body<MK, NJ, VEC, WVEC>(X, W, P, n, lw, wsi, wsj, out, osp, osj, (int)blockIdx.x);
+  rc_cols_body<MK, NJ, WVEC>(X, W, P, n, lw, wsi, wsj, out, osp, osj, (int)blockIdx.x);
 }
 
 template <int MK, int NJ>
 static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_t wsi, int64_t wsj, int lw, void* out,
                             bool out_jmajor, hipStream_t st) {
-  using Po = Pol<MK>;
-  using T = typename Po::T;
-  constexpr int VE = 16 / (int)sizeof(T);
-  const uintptr_t xa = (uintptr_t)X, wa = (uintptr_t)W, oa = (uintptr_t)out;
+  using T = typename Pol<MK>::T;
   const int64_t m = v.P * v.S;
-  const bool wvec = (wsi == 1) && (wsj % VE == 0) && (wa % 16 == 0);
+  const bool wvec = wsi == 1;  // W contiguous along the reduction index
   if (v.S == 1) {
     const int64_t osp = out_jmajor ? 1 : lw, osj = out_jmajor ? m : 1;
     const unsigned blocks = (unsigned)((v.P + 63) / 64);
-    const bool vec = (v.n % Po::KC == 0) && (xa % 16 == 0);
-#define TK_RC_COLS(V, WV)                                                                                    \
-  hipLaunchKernelGGL((k_rc_cols<MK, NJ, V, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.P, \
-                     v.n, lw, wsi, wsj, (T*)out, osp, osj)
-    if (vec && wvec) TK_RC_COLS(true, true);
-    else if (vec) TK_RC_COLS(true, false);
-    else if (wvec) TK_RC_COLS(false, true);
-    else TK_RC_COLS(false, false);
+#define TK_RC_COLS(WV)                                                                                         \
+  hipLaunchKernelGGL((k_rc_cols<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.P, v.n, \
+                     lw, wsi, wsj, (T*)out, osp, osj)
+    if (wvec) TK_RC_COLS(true);
+    else TK_RC_COLS(false);
 #undef TK_RC_COLS
   } else {
     const int64_t osp = out_jmajor ? v.S : (int64_t)lw * v.S, osj = out_jmajor ? m : v.S;
@@ -805,14 +782,11 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     const int64_t ntiles = v.P * tpp;
     const int ksplit = ntiles < 2048 ? 1 : 0;  // split the rows when tiles alone cannot fill the chip
     const unsigned blocks = (unsigned)(ksplit ? ntiles : (ntiles + 3) / 4);
-    const bool vec = (v.S % Po::MV == 0) && (xa % 16 == 0) && (oa % 16 == 0) && (osj % VE == 0) && (osp % VE == 0);
-#define TK_RC_ROWS(V, WV)                                                                                        \
-  hipLaunchKernelGGL((k_rc_rows<MK, NJ, V, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
+#define TK_RC_ROWS(WV)                                                                                            \
+  hipLaunchKernelGGL((k_rc_rows<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
                      lw, wsi, wsj, tpp, ntiles, ksplit, (T*)out, osp, osj)
-    if (vec && wvec) TK_RC_ROWS(true, true);
-    else if (vec) TK_RC_ROWS(true, false);
-    else if (wvec) TK_RC_ROWS(false, true);
-    else TK_RC_ROWS(false, false);
+    if (wvec) TK_RC_ROWS(true);
+    else TK_RC_ROWS(false);
 #undef TK_RC_ROWS
   }
   return hipGetLastError();
@@ -971,23 +945,23 @@ __device__ __forceinline__ void b_fill(const BFill& d, int bid) {
 }
 template <int NJ>
 __device__ __forceinline__ void b_cr_lds(const BCrLds& d, int bid) {
-  cr_lds_body<MF_F32, NJ, false>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.nrb, d.part, bid);
+  cr_lds_body<MF_F32, NJ>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.nrb, d.part, bid);
 }
 template <int NJ>
 __device__ __forceinline__ void b_cr_cols(const BCrCols& d, int bid) {
-  cr_cols_body<MF_F32, NJ, false, false>(d.X, d.Bt, d.P, d.n, d.l, d.nsteps, d.nsplit, d.nrb, d.part, bid);
+  cr_cols_body<MF_F32, NJ>(d.X, d.Bt, d.P, d.n, d.l, d.nsteps, d.nsplit, d.nrb, d.part, bid);
 }
 __device__ __forceinline__ void b_reduce(const BReduce& d, int bid) {
   reduce_splits_body<float, double>(d.part, d.nsplit, d.nl, d.qsub, d.alpha, d.Y, bid);
 }
 template <int NJ>
 __device__ __forceinline__ void b_rc_rows(const BRcRows& d, int bid) {
-  rc_rows_body<MF_F32, NJ, false, false>(d.X, d.W, d.n, d.S, d.lw, d.wsi, d.wsj, d.tpp, d.ntiles, d.ksplit, d.out,
+  rc_rows_body<MF_F32, NJ, true>(d.X, d.W, d.n, d.S, d.lw, d.wsi, d.wsj, d.tpp, d.ntiles, d.ksplit, d.out,
                                          d.osp, d.osj, bid);
 }
 template <int NJ>
 __device__ __forceinline__ void b_rc_cols(const BRcCols& d, int bid) {
-  rc_cols_body<MF_F32, NJ, false, false>(d.X, d.W, d.P, d.n, d.lw, d.wsi, d.wsj, d.out, d.osp, d.osj, bid);
+  rc_cols_body<MF_F32, NJ, true>(d.X, d.W, d.P, d.n, d.lw, d.wsi, d.wsj, d.out, d.osp, d.osj, bid);
 }
 
 template <int NJ>

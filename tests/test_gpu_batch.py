@@ -28,10 +28,19 @@ def T():
 P, Q = 8, 1
 
 
+def _at_odd_address(t):
+    buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+    v = buf[1:].view(t.shape)
+    v.copy_(t)
+    return v
+
+
 def _requests(count, seed, n_lo=24, n_hi=70):
+    """Seeded requests; every third tensor starts one element past an aligned address."""
     reqs = gen.request_stream(count, 0.0, seed=seed, n_lo=n_lo, n_hi=n_hi, r_lo=3, r_hi=20)
     dev = torch.device("cuda:0")
-    return reqs, [gen.request_tensor_device(r, dev) for r in reqs]
+    ts = [gen.request_tensor_device(r, dev) for r in reqs]
+    return reqs, [_at_odd_address(t) if i % 3 == 1 else t for i, t in enumerate(ts)]
 
 
 def _single(T, A, ranks, seed):

@@ -9,6 +9,8 @@ product entry, ||A|| for a reconstruction, Sigma_1 for a shift); subspace
 sine distance <= 1e-4 where the oracle's spectral gap is at least 1e-2
 (FP32) / 1e-6 (FP64) of Sigma_1.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -128,6 +130,54 @@ def test_core_matches_oracle(T, prec, dims, mode, r):
     xk = unfold(_np(x), mode)
     scale = np.sqrt(np.sum(_np(u) ** 2, axis=0)).max() * np.sqrt(np.sum(xk ** 2, axis=0)).max()
     assert np.max(np.abs(out - ref)) <= TOL[prec] * scale
+
+
+def _dev_offset(a, dtype):
+    """`a` on the device at a base address one element past a 256-byte boundary."""
+    a = np.ascontiguousarray(a)
+    buf = torch.empty(a.size + 1, dtype=dtype, device="cuda")
+    v = buf[1:].view(a.shape)
+    v.copy_(torch.from_numpy(a).to(dtype=dtype))
+    return v
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,mode,l", [((37, 130, 29), 1, 33), ((61, 45, 23), 0, 20), ((61, 45, 23), 2, 17),
+                                         ((50, 33), 1, 7)])
+def test_products_at_unaligned_addresses(T, prec, dims, mode, l):
+    """Inputs and outputs that start one element past an aligned address, with
+    odd row lengths: the wide loads and stores take any element address."""
+    dt = DT[prec]
+    g = gen.rng(17)
+    a = g.standard_normal(dims)
+    x = _dev_offset(a, dt)
+    assert x.data_ptr() % 16 != 0
+    xa = _np(x)
+    xk = unfold(xa, mode)
+    # sketch (column reduction)
+    y = _np(T.sketch(x, mode, l, seed=5, precision=prec))
+    om = orc_rng.gaussian_omega(5, mode, xk.shape[1], l)
+    assert np.all(np.abs(y - orc.sketch(xa, mode, om)) <= TOL[prec] * _row_col_scale(xk, om))
+    # raw power step (row contraction then column reduction), Q at an odd address
+    q0 = np.linalg.qr(g.standard_normal((dims[mode], l)))[0]
+    q = _dev_offset(q0, dt)
+    al = torch.tensor([0.25], dtype=torch.float64, device="cuda")
+    m = _np(T.shifted_power(x, mode, q, al, raw=True, precision=prec))
+    ref = orc.shifted_power(xa, mode, _np(q), 0.25)
+    assert np.max(np.abs(m - ref)) <= TOL[prec] * np.linalg.norm(xa) ** 2
+    # core step with U and the output at odd addresses
+    r = min(l, dims[mode])
+    u = _dev_offset(np.linalg.qr(g.standard_normal((dims[mode], r)))[0], dt)
+    od = list(dims)
+    od[mode] = r
+    out = _dev_offset(np.zeros(od), dt)
+    sh = T._shape(x.shape)
+    T._check(T.lib.tucker_core(ctypes.byref(sh), mode, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(u.data_ptr()), r,
+                               T._PREC[prec], ctypes.c_void_p(out.data_ptr()), T._stream(x.device)))
+    torch.cuda.synchronize()
+    refc = orc.core_step(xa, mode, _np(u))
+    scale = np.sqrt(np.sum(_np(u) ** 2, axis=0)).max() * np.sqrt(np.sum(xk ** 2, axis=0)).max()
+    assert np.max(np.abs(_np(out) - refc)) <= TOL[prec] * scale
 
 
 # --------------------------------------------------------------- svd econ
