@@ -443,6 +443,19 @@ void batch_phase_work(BatchKind kind, int k, int role, const Plan& pl, double* b
   *flops += 2.0 * N * w;
 }
 
+// Splits of a request's column reduction inside a batch: the batch already
+// fills the device, so a split covers at least 32 stages (S > 1) or 8 steps
+// (S == 1), and never more splits than the request's own workspace holds.
+// Depends on the request's shape only, so a request computes the same alone
+// and in any mix.
+int batch_colreduce_splits(const View3& v, int l) {
+  int64_t nsteps, spp;
+  int nrb;
+  cr_geometry(v, &nsteps, &spp, &nrb);
+  const int64_t ns = std::max<int64_t>(1, nsteps / (v.S > 1 ? 32 : 8));
+  return (int)std::min<int64_t>(ns, colreduce_splits(v, l));
+}
+
 // Fills one phase's descriptor for item b (returns its work items).
 int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const SolveWs& w,
                    const tucker_batch_item& it, tucker_shift shift, int d, void* dst) {
@@ -451,7 +464,7 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
   const int64_t n = v.n, m = pl.m[k];
   const OrthWs ows = carve_orth(w.orth, n, l);
   const void* X = k == 0 ? it.A : w.xbuf[(k - 1) & 1];
-  const int nsplit = colreduce_splits(v, l);
+  const int nsplit = batch_colreduce_splits(v, l);
   const int nblk = (int)((n + 63) / 64);
   double* alpha = w.alpha + k;
   switch (kind) {
@@ -528,6 +541,7 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
         int ksplit;
         int64_t tpp;
         const int64_t ntiles = rc_rows_tiles(v, &ksplit, &tpp);
+        ksplit = 0;  // in a batch each wave owns a tile and all n rows (longer streams, no LDS reduction)
         b->X = (const float*)X;
         b->W = (const float*)W;
         b->out = (float*)out;

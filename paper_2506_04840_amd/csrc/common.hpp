@@ -111,24 +111,51 @@ __device__ __forceinline__ void gaussian4_f32(uint64_t seed, uint32_t mode, uint
 // Persistent batched launch: the grid's workgroups loop over the work items
 // of all requests in the table (hdr[0] = requests, hdr[1 + b] = first item of
 // request b, hdr[1 + nreq] = total) and run the request's workgroup body F
-// with the request-local block index. A barrier separates consecutive items
-// so a body may leave some waves early and reuse LDS freely.
+// with the request-local block index. A workgroup's items only move forward,
+// so the request of the previous item bounds the search for the next one
+// (no search while the item stays in the same request). A barrier separates
+// consecutive items so a body may leave some waves early and reuse LDS.
 template <typename D, void (*F)(const D&, int)>
 __global__ __launch_bounds__(256) void k_persist(const int* __restrict__ hdr, const D* __restrict__ desc) {
   const int nreq = hdr[0];
   const int total = hdr[1 + nreq];
+  int b = 0;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    int lo = 0, hi = nreq - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (hdr[1 + mid] <= w)
-        lo = mid;
-      else
-        hi = mid - 1;
+    if (hdr[2 + b] <= w) {
+      int lo = b + 1, hi = nreq - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (hdr[1 + mid] <= w)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      b = lo;
     }
-    F(desc[lo], w - hdr[1 + lo]);
+    F(desc[b], w - hdr[1 + b]);
     __syncthreads();
   }
+}
+
+// Workgroups of a 256-thread kernel resident on the whole device at once
+// (occupancy per CU x CUs), queried once per kernel and device: the grid of a
+// persistent launch, so that every workgroup runs from the start.
+template <typename Kern>
+inline int resident_grid(Kern kernel) {
+  static int cache[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int g = cache[dev];
+  if (g == 0) {
+    int per = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(kernel), 256, 0) !=
+            hipSuccess || per < 1)
+      per = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    g = per * cus;
+    cache[dev] = g;
+  }
+  return g;
 }
 
 }  // namespace tk

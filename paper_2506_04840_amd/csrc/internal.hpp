@@ -223,8 +223,6 @@ enum BatchKind {
   BK_GRAM, BK_PASS, BK_SVD, BK_ROTATE, BK_SIGNFIX, BK_COUNT
 };
 size_t batch_desc_bytes(BatchKind kind);
-// Persistent grid of each kind (workgroups; a multiple of 8).
-int batch_grid(BatchKind kind);
 hipError_t launch_batch_ttm(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
 hipError_t launch_batch_orth(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
 // Work items (workgroups) of one request for the geometry-driven kinds.

@@ -1005,41 +1005,25 @@ size_t batch_desc_bytes(BatchKind kind) {
   }
 }
 
-int batch_grid(BatchKind kind) {
-  switch (kind) {
-    case BK_INIT: return 8;
-    case BK_SVD: return 256;        // one workgroup per request
-    case BK_GRAM:
-    case BK_PASS: return 512;       // 64-row blocks, 66 KB / 56 KB of LDS
-    default: return 1024;
-  }
-}
-
 template <int LP, int RPT>
 static hipError_t batch_orth_lp(BatchKind kind, const int* hdr, const void* desc, hipStream_t st) {
-  const dim3 grid(batch_grid(kind)), blk(256);
+#define TK_PERSIST(D, F)                                                                                      \
+  {                                                                                                           \
+    auto kern = k_persist<D, F>;                                                                              \
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern)), dim3(256), 0, st, hdr, (const D*)desc);               \
+  }                                                                                                           \
+  break
   switch (kind) {
-    case BK_INIT:
-      hipLaunchKernelGGL((k_persist<BInit, b_init>), grid, blk, 0, st, hdr, (const BInit*)desc);
-      break;
-    case BK_GRAM:
-      hipLaunchKernelGGL((k_persist<BGram, b_gram<LP>>), grid, blk, 0, st, hdr, (const BGram*)desc);
-      break;
-    case BK_PASS:
-      hipLaunchKernelGGL((k_persist<BPass, b_pass<LP>>), grid, blk, 0, st, hdr, (const BPass*)desc);
-      break;
-    case BK_SVD:
-      hipLaunchKernelGGL((k_persist<BSvd, b_svd<RPT>>), grid, blk, 0, st, hdr, (const BSvd*)desc);
-      break;
-    case BK_ROTATE:
-      hipLaunchKernelGGL((k_persist<BRotate, b_rotate>), grid, blk, 0, st, hdr, (const BRotate*)desc);
-      break;
-    case BK_SIGNFIX:
-      hipLaunchKernelGGL((k_persist<BSignfix, b_signfix>), grid, blk, 0, st, hdr, (const BSignfix*)desc);
-      break;
+    case BK_INIT: TK_PERSIST(BInit, b_init);
+    case BK_GRAM: TK_PERSIST(BGram, b_gram<LP>);
+    case BK_PASS: TK_PERSIST(BPass, b_pass<LP>);
+    case BK_SVD: TK_PERSIST(BSvd, b_svd<RPT>);
+    case BK_ROTATE: TK_PERSIST(BRotate, b_rotate);
+    case BK_SIGNFIX: TK_PERSIST(BSignfix, b_signfix);
     default:
       return hipErrorInvalidValue;
   }
+#undef TK_PERSIST
   return hipGetLastError();
 }
 

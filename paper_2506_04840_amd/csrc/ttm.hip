@@ -158,11 +158,13 @@ struct LdsPol<MF_BF16> {
   static constexpr int KT = 64, RV = 8;
 };
 
-template <int MK, int NJ>
+// EDGE: 0 when KT divides S (no edge stage), 1 when the 16-byte group
+// divides S (an edge-stage group is whole or absent), 2 otherwise.
+template <int MK, int NJ, int EDGE>
 __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restrict__ X,
                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
                                                 int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
-                                                int nrblocks, typename Pol<MK>::part_t* __restrict__ part, int bid) {
+                                                typename Pol<MK>::part_t* __restrict__ part, int split, int rb) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   using LT = typename LdsPol<MK>::LT;
@@ -174,18 +176,39 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
   __shared__ __align__(16) LT xs[2][64][LS];
   __shared__ __align__(16) LT bs[2][16 * NJ][LS];
 
-  int split, rb;
-  if (!xcd_decode(bid, nsplit, nrblocks, &split, &rb)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int mm = lane & 15, g = lane >> 4;
   const int64_t r0 = (int64_t)rb * 64;
   const int64_t t0 = nsteps * split / nsplit, t1 = nsteps * (split + 1) / nsplit;
 
   using V4 = float4;  // 16 raw bytes
+  // A stage whose KT columns all lie inside the row (every stage but the
+  // last of each p when KT does not divide S) is read with plain 16-byte
+  // loads; the edge stage guards each group (EDGE 1) or counts its elements
+  // (EDGE 2).
   auto gload = [&](int64_t t, V4 (&xr)[XU], V4 (&br)[BU]) {
     const int64_t p = t / spp;
     const int64_t s0 = (t - p * spp) * KT;
     const bool live = t < t1;
+    if (EDGE != 2 || s0 + KT <= S) {
+      const int64_t slim = EDGE == 0 ? KT : S - s0;  // groups at u * VE < slim exist
+#pragma unroll
+      for (int q = 0; q < XU; ++q) {
+        const int L = q * 256 + tid, row = L / UPR, u = L % UPR;
+        const int64_t i = r0 + row;
+        const f4u_t* src = reinterpret_cast<const f4u_t*>(X + (p * n + i) * S + s0 + (int64_t)u * VE);
+        const f4u_t v = (live && i < n && u * VE < slim) ? *src : f4u_t{0.f, 0.f, 0.f, 0.f};
+        xr[q] = V4{v[0], v[1], v[2], v[3]};
+      }
+#pragma unroll
+      for (int q = 0; q < BU; ++q) {
+        const int L = q * 256 + tid, j = L / UPR, u = L % UPR;
+        const f4u_t* src = reinterpret_cast<const f4u_t*>(Bt + (int64_t)j * m + p * S + s0 + (int64_t)u * VE);
+        const f4u_t v = (live && j < l && u * VE < slim) ? *src : f4u_t{0.f, 0.f, 0.f, 0.f};
+        br[q] = V4{v[0], v[1], v[2], v[3]};
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < XU; ++q) {
       const int L = q * 256 + tid, row = L / UPR, u = L % UPR;
@@ -276,12 +299,14 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
     }
 }
 
-template <int MK, int NJ>
+template <int MK, int NJ, int EDGE>
 __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __restrict__ X,
                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
                                                 int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
                                                 int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
-  cr_lds_body<MK, NJ>(X, Bt, n, S, l, m, spp, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
+  int split, rb;
+  if (!xcd_decode((int)blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  cr_lds_body<MK, NJ, EDGE>(X, Bt, n, S, l, m, spp, nsteps, nsplit, part, split, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -292,14 +317,12 @@ __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __res
 template <int MK, int NJ>
 __device__ __forceinline__ void cr_cols_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ Bt, int64_t P, int64_t n,
-                                                 int l, int64_t nsteps, int nsplit, int nrblocks,
-                                                 typename Pol<MK>::part_t* __restrict__ part, int bid) {
+                                                 int l, int64_t nsteps, int nsplit,
+                                                 typename Pol<MK>::part_t* __restrict__ part, int split, int rb) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
   constexpr int KB = (KL == 1) ? 4 : KL;
-  int split, rb;
-  if (!xcd_decode(bid, nsplit, nrblocks, &split, &rb)) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int mm = lane & 15, g = lane >> 4;
   const int64_t r0 = ((int64_t)rb * 4 + wave) * 64;
@@ -369,7 +392,9 @@ __global__ __launch_bounds__(256) void k_cr_cols(const typename Pol<MK>::T* __re
                                                  const typename Pol<MK>::T* __restrict__ Bt, int64_t P, int64_t n,
                                                  int l, int64_t nsteps, int nsplit, int nrblocks,
                                                  typename Pol<MK>::part_t* __restrict__ part) {
-  cr_cols_body<MK, NJ>(X, Bt, P, n, l, nsteps, nsplit, nrblocks, part, (int)blockIdx.x);
+  int split, rb;
+  if (!xcd_decode((int)blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  cr_cols_body<MK, NJ>(X, Bt, P, n, l, nsteps, nsplit, part, split, rb);
 }
 
 static void cr_geom(tucker_precision prec, const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
@@ -430,9 +455,17 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
   if (v.S == 1)
     hipLaunchKernelGGL((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l,
                        nsteps, nsplit, nrb, (PT*)part);
-  else
-    hipLaunchKernelGGL((k_cr_lds<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n, v.S, l, m,
-                       spp, nsteps, nsplit, nrb, (PT*)part);
+  else {
+    constexpr int VE = 16 / (int)sizeof(T);
+    const int edge = v.S % LdsPol<MK>::KT == 0 ? 0 : (v.S % VE == 0 ? 1 : 2);
+#define TK_CR_LDS(E)                                                                                       \
+  hipLaunchKernelGGL((k_cr_lds<MK, NJ, E>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n, v.S, l, \
+                     m, spp, nsteps, nsplit, nrb, (PT*)part)
+    if (edge == 0) TK_CR_LDS(0);
+    else if (edge == 1) TK_CR_LDS(1);
+    else TK_CR_LDS(2);
+#undef TK_CR_LDS
+  }
   return hipGetLastError();
 }
 
@@ -635,8 +668,9 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
         T* dst = op + (int64_t)j * osj + c;
         if constexpr (MV == 4) {
           if (c + 3 < S) {
-            *reinterpret_cast<f4u_t*>(dst) = f4u_t((float)acc[h * MV + 0][u][v], (float)acc[h * MV + 1][u][v],
-                                                          (float)acc[h * MV + 2][u][v], (float)acc[h * MV + 3][u][v]);
+            const f4u_t o = {(float)acc[h * MV + 0][u][v], (float)acc[h * MV + 1][u][v],
+                             (float)acc[h * MV + 2][u][v], (float)acc[h * MV + 3][u][v]};
+            *reinterpret_cast<f4u_t*>(dst) = o;
             continue;
           }
         }
@@ -925,14 +959,14 @@ hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Batched persistent launches of the product kernels (FP32 storage, scalar
-// loads so any shape and alignment fits one instantiation).
+// Batched persistent launches of the product kernels (FP32 storage; one
+// instantiation per column class fits every shape and address).
 // ---------------------------------------------------------------------------
 void cr_geometry(const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
   cr_geom(TUCKER_FP32, v, nsteps, spp, nrblocks);
 }
-int64_t cr_lds_items(int64_t n, int nsplit) { return (int64_t)((nsplit + 7) / 8) * 8 * ((n + 63) / 64); }
-int64_t cr_cols_items(int64_t n, int nsplit) { return (int64_t)((nsplit + 7) / 8) * 8 * ((n + 255) / 256); }
+int64_t cr_lds_items(int64_t n, int nsplit) { return (int64_t)nsplit * ((n + 63) / 64); }
+int64_t cr_cols_items(int64_t n, int nsplit) { return (int64_t)nsplit * ((n + 255) / 256); }
 int64_t rc_rows_tiles(const View3& v, int* ksplit, int64_t* tpp) {
   *tpp = (v.S + 63) / 64;
   const int64_t ntiles = v.P * *tpp;
@@ -945,11 +979,12 @@ __device__ __forceinline__ void b_fill(const BFill& d, int bid) {
 }
 template <int NJ>
 __device__ __forceinline__ void b_cr_lds(const BCrLds& d, int bid) {
-  cr_lds_body<MF_F32, NJ>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.nrb, d.part, bid);
+  cr_lds_body<MF_F32, NJ, 2>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.part, bid / d.nrb,
+                                bid % d.nrb);
 }
 template <int NJ>
 __device__ __forceinline__ void b_cr_cols(const BCrCols& d, int bid) {
-  cr_cols_body<MF_F32, NJ>(d.X, d.Bt, d.P, d.n, d.l, d.nsteps, d.nsplit, d.nrb, d.part, bid);
+  cr_cols_body<MF_F32, NJ>(d.X, d.Bt, d.P, d.n, d.l, d.nsteps, d.nsplit, d.part, bid / d.nrb, bid % d.nrb);
 }
 __device__ __forceinline__ void b_reduce(const BReduce& d, int bid) {
   reduce_splits_body<float, double>(d.part, d.nsplit, d.nl, d.qsub, d.alpha, d.Y, bid);
@@ -966,29 +1001,23 @@ __device__ __forceinline__ void b_rc_cols(const BRcCols& d, int bid) {
 
 template <int NJ>
 static hipError_t batch_ttm_nj(BatchKind kind, const int* hdr, const void* desc, hipStream_t st) {
-  const dim3 grid(batch_grid(kind)), blk(256);
+#define TK_PERSIST(D, F)                                                                                      \
+  {                                                                                                           \
+    auto kern = k_persist<D, F>;                                                                              \
+    hipLaunchKernelGGL(kern, dim3(resident_grid(kern)), dim3(256), 0, st, hdr, (const D*)desc);               \
+  }                                                                                                           \
+  break
   switch (kind) {
-    case BK_FILL:
-      hipLaunchKernelGGL((k_persist<BFill, b_fill>), grid, blk, 0, st, hdr, (const BFill*)desc);
-      break;
-    case BK_CR_LDS:
-      hipLaunchKernelGGL((k_persist<BCrLds, b_cr_lds<NJ>>), grid, blk, 0, st, hdr, (const BCrLds*)desc);
-      break;
-    case BK_CR_COLS:
-      hipLaunchKernelGGL((k_persist<BCrCols, b_cr_cols<NJ>>), grid, blk, 0, st, hdr, (const BCrCols*)desc);
-      break;
-    case BK_REDUCE:
-      hipLaunchKernelGGL((k_persist<BReduce, b_reduce>), grid, blk, 0, st, hdr, (const BReduce*)desc);
-      break;
-    case BK_RC_ROWS:
-      hipLaunchKernelGGL((k_persist<BRcRows, b_rc_rows<NJ>>), grid, blk, 0, st, hdr, (const BRcRows*)desc);
-      break;
-    case BK_RC_COLS:
-      hipLaunchKernelGGL((k_persist<BRcCols, b_rc_cols<NJ>>), grid, blk, 0, st, hdr, (const BRcCols*)desc);
-      break;
+    case BK_FILL: TK_PERSIST(BFill, b_fill);
+    case BK_CR_LDS: TK_PERSIST(BCrLds, b_cr_lds<NJ>);
+    case BK_CR_COLS: TK_PERSIST(BCrCols, b_cr_cols<NJ>);
+    case BK_REDUCE: TK_PERSIST(BReduce, b_reduce);
+    case BK_RC_ROWS: TK_PERSIST(BRcRows, b_rc_rows<NJ>);
+    case BK_RC_COLS: TK_PERSIST(BRcCols, b_rc_cols<NJ>);
     default:
       return hipErrorInvalidValue;
   }
+#undef TK_PERSIST
   return hipGetLastError();
 }
 
