@@ -294,7 +294,7 @@ def serving_main(args):
     _log("warm")
 
     # timed region: K bursts of every request through the batching server
-    srv.batch_sizes = []
+    srv.batch_sizes, srv.inflight = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -303,6 +303,7 @@ def serving_main(args):
     elapsed = time.perf_counter() - t0
     cap = args.steps * len(jb) / elapsed
     mean_batch = float(np.mean(srv.batch_sizes))
+    mean_inflight = float(np.mean(srv.inflight))
     _log("batched burst: %.1f approximations/s" % cap)
     if args.burst_only:
         print(json.dumps({"metric": METRIC, "value": round(cap, 2), "unit": "approximations/s", "n_gpus": 1,
@@ -337,21 +338,22 @@ def serving_main(args):
         rate = frac * cap
         arr = gen.poisson_arrivals(len(reqs), rate, seed=c["data_seed"])
         jp = jobs(arr)
-        srv.batch_sizes = []
+        srv.batch_sizes, srv.inflight = [], []
         torch.cuda.synchronize()
         out = srv.run(jp, t0=time.perf_counter())
         st = serve.latency_stats(out)
         st.update({"rate_per_s": round(rate, 1), "load": frac, "mean_batch": round(float(np.mean(srv.batch_sizes)), 2),
-                   "batches": len(srv.batch_sizes)})
+                   "batches": len(srv.batch_sizes), "mean_inflight_requests": round(float(np.mean(srv.inflight)), 1)})
         poisson.append({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
         _log("poisson %.1f/s: p50 %.2f ms p99 %.2f ms" % (rate, st["p50_ms"], st["p99_ms"]))
 
-    # dominant product kernel of the batched path: HIP events around each batched phase (direct steps)
+    # dominant product kernel of the batched path: HIP events around each batched phase (direct steps, one
+    # batch on the device at a time so that a phase's events time that phase alone)
     roof = None
     if not args.no_kernel_timing:
         timed = {}
         srv_t = serve.BatchServer(capacity=c["capacity"], q=c["q"], p=c["p"], lclass=c["lclass"],
-                                  ws_bytes=c["ws_bytes"], device=dev, use_graphs=False)
+                                  ws_bytes=c["ws_bytes"], device=dev, use_graphs=False, overlap=False)
         for kern in ("colreduce", "rowcontract"):
             T.timing_enable(kern, capacity=65536)
             torch.cuda.synchronize()
@@ -405,6 +407,7 @@ def serving_main(args):
             "single_approx_per_s": round(single_rate, 2),
             "speedup": round(cap / single_rate, 3),
             "burst_mean_batch": round(mean_batch, 2),
+            "burst_mean_inflight_requests": round(mean_inflight, 1),
             "rel_error_batched": {"mean": float(re_b.mean()), "max": float(re_b.max())},
             "rel_error_single": {"mean": float(re_s.mean()), "max": float(re_s.max())},
             "rel_error_max_abs_diff": float(np.max(np.abs(re_b - re_s))),

@@ -6,10 +6,12 @@ the batch fits the capacity and the workspace budget, writes the batch plan
 (host only) and replays a graph captured once per slot: the library's
 persistent batched kernels run every phase of Algorithm 3 for all requests of
 the batch in one launch each. Requests of different orders go to different
-slot pairs (a plan holds one order). Two slots per order alternate, so the
-next batch is admitted and planned while the previous one runs; a request's
-latency runs from its arrival to the moment its batch's completion event is
-seen by the loop.
+slot pairs (a plan holds one order). Each slot has its own stream and
+workspace, so two batches run on the device at once: the latency-bound small
+SVD and orthonormalisation phases of one overlap the bandwidth-bound mode
+products of the other, and a batch is admitted and planned as soon as a slot
+is free. A request's latency runs from its arrival to the moment its batch's
+completion event is seen by the loop.
 
 A request's descriptor (shape, ranks, seed and device pointers of A, G and the
 U_k) is built once when the request is made (Job.prepare), as a client would
@@ -63,6 +65,7 @@ class Job:
 class _Slot:
     def __init__(self, capacity, order, q, p, lclass, ws_bytes, shift, device):
         self.solver = T.BatchSolver(capacity, order, q, p, lclass, ws_bytes, shift, device)
+        self.stream = torch.cuda.Stream(device=self.solver.device)  # default priority
         self.graph = None
         self.event = None
         self.jobs: List[Job] = []
@@ -87,15 +90,19 @@ class BatchServer:
     """Continuous batching over two graph-replayed slots per tensor order."""
 
     def __init__(self, capacity=256, q=1, p=8, lclass=48, ws_bytes=8 << 30, shift="adaptive", device="cuda",
-                 use_graphs=True, orders=(3,)):
+                 use_graphs=True, orders=(3,), overlap=True):
+        """overlap=False runs every batch on the caller's current stream (one
+        batch on the device at a time), e.g. to time each phase alone."""
         self.device = torch.device(device)
+        self.overlap = overlap
         self.p, self.q, self.lclass, self.shift = p, q, lclass, shift
         self.capacity, self.ws_bytes = capacity, ws_bytes
         self.use_graphs = use_graphs
         self.slots: Dict[int, List[_Slot]] = {}
         for d in orders:
             self._slots_for(d)
-        self.batch_sizes: List[int] = []
+        self.batch_sizes: List[int] = []  # requests per launched batch
+        self.inflight: List[int] = []     # requests on the device right after each launch
 
     def _slots_for(self, d: int) -> List[_Slot]:
         if d not in self.slots:
@@ -112,13 +119,17 @@ class BatchServer:
         return s.ws.numel() - s.table_bytes
 
     def _launch(self, slot: _Slot, jobs: List[Job]):
+        # the plan buffer is free: the slot's previous step has completed
         slot.solver.plan([j.item for j in jobs])
-        if self.use_graphs:
-            slot.graph.replay()
-        else:
-            slot.solver.step()
-        slot.event = torch.cuda.Event()
-        slot.event.record()
+        stream = slot.stream if self.overlap else torch.cuda.current_stream(self.device)
+        stream.wait_stream(torch.cuda.current_stream(self.device))  # inputs written on the caller's stream
+        with torch.cuda.stream(stream):
+            if self.use_graphs:
+                slot.graph.replay()
+            else:
+                slot.solver.step()
+            slot.event = torch.cuda.Event()
+            slot.event.record()
         slot.jobs = jobs
         self.batch_sizes.append(len(jobs))
 
@@ -144,7 +155,9 @@ class BatchServer:
         return batch
 
     def run(self, jobs: Sequence[Job], t0: Optional[float] = None) -> List[Job]:
-        """Serve prepared `jobs` (arrival seconds relative to t0); returns them with .done set."""
+        """Serve prepared `jobs` (arrival seconds relative to t0); returns them with .done set.
+        The results are complete on the device when run returns (every slot's
+        completion event has been seen)."""
         for j in jobs:
             if j.item is None:
                 j.prepare(self.p, self.q)
@@ -172,6 +185,7 @@ class BatchServer:
                     batch = self._admit(waiting, d)
                     self._launch(free[0], batch)
                     busy.append(free[0])
+                    self.inflight.append(sum(len(s.jobs) for s in busy))
                     continue
             if pending and not waiting and not busy:
                 time.sleep(min(200e-6, max(0.0, pending[0].arrival - now)))
