@@ -108,6 +108,15 @@ __device__ __forceinline__ void gaussian4_f32(uint64_t seed, uint32_t mode, uint
   out[3] = r * sn;
 }
 
+// Workgroup barrier that orders LDS only: global loads in flight (a
+// prefetched stage) stay in flight across it, where __syncthreads would wait
+// for every outstanding global access.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Persistent batched launch: the grid's workgroups loop over the work items
 // of all requests in the table (hdr[0] = requests, hdr[1 + b] = first item of
 // request b, hdr[1 + nreq] = total) and run the request's workgroup body F

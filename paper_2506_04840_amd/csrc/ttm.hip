@@ -82,6 +82,11 @@ __device__ __forceinline__ typename Pol<MK>::acc_t mma(const typename Pol<MK>::T
   }
 }
 
+// Wave index within the workgroup, known to the compiler as wave-uniform (a
+// scalar register), so that loop bounds and tile choices derived from it
+// become scalar branches rather than exec-mask loops.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // 16 raw bytes with only 4-byte alignment: global loads and stores of this
 // type are single dwordx4 accesses at any element address, so rows of any
 // length (odd unfolding widths, sub-tensors at odd offsets) take the wide path.
@@ -176,39 +181,56 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
   __shared__ __align__(16) LT xs[2][64][LS];
   __shared__ __align__(16) LT bs[2][16 * NJ][LS];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
   const int64_t r0 = (int64_t)rb * 64;
   const int64_t t0 = nsteps * split / nsplit, t1 = nsteps * (split + 1) / nsplit;
 
   using V4 = float4;  // 16 raw bytes
-  // A stage whose KT columns all lie inside the row (every stage but the
-  // last of each p when KT does not divide S) is read with plain 16-byte
-  // loads; the edge stage guards each group (EDGE 1) or counts its elements
-  // (EDGE 2).
+  // Stage loads. A stage whose KT columns all lie inside the row (every stage
+  // but the last of each p when KT does not divide S), and the edge stage when
+  // a 16-byte group divides S (EDGE 1), are read with unconditional loads:
+  // rows past n and Bt rows past l are clamped (they feed only outputs that
+  // are never written), a stage past the split re-reads its last stage (it is
+  // never computed), and EDGE 1 groups at or past S are clamped to the row's
+  // last group and zeroed in X. Without a branch around a load the compiler
+  // keeps the prefetched stage in flight across the compute. EDGE 2 edge
+  // stages count their elements.
+  // Stage cursor (p, s0 of the next stage to load): one division per split,
+  // then advanced by scalar selects; it stays on the split's last stage.
+  int64_t cp = t0 / spp, cs = (t0 - (t0 / spp) * spp) * KT, cleft = t1 - t0;
+  const int64_t rowlen = spp * KT;
   auto gload = [&](int64_t t, V4 (&xr)[XU], V4 (&br)[BU]) {
-    const int64_t p = t / spp;
-    const int64_t s0 = (t - p * spp) * KT;
-    const bool live = t < t1;
+    const int64_t p = cp, s0 = cs;
+    {
+      const bool adv = cleft > 1;
+      const int64_t ns = cs + KT;
+      const bool wrap = ns == rowlen;
+      cs = adv ? (wrap ? 0 : ns) : cs;
+      cp = adv && wrap ? cp + 1 : cp;
+      cleft = adv ? cleft - 1 : cleft;
+    }
     if (EDGE != 2 || s0 + KT <= S) {
-      const int64_t slim = EDGE == 0 ? KT : S - s0;  // groups at u * VE < slim exist
 #pragma unroll
       for (int q = 0; q < XU; ++q) {
         const int L = q * 256 + tid, row = L / UPR, u = L % UPR;
-        const int64_t i = r0 + row;
-        const f4u_t* src = reinterpret_cast<const f4u_t*>(X + (p * n + i) * S + s0 + (int64_t)u * VE);
-        const f4u_t v = (live && i < n && u * VE < slim) ? *src : f4u_t{0.f, 0.f, 0.f, 0.f};
+        const int64_t i = min<int64_t>(r0 + row, n - 1);
+        const int64_t sg = s0 + (int64_t)u * VE;
+        const bool in = EDGE == 0 || sg < S;
+        f4u_t v = *reinterpret_cast<const f4u_t*>(X + (p * n + i) * S + (in ? sg : S - VE));
+        if (EDGE != 0) v = in ? v : f4u_t{0.f, 0.f, 0.f, 0.f};
         xr[q] = V4{v[0], v[1], v[2], v[3]};
       }
 #pragma unroll
       for (int q = 0; q < BU; ++q) {
-        const int L = q * 256 + tid, j = L / UPR, u = L % UPR;
-        const f4u_t* src = reinterpret_cast<const f4u_t*>(Bt + (int64_t)j * m + p * S + s0 + (int64_t)u * VE);
-        const f4u_t v = (live && j < l && u * VE < slim) ? *src : f4u_t{0.f, 0.f, 0.f, 0.f};
+        const int L = q * 256 + tid, j = min(L / UPR, l - 1), u = L % UPR;
+        const int64_t sg = s0 + (int64_t)u * VE;
+        const f4u_t v = *reinterpret_cast<const f4u_t*>(Bt + (int64_t)j * m + p * S + (EDGE == 0 || sg < S ? sg : S - VE));
         br[q] = V4{v[0], v[1], v[2], v[3]};
       }
       return;
     }
+    const bool live = t < t1;
 #pragma unroll
     for (int q = 0; q < XU; ++q) {
       const int L = q * 256 + tid, row = L / UPR, u = L % UPR;
@@ -273,21 +295,28 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
   };
 
   V4 xa[XU], ba[BU], xb[XU], bb[BU];
-  gload(t0, xa, ba);
-  gload(t0 + 1, xb, bb);
-  lstore(0, xa, ba);
-  __syncthreads();
-  for (int64_t t = t0; t < t1; t += 2) {
-    // stage t in buffer 0, stage t + 1 in registers xb/bb
-    gload(t + 2, xa, ba);
-    compute(0);
-    lstore(1, xb, bb);
-    __syncthreads();
-    if (t + 1 >= t1) break;
-    gload(t + 3, xb, bb);
-    compute(1);
+  if (t0 < t1) {  // a split always holds a stage; the guard keeps every address in range
+    gload(t0, xa, ba);
+    gload(t0 + 1, xb, bb);
     lstore(0, xa, ba);
-    __syncthreads();
+    lds_barrier();
+    // pairs of stages with no exit inside the body (an exit would let the
+    // compiler sink the stage t + 2 loads below it, after the t + 3 loads)
+    int64_t t = t0;
+    for (; t + 1 < t1; t += 2) {
+      // stage t in buffer 0, stage t + 1 in registers xb/bb
+      gload(t + 2, xa, ba);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(0);
+      lstore(1, xb, bb);
+      lds_barrier();
+      gload(t + 3, xb, bb);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(1);
+      lstore(0, xa, ba);
+      lds_barrier();
+    }
+    if (t < t1) compute(0);  // odd stage count: the last stage is in buffer 0
   }
 #pragma unroll
   for (int u = 0; u < NJ; ++u)
@@ -323,7 +352,7 @@ __device__ __forceinline__ void cr_cols_body(const typename Pol<MK>::T* __restri
   using T = typename Po::T;
   constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
   constexpr int KB = (KL == 1) ? 4 : KL;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
   const int64_t r0 = ((int64_t)rb * 4 + wave) * 64;
   if (r0 >= n) return;
@@ -565,7 +594,7 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
   using T = typename Po::T;
   constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
   constexpr int KB = (KL == 1) ? 4 : KL, ROWS = 4 * KB;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
   // ksplit: the 4 waves of a workgroup share one tile and split the n rows
   // (in whole batches), adding their partial tiles in wave order at the end
@@ -620,14 +649,66 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
 #pragma unroll
         for (int u = 0; u < NJ; ++u) acc[tm][u] = mma<MK>(&fa[tm][q], &fb[u][q], acc[tm][u]);
   };
+  // Interior: pairs of whole batches of a full-width tile, read with
+  // unconditional loads (W rows j >= lw are clamped to lw - 1: they feed only
+  // output columns that are never written). With no branch around a load the
+  // compiler keeps the next batch in flight across this batch's MFMAs; the
+  // prefetch past the last pair re-reads that pair. The remaining rows (and
+  // every row of an edge tile) take the guarded path.
+  const bool wide = live && s0 + 64 <= S;
+  const int64_t npair = (WVEC && wide) ? (iw1 - iw0) / (2 * ROWS) : 0;
+  auto ffetch = [&](int64_t i0, T (&fa)[4][KB], T (&fb)[NJ][KB]) {
+    const int64_t iq = i0 + KB * g;
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        T v[MV];
+        *reinterpret_cast<f4u_t*>(v) =
+            *reinterpret_cast<const f4u_t*>(xp + (iq + q) * S + s0 + h * 16 * MV + MV * mm);
+#pragma unroll
+        for (int vv = 0; vv < MV; ++vv) fa[h * MV + vv][q] = v[vv];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const T* wr = W + (int64_t)min(16 * u + mm, lw - 1) * wsj + iq;
+#pragma unroll
+      for (int c = 0; c < (int)(sizeof(T) * KB / 16); ++c)
+        *reinterpret_cast<f4u_t*>(reinterpret_cast<char*>(fb[u]) + 16 * c) =
+            *reinterpret_cast<const f4u_t*>(reinterpret_cast<const char*>(wr) + 16 * c);
+    }
+  };
   T a0[4][KB], b0[NJ][KB], a1[4][KB], b1[NJ][KB];
-  fetch(iw0, a0, b0);
-  fetch(iw0 + ROWS, a1, b1);
-  for (int64_t i0 = iw0; i0 < iw1; i0 += 2 * ROWS) {
-    compute(a0, b0);
-    fetch(i0 + 2 * ROWS, a0, b0);  // zero-filled past the wave's last row
-    compute(a1, b1);
-    fetch(i0 + 3 * ROWS, a1, b1);
+  int64_t ig = iw0;  // first row of the guarded remainder
+  if (npair > 0) {
+    const int64_t last = iw0 + (2 * npair - 2) * ROWS;
+    ffetch(iw0, a0, b0);
+    ffetch(iw0 + ROWS, a1, b1);
+    for (int64_t k = 0; k < npair; ++k) {
+      const int64_t nx = min<int64_t>(iw0 + (2 * k + 2) * ROWS, last);
+      // scheduling fences keep the pipeline order: a batch's loads are issued
+      // right after the MFMAs that free its registers, one batch ahead
+      compute(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      ffetch(nx, a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      ffetch(nx + ROWS, a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    ig = iw0 + 2 * npair * ROWS;
+  }
+  if (ig < iw1) {
+    fetch(ig, a0, b0);
+    fetch(ig + ROWS, a1, b1);
+    for (int64_t i0 = ig; i0 < iw1; i0 += 2 * ROWS) {
+      compute(a0, b0);
+      fetch(i0 + 2 * ROWS, a0, b0);  // zero-filled past the wave's last row
+      compute(a1, b1);
+      fetch(i0 + 3 * ROWS, a1, b1);
+    }
   }
   if (ksplit) {
     using AE = typename Po::part_t;
@@ -704,7 +785,7 @@ __device__ __forceinline__ void rc_cols_body(const typename Pol<MK>::T* __restri
   using Po = Pol<MK>;
   using T = typename Po::T;
   constexpr int KC = Po::KC;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
   const int64_t p0 = (int64_t)bid * 64;
   if (p0 >= P) return;
