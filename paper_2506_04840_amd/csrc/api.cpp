@@ -452,8 +452,11 @@ int batch_colreduce_splits(const View3& v, int l) {
   int64_t nsteps, spp;
   int nrb;
   cr_geometry(v, &nsteps, &spp, &nrb);
-  const int64_t ns = std::max<int64_t>(1, nsteps / (v.S > 1 ? 32 : 8));
-  return (int)std::min<int64_t>(ns, colreduce_splits(v, l));
+  int64_t ns = std::max<int64_t>(1, nsteps / (v.S > 1 ? 32 : 8));
+  ns = std::min<int64_t>(ns, colreduce_splits(v, l));
+  // a multiple of 8 from 8 up: the row blocks of one split then share an XCD
+  // (and its L2 copy of the split's slice of the skinny operand)
+  return (int)(ns >= 8 ? ns / 8 * 8 : ns);
 }
 
 // Fills one phase's descriptor for item b (returns its work items).

@@ -1058,14 +1058,32 @@ int64_t rc_rows_tiles(const View3& v, int* ksplit, int64_t* tpp) {
 __device__ __forceinline__ void b_fill(const BFill& d, int bid) {
   fill_gaussian_body<float>(d.seed, d.mode, 0, d.rows, d.cols, d.ld, 1, d.out, bid);
 }
+// Request-local item -> (split, row block). Workgroups take items round robin
+// and are dealt to the 8 XCDs round robin, so items whose local index agrees
+// mod 8 run on one XCD whatever the request's first item; with a split count
+// that is a multiple of 8 the row blocks of one split share an XCD (and its L2
+// copy of the split's slice of the skinny operand).
+__device__ __forceinline__ void batch_split_rb(int it, int nsplit, int nrb, int* split, int* rb) {
+  if (nsplit % 8 == 0) {
+    const int li = it >> 3;
+    *rb = li % nrb;
+    *split = (li / nrb) * 8 + (it & 7);
+  } else {
+    *split = it / nrb;
+    *rb = it % nrb;
+  }
+}
 template <int NJ>
 __device__ __forceinline__ void b_cr_lds(const BCrLds& d, int bid) {
-  cr_lds_body<MF_F32, NJ, 2>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.part, bid / d.nrb,
-                                bid % d.nrb);
+  int split, rb;
+  batch_split_rb(bid, d.nsplit, d.nrb, &split, &rb);
+  cr_lds_body<MF_F32, NJ, 2>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.part, split, rb);
 }
 template <int NJ>
 __device__ __forceinline__ void b_cr_cols(const BCrCols& d, int bid) {
-  cr_cols_body<MF_F32, NJ>(d.X, d.Bt, d.P, d.n, d.l, d.nsteps, d.nsplit, d.part, bid / d.nrb, bid % d.nrb);
+  int split, rb;
+  batch_split_rb(bid, d.nsplit, d.nrb, &split, &rb);
+  cr_cols_body<MF_F32, NJ>(d.X, d.Bt, d.P, d.n, d.l, d.nsteps, d.nsplit, d.part, split, rb);
 }
 __device__ __forceinline__ void b_reduce(const BReduce& d, int bid) {
   reduce_splits_body<float, double>(d.part, d.nsplit, d.nl, d.qsub, d.alpha, d.Y, bid);

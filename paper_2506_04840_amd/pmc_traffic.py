@@ -23,15 +23,25 @@ import re
 CLASSES = {
     "colreduce": r"tk::k_cr_(lds|cols)<",
     "rowcontract": r"tk::k_rc_(rows|cols)<",
+    # persistent batched kernels: the profiler may print them mangled
+    "batched_colreduce": r"k_persist<tk::BCr(Lds|Cols),|k_persistINS_\d+BCr(Lds|Cols)E",
+    "batched_rowcontract": r"k_persist<tk::BRc(Rows|Cols),|k_persistINS_\d+BRc(Rows|Cols)E",
 }
 COPY = r"__amd_rocclr_copyBuffer"
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
 
 
+SOURCES = ("ttm.hip", "common.hpp", "internal.hpp", "api.cpp")
+
+
 def source_digest() -> str:
-    """sha256 of the mode-product kernel source the counters describe."""
-    with open(os.path.join(CSRC, "ttm.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """sha256 over the sources that shape the product launches the counters
+    describe (kernels, persistent wrapper, launch and split policies)."""
+    h = hashlib.sha256()
+    for name in SOURCES:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def _rows(path: str, pattern: str):

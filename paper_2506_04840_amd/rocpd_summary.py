@@ -1,24 +1,61 @@
-"""Print a kernel summary (calls, total/avg/min/max us, share) from a rocprofv3 rocpd database.
+"""Kernel summary (calls, total/avg/min/max us, share) of a rocprofv3 kernel trace.
 
-usage: python -m paper_2506_04840_amd.rocpd_summary <run_results.db> [top_n]
+Reads a rocpd database (run_results.db) or a kernel-trace CSV
+(run_kernel_trace.csv). Persistent batched kernels are listed as
+k_persist<Desc> (the profiler prints them mangled). The last block gives the
+product kernel classes (launch count and average duration), the figures the
+benchmark's launch-timing hooks report for the same classes.
+
+usage: python -m paper_2506_04840_amd.rocpd_summary <run_results.db | run_kernel_trace.csv> [top_n]
 """
+import collections
+import csv
+import re
 import sqlite3
 import sys
 
+from .pmc_traffic import CLASSES
+
+
+def _rows(path):
+    """(name, duration_ns) of every kernel dispatch."""
+    if path.endswith(".csv"):
+        for r in csv.DictReader(open(path)):
+            yield r["Kernel_Name"], int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    else:
+        c = sqlite3.connect(path)
+        for name, dur in c.execute("select name, duration from kernels"):
+            yield name, int(dur)
+
+
+def _short(name):
+    m = re.match(r"_ZN2tk9k_persistINS_\d+(\w+?)E", name)
+    if m:
+        inner = re.search(r"_ZNS_\d+(b_\w+?)(?:ILi(\d+)E)?E", name)
+        body = inner.group(1) + ("<%s>" % inner.group(2) if inner and inner.group(2) else "") if inner else "?"
+        return "k_persist<%s, %s>" % (m.group(1), body)
+    return name.split("(")[0]
+
 
 def main():
-    db = sys.argv[1]
+    path = sys.argv[1]
     top = int(sys.argv[2]) if len(sys.argv) > 2 else 30
-    c = sqlite3.connect(db)
-    rows = list(c.execute(
-        "select name, count(*), sum(duration), avg(duration), min(duration), max(duration) "
-        "from kernels group by name order by sum(duration) desc"))
-    total = sum(r[2] for r in rows)
+    agg = collections.defaultdict(list)
+    cls = collections.defaultdict(list)
+    for name, dur in _rows(path):
+        agg[_short(name)].append(dur)
+        for k, rx in CLASSES.items():
+            if re.search(rx, name):
+                cls[k].append(dur)
+    total = sum(sum(v) for v in agg.values())
     print("%-70s %7s %12s %10s %10s %10s %6s" % ("kernel", "calls", "total_us", "avg_us", "min_us", "max_us", "pct"))
-    for name, n, tot, avg, mn, mx in rows[:top]:
-        short = name.split("(")[0][:70]
-        print("%-70s %7d %12.1f %10.2f %10.2f %10.2f %6.2f" % (short, n, tot / 1e3, avg / 1e3, mn / 1e3, mx / 1e3,
-                                                              100.0 * tot / total))
+    for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        print("%-70s %7d %12.1f %10.2f %10.2f %10.2f %6.2f" % (name[:70], len(v), sum(v) / 1e3, sum(v) / len(v) / 1e3,
+                                                              min(v) / 1e3, max(v) / 1e3, 100.0 * sum(v) / total))
+    print()
+    print("%-24s %7s %12s %10s" % ("kernel class", "calls", "total_us", "avg_us"))
+    for k, v in cls.items():
+        print("%-24s %7d %12.1f %10.2f" % (k, len(v), sum(v) / 1e3, sum(v) / len(v) / 1e3))
 
 
 if __name__ == "__main__":
