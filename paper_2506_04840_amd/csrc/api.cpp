@@ -239,32 +239,39 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     const int rc = side_ctx(&side);
     if (rc) return rc;
   }
+  // BF16 operands: the products of the last step (the sketch when q = 0) run
+  // on FP32 operands, with FP32 orthonormalisation settings, so the final
+  // subspace carries FP32 rather than BF16 rounding (storage is FP32 either way)
+  auto step_prec = [&](int t) { return prec == TUCKER_BF16 && t == q ? TUCKER_FP32 : prec; };
   hipError_t e;
   // sketch: Y = X_(k) Omega_k, then its CholeskyQR
   e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, true, w.omz,
                            st);
-  if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
-  if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
+  if (e == hipSuccess) e = launch_colreduce(step_prec(0), v, X, w.omz, l, w.part, nsplit, st);
+  if (e == hipSuccess)
+    e = launch_reduce_splits(step_prec(0), w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_set_double(alpha, 0.0, st);
-  if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, prec, w.qt, ows, cseed, 0, st);
+  if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, step_prec(0), w.qt, ows, cseed, 0, st);
   for (int t = 1; t <= q && e == hipSuccess; ++t) {
+    const tucker_precision tp = step_prec(t);
     // small SVD of step t - 1 beside the products of step t
     e = hipEventRecord(side->qr_done, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->qr_done, 0);
     if (e == hipSuccess)
-      e = launch_orth_svd(l, prec, ows, w.sigma, t == 1 ? nullptr : alpha_upd, info, k, t - 1, side->s);
+      e = launch_orth_svd(l, step_prec(t - 1), ows, w.sigma, t == 1 ? nullptr : alpha_upd, info, k, t - 1, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->svd_done, side->s);
     // Z = X_(k)^T Q3 (j-major), Y' = X_(k) Z
-    if (e == hipSuccess) e = launch_rowcontract(prec, v, X, w.qt, 1, n, l, w.omz, true, st);
-    if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
+    if (e == hipSuccess) e = launch_rowcontract(tp, v, X, w.qt, 1, n, l, w.omz, true, st);
+    if (e == hipSuccess) e = launch_colreduce(tp, v, X, w.omz, l, w.part, nsplit, st);
     // Y = (Y' - alpha Q3) J, then its CholeskyQR
     if (e == hipSuccess) e = hipStreamWaitEvent(st, side->svd_done, 0);
     if (e == hipSuccess)
-      e = launch_reduce_splits(prec, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
-    if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, prec, w.qt, ows, cseed, t, st);
+      e = launch_reduce_splits(tp, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
+    if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, tp, w.qt, ows, cseed, t, st);
   }
   // last small SVD on the caller's stream, then Q = Q3 J
-  if (e == hipSuccess) e = launch_orth_svd(l, prec, ows, w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q, st);
+  if (e == hipSuccess)
+    e = launch_orth_svd(l, step_prec(q), ows, w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q, st);
   if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, nullptr, w.q64, st);
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch");
 }

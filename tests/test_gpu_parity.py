@@ -355,3 +355,22 @@ def test_edge_shapes(T):
     for dims, ranks, p, q in cases:
         a, _, _ = gen.random_tucker(dims, tuple(min(r + 1, n) for r, n in zip(ranks, dims)), 0.05, seed=len(dims))
         _compare_solve(_dev(a, torch.float64), a, ranks, p, q, "adaptive", "st", "fp64", check_core=False)
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_solve_bf16_reaches_fp32_error(T, q):
+    """BF16 operands: the last step's products run on FP32 operands, so the
+    final subspace, the reconstruction and the relative error match the FP64
+    oracle to the FP32 tolerance although the earlier passes round to BF16."""
+    a, _, _ = gen.random_tucker((150, 140, 130), (12, 12, 12), 1e-4, seed=7)
+    x = _dev(a, torch.float32)
+    a32 = _np(x)
+    res = orc.randomized_hosvd(a32, (12, 12, 12), 8, q, shift="adaptive", variant="st", seed=3)
+    re_o = orc.rel_error(a32, res)
+    G, U, info = T.rsthosvd(x, (12, 12, 12), p=8, q=q, seed=3, precision="bf16")
+    torch.cuda.synchronize()
+    g, us = _np(G), [_np(u) for u in U]
+    rec = reconstruct(g, us)
+    na = np.linalg.norm(a32)
+    assert np.linalg.norm(rec - reconstruct(res.core, res.factors)) / na <= 1e-5
+    assert abs(np.linalg.norm(a32 - rec) / na - re_o) <= 1e-6
