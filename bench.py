@@ -88,6 +88,33 @@ def measured_traffic(kernel, workload):
     return rec["traffic_bytes_per_launch"]
 
 
+def copy_bandwidth(dev, nbytes=1 << 30, reps=5):
+    """HBM bandwidth of a plain device-to-device copy (GB/s, read + write
+    bytes), the measured ceiling a streaming kernel is compared with."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbs
+
+
+def step_percentiles(events):
+    """p10 / p50 / p90 of per-step milliseconds from consecutive event pairs."""
+    import numpy as np
+    ms = np.array([a.elapsed_time(b) for a, b in zip(events[:-1], events[1:])])
+    return {"p10": round(float(np.percentile(ms, 10)), 4), "p50": round(float(np.percentile(ms, 50)), 4),
+            "p90": round(float(np.percentile(ms, 90)), 4)}
+
+
 def reconstruct_torch(G, U):
     import torch
     t = G
@@ -168,14 +195,18 @@ def main():
         solver.run(A)
     torch.cuda.synchronize()
 
-    # timed region: K whole solves
+    # timed region: K whole solves (events between solves give the per-step spread, no synchronisation)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    evs[0].record()
+    for i in range(args.steps):
         solver.run(A)
+        evs[i + 1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = 1e3 * elapsed / args.steps
+    spread = step_percentiles(evs)
 
     # relative error of the result (measurement, outside the timed region)
     G, U = solver.G.double(), [u.double() for u in solver.U]
@@ -206,6 +237,9 @@ def main():
             roof["traffic_unit"] = "bytes/launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         roof["kernel"] = kern
         roof["per_step_ms"] = {k: round(v["ms"] / args.steps, 4) for k, v in timed.items()}
+        if roof["bound"] == "hbm":
+            roof["copy_gbs"] = round(copy_bandwidth(dev), 1)
+            roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_gbs"], 4)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -224,6 +258,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_spread": spread,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -368,6 +403,9 @@ def serving_main(args):
         kern = max(timed, key=lambda k: timed[k]["ms"])
         roof = _roof_from_timing(timed[kern])
         roof["kernel"] = "batched " + kern
+        if roof["bound"] == "hbm":
+            roof["copy_gbs"] = round(copy_bandwidth(dev), 1)
+            roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_gbs"], 4)
         roof["traffic"] = measured_traffic("batched_" + kern, SERVING)
         if roof["traffic"] is not None:
             roof["traffic_unit"] = "bytes/launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
