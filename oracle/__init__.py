@@ -10,7 +10,8 @@ Contents:
              defines the Gaussian test matrices Omega_k.
   tensor   - mode-k unfolding, folding, mode-k product, Frobenius norms.
   rhosvd   - the method itself (shifted randomized T-HOSVD and ST-HOSVD, the
-             unshifted model, the deterministic HOSVD) step by step in FP64.
+             unshifted model, the deterministic HOSVD, the power count chosen
+             per mode by the per-vector-error test) step by step in FP64.
 
 Parity status: every function is pinned by tests under tests/ against values
 the paper prints, closed forms, invariants or brute force (test_oracle_*.py

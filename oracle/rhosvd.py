@@ -9,6 +9,8 @@ Follows, in the paper's order and notation:
     shift "adaptive".
   * Appendix Algorithm A.1 (the unshifted randomized model): the same routine
     with shift "none" (alpha stays 0).
+  * Algorithm 4 (Algorithm 3 with the power count of each mode chosen by the
+    per-vector-error criterion): ``randomized_sthosvd_pve``.
 
 Per mode k, on X = A (variant t) or X = the partially contracted core
 (variant st, dims r_1..r_{k-1}, n_k..n_d):
@@ -137,6 +139,72 @@ def randomized_hosvd(a: np.ndarray, ranks: Sequence[int], p: int, q: int, *,
         g = core_step(g, k, u_k)
         logs.append(ModeLog(l_k, m_k, alphas, sigmas))
     return Result(g, factors, logs)
+
+
+@dataclasses.dataclass
+class PveResult(Result):
+    qs: List[int] = dataclasses.field(default_factory=list)   # power steps taken per mode
+
+
+def pve_converged(sig_t: np.ndarray, sig_hat: np.ndarray, r: int, tol: float) -> bool:
+    """Algorithm 4's stopping test: the largest change of the first r_k
+    estimates sigma_t(i) = Sigma(i,i) + alpha_{t-1} since the previous step is
+    at most tol times the (r_k+1)-th estimate (the l_k-th when l_k = r_k)."""
+    ref = sig_t[min(r, len(sig_t) - 1)]
+    return float(np.max(np.abs(sig_t[:r] - sig_hat[:r]))) <= tol * ref
+
+
+def randomized_sthosvd_pve(a: np.ndarray, ranks: Sequence[int], p: int, q_max: int, tol: float, *,
+                           shift: str = "adaptive", seed: int = 1,
+                           omega: Optional[OmegaProvider] = None) -> PveResult:
+    """Algorithm 4: shifted randomized ST-HOSVD whose power count q_k per mode
+    stops at the first t <= q_max that passes ``pve_converged`` (the test comes
+    before the shift update; sigma-hat starts at zero, so t = 1 passes only for
+    an unbounded tol). shift "none" keeps alpha at zero.
+
+    Readings: the printed test's right-hand side is garbled; it is read as tol
+    times sigma_t(r_k + 1), the first discarded estimate, and sigma_t(l_k) stands
+    in when l_k = r_k. q_max >= 1."""
+    if shift not in ("adaptive", "none"):
+        raise ValueError("bad shift")
+    if q_max < 1:
+        raise ValueError("q_max must be at least 1")
+    a = np.asarray(a, dtype=np.float64)
+    g = a.copy()
+    factors: List[np.ndarray] = []
+    logs: List[ModeLog] = []
+    qs: List[int] = []
+    for k in range(a.ndim):
+        n_k = g.shape[k]
+        m_k = g.size // n_k
+        r_k = int(ranks[k])
+        if not (1 <= r_k <= n_k and r_k <= m_k):
+            raise ValueError("infeasible rank at mode %d" % k)
+        l_k = sketch_width(r_k, p, n_k, m_k)
+        om = omega(k, m_k, l_k) if omega is not None else gaussian_omega(seed, k, m_k, l_k)
+        qm, s = svd_econ(sketch(g, k, om))
+        alpha = 0.0
+        sig_hat = np.zeros(l_k)
+        alphas, sigmas = [alpha], [s]
+        q_k = 0
+        for _t in range(q_max):
+            q_k += 1
+            qm, s = svd_econ(shifted_power(g, k, qm, alpha))
+            sig_t = s + alpha
+            sigmas.append(s)
+            if pve_converged(sig_t, sig_hat, r_k, tol):
+                alphas.append(alpha)
+                break
+            if shift == "adaptive":
+                alpha = shift_update(alpha, s[l_k - 1])
+            alphas.append(alpha)
+            sig_hat = sig_t
+        u_k = sign_fix(qm[:, :r_k])
+        factors.append(u_k)
+        g = core_step(g, k, u_k)
+        logs.append(ModeLog(l_k, m_k, alphas, sigmas))
+        qs.append(q_k)
+    return PveResult(g, factors, logs, qs)
 
 
 def hosvd_full(a: np.ndarray, ranks: Sequence[int], variant: str = "st") -> Result:

@@ -242,3 +242,75 @@ def test_table3_tensor_c_singular_values():
     for k in range(3):
         s = np.linalg.svd(unfold(a, k), compute_uv=False)
         np.testing.assert_allclose(s, v, rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------------------- Algorithm 4 (PVE-controlled q)
+
+from oracle.rhosvd import pve_converged, randomized_sthosvd_pve  # noqa: E402
+
+
+def test_pve_stopping_test_by_hand():
+    """The stopping test on numbers worked out by hand: r = 2 estimates, the
+    third is the reference (tol times sigma_t(r + 1))."""
+    sig_t = np.array([10.0, 5.0, 1.0, 0.2])
+    sig_hat = np.array([9.9, 5.05, 0.5, 0.1])
+    # largest change among the first two estimates: |10 - 9.9| = 0.1; reference sigma_t(3) = 1.0
+    assert pve_converged(sig_t, sig_hat, 2, 0.1 + 1e-15)
+    assert not pve_converged(sig_t, sig_hat, 2, 0.09)
+    # the third estimate (change 0.5) is not among the first r = 2
+    assert pve_converged(sig_t, sig_hat, 2, 0.11)
+    # l = r: the last estimate stands in for the reference
+    assert pve_converged(sig_t[:2], sig_hat[:2], 2, 0.1 / 5.0 + 1e-15)
+    assert not pve_converged(sig_t[:2], sig_hat[:2], 2, 0.019)
+    # sigma-hat = 0 (first step) passes only when tol >= sigma_1 / sigma_{r+1}
+    assert not pve_converged(sig_t, np.zeros(4), 2, 9.99)
+    assert pve_converged(sig_t, np.zeros(4), 2, 10.0)
+
+
+@pytest.mark.parametrize("shift", ["adaptive", "none"])
+def test_pve_tol_zero_is_algorithm_3_with_q_max(shift):
+    """tol = 0 never stops early (the estimates of a noisy tensor keep moving):
+    q_k = q_max and every result equals Algorithm 3 with q = q_max."""
+    a, _, _ = random_tucker((24, 22, 20), (4, 5, 3), 1e-2, seed=31)
+    res = randomized_sthosvd_pve(a, (4, 5, 3), 4, 4, 0.0, shift=shift, seed=2)
+    ref = randomized_hosvd(a, (4, 5, 3), 4, 4, shift=shift, variant="st", seed=2)
+    assert res.qs == [4, 4, 4]
+    assert np.array_equal(res.core, ref.core)
+    for u, v in zip(res.factors, ref.factors):
+        assert np.array_equal(u, v)
+    for lp, lr in zip(res.logs, ref.logs):
+        assert lp.alphas == lr.alphas
+
+
+def test_pve_unbounded_tol_is_algorithm_3_with_one_step():
+    """tol = inf stops after the first power step: q_k = 1 and the result
+    equals Algorithm 3 with q = 1."""
+    a, _, _ = random_tucker((24, 22, 20), (4, 5, 3), 1e-2, seed=32)
+    res = randomized_sthosvd_pve(a, (4, 5, 3), 4, 6, np.inf, seed=2)
+    ref = randomized_hosvd(a, (4, 5, 3), 4, 1, variant="st", seed=2)
+    assert res.qs == [1, 1, 1]
+    assert np.array_equal(res.core, ref.core)
+
+
+def test_pve_first_mode_steps_fall_with_tol():
+    """Mode 1 runs the same iteration for every tol (only the stop differs), so
+    its power count cannot grow as tol grows; a tighter tol never lowers the RE
+    reached by much."""
+    a, _, _ = random_tucker((40, 36, 32), (6, 6, 6), 5e-2, seed=33)
+    prev = None
+    for tol in (1e-4, 1e-3, 1e-2, 1e-1, 0.5, 2.0):
+        res = randomized_sthosvd_pve(a, (6, 6, 6), 3, 40, tol, seed=5)
+        if prev is not None:
+            assert res.qs[0] <= prev
+        prev = res.qs[0]
+        assert 1 <= min(res.qs) and max(res.qs) <= 40
+
+
+def test_pve_reaches_the_q_max_error():
+    """With a clear gap, tol = 0.5 stops after few steps at the relative error
+    of q_max steps (the paper's observation for its tensors)."""
+    a, _, _ = random_tucker((40, 36, 32), (6, 6, 6), 1e-3, seed=34)
+    res = randomized_sthosvd_pve(a, (6, 6, 6), 4, 20, 0.5, seed=7)
+    full = randomized_hosvd(a, (6, 6, 6), 4, 20, variant="st", seed=7)
+    assert max(res.qs) <= 5
+    assert abs(rel_error(a, res) - rel_error(a, full)) <= 1e-6 * rel_error(a, full)
