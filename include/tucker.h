@@ -50,6 +50,7 @@ extern "C" {
 
 #define TUCKER_MAX_ORDER 8
 #define TUCKER_MAX_Q 16 /* largest power count q */
+#define TUCKER_MAX_Q_PVE 1000 /* largest q_max of tucker_rsthosvd_pve */
 #define TUCKER_MAX_L 64 /* largest sketch width l_k = min(r_k + p, n_k, m_k) */
 
 typedef enum {
@@ -194,6 +195,28 @@ int tucker_rthosvd(const tucker_shape* shape, const void* A, const int64_t* rank
 int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
                     tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                     tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Algorithm 4: shifted randomized ST-HOSVD whose power count q_k is chosen per
+ * mode by the per-vector-error test (Appendix, PVE accuracy control). Mode k
+ * runs power steps t = 1, 2, ..., q_max and stops after the first step whose
+ * estimates sigma_t(i) = Sigma_t(i,i) + alpha_{t-1} moved, for i <= r_k, by at
+ * most tol * sigma_t(r_k + 1) since the previous step (sigma_t(l_k) when
+ * l_k = r_k; the estimates of the step before the first are zero). The test
+ * comes before that step's shift update, which is then skipped. With FP32
+ * (and BF16) operands a change below 1e-6 sigma_t(1), the rounding level of
+ * the iterate, counts as none (FP64: the test as printed). q_used[k]
+ * receives q_k (host array, d entries). The remaining arguments are those of
+ * tucker_rsthosvd (workspace tucker_workspace_bytes(..., min(q_max, 16),
+ * prec, 1)); info logs the first TUCKER_MAX_Q steps.
+ * Synchronisation: the next step's launch depends on this step's test, so the
+ * call reads a 4-byte device flag after every power step and synchronises
+ * `stream` that often; it returns with the solve complete.
+ * BF16 operands: every power step runs on FP32 operands (any step may be the
+ * last). EINVAL for q_max outside 1..TUCKER_MAX_Q_PVE, tol < 0 or NaN, or a
+ * null q_used; otherwise as tucker_rsthosvd. */
+int tucker_rsthosvd_pve(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q_max,
+                        double tol, tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                        tucker_info* info, int32_t* q_used, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- Launch timing (measurement only) ---------------------------------------
  * When a kernel class is enabled, every launch of that class records a pair

@@ -157,6 +157,8 @@ struct SolveWs {
   double* alpha;
   double* normpart;
   void* orth;
+  double* sig_hat;  // per-vector-error estimates of the previous step (Algorithm 4)
+  int* stop;        // its stopping flag
 };
 
 size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveWs* w) {
@@ -179,6 +181,8 @@ size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveW
   w->alpha = (double*)take(TUCKER_MAX_ORDER * 8);
   w->normpart = (double*)take(1024 * 8);
   w->orth = take(pl.orth_bytes);
+  w->sig_hat = (double*)take(TUCKER_MAX_L * 8);
+  w->stop = (int*)take(64);
   return off;
 }
 
@@ -276,11 +280,59 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch");
 }
 
+// Algorithm 4 for mode k: the same steps as mode_factor with q_max power
+// steps at most; the small SVD of each step evaluates the per-vector-error
+// test and the host reads its flag (4 bytes, one stream synchronisation per
+// step) before launching the next step. No side stream: the next step's
+// launch depends on this step's SVD. *q_used = steps taken.
+int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol, tucker_shift shift, uint64_t seed,
+                    tucker_precision prec, tucker_info* info, const SolveWs& w, hipStream_t st, int32_t* q_used) {
+  const View3 v = pl.v[k];
+  const int l = pl.l[k];
+  const int64_t n = v.n, m = pl.m[k];
+  const int nsplit = colreduce_splits(v, l);
+  const OrthWs ows = carve_orth(w.orth, n, l);
+  const uint64_t cseed = completion_seed(seed, k);
+  double* alpha = w.alpha + k;
+  double* alpha_upd = shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr;
+  // BF16 operands: FP32 products for the steps that may be the last (as mode_factor's last step)
+  const tucker_precision tp = prec == TUCKER_BF16 ? TUCKER_FP32 : prec;
+  // FP32 iterates: estimate changes below 1e-6 sigma_t(1) are rounding (the
+  // level below which the small SVD already treats directions as noise)
+  const SvdPve pve{(int)pl.r[k], tol, tp == TUCKER_FP64 ? 0.0 : 1e-6, alpha, w.sig_hat, w.stop};
+  hipError_t e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l,
+                                      true, w.omz, st);
+  if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
+  if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
+  if (e == hipSuccess) e = launch_set_double(alpha, 0.0, st);
+  if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, prec, w.qt, ows, cseed, 0, st);
+  if (e == hipSuccess) e = launch_orth_svd(l, prec, ows, w.sigma, nullptr, info, k, 0, st, &pve);
+  int t = 0;
+  while (e == hipSuccess && t < q_max) {
+    ++t;
+    // Z = X_(k)^T Q3, Y' = X_(k) Z, Y = (Y' - alpha Q3) J (reading R1), CholeskyQR, small SVD + test
+    e = launch_rowcontract(tp, v, X, w.qt, 1, n, l, w.omz, true, st);
+    if (e == hipSuccess) e = launch_colreduce(tp, v, X, w.omz, l, w.part, nsplit, st);
+    if (e == hipSuccess) e = launch_reduce_splits(tp, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
+    if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, tp, w.qt, ows, cseed, t, st);
+    if (e == hipSuccess) e = launch_orth_svd(l, tp, ows, w.sigma, alpha_upd, info, k, t, st, &pve);
+    int halt = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&halt, w.stop, sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && halt) break;
+  }
+  if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, nullptr, w.q64, st);
+  *q_used = t;
+  return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch (per-vector-error)");
+}
+
 int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
           tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
-          void* ws, size_t ws_bytes, hipStream_t st) {
+          void* ws, size_t ws_bytes, hipStream_t st, double pve_tol = -1.0, int32_t* q_used = nullptr) {
   Plan pl;
-  int rc = make_plan(shape, ranks, p, q, prec, st_variant, &pl);
+  // with the per-vector-error test q is the largest power count; the plan (and
+  // the per-step logs) cover the first TUCKER_MAX_Q steps
+  int rc = make_plan(shape, ranks, p, pve_tol >= 0.0 ? std::min<int32_t>(q, TUCKER_MAX_Q) : q, prec, st_variant, &pl);
   if (rc) return rc;
   if (shift != TUCKER_SHIFT_ADAPTIVE && shift != TUCKER_SHIFT_NONE) return fail(TUCKER_EINVAL, "bad shift mode");
   if (A == nullptr || G == nullptr || U == nullptr) return fail(TUCKER_EINVAL, "null tensor, core or factor array");
@@ -306,7 +358,8 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
 
   for (int k = 0; k < pl.d; ++k) {
     const void* Xk = st_variant ? X : A;
-    rc = mode_factor(pl, k, Xk, q, shift, seed, prec, info, w, st);
+    rc = pve_tol >= 0.0 ? mode_factor_pve(pl, k, Xk, q, pve_tol, shift, seed, prec, info, w, st, q_used + k)
+                        : mode_factor(pl, k, Xk, q, shift, seed, prec, info, w, st);
     if (rc) return rc;
     e = launch_signfix(prec, w.q64, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], w.ut, st);
     if (e != hipSuccess) return dev_check(e, "sign rule launch");
@@ -795,6 +848,16 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
                     tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                     tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
   return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream);
+}
+
+int tucker_rsthosvd_pve(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q_max,
+                        double tol, tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                        tucker_info* info, int32_t* q_used, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (q_max < 1 || q_max > TUCKER_MAX_Q_PVE)
+    return fail(TUCKER_EINVAL, "q_max = %d outside 1..%d", q_max, TUCKER_MAX_Q_PVE);
+  if (!(tol >= 0.0)) return fail(TUCKER_EINVAL, "tol must be >= 0 (got %g)", tol);
+  if (q_used == nullptr) return fail(TUCKER_EINVAL, "q_used is null");
+  return solve(true, shape, A, ranks, p, q_max, shift, seed, prec, G, U, info, ws, ws_bytes, stream, tol, q_used);
 }
 
 size_t tucker_batch_plan_bytes(int32_t capacity, int32_t order, int32_t q) {

@@ -92,8 +92,24 @@ hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucke
 // [mode][step], and status bits are or-ed into info->flags.
 // `prec` is the precision the iterate's products ran in (sets the rotation
 // thresholds).
+// Per-vector-error stopping test of Algorithm 4, evaluated by the small SVD of
+// step `step` (nullptr: off). At step 0 it clears sig_hat and *stop. At step
+// t >= 1 it forms sigma_t(i) = Sigma(i,i) + alpha_{t-1} (alpha_{t-1} read from
+// alpha_prev), sets *stop when max_{i < r} |sigma_t(i) - sig_hat(i)| <= tol *
+// sigma_t(min(r, l - 1)) (0-based), skips the shift update then, and else
+// stores sigma_t into sig_hat.
+// floor: changes below floor * sigma_t(1) count as none (the rounding level of
+// an iterate formed from FP32 products; 0 for FP64, the test as printed).
+struct SvdPve {
+  int r;
+  double tol;
+  double floor;
+  const double* alpha_prev;
+  double* sig_hat;  // l doubles
+  int* stop;
+};
 hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
-                           tucker_info* info, int mode, int step, hipStream_t st);
+                           tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve = nullptr);
 // Q = Q3 Wm to q_out (n x l, `prec` storage), qt (j-major l x n, `prec`
 // storage) and q64 (n x l, FP64), each when not nullptr.
 hipError_t launch_orth_rotate(int64_t n, int l, const OrthWs& ws, tucker_precision prec, void* q_out, void* qt,

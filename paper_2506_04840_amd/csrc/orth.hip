@@ -580,7 +580,9 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
                                                    const int* __restrict__ status, double tol, double negl,
                                                    double* __restrict__ Wm, double* __restrict__ sigma,
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
-                                                   int mode, int step, int bid) {
+                                                   int mode, int step, int pve_r, double pve_tol, double pve_floor,
+                                                   const double* __restrict__ alpha_prev, double* __restrict__ sig_hat,
+                                                   int* __restrict__ stop, int bid) {
   __shared__ double A[kMaxL][OR_LS];  // A[a][x] = column a of R^T = row a of R
   __shared__ double J[kMaxL][OR_LS];  // J[a][x] = column a of the rotation
   __shared__ double sv[kMaxL];
@@ -717,10 +719,26 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
     for (int j = tid; j < l; j += 256) sigma[j] = sv[perm[j]];
   if (tid == 0) {
     const double s1 = sv[perm[0]], sl = sv[perm[l - 1]];
+    // per-vector-error test (Algorithm 4): before the shift update
+    bool halt = false;
+    if (pve_tol >= 0.0) {
+      if (step == 0) {
+        for (int i = 0; i < l; ++i) sig_hat[i] = 0.0;
+        *stop = 0;
+      } else {
+        const double ap = alpha_prev != nullptr ? *alpha_prev : 0.0;
+        double mx = 0.0;
+        for (int i = 0; i < pve_r; ++i) mx = fmax(mx, fabs(sv[perm[i]] + ap - sig_hat[i]));
+        halt = mx <= fmax(pve_tol * (sv[perm[min(pve_r, l - 1)]] + ap), pve_floor * (sv[perm[0]] + ap));
+        *stop = halt ? 1 : 0;
+        if (!halt)
+          for (int i = 0; i < l; ++i) sig_hat[i] = sv[perm[i]] + ap;
+      }
+    }
     double al = 0.0;
     if (alpha != nullptr) {
       al = *alpha;
-      if (sl > al) al = 0.5 * (sl + al);
+      if (sl > al && !halt) al = 0.5 * (sl + al);
       *alpha = al;
     }
     if (info != nullptr && mode >= 0 && mode < TUCKER_MAX_ORDER && step >= 0 && step <= TUCKER_MAX_Q) {
@@ -739,8 +757,11 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
                                                    const int* __restrict__ status, double tol, double negl,
                                                    double* __restrict__ Wm, double* __restrict__ sigma,
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
-                                                   int mode, int step) {
-  small_svd_body<RPT>(Rg, l, status, tol, negl, Wm, sigma, alpha, info, mode, step, (int)blockIdx.x);
+                                                   int mode, int step, int pve_r, double pve_tol, double pve_floor,
+                                                   const double* __restrict__ alpha_prev, double* __restrict__ sig_hat,
+                                                   int* __restrict__ stop) {
+  small_svd_body<RPT>(Rg, l, status, tol, negl, Wm, sigma, alpha, info, mode, step, pve_r, pve_tol, pve_floor,
+                      alpha_prev, sig_hat, stop, (int)blockIdx.x);
 }
 
 // Q = Q3 Wm, written in the storage precision (and optionally in FP64).
@@ -818,13 +839,16 @@ hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucke
 
 template <int RPT>
 static void svd_launch(int l, const OrthWs& ws, double tol, double negl, double* sigma, double* alpha,
-                       tucker_info* info, int mode, int step, hipStream_t st) {
+                       tucker_info* info, int mode, int step, const SvdPve& pv, hipStream_t st) {
   hipLaunchKernelGGL((k_small_svd<RPT>), dim3(1), dim3(256), 0, st, (const double*)ws.R, l, (const int*)ws.status,
-                     tol, negl, ws.Wm, sigma, alpha, info, mode, step);
+                     tol, negl, ws.Wm, sigma, alpha, info, mode, step, pv.r, pv.tol, pv.floor, pv.alpha_prev,
+                     pv.sig_hat, pv.stop);
 }
 
 hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
-                           tucker_info* info, int mode, int step, hipStream_t st) {
+                           tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve) {
+  const SvdPve off{0, -1.0, 0.0, nullptr, nullptr, nullptr};
+  const SvdPve& pv = pve != nullptr ? *pve : off;
   // Rotation thresholds by the precision the iterate was formed in: FP64
   // converges to l u; FP32 and BF16 iterates carry rounding noise near 1e-7
   // and 1e-3 of their norm, which bounds what their singular values and
@@ -833,14 +857,14 @@ hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, doubl
   const double tol = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-8 : 1e-7;
   const double negl = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-6 : 1e-4;
   switch ((l + 7) / 8) {
-    case 1: svd_launch<1>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
-    case 2: svd_launch<2>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
-    case 3: svd_launch<3>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
-    case 4: svd_launch<4>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
-    case 5: svd_launch<5>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
-    case 6: svd_launch<6>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
-    case 7: svd_launch<7>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
-    case 8: svd_launch<8>(l, ws, tol, negl, sigma, alpha, info, mode, step, st); break;
+    case 1: svd_launch<1>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 2: svd_launch<2>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 3: svd_launch<3>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 4: svd_launch<4>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 5: svd_launch<5>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 6: svd_launch<6>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 7: svd_launch<7>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 8: svd_launch<8>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -978,7 +1002,8 @@ __device__ __forceinline__ void b_pass(const BPass& d, int bid) {
 }
 template <int RPT>
 __device__ __forceinline__ void b_svd(const BSvd& d, int bid) {
-  small_svd_body<RPT>(d.Rg, d.l, d.status, d.tol, d.negl, d.Wm, d.sigma, d.alpha, d.info, d.mode, d.step, bid);
+  small_svd_body<RPT>(d.Rg, d.l, d.status, d.tol, d.negl, d.Wm, d.sigma, d.alpha, d.info, d.mode, d.step, 0, -1.0,
+                      0.0, nullptr, nullptr, nullptr, bid);
 }
 __device__ __forceinline__ void b_rotate(const BRotate& d, int bid) {
   rotate_body<float>(d.Q3, d.n, d.l, d.Wm, (float*)nullptr, (float*)nullptr, d.q64, bid);

@@ -83,6 +83,27 @@ def test_error_codes_before_any_launch():
     assert rc == -1
 
 
+def test_pve_entry_point_validates_on_the_host():
+    """Algorithm 4's entry point rejects a bad q_max, tol or q_used before any
+    device work."""
+    import math
+    from paper_2506_04840_amd import _lib
+    L = _lib.lib
+    s = _lib._shape((10, 10, 10))
+    r = (ctypes.c_int64 * 3)(2, 2, 2)
+    qu = (ctypes.c_int32 * 3)()
+    p16 = ctypes.c_void_p(16)
+    u = (ctypes.c_void_p * 3)(16, 16, 16)
+    args = lambda qmax, tol, q: (ctypes.byref(s), p16, r, 2, qmax, ctypes.c_double(tol), 0, 1, 1, p16, u, None, q,
+                                 p16, 1 << 30, None)
+    assert L.tucker_rsthosvd_pve(*args(0, 0.5, qu)) == -1
+    assert L.tucker_rsthosvd_pve(*args(_lib.MAX_Q_PVE + 1, 0.5, qu)) == -1
+    assert L.tucker_rsthosvd_pve(*args(5, -0.1, qu)) == -1
+    assert L.tucker_rsthosvd_pve(*args(5, math.nan, qu)) == -1
+    assert L.tucker_rsthosvd_pve(*args(5, 0.5, None)) == -1
+    assert "q_max" in L.tucker_status_string(L.tucker_rsthosvd_pve(*args(0, 0.5, qu))).decode()
+
+
 def test_python_binding_rejects_host_tensors():
     import torch
     from paper_2506_04840_amd import _lib

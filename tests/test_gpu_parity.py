@@ -374,3 +374,69 @@ def test_solve_bf16_reaches_fp32_error(T, q):
     na = np.linalg.norm(a32)
     assert np.linalg.norm(rec - reconstruct(res.core, res.factors)) / na <= 1e-5
     assert abs(np.linalg.norm(a32 - rec) / na - re_o) <= 1e-6
+
+
+# --------------------------------------------------------------- Algorithm 4 (PVE-controlled q)
+
+def _pve_ratios(res, ranks):
+    """Per mode, the tol each power step needed to stop there (from the oracle's
+    logs): max_{i<r} |sigma_t(i) - sigma_{t-1}(i)| / sigma_t(r + 1)."""
+    out = []
+    for k, lg in enumerate(res.logs):
+        r = ranks[k]
+        prev = np.zeros(lg.l)
+        rat = []
+        for t in range(1, len(lg.sigmas)):
+            sig = lg.sigmas[t] + lg.alphas[t - 1]
+            rat.append(np.max(np.abs(sig[:r] - prev[:r])) / sig[min(r, lg.l - 1)])
+            prev = sig
+        out.append(rat)
+    return out
+
+
+@pytest.mark.parametrize("target", ["zero", "mid", "inf"])
+def test_solve_pve_fp64_matches_oracle(T, target):
+    """Algorithm 4 in FP64 against the oracle: the same power counts q_k (tol
+    chosen away from every step's threshold, where rounding could flip the
+    decision) and the reconstruction within 1e-10."""
+    a, _, _ = gen.random_tucker((33, 45, 28), (5, 6, 4), 0.05, seed=21)
+    ranks, p, qmax = (5, 6, 4), 6, 12
+    if target == "zero":
+        tol = 0.0
+    elif target == "inf":
+        tol = float("inf")
+    else:
+        probe = orc.randomized_sthosvd_pve(a, ranks, p, qmax, 0.0, seed=1)
+        rats = _pve_ratios(probe, ranks)
+        tol = float(np.sqrt(rats[0][1] * rats[0][2]))  # mode 1 stops at its third step
+        for _ in range(20):
+            res = orc.randomized_sthosvd_pve(a, ranks, p, qmax, tol, seed=1)
+            if all(abs(x / tol - 1.0) > 1e-6 for rr in _pve_ratios(res, ranks) for x in rr):
+                break
+            tol *= 1.37
+    res = orc.randomized_sthosvd_pve(a, ranks, p, qmax, tol, seed=1)
+    G, U, info, qs = T.rsthosvd_pve(_dev(a, torch.float64), ranks, p=p, q_max=qmax, tol=tol, seed=1,
+                                    precision="fp64")
+    torch.cuda.synchronize()
+    assert qs == res.qs, (qs, res.qs, tol)
+    na = np.linalg.norm(a)
+    d = np.linalg.norm(reconstruct(_np(G), [_np(u) for u in U]) - reconstruct(res.core, res.factors)) / na
+    assert d <= 1e-10, d
+    for k, lg in enumerate(res.logs):
+        for t in range(min(qs[k], 16) + 1):
+            assert abs(info["alpha"][k][t] - lg.alphas[t]) <= 1e-10 * lg.sigmas[t][0], (k, t)
+
+
+def test_solve_pve_fp32_reaches_oracle_error(T):
+    """FP32 storage, tol = 0.5 (the paper's recommended setting). Estimate
+    changes below the FP32 iterate's rounding level count as none, so a mode
+    may stop before the FP64 oracle does (never more than one step later); the
+    relative error is the oracle's."""
+    a, _, _ = gen.random_tucker((60, 50, 40), (8, 7, 6), 1e-3, seed=22)
+    a32 = a.astype(np.float32).astype(np.float64)
+    res = orc.randomized_sthosvd_pve(a32, (8, 7, 6), 8, 20, 0.5, seed=4)
+    G, U, info, qs = T.rsthosvd_pve(_dev(a32, torch.float32), (8, 7, 6), p=8, q_max=20, tol=0.5, seed=4)
+    torch.cuda.synchronize()
+    assert all(1 <= x <= y + 1 for x, y in zip(qs, res.qs)), (qs, res.qs)
+    rec = reconstruct(_np(G), [_np(u) for u in U])
+    assert abs(np.linalg.norm(a32 - rec) / np.linalg.norm(a32) - orc.rel_error(a32, res)) <= 1e-6
