@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "bf16"])
     ap.add_argument("--q", type=int, default=None)
     ap.add_argument("--shift", default="adaptive", choices=["adaptive", "none"])
+    ap.add_argument("--pve", type=float, default=None, metavar="TOL",
+                    help="Algorithm 4: power count per mode by the per-vector-error test with this tol "
+                         "(--q is then q_max, default 20)")
     ap.add_argument("--kernel", default="auto", choices=["auto", "colreduce", "rowcontract"],
                     help="kernel class reported in the roofline object (auto: the larger summed launch time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -123,7 +126,7 @@ def reconstruct_torch(G, U):
     return t
 
 
-def cpu_baseline(workload, cfg, a_host, shift, q):
+def cpu_baseline(workload, cfg, a_host, shift, q, pve=None):
     """The FP64 oracle, untuned, on the host cores: one whole solve of the same
     workload when that takes seconds, else a bounded slab scaled by work."""
     import numpy as np
@@ -145,12 +148,17 @@ def cpu_baseline(workload, cfg, a_host, shift, q):
             "x".join(map(str, a.shape)), scale)
     a64 = a.astype(np.float64)
     t0 = time.perf_counter()
-    res = orc.randomized_hosvd(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1)
+    if pve is not None:
+        res = orc.randomized_sthosvd_pve(a64, cfg["ranks"], cfg["p"], q, pve, shift=shift, seed=1)
+    else:
+        res = orc.randomized_hosvd(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1)
     dt = (time.perf_counter() - t0) * scale
     out = {"value": 1.0 / dt, "unit": "approximations/s", "cores": int(threads), "kind": "oracle",
            "sample": sample, "seconds_per_solve": dt}
     if scale == 1.0:
         out["rel_error"] = orc.rel_error(a64, res)  # the FP64 oracle's RE on the same tensor and sketch
+        if pve is not None:
+            out["q_used"] = list(res.qs)
     return out
 
 
@@ -189,8 +197,15 @@ def main():
             A = A.double()
         a_host_store = None
 
-    solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
-                      sequential=(cfg["variant"] == "st"), device=dev)
+    if args.pve is not None:
+        if cfg["variant"] != "st":
+            raise SystemExit("--pve applies to ST-HOSVD workloads")
+        q = 20 if args.q is None else args.q
+        solver = T.PveSolver(A.shape, cfg["ranks"], cfg["p"], q, args.pve, args.shift, seed=w.sketch_seed,
+                             precision=prec, device=dev)
+    else:
+        solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
+                          sequential=(cfg["variant"] == "st"), device=dev)
     for _ in range(args.warmup):
         solver.run(A)
     torch.cuda.synchronize()
@@ -245,7 +260,7 @@ def main():
     if not args.no_cpu_baseline:
         if a_host_store is None:
             a_host_store = A.double().cpu().numpy() if A.numel() <= 3e8 else A.float().cpu().numpy()
-        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q)
+        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q, args.pve)
         if "rel_error" in cpu:
             cpu["rel_error_gpu_minus_oracle"] = re - cpu["rel_error"]
 
@@ -270,6 +285,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.pve is not None:
+        line["config"].update({"algorithm": "4 (per-vector-error q)", "tol": args.pve, "q_max": q,
+                               "q_used": solver.q_used})
     print(json.dumps(line), flush=True)
 
 
