@@ -895,7 +895,9 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     const int64_t osp = out_jmajor ? v.S : (int64_t)lw * v.S, osj = out_jmajor ? m : v.S;
     const int64_t tpp = (v.S + 63) / 64;
     const int64_t ntiles = v.P * tpp;
-    const int ksplit = ntiles < 2048 ? 1 : 0;  // split the rows when tiles alone cannot fill the chip
+    // split the rows while the tiles fill fewer than two rounds of the ~2048
+    // resident waves (one partial round would leave most of the chip idle)
+    const int ksplit = ntiles < 4096 ? 1 : 0;
     const unsigned blocks = (unsigned)(ksplit ? ntiles : (ntiles + 3) / 4);
 #define TK_RC_ROWS(WV)                                                                                            \
   hipLaunchKernelGGL((k_rc_rows<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
@@ -1051,7 +1053,7 @@ int64_t cr_cols_items(int64_t n, int nsplit) { return (int64_t)nsplit * ((n + 25
 int64_t rc_rows_tiles(const View3& v, int* ksplit, int64_t* tpp) {
   *tpp = (v.S + 63) / 64;
   const int64_t ntiles = v.P * *tpp;
-  *ksplit = ntiles < 2048 ? 1 : 0;
+  *ksplit = ntiles < 4096 ? 1 : 0;
   return ntiles;
 }
 
