@@ -7,7 +7,8 @@ package imports nothing from the product.
 
 Contents:
   philox   - Philox4x32-10 counter-based generator and the Box-Muller map that
-             defines the Gaussian test matrices Omega_k.
+             defines the Gaussian test matrices Omega_k; the uniform and
+             Khatri-Rao test matrices of the same streams.
   tensor   - mode-k unfolding, folding, mode-k product, Frobenius norms.
   rhosvd   - the method itself (shifted randomized T-HOSVD and ST-HOSVD, the
              unshifted model, the deterministic HOSVD, the power count chosen
