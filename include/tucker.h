@@ -122,6 +122,35 @@ size_t tucker_op_workspace_bytes(const tucker_shape* shape, int32_t mode, int64_
 int tucker_fill_gaussian(uint64_t seed, int32_t mode, int64_t row0, int64_t rows, int64_t cols,
                          tucker_precision prec, void* out, hipStream_t stream);
 
+/* Test-matrix kinds (section 5, comparison of random matrices). */
+typedef enum {
+  TUCKER_OMEGA_GAUSSIAN = 0,    /* standard Gaussian (the default of every solve) */
+  TUCKER_OMEGA_UNIFORM = 1,     /* i.i.d. uniform on [-1, 1] */
+  TUCKER_OMEGA_KR_GAUSSIAN = 2, /* Khatri-Rao product of Gaussian factors */
+  TUCKER_OMEGA_KR_UNIFORM = 3   /* Khatri-Rao product of uniform factors */
+} tucker_omega;
+
+/* Omega_mode[row0 : row0 + rows, 0 : cols] of test-matrix kind `kind` for a
+ * tensor of order d with current sizes dims[0..d-1] (the matrix has
+ * prod_{i != mode} dims[i] rows, in the column order of the mode unfolding),
+ * row-major into `out` (FP64 for TUCKER_FP64, FP32 otherwise). Streams of the
+ * Philox4x32-10 generator of tucker_fill_gaussian: the fourth counter word is
+ * `mode` for the dense kinds and 4096 + 16 mode + i for the Khatri-Rao factor
+ * of mode i; uniform streams add 2^30 and map word (col mod 4) of the block to
+ * (w + 1/2) 2^-31 - 1. Khatri-Rao: entry [c, j] is the product, in increasing
+ * mode order, of the factors' entries [c_i, j], where (c_i) is c in row-major
+ * order over the other modes. Gaussian kind: the same values as
+ * tucker_fill_gaussian. EINVAL: bad kind, d outside 1..8, mode outside 0..d-1,
+ * a size < 1, negative rows / cols / row0, out null with rows*cols > 0. */
+int tucker_fill_test_matrix(int32_t kind, uint64_t seed, int32_t mode, int32_t d, const int64_t* dims, int64_t row0,
+                            int64_t rows, int64_t cols, tucker_precision prec, void* out, hipStream_t stream);
+
+/* Options of the _ex solves. */
+typedef struct {
+  int32_t omega;        /* tucker_omega; TUCKER_OMEGA_GAUSSIAN gives the plain solves */
+  int32_t reserved[7];  /* zero */
+} tucker_options;
+
 /* Sketch Y = X_(mode) Omega_mode (Algorithms 2 and 3: the first product of
  * each mode). X has `shape` (FP64 for TUCKER_FP64, FP32 otherwise). Omega
  * is the m x l matrix of tucker_fill_gaussian(seed, mode, 0, m, l) with
@@ -195,6 +224,18 @@ int tucker_rthosvd(const tucker_shape* shape, const void* A, const int64_t* rank
 int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
                     tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                     tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* tucker_rthosvd / tucker_rsthosvd with options (opt may be NULL: the plain
+ * call). Mode k draws its test matrix of kind opt->omega as
+ * tucker_fill_test_matrix(kind, seed, k, d, current sizes), the current sizes
+ * being A's for T-HOSVD and (r_1..r_{k-1}, n_k..n_d) for ST-HOSVD. EINVAL for
+ * an unknown kind or nonzero reserved fields; otherwise as the plain calls. */
+int tucker_rthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                      tucker_shift shift, uint64_t seed, tucker_precision prec, const tucker_options* opt, void* G,
+                      void* const* U, tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);
+int tucker_rsthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                       tucker_shift shift, uint64_t seed, tucker_precision prec, const tucker_options* opt, void* G,
+                       void* const* U, tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* Algorithm 4: shifted randomized ST-HOSVD whose power count q_k is chosen per
  * mode by the per-vector-error test (Appendix, PVE accuracy control). Mode k

@@ -53,6 +53,13 @@ class Info(ctypes.Structure):
 INFO_BYTES = ctypes.sizeof(Info)
 
 
+class Options(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+OMEGA = {"gaussian": 0, "uniform": 1, "kr_gaussian": 2, "kr_uniform": 3}
+
+
 class BatchItem(ctypes.Structure):
     _fields_ = [
         ("shape", Shape),
@@ -83,6 +90,11 @@ SIGNATURES = {
                                       _SZ, _P]),
     "tucker_rsthosvd": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P, _P,
                                        _SZ, _P]),
+    "tucker_fill_test_matrix": (ctypes.c_int, [_I32, _U64, _I32, _I32, _P, _I64, _I64, _I64, ctypes.c_int, _P, _P]),
+    "tucker_rthosvd_ex": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P,
+                                         _P, _P, _SZ, _P]),
+    "tucker_rsthosvd_ex": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P,
+                                          _P, _P, _SZ, _P]),
     "tucker_rsthosvd_pve": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, _D, ctypes.c_int, _U64, ctypes.c_int, _P, _P,
                                            _P, _P, _P, _SZ, _P]),
     "tucker_timing_enable": (ctypes.c_int, [_I32, _I32]),
@@ -192,7 +204,9 @@ class Solver:
     """
 
     def __init__(self, dims, ranks, p=10, q=1, shift="adaptive", seed=1, precision="fp32", sequential=True,
-                 device="cuda"):
+                 device="cuda", omega="gaussian"):
+        self.opt = Options()
+        self.opt.omega = OMEGA[omega]
         self.dims = tuple(int(x) for x in dims)
         self.ranks = tuple(int(x) for x in ranks)
         self.p, self.q, self.seed = int(p), int(q), int(seed)
@@ -215,6 +229,13 @@ class Solver:
 
     def _call(self, A: Optional[torch.Tensor] = None, dry: bool = False):
         fn = lib.tucker_rsthosvd if self.sequential else lib.tucker_rthosvd
+        if self.opt.omega != 0 and not dry:
+            fx = lib.tucker_rsthosvd_ex if self.sequential else lib.tucker_rthosvd_ex
+            _check(fx(ctypes.byref(self._shape), ctypes.c_void_p(A.data_ptr()), self._ranks, self.p, self.q,
+                      self.shift, ctypes.c_uint64(self.seed), self.prec, ctypes.byref(self.opt),
+                      ctypes.c_void_p(self.G.data_ptr()), self._uptr, ctypes.c_void_p(self.info.data_ptr()),
+                      ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws.numel()), _stream(self.device)))
+            return
         if dry:
             s = _shape(self.dims)
             r = (ctypes.c_int64 * len(self.ranks))(*self.ranks)
@@ -274,20 +295,35 @@ def rsthosvd_pve(A: torch.Tensor, ranks, p=10, q_max=20, tol=0.5, shift="adaptiv
     return s.G, s.U, read_info(s.info), s.q_used
 
 
-def rsthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None):
+def rsthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
+             omega: str = "gaussian"):
     """Shifted randomized ST-HOSVD (Algorithm 3). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
-    s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], True, A.device)
+    s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], True, A.device,
+               omega)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
 
 
-def rthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None):
+def rthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
+            omega: str = "gaussian"):
     """Shifted randomized T-HOSVD (Algorithm 2). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
-    s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], False, A.device)
+    s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], False, A.device,
+               omega)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
+
+
+def fill_test_matrix(kind: str, seed: int, mode: int, dims, rows: int, cols: int, precision: str = "fp64",
+                     row0: int = 0, device="cuda") -> torch.Tensor:
+    """Rows row0 .. row0+rows of test matrix `kind` for mode `mode` of a tensor with sizes `dims`."""
+    prec = _PREC[precision]
+    out = torch.empty((rows, cols), dtype=storage_dtype(prec), device=device)
+    d = (ctypes.c_int64 * len(dims))(*[int(x) for x in dims])
+    _check(lib.tucker_fill_test_matrix(OMEGA[kind], ctypes.c_uint64(seed), mode, len(dims), d, row0, rows, cols, prec,
+                                       ctypes.c_void_p(out.data_ptr()), _stream(out.device)))
+    return out
 
 
 def fill_gaussian(seed: int, mode: int, rows: int, cols: int, precision: str = "fp64", row0: int = 0,

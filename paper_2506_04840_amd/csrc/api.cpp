@@ -229,7 +229,7 @@ int side_ctx(SideCtx** out) {
 // alpha Q3) J = X X^T Q - alpha Q, the same iterate. On return ws.q64 holds
 // the left singular vectors of the last iterate (FP64, n x l, descending).
 int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
-                tucker_info* info, const SolveWs& w, hipStream_t st) {
+                tucker_info* info, const SolveWs& w, hipStream_t st, const OmegaSpec& om) {
   const View3 v = pl.v[k];
   const int l = pl.l[k];
   const int64_t n = v.n, m = pl.m[k];
@@ -249,8 +249,8 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   auto step_prec = [&](int t) { return prec == TUCKER_BF16 && t == q ? TUCKER_FP32 : prec; };
   hipError_t e;
   // sketch: Y = X_(k) Omega_k, then its CholeskyQR
-  e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, true, w.omz,
-                           st);
+  e = launch_fill_omega(om, prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, true, w.omz,
+                        st);
   if (e == hipSuccess) e = launch_colreduce(step_prec(0), v, X, w.omz, l, w.part, nsplit, st);
   if (e == hipSuccess)
     e = launch_reduce_splits(step_prec(0), w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
@@ -328,7 +328,8 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
 
 int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
           tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
-          void* ws, size_t ws_bytes, hipStream_t st, double pve_tol = -1.0, int32_t* q_used = nullptr) {
+          void* ws, size_t ws_bytes, hipStream_t st, double pve_tol = -1.0, int32_t* q_used = nullptr,
+          int omega_kind = TUCKER_OMEGA_GAUSSIAN) {
   Plan pl;
   // with the per-vector-error test q is the largest power count; the plan (and
   // the per-step logs) cover the first TUCKER_MAX_Q steps
@@ -358,8 +359,12 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
 
   for (int k = 0; k < pl.d; ++k) {
     const void* Xk = st_variant ? X : A;
+    // the tensor mode k works on: A (T-HOSVD), or A with modes < k contracted (ST-HOSVD)
+    int64_t curk[TUCKER_MAX_ORDER];
+    for (int i = 0; i < pl.d; ++i) curk[i] = (st_variant && i < k) ? pl.r[i] : pl.dims[i];
+    const OmegaSpec om = omega_spec(omega_kind, pl.d, curk, k);
     rc = pve_tol >= 0.0 ? mode_factor_pve(pl, k, Xk, q, pve_tol, shift, seed, prec, info, w, st, q_used + k)
-                        : mode_factor(pl, k, Xk, q, shift, seed, prec, info, w, st);
+                        : mode_factor(pl, k, Xk, q, shift, seed, prec, info, w, st, om);
     if (rc) return rc;
     e = launch_signfix(prec, w.q64, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], w.ut, st);
     if (e != hipSuccess) return dev_check(e, "sign rule launch");
@@ -848,6 +853,55 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
                     tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                     tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
   return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream);
+}
+
+static int check_options(const tucker_options* opt, int* kind) {
+  *kind = TUCKER_OMEGA_GAUSSIAN;
+  if (opt == nullptr) return TUCKER_OK;
+  if (opt->omega < TUCKER_OMEGA_GAUSSIAN || opt->omega > TUCKER_OMEGA_KR_UNIFORM)
+    return fail(TUCKER_EINVAL, "unknown test-matrix kind %d", opt->omega);
+  for (int i = 0; i < 7; ++i)
+    if (opt->reserved[i] != 0) return fail(TUCKER_EINVAL, "tucker_options.reserved[%d] is not zero", i);
+  *kind = opt->omega;
+  return TUCKER_OK;
+}
+
+int tucker_rthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                      tucker_shift shift, uint64_t seed, tucker_precision prec, const tucker_options* opt, void* G,
+                      void* const* U, tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
+  int kind;
+  const int rc = check_options(opt, &kind);
+  if (rc) return rc;
+  return solve(false, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream, -1.0, nullptr, kind);
+}
+
+int tucker_rsthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                       tucker_shift shift, uint64_t seed, tucker_precision prec, const tucker_options* opt, void* G,
+                       void* const* U, tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
+  int kind;
+  const int rc = check_options(opt, &kind);
+  if (rc) return rc;
+  return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream, -1.0, nullptr, kind);
+}
+
+int tucker_fill_test_matrix(int32_t kind, uint64_t seed, int32_t mode, int32_t d, const int64_t* dims, int64_t row0,
+                            int64_t rows, int64_t cols, tucker_precision prec, void* out, hipStream_t stream) {
+  if (!valid_prec(prec)) return fail(TUCKER_EINVAL, "bad precision %d", (int)prec);
+  if (kind < TUCKER_OMEGA_GAUSSIAN || kind > TUCKER_OMEGA_KR_UNIFORM)
+    return fail(TUCKER_EINVAL, "unknown test-matrix kind %d", kind);
+  if (d < 1 || d > TUCKER_MAX_ORDER) return fail(TUCKER_EINVAL, "order %d outside 1..%d", d, TUCKER_MAX_ORDER);
+  if (mode < 0 || mode >= d) return fail(TUCKER_EINVAL, "mode %d outside 0..%d", mode, d - 1);
+  if (dims == nullptr) return fail(TUCKER_EINVAL, "dims is null");
+  for (int i = 0; i < d; ++i)
+    if (dims[i] < 1) return fail(TUCKER_EINVAL, "dims[%d] = %lld < 1", i, (long long)dims[i]);
+  if (rows < 0 || cols < 0 || row0 < 0) return fail(TUCKER_EINVAL, "negative rows, cols or row0");
+  if (cols > ((int64_t)1 << 30) || rows > ((int64_t)1 << 40)) return fail(TUCKER_EINVAL, "matrix too large");
+  if (rows * cols == 0) return TUCKER_OK;
+  if (out == nullptr) return fail(TUCKER_EINVAL, "out is null");
+  const OmegaSpec sp = omega_spec(kind, d, dims, mode);
+  return dev_check(launch_fill_omega(sp, prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)mode, row0,
+                                     rows, (int)cols, false, out, stream),
+                   "fill launch");
 }
 
 int tucker_rsthosvd_pve(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q_max,

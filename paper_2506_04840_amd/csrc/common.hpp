@@ -108,6 +108,26 @@ __device__ __forceinline__ void gaussian4_f32(uint64_t seed, uint32_t mode, uint
   out[3] = r * sn;
 }
 
+// Uniform [-1, 1] entries of stream `tag` (the uniform bit 2^30 is added
+// here): entry [c, 4g + q] = (w_q + 1/2) 2^-31 - 1 of the Philox block at
+// counter (c lo, c hi, g, tag + 2^30). Formed exactly in FP64, rounded once
+// for FP32.
+__device__ __forceinline__ void uniform4_f64(uint64_t seed, uint32_t tag, uint64_t c, uint32_t g, double out[4]) {
+  const U32x4 w = philox4x32_10(U32x4{(uint32_t)c, (uint32_t)(c >> 32), g, tag + (1u << 30)}, (uint32_t)seed,
+                                (uint32_t)(seed >> 32));
+  const double sc = 4.656612873077392578125e-10;  // 2^-31
+  out[0] = ((double)w.x + 0.5) * sc - 1.0;
+  out[1] = ((double)w.y + 0.5) * sc - 1.0;
+  out[2] = ((double)w.z + 0.5) * sc - 1.0;
+  out[3] = ((double)w.w + 0.5) * sc - 1.0;
+}
+__device__ __forceinline__ void uniform4_f32(uint64_t seed, uint32_t tag, uint64_t c, uint32_t g, float out[4]) {
+  double d[4];
+  uniform4_f64(seed, tag, c, g, d);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = (float)d[q];
+}
+
 // Workgroup barrier that orders LDS only: global loads in flight (a
 // prefetched stage) stay in flight across it, where __syncthreads would wait
 // for every outstanding global access.

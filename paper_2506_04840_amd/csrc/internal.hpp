@@ -39,6 +39,20 @@ inline size_t elem_bytes(tucker_precision p) { return p == TUCKER_FP64 ? 8 : 4; 
 hipError_t launch_fill_gaussian(tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0,
                                 int64_t rows, int cols, bool jmajor, void* out, hipStream_t st);
 
+// Test matrix of any kind (TUCKER_OMEGA_*) for mode `mode`: nfac other modes
+// of sizes fdim[0..nfac-1] (increasing mode order, product = the matrix's row
+// count) with Khatri-Rao stream tags ftag[]. Layout as launch_fill_gaussian.
+struct OmegaSpec {
+  int32_t kind;
+  int32_t nfac;
+  int64_t fdim[TUCKER_MAX_ORDER];
+  uint32_t ftag[TUCKER_MAX_ORDER];
+};
+// The spec of mode k's test matrix for a tensor whose current sizes are cur[0..d-1].
+OmegaSpec omega_spec(int kind, int d, const int64_t* cur, int k);
+hipError_t launch_fill_omega(const OmegaSpec& sp, tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0,
+                             int64_t rows, int cols, bool jmajor, void* out, hipStream_t st);
+
 // ---- mode products ----------------------------------------------------------
 // Column reduction: part[split][i][j] = sum over the split's columns c of
 // X_(k)[i, c] * B[c, j], B stored j-major as Bt[j * m + c] (m = P S).

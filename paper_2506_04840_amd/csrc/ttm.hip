@@ -963,6 +963,88 @@ __global__ __launch_bounds__(256) void k_fill_gaussian(uint64_t seed, uint32_t m
   fill_gaussian_body<T>(seed, mode, row0, rows, cols, ld, jmajor, out, (int)blockIdx.x);
 }
 
+// ---------------------------------------------------------------------------
+// Test matrices of the other kinds (section 5): uniform [-1, 1] entries, and
+// Khatri-Rao products whose entry [c, j] multiplies, in increasing mode
+// order, the entries [c_i, j] of one small Gaussian or uniform factor per
+// other mode (c_i: c in row-major order over those modes). Factor f of
+// mode k is stream 4096 + 16 k + i (i its mode).
+// ---------------------------------------------------------------------------
+OmegaSpec omega_spec(int kind, int d, const int64_t* cur, int k) {
+  OmegaSpec sp{};
+  sp.kind = kind;
+  for (int i = 0; i < d; ++i) {
+    if (i == k) continue;
+    sp.fdim[sp.nfac] = cur[i];
+    sp.ftag[sp.nfac] = 4096u + 16u * (uint32_t)k + (uint32_t)i;
+    ++sp.nfac;
+  }
+  return sp;
+}
+
+template <typename T>
+__device__ __forceinline__ void omega4(int kr_uniform, uint64_t seed, uint32_t tag, uint64_t c, uint32_t g, T v[4]) {
+  if constexpr (sizeof(T) == 8) {
+    if (kr_uniform) uniform4_f64(seed, tag, c, g, v);
+    else gaussian4_f64(seed, tag, c, g, v);
+  } else {
+    if (kr_uniform) uniform4_f32(seed, tag, c, g, v);
+    else gaussian4_f32(seed, tag, c, g, v);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill_omega(OmegaSpec sp, uint64_t seed, uint32_t mode, int64_t row0,
+                                                    int64_t rows, int cols, int64_t ld, int jmajor, T* __restrict__ out) {
+  const int groups = (cols + 3) / 4;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * groups) return;
+  const int g = (int)(e / rows);
+  const int64_t c = e - (int64_t)g * rows;
+  const uint64_t row = (uint64_t)(row0 + c);
+  T v[4];
+  if (sp.kind == TUCKER_OMEGA_GAUSSIAN || sp.kind == TUCKER_OMEGA_UNIFORM) {
+    omega4<T>(sp.kind == TUCKER_OMEGA_UNIFORM, seed, mode, row, (uint32_t)g, v);
+  } else {
+    const int uni = sp.kind == TUCKER_OMEGA_KR_UNIFORM;
+    uint64_t ci[TUCKER_MAX_ORDER];
+    uint64_t rem = row;
+    for (int f = sp.nfac - 1; f >= 0; --f) {  // the last other mode varies fastest
+      ci[f] = rem % (uint64_t)sp.fdim[f];
+      rem /= (uint64_t)sp.fdim[f];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = T(1);
+    for (int f = 0; f < sp.nfac; ++f) {
+      T fv[4];
+      omega4<T>(uni, seed, sp.ftag[f], ci[f], (uint32_t)g, fv);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) v[q] *= fv[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = 4 * g + q;
+    if (j < cols) out[jmajor ? (int64_t)j * ld + c : c * cols + j] = v[q];
+  }
+}
+
+hipError_t launch_fill_omega(const OmegaSpec& sp, tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0,
+                             int64_t rows, int cols, bool jmajor, void* out, hipStream_t st) {
+  if (sp.kind == TUCKER_OMEGA_GAUSSIAN) return launch_fill_gaussian(prec, seed, mode, row0, rows, cols, jmajor, out, st);
+  if (sp.kind < 0 || sp.kind > TUCKER_OMEGA_KR_UNIFORM || rows <= 0 || cols <= 0) return hipErrorInvalidValue;
+  TimingScope ts(KC_FILL, st, (double)rows * cols * elem_bytes(prec), 0.0);
+  const int64_t work = rows * ((cols + 3) / 4);
+  const unsigned blocks = (unsigned)((work + 255) / 256);
+  if (prec == TUCKER_FP64)
+    hipLaunchKernelGGL((k_fill_omega<double>), dim3(blocks), dim3(256), 0, st, sp, seed, mode, row0, rows, cols, rows,
+                       jmajor ? 1 : 0, (double*)out);
+  else
+    hipLaunchKernelGGL((k_fill_omega<float>), dim3(blocks), dim3(256), 0, st, sp, seed, mode, row0, rows, cols, rows,
+                       jmajor ? 1 : 0, (float*)out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_gaussian(tucker_precision prec, uint64_t seed, uint32_t mode, int64_t row0, int64_t rows,
                                 int cols, bool jmajor, void* out, hipStream_t st) {
   const int64_t work = rows * (int64_t)((cols + 3) / 4);

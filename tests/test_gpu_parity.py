@@ -440,3 +440,47 @@ def test_solve_pve_fp32_reaches_oracle_error(T):
     assert all(1 <= x <= y + 1 for x, y in zip(qs, res.qs)), (qs, res.qs)
     rec = reconstruct(_np(G), [_np(u) for u in U])
     assert abs(np.linalg.norm(a32 - rec) / np.linalg.norm(a32) - orc.rel_error(a32, res)) <= 1e-6
+
+
+# --------------------------------------------------------------- other test matrices (section 5)
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["gaussian", "uniform", "kr_gaussian", "kr_uniform"])
+def test_fill_test_matrix_matches_oracle(T, kind, prec):
+    dims, mode, l = (7, 9, 5, 6), 2, 13
+    m = 7 * 9 * 6
+    g = _np(T.fill_test_matrix(kind, 11, mode, dims, m, l, prec))
+    o = orc_rng.omega_matrix(kind, 11, mode, [7, 9, 6], l)
+    err = np.abs(g - o)
+    if prec == "fp64":
+        assert np.all(err <= 1e-12 * np.maximum(1.0, np.abs(o)))
+    elif kind == "uniform":
+        assert np.all(err <= 6e-8)  # one rounding of the exact FP64 value
+    else:
+        # FP32 Box-Muller (relative 1e-6 but for tiny values), one factor per other mode
+        assert np.all(err <= 1e-5 * np.abs(o) + 3e-3)
+        assert np.median(err / np.maximum(np.abs(o), 1e-3)) < 3e-6
+    # a row window addresses the same entries
+    gw = _np(T.fill_test_matrix(kind, 11, mode, dims, 50, l, prec, row0=100))
+    assert np.array_equal(gw, g[100:150])
+
+
+@pytest.mark.parametrize("variant", ["t", "st"])
+@pytest.mark.parametrize("kind", ["uniform", "kr_gaussian", "kr_uniform"])
+def test_solve_with_other_test_matrices(T, kind, variant):
+    """Whole FP64 solves drawing each kind of test matrix: the oracle, given
+    the same matrices (the unfolding's other sizes; ST: ranks of the modes
+    already processed), reaches the same reconstruction to 1e-10."""
+    a, _, _ = gen.random_tucker((26, 30, 22), (5, 6, 4), 0.05, seed=23)
+    ranks, p, q = (5, 6, 4), 5, 1
+
+    def om(k, m, l):
+        cur = [ranks[i] if (variant == "st" and i < k) else a.shape[i] for i in range(3)]
+        return orc_rng.omega_matrix(kind, 3, k, [cur[i] for i in range(3) if i != k], l)
+
+    res = orc.randomized_hosvd(a, ranks, p, q, variant=variant, seed=3, omega=om)
+    fn = T.rsthosvd if variant == "st" else T.rthosvd
+    G, U, info = fn(_dev(a, torch.float64), ranks, p=p, q=q, seed=3, precision="fp64", omega=kind)
+    torch.cuda.synchronize()
+    d = np.linalg.norm(reconstruct(_np(G), [_np(u) for u in U]) - reconstruct(res.core, res.factors))
+    assert d / np.linalg.norm(a) <= 1e-10
