@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "fp32", "bf16"])
     ap.add_argument("--q", type=int, default=None)
     ap.add_argument("--shift", default="adaptive", choices=["adaptive", "none"])
+    ap.add_argument("--omega", default="gaussian", choices=["gaussian", "uniform", "kr_gaussian", "kr_uniform"],
+                    help="test-matrix kind (section 5's comparison of random matrices)")
     ap.add_argument("--pve", type=float, default=None, metavar="TOL",
                     help="Algorithm 4: power count per mode by the per-vector-error test with this tol "
                          "(--q is then q_max, default 20)")
@@ -126,7 +128,7 @@ def reconstruct_torch(G, U):
     return t
 
 
-def cpu_baseline(workload, cfg, a_host, shift, q, pve=None):
+def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian"):
     """The FP64 oracle, untuned, on the host cores: one whole solve of the same
     workload when that takes seconds, else a bounded slab scaled by work."""
     import numpy as np
@@ -151,7 +153,16 @@ def cpu_baseline(workload, cfg, a_host, shift, q, pve=None):
     if pve is not None:
         res = orc.randomized_sthosvd_pve(a64, cfg["ranks"], cfg["p"], q, pve, shift=shift, seed=1)
     else:
-        res = orc.randomized_hosvd(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1)
+        om = None
+        if omega != "gaussian":
+            from oracle.philox import omega_matrix
+            ranks, dims, st = cfg["ranks"], a64.shape, cfg["variant"] == "st"
+
+            def om(k, m, l):
+                cur = [ranks[i] if (st and i < k) else dims[i] for i in range(len(dims))]
+                return omega_matrix(omega, 1, k, [cur[i] for i in range(len(dims)) if i != k], l)
+        res = orc.randomized_hosvd(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1,
+                                   omega=om)
     dt = (time.perf_counter() - t0) * scale
     out = {"value": 1.0 / dt, "unit": "approximations/s", "cores": int(threads), "kind": "oracle",
            "sample": sample, "seconds_per_solve": dt}
@@ -205,7 +216,7 @@ def main():
                              precision=prec, device=dev)
     else:
         solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
-                          sequential=(cfg["variant"] == "st"), device=dev)
+                          sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega)
     for _ in range(args.warmup):
         solver.run(A)
     torch.cuda.synchronize()
@@ -260,7 +271,7 @@ def main():
     if not args.no_cpu_baseline:
         if a_host_store is None:
             a_host_store = A.double().cpu().numpy() if A.numel() <= 3e8 else A.float().cpu().numpy()
-        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q, args.pve)
+        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q, args.pve, args.omega)
         if "rel_error" in cpu:
             cpu["rel_error_gpu_minus_oracle"] = re - cpu["rel_error"]
 
@@ -285,6 +296,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if args.omega != "gaussian":
+        line["config"]["omega"] = args.omega
     if args.pve is not None:
         line["config"].update({"algorithm": "4 (per-vector-error q)", "tol": args.pve, "q_max": q,
                                "q_used": solver.q_used})

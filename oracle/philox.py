@@ -1,4 +1,4 @@
-"""Counter-based Gaussian test matrices, FP64 reference.
+"""Counter-based test matrices (Gaussian, uniform, Khatri-Rao), FP64 reference.
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
