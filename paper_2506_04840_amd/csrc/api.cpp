@@ -145,6 +145,19 @@ int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_
   return TUCKER_OK;
 }
 
+struct ModeWs {
+  void* omz;
+  void* part;
+  double* y64;
+  void* qt;
+  void* ut;
+  double* q64;
+  double* sigma;
+  void* orth;
+  double* sig_hat;
+  int* stop;
+};
+
 struct SolveWs {
   void* xbuf[2];
   void* omz;
@@ -159,6 +172,27 @@ struct SolveWs {
   void* orth;
   double* sig_hat;  // per-vector-error estimates of the previous step (Algorithm 4)
   int* stop;        // its stopping flag
+  ModeWs mode_store[TUCKER_MAX_ORDER];
+  ModeWs* mode[TUCKER_MAX_ORDER];  // T-HOSVD: own scratch of modes 1..d-1 (else nullptr)
+
+  // the scratch mode k works in (shared pointers stay)
+  SolveWs for_mode(int k) const {
+    SolveWs c = *this;
+    if (k >= 0 && k < TUCKER_MAX_ORDER && mode[k] != nullptr) {
+      const ModeWs& m = *mode[k];
+      c.omz = m.omz;
+      c.part = m.part;
+      c.y64 = m.y64;
+      c.qt = m.qt;
+      c.ut = m.ut;
+      c.q64 = m.q64;
+      c.sigma = m.sigma;
+      c.orth = m.orth;
+      c.sig_hat = m.sig_hat;
+      c.stop = m.stop;
+    }
+    return c;
+  }
 };
 
 size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveWs* w) {
@@ -183,6 +217,24 @@ size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveW
   w->orth = take(pl.orth_bytes);
   w->sig_hat = (double*)take(TUCKER_MAX_L * 8);
   w->stop = (int*)take(64);
+  // T-HOSVD: the modes are independent and run concurrently; modes 1..d-1
+  // get their own copy of the per-mode scratch (mode 0 uses the one above)
+  for (int k = 0; k < TUCKER_MAX_ORDER; ++k) w->mode[k] = nullptr;
+  if (!pl.st)
+    for (int k = 1; k < pl.d; ++k) {
+      ModeWs& mw = w->mode_store[k];
+      mw.omz = take((size_t)pl.omz_elems * es);
+      mw.part = take(pl.part_bytes);
+      mw.y64 = (double*)take((size_t)pl.nl_max * 8);
+      mw.qt = take((size_t)pl.nl_max * es);
+      mw.ut = take((size_t)pl.nl_max * es);
+      mw.q64 = (double*)take((size_t)pl.nl_max * 8);
+      mw.sigma = (double*)take(TUCKER_MAX_L * 8);
+      mw.orth = take(pl.orth_bytes);
+      mw.sig_hat = (double*)take(TUCKER_MAX_L * 8);
+      mw.stop = (int*)take(64);
+      w->mode[k] = &mw;
+    }
   return off;
 }
 
@@ -199,19 +251,27 @@ struct SideCtx {
   int dev = -1;
   hipStream_t s = nullptr;
   hipEvent_t qr_done = nullptr, svd_done = nullptr;
+  hipStream_t ms = nullptr;  // the mode's own stream (concurrent T-HOSVD modes 1..d-1)
+  hipEvent_t fork = nullptr, join = nullptr;
 };
-thread_local SideCtx g_side[16];
+thread_local SideCtx g_side[16][TUCKER_MAX_ORDER];
 
-int side_ctx(SideCtx** out) {
+// Streams and events of lane `lane` (a mode of a concurrent T-HOSVD; lane 0
+// otherwise), created on first use per host thread and device, default priority.
+int side_ctx(SideCtx** out, int lane = 0) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return dev_check(e, "hipGetDevice");
   if (dev < 0 || dev >= 16) return fail(TUCKER_EDEVICE, "device ordinal %d outside 0..15", dev);
-  SideCtx& c = g_side[dev];
+  if (lane < 0 || lane >= TUCKER_MAX_ORDER) return fail(TUCKER_EINVAL, "internal: lane %d", lane);
+  SideCtx& c = g_side[dev][lane];
   if (c.s == nullptr) {
     e = hipStreamCreateWithFlags(&c.s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c.qr_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c.svd_done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c.ms, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.join, hipEventDisableTiming);
     if (e != hipSuccess) return dev_check(e, "side stream setup");
     c.dev = dev;
   }
@@ -229,7 +289,7 @@ int side_ctx(SideCtx** out) {
 // alpha Q3) J = X X^T Q - alpha Q, the same iterate. On return ws.q64 holds
 // the left singular vectors of the last iterate (FP64, n x l, descending).
 int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
-                tucker_info* info, const SolveWs& w, hipStream_t st, const OmegaSpec& om) {
+                tucker_info* info, const SolveWs& w, hipStream_t st, const OmegaSpec& om, int lane = 0) {
   const View3 v = pl.v[k];
   const int l = pl.l[k];
   const int64_t n = v.n, m = pl.m[k];
@@ -240,7 +300,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   double* alpha_upd = shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr;
   SideCtx* side = nullptr;
   if (q > 0) {
-    const int rc = side_ctx(&side);
+    const int rc = side_ctx(&side, lane);
     if (rc) return rc;
   }
   // BF16 operands: the products of the last step (the sketch when q = 0) run
@@ -357,23 +417,47 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
   int64_t cur[TUCKER_MAX_ORDER];
   for (int k = 0; k < pl.d; ++k) cur[k] = pl.dims[k];
 
+  // T-HOSVD: every mode only reads A, so mode 0 runs on the caller's stream
+  // and modes 1..d-1 on their own streams (each with its own scratch and SVD
+  // side stream), forked from the caller's stream here and joined back before
+  // the core chain.
+  const bool concurrent = !st_variant && pl.d > 1 && pve_tol < 0.0;
+  SideCtx* lanes[TUCKER_MAX_ORDER] = {};
+  if (concurrent) {
+    for (int k = 1; k < pl.d; ++k) {
+      rc = side_ctx(&lanes[k], k);
+      if (rc) return rc;
+    }
+    e = hipEventRecord(lanes[1]->fork, st);
+    for (int k = 1; k < pl.d && e == hipSuccess; ++k) e = hipStreamWaitEvent(lanes[k]->ms, lanes[1]->fork, 0);
+    if (e != hipSuccess) return dev_check(e, "mode fork");
+  }
   for (int k = 0; k < pl.d; ++k) {
     const void* Xk = st_variant ? X : A;
+    const hipStream_t sk = concurrent && k > 0 ? lanes[k]->ms : st;
+    const SolveWs wk = w.for_mode(k);
     // the tensor mode k works on: A (T-HOSVD), or A with modes < k contracted (ST-HOSVD)
     int64_t curk[TUCKER_MAX_ORDER];
     for (int i = 0; i < pl.d; ++i) curk[i] = (st_variant && i < k) ? pl.r[i] : pl.dims[i];
     const OmegaSpec om = omega_spec(omega_kind, pl.d, curk, k);
-    rc = pve_tol >= 0.0 ? mode_factor_pve(pl, k, Xk, q, pve_tol, shift, seed, prec, info, w, st, q_used + k)
-                        : mode_factor(pl, k, Xk, q, shift, seed, prec, info, w, st, om);
+    rc = pve_tol >= 0.0 ? mode_factor_pve(pl, k, Xk, q, pve_tol, shift, seed, prec, info, wk, sk, q_used + k)
+                        : mode_factor(pl, k, Xk, q, shift, seed, prec, info, wk, sk, om, concurrent ? k : 0);
     if (rc) return rc;
-    e = launch_signfix(prec, w.q64, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], w.ut, st);
+    e = launch_signfix(prec, wk.q64, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], wk.ut, sk);
     if (e != hipSuccess) return dev_check(e, "sign rule launch");
     if (st_variant) {
       void* out = (k == pl.d - 1) ? G : w.xbuf[k & 1];
-      e = launch_rowcontract(core_mk, pl.v[k], X, w.ut, 1, pl.v[k].n, (int)pl.r[k], out, false, st);
+      e = launch_rowcontract(core_mk, pl.v[k], X, wk.ut, 1, pl.v[k].n, (int)pl.r[k], out, false, st);
       if (e != hipSuccess) return dev_check(e, "core launch");
       X = out;
     }
+  }
+  if (concurrent) {
+    for (int k = 1; k < pl.d && e == hipSuccess; ++k) {
+      e = hipEventRecord(lanes[k]->join, lanes[k]->ms);
+      if (e == hipSuccess) e = hipStreamWaitEvent(st, lanes[k]->join, 0);
+    }
+    if (e != hipSuccess) return dev_check(e, "mode join");
   }
   if (!st_variant) {
     for (int k = 0; k < pl.d; ++k) {

@@ -745,9 +745,9 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
       info->sigma_1[mode][step] = s1;
       info->sigma_l[mode][step] = sl;
       info->alpha[mode][step] = al;
-      info->flags |= status[0];
+      atomicOr(&info->flags, status[0]);  // modes of a T-HOSVD may run concurrently
       info->deficient[mode] = status[1];
-      info->jacobi_sweeps = max(info->jacobi_sweeps, sweeps);
+      atomicMax(&info->jacobi_sweeps, sweeps);
     }
   }
 }
