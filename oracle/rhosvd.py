@@ -107,16 +107,22 @@ OmegaProvider = Callable[[int, int, int], np.ndarray]
 
 def randomized_hosvd(a: np.ndarray, ranks: Sequence[int], p: int, q: int, *,
                      shift: str = "adaptive", variant: str = "st", seed: int = 1,
-                     omega: Optional[OmegaProvider] = None) -> Result:
-    """Algorithm 2 (variant 't') / Algorithm 3 (variant 'st'); shift 'none' = Algorithm A.1."""
+                     omega: Optional[OmegaProvider] = None, order: Optional[Sequence[int]] = None) -> Result:
+    """Algorithm 2 (variant 't') / Algorithm 3 (variant 'st'); shift 'none' = Algorithm A.1.
+    `order` is the processing order (a permutation of the modes; default
+    1..d): ST-HOSVD contracts the modes in that order, T-HOSVD is unaffected.
+    Factors and logs stay indexed by mode; Omega_k is mode k's whatever the order."""
     if shift not in ("adaptive", "none") or variant not in ("t", "st"):
         raise ValueError("bad shift or variant")
     a = np.asarray(a, dtype=np.float64)
     d = a.ndim
+    order = list(range(d)) if order is None else [int(k) for k in order]
+    if sorted(order) != list(range(d)):
+        raise ValueError("order must be a permutation of the modes")
     g = a.copy()
-    factors: List[np.ndarray] = []
-    logs: List[ModeLog] = []
-    for k in range(d):
+    factors: List[Optional[np.ndarray]] = [None] * d
+    logs: List[Optional[ModeLog]] = [None] * d
+    for k in order:
         x = a if variant == "t" else g
         n_k = x.shape[k]
         m_k = x.size // n_k
@@ -135,9 +141,14 @@ def randomized_hosvd(a: np.ndarray, ranks: Sequence[int], p: int, q: int, *,
             alphas.append(alpha)
             sigmas.append(s)
         u_k = sign_fix(qm[:, :r_k])
-        factors.append(u_k)
-        g = core_step(g, k, u_k)
-        logs.append(ModeLog(l_k, m_k, alphas, sigmas))
+        factors[k] = u_k
+        if variant == "st":
+            g = core_step(g, k, u_k)
+        logs[k] = ModeLog(l_k, m_k, alphas, sigmas)
+    if variant == "t":  # the core of T-HOSVD: A x_k U_k^T over the modes in order
+        g = a
+        for k in range(d):
+            g = core_step(g, k, factors[k])
     return Result(g, factors, logs)
 
 

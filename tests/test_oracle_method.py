@@ -314,3 +314,42 @@ def test_pve_reaches_the_q_max_error():
     full = randomized_hosvd(a, (6, 6, 6), 4, 20, variant="st", seed=7)
     assert max(res.qs) <= 5
     assert abs(rel_error(a, res) - rel_error(a, full)) <= 1e-6 * rel_error(a, full)
+
+
+# --------------------------------------------------------------- processing order
+
+def test_t_hosvd_does_not_depend_on_the_order():
+    """T-HOSVD computes every factor from A itself: any processing order gives
+    the same factors and core, bit for bit."""
+    a, _, _ = random_tucker((18, 16, 14), (4, 3, 5), 1e-2, seed=51)
+    ref = randomized_hosvd(a, (4, 3, 5), 3, 1, variant="t", seed=2)
+    res = randomized_hosvd(a, (4, 3, 5), 3, 1, variant="t", seed=2, order=(2, 0, 1))
+    assert np.array_equal(res.core, ref.core)
+    for u, v in zip(res.factors, ref.factors):
+        assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("order", [(0, 1, 2), (2, 1, 0), (1, 2, 0), (2, 0, 1)])
+def test_st_hosvd_bound_holds_in_every_order(order):
+    """ST-HOSVD's error bound ||A - Ahat||^2 <= sum_k sum_{i > r_k}
+    sigma_i(A_(k))^2 (the tails of A's own unfoldings) holds whatever the
+    processing order; here with a full-width sketch (the deterministic method)."""
+    a, _, _ = random_tucker((12, 10, 9), (3, 4, 2), 0.3, seed=52)
+    ranks = (3, 4, 2)
+    tails = sum(np.sum(np.linalg.svd(unfold(a, k), compute_uv=False)[ranks[k]:] ** 2) for k in range(3))
+    res = randomized_hosvd(a, ranks, 20, 0, variant="st", seed=3, order=order)
+    err2 = frob2(a - reconstruct(res.core, res.factors))
+    assert err2 <= tails * (1 + 1e-12)
+    assert res.core.shape == ranks
+
+
+def test_exact_rank_is_recovered_in_a_permuted_order():
+    a, _, _ = random_tucker((14, 12, 10), (3, 4, 2), 0.0, seed=53)
+    res = randomized_hosvd(a, (3, 4, 2), 2, 1, variant="st", seed=4, order=(1, 2, 0))
+    assert rel_error(a, res) < 1e-12
+
+
+def test_bad_order_rejected():
+    a, _, _ = random_tucker((6, 5, 4), (2, 2, 2), 0.0, seed=54)
+    with pytest.raises(ValueError):
+        randomized_hosvd(a, (2, 2, 2), 1, 0, order=(0, 0, 1))
