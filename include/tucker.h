@@ -145,10 +145,21 @@ typedef enum {
 int tucker_fill_test_matrix(int32_t kind, uint64_t seed, int32_t mode, int32_t d, const int64_t* dims, int64_t row0,
                             int64_t rows, int64_t cols, tucker_precision prec, void* out, hipStream_t stream);
 
-/* Options of the _ex solves. */
+/* Processing order of the modes (Section 2.2: ST-HOSVD may take the modes in
+ * any order of the symmetric group; Section 3.2 takes n_{p_1} >= ... >= n_{p_d}
+ * for its cost count). */
+typedef enum {
+  TUCKER_ORDER_NATURAL = 0,    /* 0, 1, ..., d-1 (the plain solves) */
+  TUCKER_ORDER_GIVEN = 1,      /* opt->order[0..d-1], a permutation of 0..d-1 */
+  TUCKER_ORDER_DECREASING = 2  /* by decreasing n_k; equal sizes in increasing mode */
+} tucker_order;
+
+/* Options of the _ex solves. A zeroed struct gives the plain solves. */
 typedef struct {
-  int32_t omega;        /* tucker_omega; TUCKER_OMEGA_GAUSSIAN gives the plain solves */
-  int32_t reserved[7];  /* zero */
+  int32_t omega;                    /* tucker_omega */
+  int32_t order_kind;               /* tucker_order */
+  int32_t order[TUCKER_MAX_ORDER];  /* TUCKER_ORDER_GIVEN: processing order, first d entries */
+  int32_t reserved[6];              /* zero */
 } tucker_options;
 
 /* Sketch Y = X_(mode) Omega_mode (Algorithms 2 and 3: the first product of
@@ -228,8 +239,18 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
 /* tucker_rthosvd / tucker_rsthosvd with options (opt may be NULL: the plain
  * call). Mode k draws its test matrix of kind opt->omega as
  * tucker_fill_test_matrix(kind, seed, k, d, current sizes), the current sizes
- * being A's for T-HOSVD and (r_1..r_{k-1}, n_k..n_d) for ST-HOSVD. EINVAL for
- * an unknown kind or nonzero reserved fields; otherwise as the plain calls. */
+ * being A's for T-HOSVD and, for ST-HOSVD, r_j for the modes j processed
+ * before k and n_j for the others. ST-HOSVD processes the modes in the order
+ * opt->order_kind selects: mode k works on A contracted with the U_j^T of the
+ * modes before it, so m_k, l_k and the feasibility bound r_k <= m_k follow
+ * the order, and the core is contracted in that order. T-HOSVD computes
+ * every factor from A (the order does not change its result) and contracts
+ * the core in mode order. Factors, info logs and test-matrix streams stay
+ * indexed by mode. Workspace: tucker_workspace_bytes_ex with the same opt.
+ * EINVAL for an unknown kind, an order that is not a permutation of 0..d-1
+ * or nonzero reserved fields; otherwise as the plain calls. */
+size_t tucker_workspace_bytes_ex(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q,
+                                 tucker_precision prec, int32_t sequential, const tucker_options* opt);
 int tucker_rthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
                       tucker_shift shift, uint64_t seed, tucker_precision prec, const tucker_options* opt, void* G,
                       void* const* U, tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);

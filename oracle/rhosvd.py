@@ -105,6 +105,12 @@ class Result:
 OmegaProvider = Callable[[int, int, int], np.ndarray]
 
 
+def decreasing_order(shape: Sequence[int]) -> List[int]:
+    """The processing order of the cost count in Section 3.2: the modes by
+    decreasing size n_{p_1} >= ... >= n_{p_d}; equal sizes keep increasing mode."""
+    return sorted(range(len(shape)), key=lambda k: -int(shape[k]))
+
+
 def randomized_hosvd(a: np.ndarray, ranks: Sequence[int], p: int, q: int, *,
                      shift: str = "adaptive", variant: str = "st", seed: int = 1,
                      omega: Optional[OmegaProvider] = None, order: Optional[Sequence[int]] = None) -> Result:

@@ -54,10 +54,31 @@ INFO_BYTES = ctypes.sizeof(Info)
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("omega", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("omega", ctypes.c_int32), ("order_kind", ctypes.c_int32), ("order", ctypes.c_int32 * 8),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 OMEGA = {"gaussian": 0, "uniform": 1, "kr_gaussian": 2, "kr_uniform": 3}
+ORDER_NATURAL, ORDER_GIVEN, ORDER_DECREASING = 0, 1, 2
+
+
+def make_options(omega: str = "gaussian", order=None) -> Options:
+    """Options struct: test-matrix kind and processing order (None: 0..d-1,
+    "decreasing": by decreasing mode size, or a permutation of the modes)."""
+    opt = Options()
+    opt.omega = OMEGA[omega]
+    if order is None or order == "natural":
+        opt.order_kind = ORDER_NATURAL
+    elif order == "decreasing":
+        opt.order_kind = ORDER_DECREASING
+    else:
+        perm = [int(k) for k in order]
+        if len(perm) > 8:
+            raise ValueError("order has more than 8 modes")
+        opt.order_kind = ORDER_GIVEN
+        for i, k in enumerate(perm):
+            opt.order[i] = k
+    return opt
 
 
 class BatchItem(ctypes.Structure):
@@ -78,6 +99,7 @@ _SHAPE_P = ctypes.POINTER(Shape)
 SIGNATURES = {
     "tucker_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tucker_workspace_bytes": (_SZ, [_SHAPE_P, _P, _I32, _I32, ctypes.c_int, _I32]),
+    "tucker_workspace_bytes_ex": (_SZ, [_SHAPE_P, _P, _I32, _I32, ctypes.c_int, _I32, _P]),
     "tucker_op_workspace_bytes": (_SZ, [_SHAPE_P, _I32, _I64, ctypes.c_int]),
     "tucker_fill_gaussian": (ctypes.c_int, [_U64, _I32, _I64, _I64, _I64, ctypes.c_int, _P, _P]),
     "tucker_sketch": (ctypes.c_int, [_SHAPE_P, _I32, _P, _I64, _U64, ctypes.c_int, _P, _P, _SZ, _P]),
@@ -170,9 +192,12 @@ def _dev(t: torch.Tensor, name: str) -> int:
     return t.data_ptr()
 
 
-def workspace_bytes(dims, ranks, p, q, precision: int, sequential: bool) -> int:
+def workspace_bytes(dims, ranks, p, q, precision: int, sequential: bool, opt: Optional[Options] = None) -> int:
     r = (ctypes.c_int64 * len(ranks))(*[int(x) for x in ranks])
     s = _shape(dims)
+    if opt is not None:
+        return int(lib.tucker_workspace_bytes_ex(ctypes.byref(s), r, int(p), int(q), precision,
+                                                 1 if sequential else 0, ctypes.byref(opt)))
     return int(lib.tucker_workspace_bytes(ctypes.byref(s), r, int(p), int(q), precision, 1 if sequential else 0))
 
 
@@ -204,9 +229,9 @@ class Solver:
     """
 
     def __init__(self, dims, ranks, p=10, q=1, shift="adaptive", seed=1, precision="fp32", sequential=True,
-                 device="cuda", omega="gaussian"):
-        self.opt = Options()
-        self.opt.omega = OMEGA[omega]
+                 device="cuda", omega="gaussian", order=None):
+        self.opt = make_options(omega, order)
+        self.plain = self.opt.omega == 0 and self.opt.order_kind == ORDER_NATURAL
         self.dims = tuple(int(x) for x in dims)
         self.ranks = tuple(int(x) for x in ranks)
         self.p, self.q, self.seed = int(p), int(q), int(seed)
@@ -214,7 +239,8 @@ class Solver:
         self.shift = _SHIFT[shift]
         self.sequential = bool(sequential)
         self.device = torch.device(device)
-        nbytes = workspace_bytes(self.dims, self.ranks, self.p, self.q, self.prec, self.sequential)
+        nbytes = workspace_bytes(self.dims, self.ranks, self.p, self.q, self.prec, self.sequential,
+                                 None if self.plain else self.opt)
         if nbytes == 0:
             # reproduce the detailed error
             self._call(dry=True)
@@ -229,8 +255,14 @@ class Solver:
 
     def _call(self, A: Optional[torch.Tensor] = None, dry: bool = False):
         fn = lib.tucker_rsthosvd if self.sequential else lib.tucker_rthosvd
-        if self.opt.omega != 0 and not dry:
+        if not self.plain:
             fx = lib.tucker_rsthosvd_ex if self.sequential else lib.tucker_rthosvd_ex
+            if dry:
+                s = _shape(self.dims)
+                r = (ctypes.c_int64 * len(self.ranks))(*self.ranks)
+                _check(fx(ctypes.byref(s), None, r, self.p, self.q, self.shift, self.seed, self.prec,
+                          ctypes.byref(self.opt), None, None, None, None, 0, None))
+                return
             _check(fx(ctypes.byref(self._shape), ctypes.c_void_p(A.data_ptr()), self._ranks, self.p, self.q,
                       self.shift, ctypes.c_uint64(self.seed), self.prec, ctypes.byref(self.opt),
                       ctypes.c_void_p(self.G.data_ptr()), self._uptr, ctypes.c_void_p(self.info.data_ptr()),
@@ -296,21 +328,21 @@ def rsthosvd_pve(A: torch.Tensor, ranks, p=10, q_max=20, tol=0.5, shift="adaptiv
 
 
 def rsthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
-             omega: str = "gaussian"):
+             omega: str = "gaussian", order=None):
     """Shifted randomized ST-HOSVD (Algorithm 3). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
     s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], True, A.device,
-               omega)
+               omega, order)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
 
 
 def rthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
-            omega: str = "gaussian"):
+            omega: str = "gaussian", order=None):
     """Shifted randomized T-HOSVD (Algorithm 2). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
     s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], False, A.device,
-               omega)
+               omega, order)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
 

@@ -66,6 +66,7 @@ struct Plan {
   int d;
   int64_t dims[TUCKER_MAX_ORDER];
   int64_t r[TUCKER_MAX_ORDER];
+  int ord[TUCKER_MAX_ORDER];  // processing order: ord[i] is the i-th mode processed
   int l[TUCKER_MAX_ORDER];
   int64_t m[TUCKER_MAX_ORDER];
   View3 v[TUCKER_MAX_ORDER];  // view of the tensor each mode's products read
@@ -80,8 +81,31 @@ struct Plan {
   size_t orth_bytes;
 };
 
+// Processing order of an options struct (nullptr: natural) into ord[0..d-1].
+int resolve_order(const tucker_options* opt, int d, const int64_t* dims, int* ord) {
+  for (int i = 0; i < d; ++i) ord[i] = i;
+  if (opt == nullptr || opt->order_kind == TUCKER_ORDER_NATURAL) return TUCKER_OK;
+  if (opt->order_kind == TUCKER_ORDER_DECREASING) {
+    // stable: equal sizes keep increasing mode order
+    std::stable_sort(ord, ord + d, [&](int a, int b) { return dims[a] > dims[b]; });
+    return TUCKER_OK;
+  }
+  if (opt->order_kind != TUCKER_ORDER_GIVEN) return fail(TUCKER_EINVAL, "unknown order kind %d", opt->order_kind);
+  bool seen[TUCKER_MAX_ORDER] = {};
+  for (int i = 0; i < d; ++i) {
+    const int k = opt->order[i];
+    if (k < 0 || k >= d || seen[k])
+      return fail(TUCKER_EINVAL, "order[0..%d] is not a permutation of 0..%d", d - 1, d - 1);
+    seen[k] = true;
+    ord[i] = k;
+  }
+  for (int i = d; i < TUCKER_MAX_ORDER; ++i)
+    if (opt->order[i] != 0) return fail(TUCKER_EINVAL, "order[%d] beyond the tensor order is not zero", i);
+  return TUCKER_OK;
+}
+
 int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q, tucker_precision prec,
-              bool st, Plan* pl) {
+              bool st, Plan* pl, const tucker_options* opt = nullptr) {
   int64_t numel;
   int rc = check_shape(shape, &numel);
   if (rc) return rc;
@@ -109,7 +133,11 @@ int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_
   pl->l_max = 1;
   pl->part_bytes = 256;
   pl->orth_bytes = 256;
-  for (int k = 0; k < d; ++k) {
+  rc = resolve_order(opt, d, pl->dims, pl->ord);
+  if (rc) return rc;
+  // per-mode fields are indexed by mode; ST-HOSVD's sizes follow the order
+  for (int i = 0; i < d; ++i) {
+    const int k = pl->ord[i];
     const int64_t* src = st ? cur : pl->dims;
     int64_t nk = src[k], mk = 1;
     for (int j = 0; j < d; ++j)
@@ -133,10 +161,11 @@ int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_
     pl->orth_bytes = std::max(pl->orth_bytes, orth_ws_bytes(nk, (int)lk));
     if (st) cur[k] = pl->r[k];
   }
-  // core chain intermediates (same sizes for T and ST): after contracting mode k
+  // core chain intermediates: ST contracts in processing order, T in mode order
   int64_t chain[TUCKER_MAX_ORDER];
   for (int k = 0; k < d; ++k) chain[k] = pl->dims[k];
-  for (int k = 0; k + 1 < d; ++k) {
+  for (int i = 0; i + 1 < d; ++i) {
+    const int k = st ? pl->ord[i] : i;
     chain[k] = pl->r[k];
     int64_t e = 1;
     for (int j = 0; j < d; ++j) e *= chain[j];
@@ -389,11 +418,12 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
 int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
           tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
           void* ws, size_t ws_bytes, hipStream_t st, double pve_tol = -1.0, int32_t* q_used = nullptr,
-          int omega_kind = TUCKER_OMEGA_GAUSSIAN) {
+          const tucker_options* opt = nullptr) {
   Plan pl;
   // with the per-vector-error test q is the largest power count; the plan (and
   // the per-step logs) cover the first TUCKER_MAX_Q steps
-  int rc = make_plan(shape, ranks, p, pve_tol >= 0.0 ? std::min<int32_t>(q, TUCKER_MAX_Q) : q, prec, st_variant, &pl);
+  int rc = make_plan(shape, ranks, p, pve_tol >= 0.0 ? std::min<int32_t>(q, TUCKER_MAX_Q) : q, prec, st_variant, &pl,
+                     opt);
   if (rc) return rc;
   if (shift != TUCKER_SHIFT_ADAPTIVE && shift != TUCKER_SHIFT_NONE) return fail(TUCKER_EINVAL, "bad shift mode");
   if (A == nullptr || G == nullptr || U == nullptr) return fail(TUCKER_EINVAL, "null tensor, core or factor array");
@@ -413,6 +443,7 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
     if (e != hipSuccess) return dev_check(e, "info init");
   }
   const tucker_precision core_mk = prec == TUCKER_BF16 ? TUCKER_FP32 : prec;
+  const int omega_kind = opt != nullptr ? opt->omega : TUCKER_OMEGA_GAUSSIAN;
   const void* X = A;
   int64_t cur[TUCKER_MAX_ORDER];
   for (int k = 0; k < pl.d; ++k) cur[k] = pl.dims[k];
@@ -432,13 +463,16 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
     for (int k = 1; k < pl.d && e == hipSuccess; ++k) e = hipStreamWaitEvent(lanes[k]->ms, lanes[1]->fork, 0);
     if (e != hipSuccess) return dev_check(e, "mode fork");
   }
-  for (int k = 0; k < pl.d; ++k) {
+  bool done[TUCKER_MAX_ORDER] = {};
+  for (int i = 0; i < pl.d; ++i) {
+    const int k = pl.ord[i];
     const void* Xk = st_variant ? X : A;
     const hipStream_t sk = concurrent && k > 0 ? lanes[k]->ms : st;
     const SolveWs wk = w.for_mode(k);
-    // the tensor mode k works on: A (T-HOSVD), or A with modes < k contracted (ST-HOSVD)
+    // the tensor mode k works on: A (T-HOSVD), or A with the modes processed
+    // before k contracted (ST-HOSVD)
     int64_t curk[TUCKER_MAX_ORDER];
-    for (int i = 0; i < pl.d; ++i) curk[i] = (st_variant && i < k) ? pl.r[i] : pl.dims[i];
+    for (int j = 0; j < pl.d; ++j) curk[j] = (st_variant && done[j]) ? pl.r[j] : pl.dims[j];
     const OmegaSpec om = omega_spec(omega_kind, pl.d, curk, k);
     rc = pve_tol >= 0.0 ? mode_factor_pve(pl, k, Xk, q, pve_tol, shift, seed, prec, info, wk, sk, q_used + k)
                         : mode_factor(pl, k, Xk, q, shift, seed, prec, info, wk, sk, om, concurrent ? k : 0);
@@ -446,11 +480,12 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
     e = launch_signfix(prec, wk.q64, pl.v[k].n, pl.l[k], (int)pl.r[k], U[k], wk.ut, sk);
     if (e != hipSuccess) return dev_check(e, "sign rule launch");
     if (st_variant) {
-      void* out = (k == pl.d - 1) ? G : w.xbuf[k & 1];
+      void* out = (i == pl.d - 1) ? G : w.xbuf[i & 1];
       e = launch_rowcontract(core_mk, pl.v[k], X, wk.ut, 1, pl.v[k].n, (int)pl.r[k], out, false, st);
       if (e != hipSuccess) return dev_check(e, "core launch");
       X = out;
     }
+    done[k] = true;
   }
   if (concurrent) {
     for (int k = 1; k < pl.d && e == hipSuccess; ++k) {
@@ -939,33 +974,42 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
   return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream);
 }
 
-static int check_options(const tucker_options* opt, int* kind) {
-  *kind = TUCKER_OMEGA_GAUSSIAN;
+// Field checks of an options struct (the order itself is checked against
+// the tensor order by make_plan).
+static int check_options(const tucker_options* opt) {
   if (opt == nullptr) return TUCKER_OK;
   if (opt->omega < TUCKER_OMEGA_GAUSSIAN || opt->omega > TUCKER_OMEGA_KR_UNIFORM)
     return fail(TUCKER_EINVAL, "unknown test-matrix kind %d", opt->omega);
-  for (int i = 0; i < 7; ++i)
+  if (opt->order_kind < TUCKER_ORDER_NATURAL || opt->order_kind > TUCKER_ORDER_DECREASING)
+    return fail(TUCKER_EINVAL, "unknown order kind %d", opt->order_kind);
+  for (int i = 0; i < 6; ++i)
     if (opt->reserved[i] != 0) return fail(TUCKER_EINVAL, "tucker_options.reserved[%d] is not zero", i);
-  *kind = opt->omega;
   return TUCKER_OK;
+}
+
+size_t tucker_workspace_bytes_ex(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q,
+                                 tucker_precision prec, int32_t sequential, const tucker_options* opt) {
+  if (check_options(opt)) return 0;
+  Plan pl;
+  if (make_plan(shape, ranks, p, q, prec, sequential != 0, &pl, opt)) return 0;
+  SolveWs w;
+  return solve_ws_layout(pl, prec, nullptr, &w);
 }
 
 int tucker_rthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
                       tucker_shift shift, uint64_t seed, tucker_precision prec, const tucker_options* opt, void* G,
                       void* const* U, tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
-  int kind;
-  const int rc = check_options(opt, &kind);
+  const int rc = check_options(opt);
   if (rc) return rc;
-  return solve(false, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream, -1.0, nullptr, kind);
+  return solve(false, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream, -1.0, nullptr, opt);
 }
 
 int tucker_rsthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
                        tucker_shift shift, uint64_t seed, tucker_precision prec, const tucker_options* opt, void* G,
                        void* const* U, tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
-  int kind;
-  const int rc = check_options(opt, &kind);
+  const int rc = check_options(opt);
   if (rc) return rc;
-  return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream, -1.0, nullptr, kind);
+  return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream, -1.0, nullptr, opt);
 }
 
 int tucker_fill_test_matrix(int32_t kind, uint64_t seed, int32_t mode, int32_t d, const int64_t* dims, int64_t row0,

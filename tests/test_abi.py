@@ -104,6 +104,38 @@ def test_pve_entry_point_validates_on_the_host():
     assert "q_max" in L.tucker_status_string(L.tucker_rsthosvd_pve(*args(0, 0.5, qu))).decode()
 
 
+def test_processing_order_options_on_the_host():
+    """The processing-order option: the workspace query follows the order
+    (ST-HOSVD's intermediate sizes change with it, T-HOSVD's do not), and an
+    order that is not a permutation, an unknown kind or nonzero reserved fields
+    are rejected before any device work."""
+    from paper_2506_04840_amd import _lib
+    ws = lambda seq, **kw: _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, seq, _lib.make_options(**kw))
+    nat = _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True)
+    assert nat > 0 and ws(True) == nat and ws(True, order=(0, 1, 2)) == nat
+    assert ws(True, order="decreasing") == ws(True, order=(0, 2, 1))
+    assert ws(True, order=(1, 2, 0)) > nat   # mode 1 first sketches a 12 x 2400 unfolding
+    tn = _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, False)
+    assert ws(False, order=(2, 1, 0)) == tn
+    for kw in ({"order": (0, 0, 1)}, {"order": (0, 1, 3)}, {"order": (0, 1)}, {"order": (0, 1, 2, 3)}):
+        assert ws(True, **kw) == 0, kw
+    bad = _lib.make_options()
+    bad.order_kind = 7
+    assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, bad) == 0
+    bad = _lib.make_options()
+    bad.reserved[5] = 1
+    assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, bad) == 0
+    L = _lib.lib
+    s = _lib._shape((60, 12, 40))
+    r = (ctypes.c_int64 * 3)(5, 6, 4)
+    u = (ctypes.c_void_p * 3)(16, 16, 16)
+    p16 = ctypes.c_void_p(16)
+    opt = _lib.make_options(order=(2, 2, 0))
+    rc = L.tucker_rsthosvd_ex(ctypes.byref(s), p16, r, 4, 1, 0, 1, 1, ctypes.byref(opt), p16, u, None, p16, 1 << 40,
+                              None)
+    assert rc == -1 and "permutation" in L.tucker_status_string(rc).decode()
+
+
 def test_python_binding_rejects_host_tensors():
     import torch
     from paper_2506_04840_amd import _lib

@@ -230,13 +230,14 @@ def _align_signs(ug, uo):
     return d
 
 
-def _compare_solve(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, check_core=True):
+def _compare_solve(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, check_core=True, order=None):
     from paper_2506_04840_amd import _lib as T
     fn = T.rsthosvd if variant == "st" else T.rthosvd
-    G, U, info = fn(a_dev, ranks, p=p, q=q, shift=shift, seed=seed, precision=prec)
+    G, U, info = fn(a_dev, ranks, p=p, q=q, shift=shift, seed=seed, precision=prec, order=order)
     torch.cuda.synchronize()
     g, us = _np(G), [_np(u) for u in U]
-    res = orc.randomized_hosvd(a64, ranks, p, q, shift=shift, variant=variant, seed=seed)
+    oo = orc.decreasing_order(a64.shape) if order == "decreasing" else order
+    res = orc.randomized_hosvd(a64, ranks, p, q, shift=shift, variant=variant, seed=seed, order=oo)
     tol = TOL["fp64" if prec == "fp64" else "fp32"]
     na = np.linalg.norm(a64)
     # (i) reconstruction
@@ -481,6 +482,56 @@ def test_solve_with_other_test_matrices(T, kind, variant):
     res = orc.randomized_hosvd(a, ranks, p, q, variant=variant, seed=3, omega=om)
     fn = T.rsthosvd if variant == "st" else T.rthosvd
     G, U, info = fn(_dev(a, torch.float64), ranks, p=p, q=q, seed=3, precision="fp64", omega=kind)
+    torch.cuda.synchronize()
+    d = np.linalg.norm(reconstruct(_np(G), [_np(u) for u in U]) - reconstruct(res.core, res.factors))
+    assert d / np.linalg.norm(a) <= 1e-10
+
+
+# --------------------------------------------------------------- processing order (Sections 2.2, 3.2)
+
+@pytest.mark.parametrize("order", [(2, 0, 1), (1, 2, 0), (2, 1, 0), "decreasing"])
+@pytest.mark.parametrize("q", [0, 2])
+def test_solve_st_in_processing_order_fp64(T, order, q):
+    """ST-HOSVD in a given processing order matches the oracle run in the same
+    order (reconstruction, shifts and Sigma logs per mode, subspaces, core)."""
+    a, _, _ = gen.random_tucker((33, 45, 28), (5, 6, 4), 0.05, seed=21)
+    _compare_solve(_dev(a, torch.float64), a, (5, 6, 4), 6, q, "adaptive", "st", "fp64", order=order)
+
+
+def test_solve_st_in_processing_order_fp32_order4(T):
+    a, _, _ = gen.random_tucker((20, 44, 12, 36), (4, 7, 3, 6), 0.02, seed=27)
+    a32 = a.astype(np.float32)
+    for order in ("decreasing", (3, 0, 2, 1)):
+        print("order", order, flush=True)
+        _compare_solve(_dev(a32, torch.float32), a32.astype(np.float64), (4, 7, 3, 6), 5, 1, "adaptive", "st",
+                       "fp32", order=order)
+
+
+def test_solve_t_does_not_depend_on_the_order(T):
+    a, _, _ = gen.random_tucker((33, 45, 28), (5, 6, 4), 0.05, seed=21)
+    x = _dev(a, torch.float64)
+    G0, U0, _ = T.rthosvd(x, (5, 6, 4), p=6, q=1, seed=2, precision="fp64")
+    G1, U1, _ = T.rthosvd(x, (5, 6, 4), p=6, q=1, seed=2, precision="fp64", order=(2, 0, 1))
+    torch.cuda.synchronize()
+    assert torch.equal(G0, G1)
+    for u, v in zip(U0, U1):
+        assert torch.equal(u, v)
+
+
+def test_solve_st_in_processing_order_with_khatri_rao(T):
+    """The test matrix of each mode is drawn for its current sizes, which the
+    order decides (modes processed before k have size r)."""
+    a, _, _ = gen.random_tucker((26, 30, 22), (5, 6, 4), 0.05, seed=23)
+    ranks, p, q, order = (5, 6, 4), 5, 1, (2, 0, 1)
+
+    def om(k, m, l):
+        before = order[:order.index(k)]
+        cur = [ranks[i] if i in before else a.shape[i] for i in range(3)]
+        return orc_rng.omega_matrix("kr_gaussian", 3, k, [cur[i] for i in range(3) if i != k], l)
+
+    res = orc.randomized_hosvd(a, ranks, p, q, variant="st", seed=3, omega=om, order=order)
+    G, U, _ = T.rsthosvd(_dev(a, torch.float64), ranks, p=p, q=q, seed=3, precision="fp64", omega="kr_gaussian",
+                         order=order)
     torch.cuda.synchronize()
     d = np.linalg.norm(reconstruct(_np(G), [_np(u) for u in U]) - reconstruct(res.core, res.factors))
     assert d / np.linalg.norm(a) <= 1e-10

@@ -353,3 +353,13 @@ def test_bad_order_rejected():
     a, _, _ = random_tucker((6, 5, 4), (2, 2, 2), 0.0, seed=54)
     with pytest.raises(ValueError):
         randomized_hosvd(a, (2, 2, 2), 1, 0, order=(0, 0, 1))
+
+
+def test_decreasing_order():
+    from oracle.rhosvd import decreasing_order
+    assert decreasing_order((60, 12, 40)) == [0, 2, 1]
+    assert decreasing_order((5, 7, 7, 5)) == [1, 2, 0, 3]
+    assert decreasing_order((3,)) == [0]
+    shape = (9, 30, 30, 2, 31)
+    o = decreasing_order(shape)
+    assert sorted(o) == list(range(5)) and all(shape[o[i]] >= shape[o[i + 1]] for i in range(4))
