@@ -8,7 +8,9 @@ contraction) of a tensor already resident in HBM.
 Default workload: the 400^3 smooth-function tensor a_ijk = 1/(i+j+k-2) in
 FP32, ST-HOSVD, ranks (30,30,30), p = 10, q = 3, adaptive shift.
 Other workloads: --workload tucker3_60_fp64 | tucker4_120 | tucker3_1000 |
-serving_stream_4096.
+sparse_cp3_600 | serving_stream_4096. --order natural | decreasing | i,j,k
+sets ST-HOSVD's processing order (sparse_cp3_600 is the 600 x 700 x 800
+sparse CP tensor of the paper's order study).
 
 serving_stream_4096: 4096 order-3 FP32 requests (mode sizes U{32..256},
 Tucker ranks U{4..32}, Gaussian core x Haar factors + 1e-3 noise, p = 8,
@@ -46,6 +48,7 @@ CONFIGS = {
     "tucker3_60_fp64": dict(precision="fp64", variant="t", ranks=(10, 10, 10), p=5, q=1),
     "tucker4_120": dict(precision="bf16", variant="st", ranks=(20, 20, 20, 20), p=10, q=2),
     "tucker3_1000": dict(precision="fp32", variant="st", ranks=(50, 50, 50), p=10, q=3),
+    "sparse_cp3_600": dict(precision="fp32", variant="st", ranks=(50, 50, 50), p=10, q=1),
 }
 SERVING = "serving_stream_4096"
 SERVING_CFG = dict(count=4096, n_lo=32, n_hi=256, r_lo=4, r_hi=32, eta=1e-3, p=8, q=1, capacity=256, lclass=48,
@@ -63,6 +66,9 @@ def parse():
     ap.add_argument("--shift", default="adaptive", choices=["adaptive", "none"])
     ap.add_argument("--omega", default="gaussian", choices=["gaussian", "uniform", "kr_gaussian", "kr_uniform"],
                     help="test-matrix kind (section 5's comparison of random matrices)")
+    ap.add_argument("--ranks", default=None, help="Tucker ranks as a comma list (default: the workload's)")
+    ap.add_argument("--order", default="natural",
+                    help="processing order: natural, decreasing (by mode size) or a comma list of modes")
     ap.add_argument("--pve", type=float, default=None, metavar="TOL",
                     help="Algorithm 4: power count per mode by the per-vector-error test with this tol "
                          "(--q is then q_max, default 20)")
@@ -128,7 +134,13 @@ def reconstruct_torch(G, U):
     return t
 
 
-def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian"):
+def _order_arg(text):
+    if text in ("natural", "decreasing"):
+        return None if text == "natural" else text
+    return tuple(int(x) for x in text.split(","))
+
+
+def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian", order=None):
     """The FP64 oracle, untuned, on the host cores: one whole solve of the same
     workload when that takes seconds, else a bounded slab scaled by work."""
     import numpy as np
@@ -149,6 +161,8 @@ def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian"):
         sample = "one whole solve (FP64 oracle) of the %s slab, time scaled by %.1f (numel ratio)" % (
             "x".join(map(str, a.shape)), scale)
     a64 = a.astype(np.float64)
+    # the order of the full tensor (a slab keeps every mode but the last one's size)
+    oo = orc.decreasing_order(a_host.shape) if order == "decreasing" else order
     t0 = time.perf_counter()
     if pve is not None:
         res = orc.randomized_sthosvd_pve(a64, cfg["ranks"], cfg["p"], q, pve, shift=shift, seed=1)
@@ -158,11 +172,14 @@ def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian"):
             from oracle.philox import omega_matrix
             ranks, dims, st = cfg["ranks"], a64.shape, cfg["variant"] == "st"
 
+            seq = list(range(len(dims))) if oo is None else list(oo)
+
             def om(k, m, l):
-                cur = [ranks[i] if (st and i < k) else dims[i] for i in range(len(dims))]
+                before = seq[:seq.index(k)]
+                cur = [ranks[i] if (st and i in before) else dims[i] for i in range(len(dims))]
                 return omega_matrix(omega, 1, k, [cur[i] for i in range(len(dims)) if i != k], l)
         res = orc.randomized_hosvd(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1,
-                                   omega=om)
+                                   omega=om, order=oo)
     dt = (time.perf_counter() - t0) * scale
     out = {"value": 1.0 / dt, "unit": "approximations/s", "cores": int(threads), "kind": "oracle",
            "sample": sample, "seconds_per_solve": dt}
@@ -184,6 +201,7 @@ def main():
     if args.workload == SERVING:
         serving_main(args)
         return
+    order = _order_arg(args.order)
 
     import numpy as np
     import torch
@@ -192,6 +210,8 @@ def main():
     from workloads import generators as gen
 
     cfg = dict(CONFIGS[args.workload])
+    if args.ranks is not None:
+        cfg["ranks"] = tuple(int(x) for x in args.ranks.split(","))
     prec = args.precision or cfg["precision"]
     q = cfg["q"] if args.q is None else args.q
     dev = torch.device("cuda:0")
@@ -211,12 +231,14 @@ def main():
     if args.pve is not None:
         if cfg["variant"] != "st":
             raise SystemExit("--pve applies to ST-HOSVD workloads")
+        if order is not None:
+            raise SystemExit("--pve runs in the natural order")
         q = 20 if args.q is None else args.q
         solver = T.PveSolver(A.shape, cfg["ranks"], cfg["p"], q, args.pve, args.shift, seed=w.sketch_seed,
                              precision=prec, device=dev)
     else:
         solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
-                          sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega)
+                          sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega, order=order)
     for _ in range(args.warmup):
         solver.run(A)
     torch.cuda.synchronize()
@@ -257,7 +279,9 @@ def main():
         tk = timed[kern]
         mk = "fp32" if (prec == "bf16" and kern == "rowcontract") else prec
         roof = _roof_from_timing(tk, mk)
-        traffic = measured_traffic(kern, args.workload) if prec == CONFIGS[args.workload]["precision"] else None
+        same = prec == CONFIGS[args.workload]["precision"] and cfg["ranks"] == CONFIGS[args.workload]["ranks"]
+        traffic = measured_traffic(kern, args.workload) if same and order is None and q == CONFIGS[args.workload]["q"] \
+            else None
         roof["traffic"] = traffic
         if traffic is not None:
             roof["traffic_unit"] = "bytes/launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
@@ -271,7 +295,7 @@ def main():
     if not args.no_cpu_baseline:
         if a_host_store is None:
             a_host_store = A.double().cpu().numpy() if A.numel() <= 3e8 else A.float().cpu().numpy()
-        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q, args.pve, args.omega)
+        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q, args.pve, args.omega, order)
         if "rel_error" in cpu:
             cpu["rel_error_gpu_minus_oracle"] = re - cpu["rel_error"]
 
@@ -298,6 +322,8 @@ def main():
     }
     if args.omega != "gaussian":
         line["config"]["omega"] = args.omega
+    if order is not None:
+        line["config"]["order"] = order if isinstance(order, str) else list(order)
     if args.pve is not None:
         line["config"].update({"algorithm": "4 (per-vector-error q)", "tol": args.pve, "q_max": q,
                                "q_used": solver.q_used})

@@ -22,6 +22,10 @@ Constructions (paper section 5.1):
 * ``superdiagonal``: the tendiag(v) tensor of the paper's tensor C.
 * ``tensor_c``: tendiag(v) x_1 A_1 x_2 A_2 x_3 A_3 with A_n orthogonal n x n,
   with the three spectra (slow, fast, S-shaped) of section 5.1.
+* ``sparse_cp_factors``: the sparse CP tensor of the processing-order study
+  (section 3.2): sum_i w_i x_i o y_i o z_i with w_i = 1000/i for the first 50
+  terms and 1/i for the others, every vector with a 0.05 fraction of nonzero
+  entries, uniform on (0, 1), at positions drawn without replacement.
 """
 from __future__ import annotations
 
@@ -116,6 +120,31 @@ def tensor_c(kind: str, n: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
     return np.ascontiguousarray(t), v
 
 
+def sparse_cp_factors(dims: Sequence[int], seed: int, nterms: int = 600, heavy: int = 50,
+                      density: float = 0.05) -> Tuple[np.ndarray, List[np.ndarray]]:
+    """Weights w (nterms) and one n_k x nterms factor per mode whose columns are
+    sparse vectors (round(density n_k) nonzeros, at least one)."""
+    gen = rng(seed)
+    i = np.arange(1, nterms + 1, dtype=np.float64)
+    w = np.where(i <= heavy, 1000.0 / i, 1.0 / i)
+    factors = []
+    for n in dims:
+        f = np.zeros((n, nterms))
+        nnz = max(1, int(round(density * n)))
+        for j in range(nterms):
+            rows = gen.choice(n, size=nnz, replace=False)
+            f[rows, j] = gen.uniform(0.0, 1.0, size=nnz)
+        factors.append(f)
+    return w, factors
+
+
+def cp_tensor(w: np.ndarray, factors: Sequence[np.ndarray]) -> np.ndarray:
+    """Dense sum_i w_i f1_i o f2_i o ... (order 3)."""
+    if len(factors) != 3:
+        raise ValueError("order-3 CP tensors only")
+    return np.ascontiguousarray(np.einsum("i,ai,bi,ci->abc", w, *factors, optimize=True))
+
+
 # --------------------------------------------------------------------------
 # Named workloads: the paper's section 5 test tensors at the sizes measured
 # here (Hilbert, Tucker-plus-noise, tensor C, an order-4 Tucker tensor).
@@ -140,6 +169,7 @@ WORKLOADS = {
     "hilbert3_400": Workload("hilbert3_400", (400, 400, 400), (30, 30, 30), 10, 3, "st", "fp32"),
     "tucker4_120": Workload("tucker4_120", (120, 120, 120, 120), (20, 20, 20, 20), 10, 2, "st", "fp32"),
     "tucker3_1000": Workload("tucker3_1000", (1000, 1000, 1000), (50, 50, 50), 10, 3, "st", "fp32"),
+    "sparse_cp3_600": Workload("sparse_cp3_600", (600, 700, 800), (50, 50, 50), 10, 1, "st", "fp32"),
 }
 
 
@@ -160,6 +190,8 @@ def make_tensor(name: str, dims: Sequence[int] | None = None) -> np.ndarray:
         core = superdiagonal(1.0 / np.arange(1, r + 1, dtype=np.float64), (r,) * len(dims))
         a, _, _ = random_tucker(dims, (r,) * len(dims), 1e-4, w.data_seed, core=core)
         return a
+    if name == "sparse_cp3_600":
+        return cp_tensor(*sparse_cp_factors(dims, w.data_seed))
     raise KeyError(name)
 
 
@@ -179,6 +211,17 @@ def build_on_device(name: str, device, dims: Sequence[int] | None = None, seed: 
     seed = w.data_seed if seed is None else seed
     if name == "hilbert3_400":
         return torch.from_numpy(hilbert_tensor(dims).astype(np.float32)).to(device)
+    if name == "sparse_cp3_600":
+        # factors from the host generator; the expansion (n_1 x (n_2 n_3) times
+        # the terms) in FP64 on the device, one slab of mode-1 rows at a time
+        wt, fs = sparse_cp_factors(dims, seed)
+        x = torch.from_numpy(fs[0] * wt).to(device)
+        y, z = (torch.from_numpy(f).to(device) for f in fs[1:])
+        out = torch.empty(dims, dtype=torch.float32, device=device)
+        for b0 in range(0, dims[1], 100):
+            kr = (y[b0:b0 + 100, None, :] * z[None, :, :]).reshape(-1, x.shape[1])
+            out[:, b0:b0 + 100, :] = (x @ kr.T).reshape(dims[0], -1, dims[2]).float()
+        return out
     r = {"tucker3_60_fp64": 10, "tucker4_120": 20, "tucker3_1000": 50}[name]
     eta = {"tucker3_60_fp64": 1e-3, "tucker4_120": 1e-2, "tucker3_1000": 1e-4}[name]
     gen = rng(seed)
