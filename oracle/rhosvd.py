@@ -11,6 +11,9 @@ Follows, in the paper's order and notation:
     with shift "none" (alpha stays 0).
   * Algorithm 4 (Algorithm 3 with the power count of each mode chosen by the
     per-vector-error criterion): ``randomized_sthosvd_pve``.
+  * Appendix Algorithms A.2 and B.1 (the holistic variants: range finders
+    kept at width l_k, then a deterministic HOSVD of the small tensor):
+    ``randomized_hosvd_holistic``.
 
 Per mode k, on X = A (variant t) or X = the partially contracted core
 (variant st, dims r_1..r_{k-1}, n_k..n_d):
@@ -51,15 +54,20 @@ def svd_econ(y: np.ndarray):
     return q, s
 
 
+def column_signs(u: np.ndarray) -> np.ndarray:
+    """Sign of each column's largest-|.| entry (first on ties; +1 for a zero column)."""
+    idx = np.argmax(np.abs(u), axis=0)
+    s = np.sign(u[idx, np.arange(u.shape[1])])
+    s[s == 0] = 1.0
+    return s
+
+
 def sign_fix(u: np.ndarray) -> np.ndarray:
     """Flip columns so each column's largest-|.| entry is positive (first on ties)."""
     u = np.array(u, dtype=np.float64, copy=True)
     if u.size == 0:
         return u
-    idx = np.argmax(np.abs(u), axis=0)
-    s = np.sign(u[idx, np.arange(u.shape[1])])
-    s[s == 0] = 1.0
-    return u * s[None, :]
+    return u * column_signs(u)[None, :]
 
 
 def sketch_width(r: int, p: int, n: int, m: int) -> int:
@@ -237,6 +245,94 @@ def hosvd_full(a: np.ndarray, ranks: Sequence[int], variant: str = "st") -> Resu
         g = core_step(g, k, u_k)
         logs.append(ModeLog(qm.shape[1], x.size // x.shape[k], [0.0], [s]))
     return Result(g, factors, logs)
+
+
+def randomized_hosvd_holistic(a: np.ndarray, ranks: Sequence[int], p: int, q: int, *,
+                              shift: str = "adaptive", variant: str = "st", seed: int = 1,
+                              omega: Optional[OmegaProvider] = None,
+                              order: Optional[Sequence[int]] = None) -> Result:
+    """The holistic variants of Appendices A and B: Algorithm B.1 (variant 'st',
+    shift 'adaptive'), its unshifted model Algorithm A.2 (shift 'none'), and the
+    T-HOSVD analogue the paper names but does not print (variant 't').
+
+    Phase 1, per mode k in the processing order, on X = A (variant t) or on the
+    partially contracted tensor B (variant st, modes processed before k have
+    size l_j): the range finder of Algorithms 2 / 3 with l_k = min(r_k + p, n_k,
+    m_k) columns, all kept: Q_k (n_k x l_k). Variant st contracts
+    B <- B x_k Q_k^T at once; variant t forms B = A x_1 Q_1^T ... x_d Q_d^T
+    after the loop.
+    Phase 2, on the small tensor B (l_1 x ... x l_d): the deterministic
+    ST-HOSVD (variant st) or T-HOSVD (variant t, the revision the paper allows
+    for that step) with ranks r, in the same processing order: V_k = the
+    leading r_k left singular vectors of C_(k) (C = B for t, B contracted by
+    the V_j of the modes before k for st); U_k = Q_k V_k with the sign rule,
+    V_k's columns flipped with U_k's; G = B x_1 V_1^T ... x_d V_d^T.
+
+    Readings: Algorithm B.1 orthonormalises the sketch without an SVD and
+    starts from alpha_0 = 0; an SVD spans the same columns and, for q >= 1,
+    the last step's SVD fixes Q_k whatever basis the earlier steps used, so
+    the first step here is the one of Algorithms 2 / 3. Algorithm A.2 takes
+    every Q_k from an orthonormalisation; here Q_k is the last iterate's left
+    singular vectors (the same span; in the ST form another basis changes the
+    coordinates the next mode's test matrix multiplies, so the two agree in
+    distribution). Logs are those of phase 1."""
+    if shift not in ("adaptive", "none") or variant not in ("t", "st"):
+        raise ValueError("bad shift or variant")
+    a = np.asarray(a, dtype=np.float64)
+    d = a.ndim
+    order = list(range(d)) if order is None else [int(k) for k in order]
+    if sorted(order) != list(range(d)):
+        raise ValueError("order must be a permutation of the modes")
+    b = a.copy()
+    qs: List[Optional[np.ndarray]] = [None] * d
+    logs: List[Optional[ModeLog]] = [None] * d
+    for k in order:
+        x = a if variant == "t" else b
+        n_k = x.shape[k]
+        m_k = x.size // n_k
+        r_k = int(ranks[k])
+        if not (1 <= r_k <= n_k and r_k <= m_k):
+            raise ValueError("infeasible rank at mode %d" % k)
+        l_k = sketch_width(r_k, p, n_k, m_k)
+        om = omega(k, m_k, l_k) if omega is not None else gaussian_omega(seed, k, m_k, l_k)
+        qm, s = svd_econ(sketch(x, k, om))
+        alpha = 0.0
+        alphas, sigmas = [alpha], [s]
+        for _t in range(q):
+            qm, s = svd_econ(shifted_power(x, k, qm, alpha))
+            if shift == "adaptive":
+                alpha = shift_update(alpha, s[l_k - 1])
+            alphas.append(alpha)
+            sigmas.append(s)
+        qs[k] = qm
+        if variant == "st":
+            b = core_step(b, k, qm)
+        logs[k] = ModeLog(l_k, m_k, alphas, sigmas)
+    if variant == "t":
+        for k in range(d):
+            b = core_step(b, k, qs[k])
+    # phase 2: the deterministic (S)T-HOSVD of B
+    c = b.copy()
+    factors: List[Optional[np.ndarray]] = [None] * d
+    vs: List[Optional[np.ndarray]] = [None] * d
+    for k in order:
+        x = b if variant == "t" else c
+        r_k = int(ranks[k])
+        if r_k > min(x.shape[k], x.size // x.shape[k]):
+            raise ValueError("infeasible rank at mode %d in the small tensor" % k)
+        vm, _ = svd_econ(unfold(x, k))
+        v_k = vm[:, :r_k]
+        u_k = qs[k] @ v_k
+        sg = column_signs(u_k)
+        factors[k] = u_k * sg[None, :]
+        vs[k] = v_k * sg[None, :]
+        if variant == "st":
+            c = core_step(c, k, vs[k])
+    if variant == "t":
+        c = b
+        for k in range(d):
+            c = core_step(c, k, vs[k])
+    return Result(c, factors, logs)
 
 
 def rel_error(a: np.ndarray, res: Result) -> float:

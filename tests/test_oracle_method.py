@@ -363,3 +363,72 @@ def test_decreasing_order():
     shape = (9, 30, 30, 2, 31)
     o = decreasing_order(shape)
     assert sorted(o) == list(range(5)) and all(shape[o[i]] >= shape[o[i + 1]] for i in range(4))
+
+
+# --------------------------------------------------------------- holistic variants (Appendices A, B)
+
+from oracle.rhosvd import randomized_hosvd_holistic  # noqa: E402
+
+
+@pytest.mark.parametrize("variant", ["t", "st"])
+@pytest.mark.parametrize("q,shift", [(0, "adaptive"), (2, "adaptive"), (2, "none")])
+def test_holistic_full_width_is_the_deterministic_hosvd(variant, q, shift):
+    """With l_k = n_k the range finder spans everything (B is A rotated mode by
+    mode), so the holistic result is Algorithm 1's: the same factors after the
+    sign rule and the same core."""
+    a, _, _ = random_tucker((9, 8, 7), (3, 4, 2), 0.3, seed=61)
+    ranks = (3, 4, 2)
+    ref = hosvd_full(a, ranks, variant)
+    res = randomized_hosvd_holistic(a, ranks, 50, q, shift=shift, variant=variant, seed=5)
+    assert [lg.l for lg in res.logs] == [9, 8, 7]
+    for u, v in zip(res.factors, ref.factors):
+        assert np.max(np.abs(u - v)) < 1e-10
+    assert np.max(np.abs(res.core - ref.core)) < 1e-10 * np.linalg.norm(a)
+
+
+@pytest.mark.parametrize("variant", ["t", "st"])
+@pytest.mark.parametrize("shift", ["adaptive", "none"])
+def test_holistic_recovers_exact_rank(variant, shift):
+    a, _, _ = random_tucker((20, 18, 16), (3, 5, 4), 0.0, seed=62)
+    res = randomized_hosvd_holistic(a, (3, 5, 4), 4, 1, shift=shift, variant=variant, seed=6)
+    assert rel_error(a, res) < 1e-12
+    for u in res.factors:
+        assert np.max(np.abs(u.T @ u - np.eye(u.shape[1]))) < 1e-12
+
+
+def test_holistic_unshifted_spans_as_orth_iteration():
+    """Algorithm A.2 orthonormalises every iterate with a QR factorisation; with
+    alpha = 0 the SVD-based steps span the same columns. In the T-HOSVD form
+    every mode reads A, so the Q_k differ only by a rotation inside their span,
+    which phase 2 absorbs: an independent QR form of phase 1 followed by
+    Algorithm 1 of the small tensor gives the same approximation. (In the
+    ST-HOSVD form the rotation of Q_k changes the coordinates the next mode's
+    test matrix multiplies, so only the distribution agrees.)"""
+    a, _, _ = random_tucker((16, 14, 12), (4, 3, 5), 0.1, seed=63)
+    ranks, p, q = (4, 3, 5), 3, 2
+    res = randomized_hosvd_holistic(a, ranks, p, q, shift="none", variant="t", seed=7)
+    from oracle.philox import gaussian_omega
+    from oracle.tensor import mode_product
+    qs = []
+    for k in range(3):
+        xk = unfold(a, k)
+        l_k = min(ranks[k] + p, xk.shape[0], xk.shape[1])
+        qm, _ = np.linalg.qr(xk @ gaussian_omega(7, k, xk.shape[1], l_k))
+        for _ in range(q):
+            qm, _ = np.linalg.qr(xk @ (xk.T @ qm))
+        qs.append(qm)
+    b = a
+    for k in range(3):
+        b = mode_product(b, qs[k].T, k)
+    small = hosvd_full(b, ranks, "t")
+    ahat_qr = reconstruct(small.core, [qm @ v for qm, v in zip(qs, small.factors)])
+    assert np.linalg.norm(reconstruct(res.core, res.factors) - ahat_qr) < 1e-10 * np.linalg.norm(a)
+
+
+def test_holistic_projection_identity_and_order():
+    a, _, _ = random_tucker((15, 13, 11), (4, 3, 3), 0.05, seed=64)
+    res = randomized_hosvd_holistic(a, (4, 3, 3), 4, 1, variant="st", seed=8, order=(2, 0, 1))
+    assert abs(rel_error(a, res) - rel_error_identity(a, res.core)) < 1e-10
+    t0 = randomized_hosvd_holistic(a, (4, 3, 3), 4, 1, variant="t", seed=8)
+    t1 = randomized_hosvd_holistic(a, (4, 3, 3), 4, 1, variant="t", seed=8, order=(1, 2, 0))
+    assert np.array_equal(t0.core, t1.core)
