@@ -159,7 +159,8 @@ typedef struct {
   int32_t omega;                    /* tucker_omega */
   int32_t order_kind;               /* tucker_order */
   int32_t order[TUCKER_MAX_ORDER];  /* TUCKER_ORDER_GIVEN: processing order, first d entries */
-  int32_t reserved[6];              /* zero */
+  int32_t holistic;                 /* 0: Algorithms 2 / 3; 1: the holistic variants (below) */
+  int32_t reserved[5];              /* zero */
 } tucker_options;
 
 /* Sketch Y = X_(mode) Omega_mode (Algorithms 2 and 3: the first product of
@@ -247,8 +248,25 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
  * every factor from A (the order does not change its result) and contracts
  * the core in mode order. Factors, info logs and test-matrix streams stay
  * indexed by mode. Workspace: tucker_workspace_bytes_ex with the same opt.
- * EINVAL for an unknown kind, an order that is not a permutation of 0..d-1
- * or nonzero reserved fields; otherwise as the plain calls. */
+ *
+ * opt->holistic = 1 selects the holistic variants of Appendices A and B
+ * (Algorithm B.1 for tucker_rsthosvd_ex with the adaptive shift, its
+ * unshifted model A.2 with TUCKER_SHIFT_NONE, and their T-HOSVD analogue for
+ * tucker_rthosvd_ex). Phase 1 runs each mode's range finder as above but keeps
+ * all l_k columns Q_k: ST-HOSVD contracts B = B x_k Q_k^T at once (later modes
+ * see size l_k there, which sets their m and l), T-HOSVD forms B = A x_1
+ * Q_1^T ... x_d Q_d^T after the loop. Phase 2 takes the deterministic
+ * ST-HOSVD (T-HOSVD) of the small tensor B (l_1 x ... x l_d) in the same
+ * order: V_k = leading r_k left singular vectors of the current unfolding
+ * (CholeskyQR and one-sided Jacobi in FP64), U_k = Q_k V_k with the sign rule,
+ * G = B x_k V_k^T with V_k's columns signed like U_k's. Info logs hold phase 1.
+ * EINVAL also when some r_k exceeds the product of the other current sizes
+ * in phase 2 (no unfolding of the small tensor has that rank); EUNSUPPORTED
+ * for order d = 1.
+ *
+ * EINVAL for an unknown kind, an order that is not a permutation of 0..d-1,
+ * holistic outside 0..1 or nonzero reserved fields; otherwise as the plain
+ * calls. */
 size_t tucker_workspace_bytes_ex(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q,
                                  tucker_precision prec, int32_t sequential, const tucker_options* opt);
 int tucker_rthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,

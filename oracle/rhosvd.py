@@ -258,7 +258,7 @@ def randomized_hosvd_holistic(a: np.ndarray, ranks: Sequence[int], p: int, q: in
     Phase 1, per mode k in the processing order, on X = A (variant t) or on the
     partially contracted tensor B (variant st, modes processed before k have
     size l_j): the range finder of Algorithms 2 / 3 with l_k = min(r_k + p, n_k,
-    m_k) columns, all kept: Q_k (n_k x l_k). Variant st contracts
+    m_k) columns, all kept, with the sign rule: Q_k (n_k x l_k). Variant st contracts
     B <- B x_k Q_k^T at once; variant t forms B = A x_1 Q_1^T ... x_d Q_d^T
     after the loop.
     Phase 2, on the small tensor B (l_1 x ... x l_d): the deterministic
@@ -275,7 +275,10 @@ def randomized_hosvd_holistic(a: np.ndarray, ranks: Sequence[int], p: int, q: in
     every Q_k from an orthonormalisation; here Q_k is the last iterate's left
     singular vectors (the same span; in the ST form another basis changes the
     coordinates the next mode's test matrix multiplies, so the two agree in
-    distribution). Logs are those of phase 1."""
+    distribution). For the same reason Q_k takes the sign rule before the
+    contraction: its column signs set the next test matrix's coordinates, and
+    the sign rule makes them independent of the SVD routine. Logs are those of
+    phase 1."""
     if shift not in ("adaptive", "none") or variant not in ("t", "st"):
         raise ValueError("bad shift or variant")
     a = np.asarray(a, dtype=np.float64)
@@ -304,9 +307,9 @@ def randomized_hosvd_holistic(a: np.ndarray, ranks: Sequence[int], p: int, q: in
                 alpha = shift_update(alpha, s[l_k - 1])
             alphas.append(alpha)
             sigmas.append(s)
-        qs[k] = qm
+        qs[k] = sign_fix(qm)
         if variant == "st":
-            b = core_step(b, k, qm)
+            b = core_step(b, k, qs[k])
         logs[k] = ModeLog(l_k, m_k, alphas, sigmas)
     if variant == "t":
         for k in range(d):

@@ -55,18 +55,20 @@ INFO_BYTES = ctypes.sizeof(Info)
 
 class Options(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_int32), ("order_kind", ctypes.c_int32), ("order", ctypes.c_int32 * 8),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("holistic", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 OMEGA = {"gaussian": 0, "uniform": 1, "kr_gaussian": 2, "kr_uniform": 3}
 ORDER_NATURAL, ORDER_GIVEN, ORDER_DECREASING = 0, 1, 2
 
 
-def make_options(omega: str = "gaussian", order=None) -> Options:
-    """Options struct: test-matrix kind and processing order (None: 0..d-1,
-    "decreasing": by decreasing mode size, or a permutation of the modes)."""
+def make_options(omega: str = "gaussian", order=None, holistic: bool = False) -> Options:
+    """Options struct: test-matrix kind, processing order (None: 0..d-1,
+    "decreasing": by decreasing mode size, or a permutation of the modes) and
+    the holistic variants of Appendices A / B."""
     opt = Options()
     opt.omega = OMEGA[omega]
+    opt.holistic = 1 if holistic else 0
     if order is None or order == "natural":
         opt.order_kind = ORDER_NATURAL
     elif order == "decreasing":
@@ -229,9 +231,9 @@ class Solver:
     """
 
     def __init__(self, dims, ranks, p=10, q=1, shift="adaptive", seed=1, precision="fp32", sequential=True,
-                 device="cuda", omega="gaussian", order=None):
-        self.opt = make_options(omega, order)
-        self.plain = self.opt.omega == 0 and self.opt.order_kind == ORDER_NATURAL
+                 device="cuda", omega="gaussian", order=None, holistic=False):
+        self.opt = make_options(omega, order, holistic)
+        self.plain = self.opt.omega == 0 and self.opt.order_kind == ORDER_NATURAL and not holistic
         self.dims = tuple(int(x) for x in dims)
         self.ranks = tuple(int(x) for x in ranks)
         self.p, self.q, self.seed = int(p), int(q), int(seed)
@@ -328,21 +330,21 @@ def rsthosvd_pve(A: torch.Tensor, ranks, p=10, q_max=20, tol=0.5, shift="adaptiv
 
 
 def rsthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
-             omega: str = "gaussian", order=None):
+             omega: str = "gaussian", order=None, holistic: bool = False):
     """Shifted randomized ST-HOSVD (Algorithm 3). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
     s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], True, A.device,
-               omega, order)
+               omega, order, holistic)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
 
 
 def rthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
-            omega: str = "gaussian", order=None):
+            omega: str = "gaussian", order=None, holistic: bool = False):
     """Shifted randomized T-HOSVD (Algorithm 2). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
     s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], False, A.device,
-               omega, order)
+               omega, order, holistic)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
 

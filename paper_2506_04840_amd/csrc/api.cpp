@@ -71,6 +71,7 @@ struct Plan {
   int64_t m[TUCKER_MAX_ORDER];
   View3 v[TUCKER_MAX_ORDER];  // view of the tensor each mode's products read
   bool st;
+  bool holistic;        // Appendix A / B variants: modes keep width l_k, then a small HOSVD
   int32_t flags;
   int64_t xbuf_elems;   // largest intermediate of the core chain
   int64_t omz_elems;    // largest m_k * l_k (Omega / Z)
@@ -79,6 +80,9 @@ struct Plan {
   int l_max;
   size_t part_bytes;
   size_t orth_bytes;
+  // holistic variants: the small tensor B (sizes l_k) and its deterministic HOSVD
+  int64_t b_elems;      // numel(B)
+  size_t orth2_bytes;   // largest orthonormalisation workspace of phase 2
 };
 
 // Processing order of an options struct (nullptr: natural) into ord[0..d-1].
@@ -116,6 +120,7 @@ int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_
   const int d = shape->order;
   pl->d = d;
   pl->st = st;
+  pl->holistic = opt != nullptr && opt->holistic != 0;
   pl->flags = 0;
   int64_t cur[TUCKER_MAX_ORDER];
   for (int k = 0; k < d; ++k) {
@@ -159,17 +164,42 @@ int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_
     pl->l_max = std::max(pl->l_max, (int)lk);
     pl->part_bytes = std::max(pl->part_bytes, colreduce_part_bytes(pl->v[k], (int)lk, prec));
     pl->orth_bytes = std::max(pl->orth_bytes, orth_ws_bytes(nk, (int)lk));
-    if (st) cur[k] = pl->r[k];
+    if (st) cur[k] = pl->holistic ? lk : pl->r[k];
   }
   // core chain intermediates: ST contracts in processing order, T in mode order
+  // (the holistic variants keep l_k columns there)
   int64_t chain[TUCKER_MAX_ORDER];
   for (int k = 0; k < d; ++k) chain[k] = pl->dims[k];
   for (int i = 0; i + 1 < d; ++i) {
     const int k = st ? pl->ord[i] : i;
-    chain[k] = pl->r[k];
+    chain[k] = pl->holistic ? pl->l[k] : pl->r[k];
     int64_t e = 1;
     for (int j = 0; j < d; ++j) e *= chain[j];
     pl->xbuf_elems = std::max(pl->xbuf_elems, e);
+  }
+  pl->b_elems = 1;
+  pl->orth2_bytes = 256;
+  if (pl->holistic && d < 2) return fail(TUCKER_EUNSUPPORTED, "the holistic variants need order d >= 2");
+  if (pl->holistic) {
+    // phase 2 walks the small tensor: mode k's unfolding is l_k x m with m the
+    // product of the other current sizes (ST: r for the modes done, l else)
+    int64_t c2[TUCKER_MAX_ORDER];
+    for (int k = 0; k < d; ++k) {
+      c2[k] = pl->l[k];
+      pl->b_elems *= pl->l[k];
+    }
+    for (int i = 0; i < d; ++i) {
+      const int k = pl->ord[i];
+      int64_t m = 1;
+      for (int j = 0; j < d; ++j)
+        if (j != k) m *= c2[j];
+      if (pl->r[k] > m)
+        return fail(TUCKER_EINVAL, "rank r[%d] = %lld exceeds the small tensor's other sizes' product %lld", k,
+                    (long long)pl->r[k], (long long)m);
+      const int64_t lk = pl->l[k];
+      pl->orth2_bytes = std::max(pl->orth2_bytes, m >= lk ? orth_ws_bytes(m, (int)lk) : orth_ws_bytes(lk, (int)m));
+      if (st) c2[k] = pl->r[k];
+    }
   }
   return TUCKER_OK;
 }
@@ -203,6 +233,15 @@ struct SolveWs {
   int* stop;        // its stopping flag
   ModeWs mode_store[TUCKER_MAX_ORDER];
   ModeWs* mode[TUCKER_MAX_ORDER];  // T-HOSVD: own scratch of modes 1..d-1 (else nullptr)
+  // holistic variants
+  double* hq64[TUCKER_MAX_ORDER];  // Q_k, n_k x l_k FP64
+  void* hqt[TUCKER_MAX_ORDER];     // Q_k^T j-major (l_k x n_k), storage precision
+  void* hvt[TUCKER_MAX_ORDER];     // signed V_k^T j-major (r_k x l_k), storage precision
+  void* bbuf;                      // the small tensor B
+  double* y2;                      // phase-2 unfolding, FP64
+  void* orth2;
+  double* v2;                      // phase-2 singular vectors (l_k x l_k at most)
+  double* sig2;
 
   // the scratch mode k works in (shared pointers stay)
   SolveWs for_mode(int k) const {
@@ -248,8 +287,27 @@ size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveW
   w->stop = (int*)take(64);
   // T-HOSVD: the modes are independent and run concurrently; modes 1..d-1
   // get their own copy of the per-mode scratch (mode 0 uses the one above)
-  for (int k = 0; k < TUCKER_MAX_ORDER; ++k) w->mode[k] = nullptr;
-  if (!pl.st)
+  for (int k = 0; k < TUCKER_MAX_ORDER; ++k) {
+    w->mode[k] = nullptr;
+    w->hq64[k] = nullptr;
+    w->hqt[k] = w->hvt[k] = nullptr;
+  }
+  w->bbuf = w->orth2 = nullptr;
+  w->y2 = w->v2 = w->sig2 = nullptr;
+  if (pl.holistic) {
+    const size_t cs = elem_bytes(prec == TUCKER_BF16 ? TUCKER_FP32 : prec);  // core-chain storage
+    for (int k = 0; k < pl.d; ++k) {
+      w->hq64[k] = (double*)take((size_t)pl.dims[k] * pl.l[k] * 8);
+      w->hqt[k] = take((size_t)pl.dims[k] * pl.l[k] * cs);
+      w->hvt[k] = take((size_t)pl.r[k] * pl.l[k] * cs);
+    }
+    w->bbuf = take((size_t)pl.b_elems * cs);
+    w->y2 = (double*)take((size_t)pl.b_elems * 8);
+    w->orth2 = take(pl.orth2_bytes);
+    w->v2 = (double*)take(TUCKER_MAX_L * TUCKER_MAX_L * 8);
+    w->sig2 = (double*)take(TUCKER_MAX_L * 8);
+  }
+  if (!pl.st && !pl.holistic)
     for (int k = 1; k < pl.d; ++k) {
       ModeWs& mw = w->mode_store[k];
       mw.omz = take((size_t)pl.omz_elems * es);
@@ -318,7 +376,8 @@ int side_ctx(SideCtx** out, int lane = 0) {
 // alpha Q3) J = X X^T Q - alpha Q, the same iterate. On return ws.q64 holds
 // the left singular vectors of the last iterate (FP64, n x l, descending).
 int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
-                tucker_info* info, const SolveWs& w, hipStream_t st, const OmegaSpec& om, int lane = 0) {
+                tucker_info* info, const SolveWs& w, hipStream_t st, const OmegaSpec& om, int lane = 0,
+                void* qt_out = nullptr) {
   const View3 v = pl.v[k];
   const int l = pl.l[k];
   const int64_t n = v.n, m = pl.m[k];
@@ -362,10 +421,10 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
       e = launch_reduce_splits(tp, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
     if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, tp, w.qt, ows, cseed, t, st);
   }
-  // last small SVD on the caller's stream, then Q = Q3 J
+  // last small SVD on the caller's stream, then Q = Q3 J (also as Q^T j-major when asked)
   if (e == hipSuccess)
     e = launch_orth_svd(l, step_prec(q), ows, w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q, st);
-  if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, nullptr, w.q64, st);
+  if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, qt_out, w.q64, st);
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch");
 }
 
@@ -415,6 +474,13 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch (per-vector-error)");
 }
 
+int solve_holistic(const Plan& pl, const void* A, tucker_shift shift, int32_t q, uint64_t seed,
+                   tucker_precision prec, void* G, void* const* U, tucker_info* info, const SolveWs& w, hipStream_t st,
+                   int omega_kind);
+int solve_modes(const Plan& pl, const void* A, tucker_shift shift, int32_t q, uint64_t seed, tucker_precision prec,
+                void* G, void* const* U, tucker_info* info, const SolveWs& w, hipStream_t st, int omega_kind,
+                double pve_tol, int32_t* q_used);
+
 int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
           tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
           void* ws, size_t ws_bytes, hipStream_t st, double pve_tol = -1.0, int32_t* q_used = nullptr,
@@ -442,8 +508,32 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
     e = launch_info_init(info, ls, pl.d, pl.flags, st);
     if (e != hipSuccess) return dev_check(e, "info init");
   }
-  const tucker_precision core_mk = prec == TUCKER_BF16 ? TUCKER_FP32 : prec;
   const int omega_kind = opt != nullptr ? opt->omega : TUCKER_OMEGA_GAUSSIAN;
+  if (pl.holistic) {
+    if (pve_tol >= 0.0) return fail(TUCKER_EUNSUPPORTED, "the per-vector-error test runs Algorithm 3 only");
+    rc = solve_holistic(pl, A, shift, q, seed, prec, G, U, info, w, st, omega_kind);
+    if (rc) return rc;
+  } else {
+    rc = solve_modes(pl, A, shift, q, seed, prec, G, U, info, w, st, omega_kind, pve_tol, q_used);
+    if (rc) return rc;
+  }
+  if (info != nullptr) {
+    int64_t gn = 1;
+    for (int k = 0; k < pl.d; ++k) gn *= pl.r[k];
+    e = launch_norm2(prec, G, gn, w.normpart, &info->normG2, st);
+    if (e != hipSuccess) return dev_check(e, "norm launch");
+  }
+  return TUCKER_OK;
+}
+
+// Algorithms 2, 3 and 4 after the plan: every mode's factor, then the core.
+int solve_modes(const Plan& pl, const void* A, tucker_shift shift, int32_t q, uint64_t seed, tucker_precision prec,
+                void* G, void* const* U, tucker_info* info, const SolveWs& w, hipStream_t st, int omega_kind,
+                double pve_tol, int32_t* q_used) {
+  const bool st_variant = pl.st;
+  hipError_t e = hipSuccess;
+  int rc = TUCKER_OK;
+  const tucker_precision core_mk = prec == TUCKER_BF16 ? TUCKER_FP32 : prec;
   const void* X = A;
   int64_t cur[TUCKER_MAX_ORDER];
   for (int k = 0; k < pl.d; ++k) cur[k] = pl.dims[k];
@@ -504,11 +594,104 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
       cur[k] = pl.r[k];
     }
   }
-  if (info != nullptr) {
-    int64_t gn = 1;
-    for (int k = 0; k < pl.d; ++k) gn *= pl.r[k];
-    e = launch_norm2(prec, G, gn, w.normpart, &info->normG2, st);
-    if (e != hipSuccess) return dev_check(e, "norm launch");
+  return TUCKER_OK;
+}
+
+// The holistic variants (Appendix Algorithms A.2 / B.1 and the T-HOSVD
+// analogue). Phase 1: each mode's range finder (mode_factor) keeps all l_k
+// columns Q_k, signed by the sign rule; ST contracts B = B x_k Q_k^T at once, T forms B from A after
+// the loop. Phase 2: the deterministic (S)T-HOSVD of B (sizes l_k): mode k's
+// unfolding (l_k x m) goes to FP64; when m >= l_k its transpose is
+// orthonormalised and V_k are the right singular vectors of the R factor,
+// else the unfolding itself and V_k are its left singular vectors; then
+// U_k = Q_k V_k with the sign rule and the core contraction by the signed V_k.
+int solve_holistic(const Plan& pl, const void* A, tucker_shift shift, int32_t q, uint64_t seed,
+                   tucker_precision prec, void* G, void* const* U, tucker_info* info, const SolveWs& w, hipStream_t st,
+                   int omega_kind) {
+  const int d = pl.d;
+  const tucker_precision core_mk = prec == TUCKER_BF16 ? TUCKER_FP32 : prec;
+  hipError_t e = hipSuccess;
+  int rc = TUCKER_OK;
+  // phase 1
+  const void* X = A;
+  bool done[TUCKER_MAX_ORDER] = {};
+  for (int i = 0; i < d; ++i) {
+    const int k = pl.ord[i];
+    int64_t curk[TUCKER_MAX_ORDER];
+    for (int j = 0; j < d; ++j) curk[j] = (pl.st && done[j]) ? pl.l[j] : pl.dims[j];
+    const OmegaSpec om = omega_spec(omega_kind, d, curk, k);
+    SolveWs wk = w;
+    wk.q64 = w.hq64[k];
+    rc = mode_factor(pl, k, pl.st ? X : A, q, shift, seed, prec, info, wk, st, om);
+    if (rc) return rc;
+    // Q_k with the sign rule (its basis fixes the coordinates the next mode's
+    // test matrix multiplies), kept in FP64 and as Q_k^T in the storage precision
+    e = launch_signcols(core_mk, w.hq64[k], pl.dims[k], pl.l[k], w.hqt[k], st);
+    if (e != hipSuccess) return dev_check(e, "sign rule launch");
+    if (pl.st) {
+      void* out = (i == d - 1) ? w.bbuf : w.xbuf[i & 1];
+      e = launch_rowcontract(core_mk, pl.v[k], X, w.hqt[k], 1, pl.dims[k], pl.l[k], out, false, st);
+      if (e != hipSuccess) return dev_check(e, "range contraction launch");
+      X = out;
+    }
+    done[k] = true;
+  }
+  if (!pl.st) {
+    int64_t cur[TUCKER_MAX_ORDER];
+    for (int k = 0; k < d; ++k) cur[k] = pl.dims[k];
+    X = A;
+    for (int k = 0; k < d; ++k) {
+      void* out = (k == d - 1) ? w.bbuf : w.xbuf[k & 1];
+      e = launch_rowcontract(core_mk, view_of(cur, d, k), X, w.hqt[k], 1, pl.dims[k], pl.l[k], out, false, st);
+      if (e != hipSuccess) return dev_check(e, "range contraction launch");
+      X = out;
+      cur[k] = pl.l[k];
+    }
+  }
+  // phase 2: the deterministic (S)T-HOSVD of B
+  int64_t cur[TUCKER_MAX_ORDER];
+  for (int k = 0; k < d; ++k) cur[k] = pl.l[k];
+  const void* C = w.bbuf;
+  for (int i = 0; i < d; ++i) {
+    const int k = pl.ord[i];
+    const View3 v = view_of(cur, d, k);
+    const int64_t lk = pl.l[k];
+    const int64_t m = v.P * v.S;
+    const bool tall = m >= lk;
+    const int64_t rows = tall ? m : lk;
+    const int cols = (int)(tall ? lk : m);
+    const OrthWs o2 = carve_orth(w.orth2, rows, cols);
+    // the unfolding is exact in FP64 whatever the storage: FP64 settings (shifted
+    // first CholeskyQR pass, rotations down to l u), so every column of V_k
+    // comes out orthonormal, also those at the storage rounding level
+    e = launch_unfold64(core_mk, v, pl.st ? C : w.bbuf, tall, w.y2, st);
+    if (e == hipSuccess)
+      e = launch_orth_qr(rows, cols, w.y2, nullptr, TUCKER_FP64, nullptr, o2,
+                         completion_seed(seed, TUCKER_MAX_ORDER + k), 0, st);
+    if (e == hipSuccess)
+      e = launch_orth_svd(cols, TUCKER_FP64, o2, w.sig2, nullptr, nullptr, -1, -1, st, nullptr,
+                          tall ? w.v2 : nullptr);
+    if (e == hipSuccess && !tall) e = launch_orth_rotate(rows, cols, o2, core_mk, nullptr, nullptr, w.v2, st);
+    if (e == hipSuccess)
+      e = launch_assemble(core_mk, w.hq64[k], pl.dims[k], (int)lk, w.v2, cols, (int)pl.r[k], U[k], w.hvt[k], st);
+    if (e != hipSuccess) return dev_check(e, "small HOSVD launch");
+    if (pl.st) {
+      void* out = (i == d - 1) ? G : w.xbuf[i & 1];
+      e = launch_rowcontract(core_mk, v, C, w.hvt[k], 1, lk, (int)pl.r[k], out, false, st);
+      if (e != hipSuccess) return dev_check(e, "core launch");
+      C = out;
+      cur[k] = pl.r[k];
+    }
+  }
+  if (!pl.st) {
+    X = w.bbuf;
+    for (int k = 0; k < d; ++k) {
+      void* out = (k == d - 1) ? G : w.xbuf[k & 1];
+      e = launch_rowcontract(core_mk, view_of(cur, d, k), X, w.hvt[k], 1, pl.l[k], (int)pl.r[k], out, false, st);
+      if (e != hipSuccess) return dev_check(e, "core launch");
+      X = out;
+      cur[k] = pl.r[k];
+    }
   }
   return TUCKER_OK;
 }
@@ -982,7 +1165,8 @@ static int check_options(const tucker_options* opt) {
     return fail(TUCKER_EINVAL, "unknown test-matrix kind %d", opt->omega);
   if (opt->order_kind < TUCKER_ORDER_NATURAL || opt->order_kind > TUCKER_ORDER_DECREASING)
     return fail(TUCKER_EINVAL, "unknown order kind %d", opt->order_kind);
-  for (int i = 0; i < 6; ++i)
+  if (opt->holistic != 0 && opt->holistic != 1) return fail(TUCKER_EINVAL, "holistic = %d is not 0 or 1", opt->holistic);
+  for (int i = 0; i < 5; ++i)
     if (opt->reserved[i] != 0) return fail(TUCKER_EINVAL, "tucker_options.reserved[%d] is not zero", i);
   return TUCKER_OK;
 }

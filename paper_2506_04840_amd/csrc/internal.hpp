@@ -122,8 +122,11 @@ struct SvdPve {
   double* sig_hat;  // l doubles
   int* stop;
 };
+// vright (when not nullptr): the right singular vectors of R (l x l, columns,
+// descending), unit columns of the rotated R^T (zero where Sigma is zero).
 hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
-                           tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve = nullptr);
+                           tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve = nullptr,
+                           double* vright = nullptr);
 // Q = Q3 Wm to q_out (n x l, `prec` storage), qt (j-major l x n, `prec`
 // storage) and q64 (n x l, FP64), each when not nullptr.
 hipError_t launch_orth_rotate(int64_t n, int l, const OrthWs& ws, tucker_precision prec, void* q_out, void* qt,
@@ -138,6 +141,18 @@ hipError_t launch_orth(int64_t n, int l, double* Y, tucker_precision prec, void*
 // n x r and Ut (when not nullptr) j-major r x n, both in `prec` storage.
 hipError_t launch_signfix(tucker_precision prec, const double* Q, int64_t n, int l, int r, void* U, void* Ut,
                           hipStream_t st);
+
+// Mode unfolding of X (view v, storage prec) in FP64: trans ? m x n : n x m
+// (m = P S, columns in row-major order over the other modes).
+hipError_t launch_unfold64(tucker_precision prec, const View3& v, const void* X, bool trans, double* Y,
+                           hipStream_t st);
+// The sign rule in place on every column of Q (FP64 n x l), and Qt = Q^T
+// j-major (l x n) in `prec` storage.
+hipError_t launch_signcols(tucker_precision prec, double* Q, int64_t n, int l, void* Qt, hipStream_t st);
+// U = (Q V(:, 0:r)) S and Vt = (V(:, 0:r) S)^T j-major (r x l), S the sign
+// rule of launch_signfix applied to Q V; Q FP64 n x l, V FP64 l x ldv.
+hipError_t launch_assemble(tucker_precision prec, const double* Q, int64_t n, int l, const double* V, int ldv, int r,
+                           void* U, void* Vt, hipStream_t st);
 
 // Small helpers.
 hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t count, double* dst,

@@ -567,7 +567,11 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
 
 // Racc = R3 R2 R1 (R3 = I when pass 3 did not run), one-sided Jacobi on
 // Racc^T, sort, shift update, log. Writes Wm (left singular vectors of R as
-// columns, descending) and sigma.
+// columns, descending), sigma and, when vright != nullptr, the right singular
+// vectors of R (l x l, columns, descending): the rotated columns of Racc^T
+// scaled to unit norm (a zero column stays zero). Columns of Racc^T left
+// unrotated as noise (below negl) are orthogonal to the others only to that
+// level.
 // Pairs follow the circle method (player 0 fixed, the others rotate); a pair
 // is left alone when its columns are orthogonal to tol relative to their
 // norms or when either column is below negl times the largest (rounding
@@ -582,7 +586,7 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
                                                    int mode, int step, int pve_r, double pve_tol, double pve_floor,
                                                    const double* __restrict__ alpha_prev, double* __restrict__ sig_hat,
-                                                   int* __restrict__ stop, int bid) {
+                                                   int* __restrict__ stop, double* __restrict__ vright, int bid) {
   __shared__ double A[kMaxL][OR_LS];  // A[a][x] = column a of R^T = row a of R
   __shared__ double J[kMaxL][OR_LS];  // J[a][x] = column a of the rotation
   __shared__ double sv[kMaxL];
@@ -714,6 +718,10 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
   for (int e = tid; e < l * l; e += 256) {
     const int x = e / l, j = e % l;
     Wm[e] = J[perm[j]][x];
+    if (vright != nullptr) {
+      const double nv = sv[perm[j]];
+      vright[e] = nv > 0.0 ? A[perm[j]][x] / nv : 0.0;
+    }
   }
   if (sigma != nullptr)
     for (int j = tid; j < l; j += 256) sigma[j] = sv[perm[j]];
@@ -759,9 +767,9 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
                                                    int mode, int step, int pve_r, double pve_tol, double pve_floor,
                                                    const double* __restrict__ alpha_prev, double* __restrict__ sig_hat,
-                                                   int* __restrict__ stop) {
+                                                   int* __restrict__ stop, double* __restrict__ vright) {
   small_svd_body<RPT>(Rg, l, status, tol, negl, Wm, sigma, alpha, info, mode, step, pve_r, pve_tol, pve_floor,
-                      alpha_prev, sig_hat, stop, (int)blockIdx.x);
+                      alpha_prev, sig_hat, stop, vright, (int)blockIdx.x);
 }
 
 // Q = Q3 Wm, written in the storage precision (and optionally in FP64).
@@ -839,14 +847,15 @@ hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucke
 
 template <int RPT>
 static void svd_launch(int l, const OrthWs& ws, double tol, double negl, double* sigma, double* alpha,
-                       tucker_info* info, int mode, int step, const SvdPve& pv, hipStream_t st) {
+                       tucker_info* info, int mode, int step, const SvdPve& pv, double* vright, hipStream_t st) {
   hipLaunchKernelGGL((k_small_svd<RPT>), dim3(1), dim3(256), 0, st, (const double*)ws.R, l, (const int*)ws.status,
                      tol, negl, ws.Wm, sigma, alpha, info, mode, step, pv.r, pv.tol, pv.floor, pv.alpha_prev,
-                     pv.sig_hat, pv.stop);
+                     pv.sig_hat, pv.stop, vright);
 }
 
 hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
-                           tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve) {
+                           tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve,
+                           double* vright) {
   const SvdPve off{0, -1.0, 0.0, nullptr, nullptr, nullptr};
   const SvdPve& pv = pve != nullptr ? *pve : off;
   // Rotation thresholds by the precision the iterate was formed in: FP64
@@ -857,14 +866,14 @@ hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, doubl
   const double tol = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-8 : 1e-7;
   const double negl = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-6 : 1e-4;
   switch ((l + 7) / 8) {
-    case 1: svd_launch<1>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
-    case 2: svd_launch<2>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
-    case 3: svd_launch<3>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
-    case 4: svd_launch<4>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
-    case 5: svd_launch<5>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
-    case 6: svd_launch<6>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
-    case 7: svd_launch<7>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
-    case 8: svd_launch<8>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, st); break;
+    case 1: svd_launch<1>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 2: svd_launch<2>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 3: svd_launch<3>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 4: svd_launch<4>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 5: svd_launch<5>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 6: svd_launch<6>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 7: svd_launch<7>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 8: svd_launch<8>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -946,6 +955,144 @@ hipError_t launch_signfix(tucker_precision prec, const double* Q, int64_t n, int
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Holistic variants: the small tensor's unfoldings in FP64 and the factor
+// assembly U_k = Q_k V_k.
+// ---------------------------------------------------------------------------
+// X viewed as P x n x S (storage T). trans: Y[(p S + s) n + i] = X[p, i, s]
+// (the transposed mode unfolding, m x n); else Y[i m + p S + s] (the
+// unfolding itself, n x m). m = P S.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unfold64(const T* __restrict__ X, int64_t P, int64_t n, int64_t S, int trans,
+                                                  double* __restrict__ Y) {
+  const int64_t total = P * n * S;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t s = e % S, t = e / S;
+    const int64_t i = t % n, p = t / n;
+    const int64_t c = p * S + s;
+    Y[trans ? c * n + i : i * (P * S) + c] = (double)X[e];
+  }
+}
+
+hipError_t launch_unfold64(tucker_precision prec, const View3& v, const void* X, bool trans, double* Y,
+                           hipStream_t st) {
+  const int64_t total = v.P * v.n * v.S;
+  const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+  if (prec == TUCKER_FP64)
+    hipLaunchKernelGGL((k_unfold64<double>), dim3(g), dim3(256), 0, st, (const double*)X, v.P, v.n, v.S, (int)trans,
+                       Y);
+  else
+    hipLaunchKernelGGL((k_unfold64<float>), dim3(g), dim3(256), 0, st, (const float*)X, v.P, v.n, v.S, (int)trans,
+                       Y);
+  return hipGetLastError();
+}
+
+// Column c of U = sign_c Q V(:, c) (Q FP64 n x l, V FP64 l x ldv, columns
+// c < r), with the sign rule of k_signfix (largest magnitude positive, lowest
+// row on ties, +1 for a zero column); Vt row c = sign_c V(:, c) (j-major r x l).
+// One workgroup per column; both passes form each entry by the same FMA chain.
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ Q, int64_t n, int l,
+                                                  const double* __restrict__ V, int ldv, int r, T* __restrict__ U,
+                                                  T* __restrict__ Vt) {
+  __shared__ double vc[kMaxL];
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int c = blockIdx.x;
+  for (int j = threadIdx.x; j < l; j += 256) vc[j] = V[(int64_t)j * ldv + c];
+  __syncthreads();
+  auto entry = [&](int64_t i) {
+    double w = 0.0;
+    for (int j = 0; j < l; ++j) w = fma(Q[i * l + j], vc[j], w);
+    return w;
+  };
+  double best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double a = fabs(entry(i));
+    if (a > best) {
+      best = a;
+      bidx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double o = bv[threadIdx.x + w];
+      const int64_t oi = bi[threadIdx.x + w];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const double sgn = entry(bi[0]) < 0.0 ? -1.0 : 1.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) U[i * r + c] = (T)(sgn * entry(i));
+  for (int j = threadIdx.x; j < l; j += 256) Vt[(int64_t)c * l + j] = (T)(sgn * vc[j]);
+}
+
+// Sign rule in place on the columns of Q (FP64 n x l, each column's largest
+// magnitude positive, lowest row on ties), also written j-major (l x n) in
+// the storage precision to Qt. One workgroup per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_signcols(double* __restrict__ Q, int64_t n, int l, T* __restrict__ Qt) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  __shared__ double sgn_s;
+  const int c = blockIdx.x;
+  double best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double a = fabs(Q[i * l + c]);
+    if (a > best) {
+      best = a;
+      bidx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double o = bv[threadIdx.x + w];
+      const int64_t oi = bi[threadIdx.x + w];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sgn_s = Q[bi[0] * l + c] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();  // the sign is read before any entry of the column changes
+  const double sgn = sgn_s;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double v = sgn * Q[i * l + c];
+    Q[i * l + c] = v;
+    Qt[(int64_t)c * n + i] = (T)v;
+  }
+}
+
+hipError_t launch_signcols(tucker_precision prec, double* Q, int64_t n, int l, void* Qt, hipStream_t st) {
+  if (prec == TUCKER_FP64)
+    hipLaunchKernelGGL((k_signcols<double>), dim3(l), dim3(256), 0, st, Q, n, l, (double*)Qt);
+  else
+    hipLaunchKernelGGL((k_signcols<float>), dim3(l), dim3(256), 0, st, Q, n, l, (float*)Qt);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(tucker_precision prec, const double* Q, int64_t n, int l, const double* V, int ldv, int r,
+                           void* U, void* Vt, hipStream_t st) {
+  if (prec == TUCKER_FP64)
+    hipLaunchKernelGGL((k_assemble<double>), dim3(r), dim3(256), 0, st, Q, n, l, V, ldv, r, (double*)U, (double*)Vt);
+  else
+    hipLaunchKernelGGL((k_assemble<float>), dim3(r), dim3(256), 0, st, Q, n, l, V, ldv, r, (float*)U, (float*)Vt);
+  return hipGetLastError();
+}
+
 __global__ void k_info_init(tucker_info* info, int32_t l0, int32_t l1, int32_t l2, int32_t l3, int32_t l4, int32_t l5,
                             int32_t l6, int32_t l7, int d, int32_t flags) {
   char* p = (char*)info;
@@ -1003,7 +1150,7 @@ __device__ __forceinline__ void b_pass(const BPass& d, int bid) {
 template <int RPT>
 __device__ __forceinline__ void b_svd(const BSvd& d, int bid) {
   small_svd_body<RPT>(d.Rg, d.l, d.status, d.tol, d.negl, d.Wm, d.sigma, d.alpha, d.info, d.mode, d.step, 0, -1.0,
-                      0.0, nullptr, nullptr, nullptr, bid);
+                      0.0, nullptr, nullptr, nullptr, nullptr, bid);
 }
 __device__ __forceinline__ void b_rotate(const BRotate& d, int bid) {
   rotate_body<float>(d.Q3, d.n, d.l, d.Wm, (float*)nullptr, (float*)nullptr, d.q64, bid);

@@ -123,7 +123,7 @@ def test_processing_order_options_on_the_host():
     bad.order_kind = 7
     assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, bad) == 0
     bad = _lib.make_options()
-    bad.reserved[5] = 1
+    bad.reserved[4] = 1
     assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, bad) == 0
     L = _lib.lib
     s = _lib._shape((60, 12, 40))
@@ -134,6 +134,26 @@ def test_processing_order_options_on_the_host():
     rc = L.tucker_rsthosvd_ex(ctypes.byref(s), p16, r, 4, 1, 0, 1, 1, ctypes.byref(opt), p16, u, None, p16, 1 << 40,
                               None)
     assert rc == -1 and "permutation" in L.tucker_status_string(rc).decode()
+
+
+def test_holistic_option_on_the_host():
+    """The holistic variants size their own workspace (Q_k at width l_k, the
+    small tensor and its HOSVD), reject a bad flag, and reject ranks that no
+    unfolding of the small tensor can carry (T-HOSVD, p = 0: l = r, so mode 2's
+    unfolding of the 1 x 1 x 3 tensor has rank 1)."""
+    from paper_2506_04840_amd import _lib
+    dims, ranks = (60, 12, 40), (5, 6, 4)
+    plain = _lib.workspace_bytes(dims, ranks, 4, 1, _lib.FP32, True)
+    hol = _lib.workspace_bytes(dims, ranks, 4, 1, _lib.FP32, True, _lib.make_options(holistic=True))
+    assert hol > plain > 0
+    # T-HOSVD: sequential modes (no per-mode scratch copies), plus the holistic buffers
+    assert _lib.workspace_bytes(dims, ranks, 4, 1, _lib.FP32, False, _lib.make_options(holistic=True)) > 0
+    bad = _lib.make_options()
+    bad.holistic = 2
+    assert _lib.workspace_bytes(dims, ranks, 4, 1, _lib.FP32, True, bad) == 0
+    assert _lib.workspace_bytes((10, 10, 10), (1, 1, 3), 0, 1, _lib.FP64, False) > 0
+    assert _lib.workspace_bytes((10, 10, 10), (1, 1, 3), 0, 1, _lib.FP64, False,
+                                _lib.make_options(holistic=True)) == 0
 
 
 def test_python_binding_rejects_host_tensors():

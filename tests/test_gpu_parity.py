@@ -535,3 +535,71 @@ def test_solve_st_in_processing_order_with_khatri_rao(T):
     torch.cuda.synchronize()
     d = np.linalg.norm(reconstruct(_np(G), [_np(u) for u in U]) - reconstruct(res.core, res.factors))
     assert d / np.linalg.norm(a) <= 1e-10
+
+
+# --------------------------------------------------------------- holistic variants (Appendices A, B)
+
+def _compare_holistic(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, order=None, tol=None):
+    fn = T_mod().rsthosvd if variant == "st" else T_mod().rthosvd
+    G, U, info = fn(a_dev, ranks, p=p, q=q, shift=shift, seed=seed, precision=prec, order=order, holistic=True)
+    torch.cuda.synchronize()
+    g, us = _np(G), [_np(u) for u in U]
+    oo = orc.decreasing_order(a64.shape) if order == "decreasing" else order
+    res = orc.randomized_hosvd_holistic(a64, ranks, p, q, shift=shift, variant=variant, seed=seed, order=oo)
+    tol = TOL["fp64" if prec == "fp64" else "fp32"] if tol is None else tol
+    na = np.linalg.norm(a64)
+    d_rec = np.linalg.norm(reconstruct(g, us) - reconstruct(res.core, res.factors)) / na
+    assert d_rec <= tol, d_rec
+    for u in us:
+        assert np.max(np.abs(u.T @ u - np.eye(u.shape[1]))) < (1e-12 if prec == "fp64" else 1e-5)
+    for k, lg in enumerate(res.logs):
+        assert info["l"][k] == lg.l
+        for t in range(q + 1):
+            assert abs(info["alpha"][k][t] - lg.alphas[t]) <= tol * lg.sigmas[t][0], (k, t)
+            assert abs(info["sigma_1"][k][t] - lg.sigmas[t][0]) <= tol * lg.sigmas[t][0], (k, t)
+    # the factors themselves where the small tensor's spectrum separates r_k
+    if prec == "fp64":
+        for k in range(len(ranks)):
+            assert np.max(np.abs(us[k] - res.factors[k])) < 1e-6 or _gap_small(res, a64, k, ranks), k
+    return G, U, info, res
+
+
+def T_mod():
+    from paper_2506_04840_amd import _lib
+    return _lib
+
+
+def _gap_small(res, a64, k, ranks):
+    s = np.linalg.svd(orc.unfold(a64, k), compute_uv=False)
+    r = ranks[k]
+    return r < len(s) and (s[r - 1] - s[r]) < 1e-6 * s[0]
+
+
+@pytest.mark.parametrize("variant", ["t", "st"])
+@pytest.mark.parametrize("q,shift", [(0, "adaptive"), (1, "adaptive"), (2, "adaptive"), (2, "none")])
+def test_holistic_fp64_matches_oracle(T, variant, q, shift):
+    a, _, _ = gen.random_tucker((33, 45, 28), (5, 6, 4), 0.05, seed=21)
+    _compare_holistic(_dev(a, torch.float64), a, (5, 6, 4), 6, q, shift, variant, "fp64")
+
+
+def test_holistic_fp32_hilbert(T):
+    a = gen.hilbert_tensor((96, 96, 96)).astype(np.float32)
+    _compare_holistic(_dev(a, torch.float32), a.astype(np.float64), (30, 30, 30), 10, 1, "adaptive", "st", "fp32")
+
+
+@pytest.mark.parametrize("order", [(2, 0, 1), "decreasing"])
+def test_holistic_in_processing_order(T, order):
+    a, _, _ = gen.random_tucker((20, 44, 31), (4, 6, 5), 0.05, seed=29)
+    _compare_holistic(_dev(a, torch.float64), a, (4, 6, 5), 5, 1, "adaptive", "st", "fp64", order=order)
+
+
+@pytest.mark.parametrize("variant", ["t", "st"])
+def test_holistic_exact_rank_and_wide_small_unfolding(T, variant):
+    """Exact Tucker rank is recovered. In the ST form the last mode's unfolding
+    of the small tensor is 13 x 4 (fewer columns than rows, rank 3): its left
+    singular vectors come from the unfolding itself rather than from its
+    transpose, through the rank-deficient CholeskyQR."""
+    a, _, _ = gen.random_tucker((5, 5, 100), (2, 2, 3), 0.0, seed=31)
+    G, U, info, res = _compare_holistic(_dev(a, torch.float64), a, (2, 2, 3), 10, 1, "adaptive", variant, "fp64")
+    rec = reconstruct(_np(G), [_np(u) for u in U])
+    assert np.linalg.norm(a - rec) / np.linalg.norm(a) < 1e-12
