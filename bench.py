@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--ranks", default=None, help="Tucker ranks as a comma list (default: the workload's)")
     ap.add_argument("--order", default="natural",
                     help="processing order: natural, decreasing (by mode size) or a comma list of modes")
+    ap.add_argument("--holistic", action="store_true",
+                    help="the holistic variants of Appendices A / B (range finders at width l, then a small HOSVD)")
     ap.add_argument("--pve", type=float, default=None, metavar="TOL",
                     help="Algorithm 4: power count per mode by the per-vector-error test with this tol "
                          "(--q is then q_max, default 20)")
@@ -140,7 +142,7 @@ def _order_arg(text):
     return tuple(int(x) for x in text.split(","))
 
 
-def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian", order=None):
+def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian", order=None, holistic=False):
     """The FP64 oracle, untuned, on the host cores: one whole solve of the same
     workload when that takes seconds, else a bounded slab scaled by work."""
     import numpy as np
@@ -178,8 +180,8 @@ def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian", or
                 before = seq[:seq.index(k)]
                 cur = [ranks[i] if (st and i in before) else dims[i] for i in range(len(dims))]
                 return omega_matrix(omega, 1, k, [cur[i] for i in range(len(dims)) if i != k], l)
-        res = orc.randomized_hosvd(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1,
-                                   omega=om, order=oo)
+        fn = orc.randomized_hosvd_holistic if holistic else orc.randomized_hosvd
+        res = fn(a64, cfg["ranks"], cfg["p"], q, shift=shift, variant=cfg["variant"], seed=1, omega=om, order=oo)
     dt = (time.perf_counter() - t0) * scale
     out = {"value": 1.0 / dt, "unit": "approximations/s", "cores": int(threads), "kind": "oracle",
            "sample": sample, "seconds_per_solve": dt}
@@ -231,14 +233,15 @@ def main():
     if args.pve is not None:
         if cfg["variant"] != "st":
             raise SystemExit("--pve applies to ST-HOSVD workloads")
-        if order is not None:
-            raise SystemExit("--pve runs in the natural order")
+        if order is not None or args.holistic:
+            raise SystemExit("--pve runs Algorithm 3 in the natural order")
         q = 20 if args.q is None else args.q
         solver = T.PveSolver(A.shape, cfg["ranks"], cfg["p"], q, args.pve, args.shift, seed=w.sketch_seed,
                              precision=prec, device=dev)
     else:
         solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
-                          sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega, order=order)
+                          sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega, order=order,
+                          holistic=args.holistic)
     for _ in range(args.warmup):
         solver.run(A)
     torch.cuda.synchronize()
@@ -280,8 +283,8 @@ def main():
         mk = "fp32" if (prec == "bf16" and kern == "rowcontract") else prec
         roof = _roof_from_timing(tk, mk)
         same = prec == CONFIGS[args.workload]["precision"] and cfg["ranks"] == CONFIGS[args.workload]["ranks"]
-        traffic = measured_traffic(kern, args.workload) if same and order is None and q == CONFIGS[args.workload]["q"] \
-            else None
+        traffic = measured_traffic(kern, args.workload) \
+            if same and order is None and not args.holistic and q == CONFIGS[args.workload]["q"] else None
         roof["traffic"] = traffic
         if traffic is not None:
             roof["traffic_unit"] = "bytes/launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
@@ -295,7 +298,8 @@ def main():
     if not args.no_cpu_baseline:
         if a_host_store is None:
             a_host_store = A.double().cpu().numpy() if A.numel() <= 3e8 else A.float().cpu().numpy()
-        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q, args.pve, args.omega, order)
+        cpu = cpu_baseline(args.workload, cfg, a_host_store, args.shift, q, args.pve, args.omega, order,
+                           args.holistic)
         if "rel_error" in cpu:
             cpu["rel_error_gpu_minus_oracle"] = re - cpu["rel_error"]
 
@@ -324,6 +328,8 @@ def main():
         line["config"]["omega"] = args.omega
     if order is not None:
         line["config"]["order"] = order if isinstance(order, str) else list(order)
+    if args.holistic:
+        line["config"]["algorithm"] = "holistic (Appendix B.1 / A.2 form)"
     if args.pve is not None:
         line["config"].update({"algorithm": "4 (per-vector-error q)", "tol": args.pve, "q_max": q,
                                "q_used": solver.q_used})
