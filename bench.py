@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--ranks", default=None, help="Tucker ranks as a comma list (default: the workload's)")
     ap.add_argument("--order", default="natural",
                     help="processing order: natural, decreasing (by mode size) or a comma list of modes")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one solve into a HIP graph and time K replays (the whole solve each time)")
     ap.add_argument("--holistic", action="store_true",
                     help="the holistic variants of Appendices A / B (range finders at width l, then a small HOSVD)")
     ap.add_argument("--pve", type=float, default=None, metavar="TOL",
@@ -242,8 +244,15 @@ def main():
         solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
                           sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega, order=order,
                           holistic=args.holistic)
+    if args.graph:
+        if args.pve is not None:
+            raise SystemExit("--graph: Algorithm 4 synchronises with the host every step")
+        solver.capture(A)
+        step = solver.replay
+    else:
+        step = lambda: solver.run(A)  # noqa: E731
     for _ in range(args.warmup):
-        solver.run(A)
+        step()
     torch.cuda.synchronize()
 
     # timed region: K whole solves (events between solves give the per-step spread, no synchronisation)
@@ -252,7 +261,7 @@ def main():
     t0 = time.perf_counter()
     evs[0].record()
     for i in range(args.steps):
-        solver.run(A)
+        step()
         evs[i + 1].record()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -330,6 +339,8 @@ def main():
         line["config"]["order"] = order if isinstance(order, str) else list(order)
     if args.holistic:
         line["config"]["algorithm"] = "holistic (Appendix B.1 / A.2 form)"
+    if args.graph:
+        line["config"]["launch"] = "HIP graph replay of the whole solve"
     if args.pve is not None:
         line["config"].update({"algorithm": "4 (per-vector-error q)", "tol": args.pve, "q_max": q,
                                "q_used": solver.q_used})

@@ -290,6 +290,30 @@ class Solver:
         self._call(A)
         return self.G, self.U
 
+    def capture(self, A: torch.Tensor) -> "torch.cuda.CUDAGraph":
+        """Record one solve of the tensor at A's address into a HIP graph (the
+        library's side streams join the capture through their events); each
+        replay() then reruns the whole solve on whatever A holds, into the same
+        G, U and info. One eager solve first creates the side streams.
+
+        Not for the concurrent T-HOSVD (its d - 1 mode streams fork from one
+        event): capturing it ended in a host segmentation fault inside the
+        capture, whose cause is not known, so it is refused."""
+        if not self.sequential and not self.opt.holistic and len(self.dims) > 1:
+            raise NotImplementedError("graph capture of the concurrent T-HOSVD modes is not supported")
+        self.run(A)
+        torch.cuda.synchronize(self.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run(A)
+        torch.cuda.synchronize(self.device)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.G, self.U
+
 
 class PveSolver(Solver):
     """Algorithm 4 (power count per mode by the per-vector-error test): q is
@@ -303,6 +327,9 @@ class PveSolver(Solver):
         super().__init__(dims, ranks, p, min(int(q_max), MAX_Q), shift, seed, precision, True, device)
         self.q_max, self.tol = int(q_max), float(tol)
         self._qused = (ctypes.c_int32 * len(self.dims))()
+
+    def capture(self, A: torch.Tensor):
+        raise RuntimeError("Algorithm 4 reads its stopping flag on the host after every step: not capturable")
 
     def _call(self, A: Optional[torch.Tensor] = None, dry: bool = False):
         if dry:

@@ -603,3 +603,46 @@ def test_holistic_exact_rank_and_wide_small_unfolding(T, variant):
     G, U, info, res = _compare_holistic(_dev(a, torch.float64), a, (2, 2, 3), 10, 1, "adaptive", variant, "fp64")
     rec = reconstruct(_np(G), [_np(u) for u in U])
     assert np.linalg.norm(a - rec) / np.linalg.norm(a) < 1e-12
+
+
+# --------------------------------------------------------------- graph replay of whole solves
+
+_T_CAPTURE_SKIP = pytest.mark.skip(reason="capturing the concurrent T-HOSVD modes ended in a host segmentation "
+                                          "fault inside graph capture; Solver.capture refuses it until the cause is "
+                                          "shown")
+
+
+@pytest.mark.parametrize("variant,q,holistic", [("st", 2, False), pytest.param("t", 1, False, marks=_T_CAPTURE_SKIP),
+                                                ("st", 1, True), ("t", 1, True)])
+def test_solve_graph_replay_equals_eager(T, variant, q, holistic):
+    """A captured solve (side streams joined through events) replayed three
+    times, with eager work and new tensor contents between replays, gives the
+    eager result bitwise each time."""
+    a, _, _ = gen.random_tucker((40, 36, 30), (5, 6, 4), 0.05, seed=37)
+    b, _, _ = gen.random_tucker((40, 36, 30), (5, 6, 4), 0.05, seed=38)
+    dev = torch.device("cuda:0")
+    s = T.Solver(a.shape, (5, 6, 4), 6, q, "adaptive", 3, "fp32", variant == "st", dev, holistic=holistic)
+    A = torch.from_numpy(a.astype(np.float32)).to(dev)
+    ref = {}
+    for name, src in (("a", a), ("b", b)):
+        A.copy_(torch.from_numpy(src.astype(np.float32)))
+        G, U = s.run(A)
+        torch.cuda.synchronize()
+        ref[name] = (G.clone(), [u.clone() for u in U])
+    A.copy_(torch.from_numpy(a.astype(np.float32)))
+    s.capture(A)
+    for rep, name in enumerate(("a", "b", "a")):
+        A.copy_(torch.from_numpy((a if name == "a" else b).astype(np.float32)))
+        _ = torch.ones(4096, device=dev).sum().item()  # eager work between replays
+        G, U = s.replay()
+        torch.cuda.synchronize()
+        print("replay", rep, name, flush=True)
+        assert torch.equal(G, ref[name][0])
+        for u, v in zip(U, ref[name][1]):
+            assert torch.equal(u, v)
+
+
+def test_concurrent_t_hosvd_capture_is_refused(T):
+    s = T.Solver((20, 18, 16), (3, 3, 3), 4, 1, "adaptive", 1, "fp32", False, torch.device("cuda:0"))
+    with pytest.raises(NotImplementedError):
+        s.capture(torch.zeros((20, 18, 16), device="cuda:0"))
