@@ -156,6 +156,22 @@ def test_holistic_option_on_the_host():
                                 _lib.make_options(holistic=True)) == 0
 
 
+def test_empty_and_oversized_shapes_rejected():
+    """A zero-size mode, order 0 and order above TUCKER_MAX_ORDER are rejected by
+    the workspace query (and by the solves, which share the plan)."""
+    from paper_2506_04840_amd import _lib
+    assert _lib.workspace_bytes((10, 0, 10), (2, 1, 2), 4, 1, _lib.FP64, True) == 0
+    assert _lib.workspace_bytes((), (), 4, 1, _lib.FP64, True) == 0
+    assert _lib.workspace_bytes((2,) * 9, (1,) * 9, 0, 1, _lib.FP64, True) == 0
+    assert _lib.workspace_bytes((2,) * 8, (1,) * 8, 0, 1, _lib.FP64, True) > 0
+    s = _lib._shape((10, 0, 10))
+    r = (ctypes.c_int64 * 3)(2, 1, 2)
+    u = (ctypes.c_void_p * 3)(16, 16, 16)
+    rc = _lib.lib.tucker_rsthosvd(ctypes.byref(s), ctypes.c_void_p(16), r, 2, 1, 0, 1, 1, ctypes.c_void_p(16), u,
+                                  None, ctypes.c_void_p(16), 1 << 30, None)
+    assert rc == -1
+
+
 def test_python_binding_rejects_host_tensors():
     import torch
     from paper_2506_04840_amd import _lib

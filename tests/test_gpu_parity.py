@@ -358,6 +358,19 @@ def test_edge_shapes(T):
         _compare_solve(_dev(a, torch.float64), a, ranks, p, q, "adaptive", "st", "fp64", check_core=False)
 
 
+@pytest.mark.parametrize("variant", ["t", "st"])
+def test_solve_largest_order_and_width(T, variant):
+    """The limits: order 8 (TUCKER_MAX_ORDER), and a mode whose sketch width is
+    l = 64 (TUCKER_MAX_L), both against the oracle in FP64."""
+    a, _, _ = gen.random_tucker((3, 4, 3, 5, 3, 2, 3, 4), (2, 2, 2, 3, 2, 2, 2, 2), 0.05, seed=41)
+    _compare_solve(_dev(a, torch.float64), a, (2, 2, 2, 3, 2, 2, 2, 2), 1, 1, "adaptive", variant, "fp64",
+                   check_core=False)
+    a, _, _ = gen.random_tucker((100, 90, 80), (54, 50, 40), 0.05, seed=42)
+    _, _, info, _ = _compare_solve(_dev(a, torch.float64), a, (54, 50, 40), 10, 1, "adaptive", variant, "fp64",
+                                   check_core=False)
+    assert info["l"][0] == 64
+
+
 @pytest.mark.parametrize("q", [0, 2])
 def test_solve_bf16_reaches_fp32_error(T, q):
     """BF16 operands: the last step's products run on FP32 operands, so the
