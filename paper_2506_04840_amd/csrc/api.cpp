@@ -1352,7 +1352,7 @@ int tucker_batch_step(const void* plan, hipStream_t stream) {
     const int cls = (kind == BK_CR_LDS || kind == BK_CR_COLS) ? KC_COLREDUCE
                     : (kind == BK_RC_ROWS || kind == BK_RC_COLS) ? KC_ROWCONTRACT
                     : kind == BK_REDUCE ? KC_REDUCE : KC_FILL;
-    TimingScope ts(cls, stream, pr[i].bytes, pr[i].flops);
+    TimingScope ts(cls, stream, pr[i].bytes, pr[i].flops, true);
     e = launch_batch_ttm(kind, h->lclass, hdr, desc, stream);
   }
   return dev_check(e, "batch step");

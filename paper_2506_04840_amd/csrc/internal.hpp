@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -20,17 +21,43 @@ enum KernelClass { KC_COLREDUCE = 0, KC_ROWCONTRACT = 1, KC_ORTH = 2, KC_FILL = 
 
 // Records a HIP event pair around the launches in its scope when `cls` is the
 // enabled class; bytes and flops are the launch's algorithmic traffic and work.
+// A kernel launched through TK_LAUNCH inside an active scope carries the pair
+// itself (hipExtLaunchKernelGGL: the dispatch records the kernel's own start
+// and end), so the pair then measures that kernel alone, without the dispatch
+// gaps of separately recorded events.
 class TimingScope {
  public:
-  TimingScope(int cls, hipStream_t st, double bytes, double flops);
+  // stamped: the scope's one kernel is launched through TK_LAUNCH, which
+  // records both events (no event is recorded around it)
+  TimingScope(int cls, hipStream_t st, double bytes, double flops, bool stamped = false);
   ~TimingScope();
   TimingScope(const TimingScope&) = delete;
   TimingScope& operator=(const TimingScope&) = delete;
+  // The scope of this host thread that is timing a launch on `st` and has not
+  // handed out its events yet (nullptr otherwise); the caller launches with
+  // start() / stop().
+  static TimingScope* claim(hipStream_t st);
+  hipEvent_t start() const;
+  hipEvent_t stop() const;
 
  private:
   int slot_;
   hipStream_t st_;
+  bool stamped_;
+  bool attached_;
+  TimingScope* prev_;
 };
+
+// hipLaunchKernelGGL, or hipExtLaunchKernelGGL with the events of the
+// thread's active timing scope on that stream.
+#define TK_LAUNCH(kern, grid, block, shm, st, ...)                                                        \
+  do {                                                                                                    \
+    ::tk::TimingScope* tk_ts_ = ::tk::TimingScope::claim(st);                                             \
+    if (tk_ts_ != nullptr)                                                                                \
+      hipExtLaunchKernelGGL(kern, grid, block, shm, st, tk_ts_->start(), tk_ts_->stop(), 0, __VA_ARGS__); \
+    else                                                                                                  \
+      hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);                                        \
+  } while (0)
 inline size_t elem_bytes(tucker_precision p) { return p == TUCKER_FP64 ? 8 : 4; }
 
 // ---- Gaussian test matrix -------------------------------------------------

@@ -1,6 +1,7 @@
 // Opt-in launch timing: when a kernel class is enabled, every launch of that
-// class is bracketed by a pair of HIP events recorded on the launch stream,
-// and its algorithmic bytes and flops are summed. Measurement only; the
+// class is timed by a pair of HIP events on the launch stream (recorded by the
+// kernel dispatch itself for launches made through TK_LAUNCH, else around
+// the launch), and its algorithmic bytes and flops are summed. Measurement only; the
 // disabled path costs one relaxed atomic load per launch.
 #include <atomic>
 #include <mutex>
@@ -32,7 +33,10 @@ Timing& state() {
 
 }  // namespace
 
-TimingScope::TimingScope(int cls, hipStream_t st, double bytes, double flops) : slot_(-1), st_(st) {
+thread_local TimingScope* g_scope = nullptr;  // innermost active scope of this host thread
+
+TimingScope::TimingScope(int cls, hipStream_t st, double bytes, double flops, bool stamped)
+    : slot_(-1), st_(st), stamped_(stamped), attached_(false), prev_(nullptr) {
   Timing& t = state();
   if (t.which.load(std::memory_order_relaxed) != cls) return;
   std::lock_guard<std::mutex> g(t.mu);
@@ -45,15 +49,30 @@ TimingScope::TimingScope(int cls, hipStream_t st, double bytes, double flops) : 
   Slot& s = t.slots[slot_];
   s.bytes = bytes;
   s.flops = flops;
-  hipEventRecord(s.a, st_);
+  if (!stamped_) hipEventRecord(s.a, st_);  // else the TK_LAUNCH dispatch records both
+  prev_ = g_scope;
+  g_scope = this;
 }
 
 TimingScope::~TimingScope() {
   if (slot_ < 0) return;
+  g_scope = prev_;
+  if (attached_) return;
   Timing& t = state();
   std::lock_guard<std::mutex> g(t.mu);
+  if (stamped_) hipEventRecord(t.slots[slot_].a, st_);  // nothing was launched: an empty interval
   hipEventRecord(t.slots[slot_].b, st_);
 }
+
+TimingScope* TimingScope::claim(hipStream_t st) {
+  TimingScope* s = g_scope;
+  if (s == nullptr || !s->stamped_ || s->attached_ || s->st_ != st) return nullptr;
+  s->attached_ = true;
+  return s;
+}
+
+hipEvent_t TimingScope::start() const { return state().slots[slot_].a; }
+hipEvent_t TimingScope::stop() const { return state().slots[slot_].b; }
 
 }  // namespace tk
 

@@ -482,13 +482,13 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
   const unsigned blocks = (unsigned)(((nsplit + 7) / 8) * 8 * nrb);
   const int64_t m = v.P * v.S;
   if (v.S == 1)
-    hipLaunchKernelGGL((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l,
+    TK_LAUNCH((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l,
                        nsteps, nsplit, nrb, (PT*)part);
   else {
     constexpr int VE = 16 / (int)sizeof(T);
     const int edge = v.S % LdsPol<MK>::KT == 0 ? 0 : (v.S % VE == 0 ? 1 : 2);
 #define TK_CR_LDS(E)                                                                                       \
-  hipLaunchKernelGGL((k_cr_lds<MK, NJ, E>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n, v.S, l, \
+  TK_LAUNCH((k_cr_lds<MK, NJ, E>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n, v.S, l, \
                      m, spp, nsteps, nsplit, nrb, (PT*)part)
     if (edge == 0) TK_CR_LDS(0);
     else if (edge == 1) TK_CR_LDS(1);
@@ -513,7 +513,7 @@ static hipError_t cr_dispatch(const View3& v, const void* X, const void* Bt, int
 hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* Bt, int l,
                             void* part, int nsplit, hipStream_t st) {
   const double N = (double)v.P * v.n * v.S, es = (double)elem_bytes(prec);
-  TimingScope ts(KC_COLREDUCE, st, N * es + N / v.n * l * es, 2.0 * N * l);
+  TimingScope ts(KC_COLREDUCE, st, N * es + N / v.n * l * es, 2.0 * N * l, true);
   switch (prec) {
     case TUCKER_FP64: return cr_dispatch<MF_F64>(v, X, Bt, l, part, nsplit, st);
     case TUCKER_FP32: return cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, st);
@@ -886,7 +886,7 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     const int64_t osp = out_jmajor ? 1 : lw, osj = out_jmajor ? m : 1;
     const unsigned blocks = (unsigned)((v.P + 63) / 64);
 #define TK_RC_COLS(WV)                                                                                         \
-  hipLaunchKernelGGL((k_rc_cols<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.P, v.n, \
+  TK_LAUNCH((k_rc_cols<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.P, v.n, \
                      lw, wsi, wsj, (T*)out, osp, osj)
     if (wvec) TK_RC_COLS(true);
     else TK_RC_COLS(false);
@@ -900,7 +900,7 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     const int ksplit = ntiles < 4096 ? 1 : 0;
     const unsigned blocks = (unsigned)(ksplit ? ntiles : (ntiles + 3) / 4);
 #define TK_RC_ROWS(WV)                                                                                            \
-  hipLaunchKernelGGL((k_rc_rows<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
+  TK_LAUNCH((k_rc_rows<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
                      lw, wsi, wsj, tpp, ntiles, ksplit, (T*)out, osp, osj)
     if (wvec) TK_RC_ROWS(true);
     else TK_RC_ROWS(false);
@@ -924,7 +924,7 @@ static hipError_t rc_dispatch(const View3& v, const void* X, const void* W, int6
 hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X, const void* W, int64_t wsi,
                               int64_t wsj, int lw, void* out, bool out_jmajor, hipStream_t st) {
   const double N = (double)v.P * v.n * v.S, es = (double)elem_bytes(mk);
-  TimingScope ts(KC_ROWCONTRACT, st, N * es + N / v.n * lw * es, 2.0 * N * lw);
+  TimingScope ts(KC_ROWCONTRACT, st, N * es + N / v.n * lw * es, 2.0 * N * lw, true);
   switch (mk) {
     case TUCKER_FP64: return rc_dispatch<MF_F64>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
     case TUCKER_FP32: return rc_dispatch<MF_F32>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
@@ -1187,7 +1187,7 @@ static hipError_t batch_ttm_nj(BatchKind kind, const int* hdr, const void* desc,
 #define TK_PERSIST(D, F)                                                                                      \
   {                                                                                                           \
     auto kern = k_persist<D, F>;                                                                              \
-    hipLaunchKernelGGL(kern, dim3(resident_grid(kern)), dim3(256), 0, st, hdr, (const D*)desc);               \
+    TK_LAUNCH(kern, dim3(resident_grid(kern)), dim3(256), 0, st, hdr, (const D*)desc);                        \
   }                                                                                                           \
   break
   switch (kind) {
