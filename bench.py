@@ -15,7 +15,8 @@ sparse CP tensor of the paper's order study).
 serving_stream_4096: 4096 order-3 FP32 requests (mode sizes U{32..256},
 Tucker ranks U{4..32}, Gaussian core x Haar factors + 1e-3 noise, p = 8,
 q = 1, adaptive shift). A step is one burst of all 4096 requests through the
-continuous-batching server (persistent batched kernels, graph replay); value
+continuous-batching server (persistent batched kernels, graph replay, a slot
+pair per width class 16 / 32 / 48 / 64 of the sketch widths); value
 is approximations/s over the timed bursts. Beside it: the same burst one
 request at a time (tucker_rsthosvd per request), the relative error of every
 request on both paths, and p50/p99 latency at Poisson arrival rates of 0.5
@@ -51,7 +52,7 @@ CONFIGS = {
     "sparse_cp3_600": dict(precision="fp32", variant="st", ranks=(50, 50, 50), p=10, q=1),
 }
 SERVING = "serving_stream_4096"
-SERVING_CFG = dict(count=4096, n_lo=32, n_hi=256, r_lo=4, r_hi=32, eta=1e-3, p=8, q=1, capacity=256, lclass=48,
+SERVING_CFG = dict(count=4096, n_lo=32, n_hi=256, r_lo=4, r_hi=32, eta=1e-3, p=8, q=1, capacity=256, lclass="auto",
                    ws_bytes=4 << 30, data_seed=0)
 
 
@@ -400,6 +401,7 @@ def serving_main(args):
     srv = serve.BatchServer(capacity=c["capacity"], q=c["q"], p=c["p"], lclass=c["lclass"], ws_bytes=c["ws_bytes"],
                             device=dev, overlap=not args.serial)
     jb = jobs()
+    srv.ensure_slots(jb)
     for _ in range(args.warmup):
         srv.run(jb[:2 * c["capacity"]])
     torch.cuda.synchronize()

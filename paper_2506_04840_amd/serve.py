@@ -6,7 +6,10 @@ the batch fits the capacity and the workspace budget, writes the batch plan
 (host only) and replays a graph captured once per slot: the library's
 persistent batched kernels run every phase of Algorithm 3 for all requests of
 the batch in one launch each. Requests of different orders go to different
-slot pairs (a plan holds one order). Each slot has its own stream and
+slot pairs (a plan holds one order), and so, with lclass="auto", do requests
+of different width classes: a request goes to the smallest class (16, 32, 48,
+64) that holds its sketch widths, since the batched kernels' tiles, registers
+and small SVDs are sized by the class. Each slot has its own stream and
 workspace, so two batches run on the device at once: the latency-bound small
 SVD and orthonormalisation phases of one overlap the bandwidth-bound mode
 products of the other, and a batch is admitted and planned as soon as a slot
@@ -46,6 +49,7 @@ class Job:
     item: Optional[T.BatchItem] = None
     ws_bytes: int = 0
     done: float = -1.0
+    key: tuple = ()   # (order, width class) of the slots that serve it
 
     def prepare(self, p: int, q: int) -> "Job":
         """Allocate G and the U_k on A's device and build the request's descriptor."""
@@ -87,35 +91,63 @@ class _Slot:
 
 
 class BatchServer:
-    """Continuous batching over two graph-replayed slots per tensor order."""
+    """Continuous batching over two graph-replayed slots per (order, width class)."""
+
+    CLASSES = (16, 32, 48, 64)
 
     def __init__(self, capacity=256, q=1, p=8, lclass=48, ws_bytes=8 << 30, shift="adaptive", device="cuda",
-                 use_graphs=True, orders=(3,), overlap=True):
-        """overlap=False runs every batch on the caller's current stream (one
-        batch on the device at a time), e.g. to time each phase alone."""
+                 use_graphs=True, orders=(), overlap=True, spill=False, max_inflight=2):
+        """lclass: the width class of every slot, or "auto" (each request to the
+        smallest class that holds its sketch widths; with spill, a batch whose
+        own class has no free slot may run in a free slot of a wider class).
+        max_inflight bounds the batches on the device at once, over all slots.
+        overlap=False runs every batch on the caller's current stream (one
+        batch on the device at a time), e.g. to time each phase alone. Slot
+        pairs are made for `orders` now (with the widest class for "auto"),
+        for the keys of a job list by ensure_slots(), and for other keys when
+        run() first sees them."""
         self.device = torch.device(device)
         self.overlap = overlap
-        self.p, self.q, self.lclass, self.shift = p, q, lclass, shift
+        self.p, self.q, self.shift = p, q, shift
+        self.classes = self.CLASSES if lclass == "auto" else (int(lclass),)
         self.capacity, self.ws_bytes = capacity, ws_bytes
         self.use_graphs = use_graphs
-        self.slots: Dict[int, List[_Slot]] = {}
+        self.spill = spill
+        self.max_inflight = max_inflight
+        self.slots: Dict[tuple, List[_Slot]] = {}
         for d in orders:
-            self._slots_for(d)
+            self._slots_for((d, self.classes[-1]))
         self.batch_sizes: List[int] = []  # requests per launched batch
         self.inflight: List[int] = []     # requests on the device right after each launch
 
-    def _slots_for(self, d: int) -> List[_Slot]:
-        if d not in self.slots:
-            pair = [_Slot(self.capacity, d, self.q, self.p, self.lclass, self.ws_bytes, self.shift, self.device)
+    def key_of(self, j: Job) -> tuple:
+        """(order, smallest class >= every sketch width min(r_k + p, n_k) of the request)."""
+        if not j.key:
+            need = max(min(r + self.p, n) for r, n in zip(j.ranks, j.A.shape))
+            fit = [c for c in self.classes if need <= c]
+            if not fit:
+                raise ValueError("request %d: sketch width %d exceeds the classes %s" % (j.rid, need, self.classes))
+            j.key = (j.A.dim(), fit[0])
+        return j.key
+
+    def ensure_slots(self, jobs: Sequence[Job]) -> None:
+        """Make (and capture) the slot pairs every key of `jobs` needs, e.g. before a timed run."""
+        for j in jobs:
+            self._slots_for(self.key_of(j))
+
+    def _slots_for(self, key: tuple) -> List[_Slot]:
+        if key not in self.slots:
+            d, lclass = key
+            pair = [_Slot(self.capacity, d, self.q, self.p, lclass, self.ws_bytes, self.shift, self.device)
                     for _ in range(2)]
             if self.use_graphs:
                 for s in pair:
                     s.capture()
-            self.slots[d] = pair
-        return self.slots[d]
+            self.slots[key] = pair
+        return self.slots[key]
 
-    def budget(self, d: int) -> int:
-        s = self._slots_for(d)[0].solver
+    def budget(self, key: tuple) -> int:
+        s = self._slots_for(key)[0].solver
         return s.ws.numel() - s.table_bytes
 
     def _launch(self, slot: _Slot, jobs: List[Job]):
@@ -133,44 +165,46 @@ class BatchServer:
         slot.jobs = jobs
         self.batch_sizes.append(len(jobs))
 
-    def _admit(self, waiting: collections.deque, d: int) -> List[Job]:
-        """FIFO among waiting requests of order d, while capacity and budget allow."""
-        batch, used, keep = [], 0, collections.deque()
-        budget = self.budget(d)
-        while waiting and len(batch) < self.capacity:
-            j = waiting.popleft()
-            if j.A.dim() != d:
-                keep.append(j)
-                continue
+    def _admit(self, queue: collections.deque, slot: _Slot) -> List[Job]:
+        """FIFO from one key's queue while capacity and the slot's budget allow."""
+        batch, used = [], 0
+        budget = slot.solver.ws.numel() - slot.solver.table_bytes
+        while queue and len(batch) < self.capacity:
+            j = queue[0]
             if j.ws_bytes > budget:
                 raise ValueError("request %d needs %d workspace bytes, budget %d" % (j.rid, j.ws_bytes, budget))
             if used + j.ws_bytes > budget:
-                keep.append(j)
                 break
-            batch.append(j)
+            batch.append(queue.popleft())
             used += j.ws_bytes
-        keep.extend(waiting)
-        waiting.clear()
-        waiting.extend(keep)
         return batch
 
     def run(self, jobs: Sequence[Job], t0: Optional[float] = None) -> List[Job]:
         """Serve prepared `jobs` (arrival seconds relative to t0); returns them with .done set.
         The results are complete on the device when run returns (every slot's
-        completion event has been seen)."""
+        completion event has been seen). Waiting requests queue per (order,
+        class) key. The key whose oldest waiting request arrived first launches
+        next, in a free slot of its own class, else (spill) of the narrowest
+        wider class of its order that has one."""
         for j in jobs:
             if j.item is None:
                 j.prepare(self.p, self.q)
-        for d in sorted({j.A.dim() for j in jobs}):
-            self._slots_for(d)
+            j.key = ()
+            self.key_of(j)
+        keys = sorted({j.key for j in jobs})
+        for key in keys:
+            self._slots_for(key)
         pending = collections.deque(sorted(jobs, key=lambda j: j.arrival))
-        waiting: collections.deque = collections.deque()
+        waiting: Dict[tuple, collections.deque] = {k: collections.deque() for k in keys}
         busy: List[_Slot] = []
         t0 = time.perf_counter() if t0 is None else t0
-        while pending or waiting or busy:
+        nwait = 0
+        while pending or nwait or busy:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
-                waiting.append(pending.popleft())
+                j = pending.popleft()
+                waiting[j.key].append(j)
+                nwait += 1
             for s in list(busy):
                 if s.event.query():
                     t = time.perf_counter() - t0
@@ -178,16 +212,22 @@ class BatchServer:
                         j.done = t
                     s.jobs = []
                     busy.remove(s)
-            if waiting:
-                d = waiting[0].A.dim()
-                free = [s for s in self.slots[d] if not s.jobs]
-                if free:
-                    batch = self._admit(waiting, d)
-                    self._launch(free[0], batch)
-                    busy.append(free[0])
-                    self.inflight.append(sum(len(s.jobs) for s in busy))
-                    continue
-            if pending and not waiting and not busy:
+            slot, key = None, None
+            for k in [] if len(busy) >= self.max_inflight else sorted((k for k in keys if waiting[k]), key=lambda k: waiting[k][0].arrival):
+                homes = [k2 for k2 in sorted(self.slots) if k2 == k or
+                         (self.spill and k2[0] == k[0] and k2[1] > k[1])]
+                slot = next((s for k2 in homes for s in self.slots[k2] if not s.jobs), None)
+                if slot is not None:
+                    key = k
+                    break
+            if slot is not None:
+                batch = self._admit(waiting[key], slot)
+                nwait -= len(batch)
+                self._launch(slot, batch)
+                busy.append(slot)
+                self.inflight.append(sum(len(s.jobs) for s in busy))
+                continue
+            if pending and not nwait and not busy:
                 time.sleep(min(200e-6, max(0.0, pending[0].arrival - now)))
             else:
                 time.sleep(10e-6)

@@ -178,3 +178,25 @@ def test_serving_loop_small_stream(T):
     for j in out[:6]:
         Gs, Us = _single(T, j.A, j.ranks, j.seed)
         _close(j.G, j.U, Gs, Us, j.A)
+
+
+def test_serving_loop_width_classes(T):
+    """lclass="auto": requests go to the smallest width class holding their
+    sketch widths (several classes in one stream), each batch of one class, and
+    every result equals its one-request solve."""
+    from paper_2506_04840_amd import serve
+    reqs, tensors = _requests(30, seed=17, n_lo=24, n_hi=90)
+    arrivals = gen.poisson_arrivals(len(reqs), 3000.0, seed=17)
+    jobs = [serve.Job(r.rid, tensors[i], r.ranks, r.seed, arrivals[i]) for i, r in enumerate(reqs)]
+    srv = serve.BatchServer(capacity=8, q=Q, p=P, lclass="auto", ws_bytes=1 << 30, device="cuda:0")
+    out = srv.run(jobs)
+    torch.cuda.synchronize()
+    keys = {j.key for j in out}
+    print("keys", sorted(keys), flush=True)
+    assert len(keys) >= 2
+    for j in out:
+        need = max(min(r + P, n) for r, n in zip(j.ranks, j.A.shape))
+        assert j.key[1] == min(c for c in (16, 32, 48, 64) if c >= need)
+    for j in out[::3]:
+        Gs, Us = _single(T, j.A, j.ranks, j.seed)
+        _close(j.G, j.U, Gs, Us, j.A)
