@@ -223,3 +223,26 @@ def test_batch_plan_on_the_host():
     # infeasible rank inside a batch is rejected like in tucker_rsthosvd
     bad = (_lib.BatchItem * 1)(_fake_item((40, 40, 40), (4, 4, 32)))
     assert L.tucker_batch_plan(cap, d, 48, 1, bad, p, q, 0, ws, 1 << 30, plan, nplan) == -1
+
+
+def test_serving_width_class_choice():
+    """A request goes to the smallest width class holding every sketch width
+    min(r_k + p, n_k); wider than 64 is refused."""
+    import types
+
+    import torch
+
+    from paper_2506_04840_amd import serve
+    srv = types.SimpleNamespace(p=8, classes=serve.BatchServer.CLASSES)
+
+    def key(dims, ranks):
+        j = serve.Job(0, torch.zeros(dims), ranks, 1, 0.0)
+        return serve.BatchServer.key_of(srv, j)
+
+    assert key((40, 50, 60), (4, 5, 8)) == (3, 16)
+    assert key((40, 50, 60), (4, 9, 8)) == (3, 32)
+    assert key((12, 50, 60), (10, 20, 24)) == (3, 32)    # min(10 + 8, 12) = 12, 28, 32
+    assert key((40, 50, 60), (4, 30, 8)) == (3, 48)
+    assert key((100, 90, 80, 70), (50, 2, 2, 2)) == (4, 64)
+    with pytest.raises(ValueError):
+        key((100, 90, 80), (60, 2, 2))
