@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--serial", action="store_true",
                     help="serving workload: one batch on the device at a time (per-phase durations as in the "
                          "launch-timing pass)")
+    ap.add_argument("--timing-pass-only", action="store_true",
+                    help="serving workload: run only the batches of the launch-timing pass (one burst, direct steps, "
+                         "one batch at a time), e.g. under a counter run")
     return ap.parse_args()
 
 
@@ -398,6 +401,20 @@ def serving_main(args):
                        .prepare(c["p"], c["q"]))
         return out
 
+    def timing_server():
+        # the launch-timing pass: direct steps (no graphs), one batch on the device at a time
+        return serve.BatchServer(capacity=c["capacity"], q=c["q"], p=c["p"], lclass=c["lclass"],
+                                 ws_bytes=c["ws_bytes"], device=dev, use_graphs=False, overlap=False)
+
+    if args.timing_pass_only:
+        jt = jobs()
+        srv_t = timing_server()
+        srv_t.run(jt, t0=time.perf_counter())
+        torch.cuda.synchronize()
+        print(json.dumps({"workload": SERVING, "timing_pass_only": True, "batches": len(srv_t.batch_sizes)}),
+              flush=True)
+        return
+
     srv = serve.BatchServer(capacity=c["capacity"], q=c["q"], p=c["p"], lclass=c["lclass"], ws_bytes=c["ws_bytes"],
                             device=dev, overlap=not args.serial)
     jb = jobs()
@@ -467,8 +484,7 @@ def serving_main(args):
     roof = None
     if not args.no_kernel_timing:
         timed = {}
-        srv_t = serve.BatchServer(capacity=c["capacity"], q=c["q"], p=c["p"], lclass=c["lclass"],
-                                  ws_bytes=c["ws_bytes"], device=dev, use_graphs=False, overlap=False)
+        srv_t = timing_server()
         for kern in ("colreduce", "rowcontract"):
             T.timing_enable(kern, capacity=65536)
             torch.cuda.synchronize()
