@@ -373,8 +373,11 @@ int side_ctx(SideCtx** out, int lane = 0) {
 // stream) and the small SVD R = J Sigma V^T (side stream except for the last
 // one). Step t + 1 runs its products on Q3 instead of Q = Q3 J; the reduce
 // subtracts alpha_t Q3 and the next Gram kernel applies J: (X X^T Q3 -
-// alpha Q3) J = X X^T Q - alpha Q, the same iterate. On return ws.q64 holds
-// the left singular vectors of the last iterate (FP64, n x l, descending).
+// alpha Q3) J = X X^T Q - alpha Q, the same iterate. Step 1 does not wait
+// for the sketch's SVD at all (alpha_0 = 0 and J_0 does not change the
+// iterate's left singular vectors): in modes whose products are short, that
+// SVD no longer sits on the critical path. On return ws.q64 holds the left
+// singular vectors of the last iterate (FP64, n x l, descending).
 int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
                 tucker_info* info, const SolveWs& w, hipStream_t st, const OmegaSpec& om, int lane = 0,
                 void* qt_out = nullptr) {
@@ -406,24 +409,34 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, step_prec(0), w.qt, ows, cseed, 0, st);
   for (int t = 1; t <= q && e == hipSuccess; ++t) {
     const tucker_precision tp = step_prec(t);
-    // small SVD of step t - 1 beside the products of step t
+    // small SVD of step t - 1 beside the products of step t (each step's R,
+    // flags and status in the set of its parity, so step t factors while the
+    // SVD of step t - 1 still reads its own)
     e = hipEventRecord(side->qr_done, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->qr_done, 0);
     if (e == hipSuccess)
-      e = launch_orth_svd(l, step_prec(t - 1), ows, w.sigma, t == 1 ? nullptr : alpha_upd, info, k, t - 1, side->s);
+      e = launch_orth_svd(l, step_prec(t - 1), orth_step_set(ows, t - 1), w.sigma, t == 1 ? nullptr : alpha_upd,
+                          info, k, t - 1, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->svd_done, side->s);
     // Z = X_(k)^T Q3 (j-major), Y' = X_(k) Z
     if (e == hipSuccess) e = launch_rowcontract(tp, v, X, w.qt, 1, n, l, w.omz, true, st);
     if (e == hipSuccess) e = launch_colreduce(tp, v, X, w.omz, l, w.part, nsplit, st);
-    // Y = (Y' - alpha Q3) J, then its CholeskyQR
-    if (e == hipSuccess) e = hipStreamWaitEvent(st, side->svd_done, 0);
+    // Y = (Y' - alpha Q3) J, then its CholeskyQR. Step 1 needs nothing from
+    // the sketch's SVD: alpha_0 = 0, and J_0 only turns the basis inside the
+    // span, which leaves the iterate's left singular vectors and values as
+    // they are; step 1 factors Y' itself and its own SVD absorbs J_0.
+    if (e == hipSuccess && t > 1) e = hipStreamWaitEvent(st, side->svd_done, 0);
     if (e == hipSuccess)
       e = launch_reduce_splits(tp, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
-    if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, tp, w.qt, ows, cseed, t, st);
+    if (e == hipSuccess)
+      e = launch_orth_qr(n, l, w.y64, t > 1 ? ows.Wm : nullptr, tp, w.qt, orth_step_set(ows, t), cseed, t, st);
   }
-  // last small SVD on the caller's stream, then Q = Q3 J (also as Q^T j-major when asked)
+  // last small SVD on the caller's stream, after the side SVDs (they share Wm
+  // and sigma); then Q = Q3 J (also as Q^T j-major when asked)
+  if (e == hipSuccess && q == 1) e = hipStreamWaitEvent(st, side->svd_done, 0);
   if (e == hipSuccess)
-    e = launch_orth_svd(l, step_prec(q), ows, w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q, st);
+    e = launch_orth_svd(l, step_prec(q), orth_step_set(ows, q), w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q,
+                        st);
   if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, qt_out, w.q64, st);
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch");
 }
@@ -943,7 +956,7 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
     case BK_GRAM: {
       BGram* b = (BGram*)dst;
       b->Y = w.y64;
-      b->Wm = t == 0 ? nullptr : ows.Wm;
+      b->Wm = t <= 1 ? nullptr : ows.Wm;  // as the one-request path: step 1 factors the unrotated iterate
       b->part = ows.part;
       b->status = ows.status;
       b->n = n;

@@ -117,9 +117,17 @@ struct OrthWs {
   double* Wm;     // l x l left singular vectors of R (columns, descending)
   int* defic;     // 3 x 64
   int* status;    // [0] flags, [1] deficient count, [2] 1 when pass 3 was skipped
+  // a second R / flags / status set, so that the factorisation of step t + 1
+  // can run while the small SVD of step t still reads its own
+  double* R_odd;
+  int* defic_odd;
+  int* status_odd;
 };
 size_t orth_ws_bytes(int64_t n, int l);
 OrthWs carve_orth(void* base, int64_t n, int l);
+// The workspace of power step `step`: R, flags and status of its parity (odd
+// steps use the second set), the rest shared.
+OrthWs orth_step_set(const OrthWs& w, int step);
 
 // CholeskyQR part of svd(Y): Y (FP64 n x l) = Q3 R with Q3 in ws.Qa and the R
 // factors in ws.R. With Wrot != nullptr, Y is first replaced in place by

@@ -45,6 +45,10 @@ size_t orth_ws_bytes(int64_t n, int l) {
   b += align_up((size_t)kMaxL * kMaxL * sizeof(double));      // Wm
   b += align_up(3 * kMaxL * sizeof(int));                     // deficiency flags
   b += align_up(4 * sizeof(int));                             // status
+  // the second set of R, flags and status (odd steps of a power iteration)
+  b += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
+  b += align_up(3 * kMaxL * sizeof(int));
+  b += align_up(4 * sizeof(int));
   return b;
 }
 
@@ -59,7 +63,20 @@ OrthWs carve_orth(void* base, int64_t n, int l) {
   w.Wm = (double*)p; p += align_up((size_t)kMaxL * kMaxL * sizeof(double));
   w.defic = (int*)p; p += align_up(3 * kMaxL * sizeof(int));
   w.status = (int*)p; p += align_up(4 * sizeof(int));
+  w.R_odd = (double*)p; p += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
+  w.defic_odd = (int*)p; p += align_up(3 * kMaxL * sizeof(int));
+  w.status_odd = (int*)p; p += align_up(4 * sizeof(int));
   return w;
+}
+
+OrthWs orth_step_set(const OrthWs& w, int step) {
+  OrthWs o = w;
+  if (step > 0 && (step & 1)) {
+    o.R = w.R_odd;
+    o.defic = w.defic_odd;
+    o.status = w.status_odd;
+  }
+  return o;
 }
 
 // Full-precision reciprocal square root: hardware estimate plus two Newton
