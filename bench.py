@@ -3,7 +3,8 @@
 
 Prints ONE JSON line. A step is one whole solve (every mode: sketch, svd,
 q shifted power steps each with its svd and shift update, sign rule, core
-contraction) of a tensor already resident in HBM.
+contraction) of a tensor already resident in HBM, replayed from a HIP graph
+captured once (--eager: launched call by call).
 
 Default workload: the 400^3 smooth-function tensor a_ijk = 1/(i+j+k-2) in
 FP32, ST-HOSVD, ranks (30,30,30), p = 10, q = 3, adaptive shift.
@@ -70,8 +71,10 @@ def parse():
     ap.add_argument("--ranks", default=None, help="Tucker ranks as a comma list (default: the workload's)")
     ap.add_argument("--order", default="natural",
                     help="processing order: natural, decreasing (by mode size) or a comma list of modes")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture one solve into a HIP graph and time K replays (the whole solve each time)")
+    ap.add_argument("--eager", action="store_true",
+                    help="time K eager solves; by default one solve is captured into a HIP graph and K replays are "
+                         "timed (each replay is a whole solve), where capture is supported (not for Algorithm 4, "
+                         "which reads a flag on the host every step, nor the concurrent T-HOSVD)")
     ap.add_argument("--holistic", action="store_true",
                     help="the holistic variants of Appendices A / B (range finders at width l, then a small HOSVD)")
     ap.add_argument("--pve", type=float, default=None, metavar="TOL",
@@ -248,9 +251,8 @@ def main():
         solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
                           sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega, order=order,
                           holistic=args.holistic)
-    if args.graph:
-        if args.pve is not None:
-            raise SystemExit("--graph: Algorithm 4 synchronises with the host every step")
+    use_graph = not args.eager and args.pve is None and (cfg["variant"] == "st" or args.holistic)
+    if use_graph:
         solver.capture(A)
         step = solver.replay
     else:
@@ -343,8 +345,7 @@ def main():
         line["config"]["order"] = order if isinstance(order, str) else list(order)
     if args.holistic:
         line["config"]["algorithm"] = "holistic (Appendix B.1 / A.2 form)"
-    if args.graph:
-        line["config"]["launch"] = "HIP graph replay of the whole solve"
+    line["config"]["launch"] = "HIP graph replay of the whole solve" if use_graph else "eager"
     if args.pve is not None:
         line["config"].update({"algorithm": "4 (per-vector-error q)", "tol": args.pve, "q_max": q,
                                "q_used": solver.q_used})
