@@ -146,10 +146,6 @@ class BatchServer:
             self.slots[key] = pair
         return self.slots[key]
 
-    def budget(self, key: tuple) -> int:
-        s = self._slots_for(key)[0].solver
-        return s.ws.numel() - s.table_bytes
-
     def _launch(self, slot: _Slot, jobs: List[Job]):
         # the plan buffer is free: the slot's previous step has completed
         slot.solver.plan([j.item for j in jobs])
