@@ -58,7 +58,7 @@ typedef enum {
   TUCKER_EINVAL = -1,      /* invalid argument (see each call) */
   TUCKER_EWORKSPACE = -2,  /* workspace pointer null or smaller than required */
   TUCKER_EDEVICE = -3,     /* a HIP call failed (launch error, no device) */
-  TUCKER_EUNSUPPORTED = -4 /* valid request outside what this build handles */
+  TUCKER_EUNSUPPORTED = -4 /* valid request outside what the library handles */
 } tucker_status;
 
 typedef enum { TUCKER_FP64 = 0, TUCKER_FP32 = 1, TUCKER_BF16 = 2 } tucker_precision;

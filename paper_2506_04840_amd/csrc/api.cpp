@@ -1,4 +1,4 @@
-// C ABI driver: argument checks, workspace carving and the launch sequence of
+// C ABI front end: argument checks, workspace carving and the launch sequence of
 // shifted randomized T-HOSVD (Algorithm 2) and ST-HOSVD (Algorithm 3).
 // Every call validates on the host first and either enqueues all its work on
 // the caller's stream or returns an error having enqueued nothing. Nothing
@@ -1038,7 +1038,7 @@ const char* tucker_status_string(int status) {
     case TUCKER_EINVAL: return "invalid argument";
     case TUCKER_EWORKSPACE: return "workspace too small";
     case TUCKER_EDEVICE: return "device error";
-    case TUCKER_EUNSUPPORTED: return "unsupported by this build";
+    case TUCKER_EUNSUPPORTED: return "unsupported by the library";
   }
   return "unknown status";
 }

@@ -1,4 +1,4 @@
-// Host-side launchers shared by the C-ABI driver and the kernel files.
+// Host-side launchers shared by the C-ABI front end and the kernel files.
 #pragma once
 
 #include <hip/hip_runtime.h>
