@@ -96,7 +96,7 @@ class BatchServer:
     CLASSES = (16, 32, 48, 64)
 
     def __init__(self, capacity=256, q=1, p=8, lclass=48, ws_bytes=8 << 30, shift="adaptive", device="cuda",
-                 use_graphs=True, orders=(), overlap=True, spill=False, max_inflight=2):
+                 use_graphs=True, orders=(), overlap=True, spill=False, max_inflight=2, poll_s=10e-6):
         """lclass: the width class of every slot, or "auto" (each request to the
         smallest class that holds its sketch widths; with spill, a batch whose
         own class has no free slot may run in a free slot of a wider class).
@@ -114,6 +114,7 @@ class BatchServer:
         self.use_graphs = use_graphs
         self.spill = spill
         self.max_inflight = max_inflight
+        self.poll_s = poll_s  # sleep between polls while batches run (0: spin)
         self.slots: Dict[tuple, List[_Slot]] = {}
         for d in orders:
             self._slots_for((d, self.classes[-1]))
@@ -225,8 +226,8 @@ class BatchServer:
                 continue
             if pending and not nwait and not busy:
                 time.sleep(min(200e-6, max(0.0, pending[0].arrival - now)))
-            else:
-                time.sleep(10e-6)
+            elif self.poll_s > 0:
+                time.sleep(self.poll_s)
         return list(jobs)
 
 
