@@ -181,17 +181,19 @@ def pve_converged(sig_t: np.ndarray, sig_hat: np.ndarray, r: int, tol: float) ->
 
 def randomized_sthosvd_pve(a: np.ndarray, ranks: Sequence[int], p: int, q_max: int, tol: float, *,
                            shift: str = "adaptive", seed: int = 1,
-                           omega: Optional[OmegaProvider] = None) -> PveResult:
+                           omega: Optional[OmegaProvider] = None, variant: str = "st") -> PveResult:
     """Algorithm 4: shifted randomized ST-HOSVD whose power count q_k per mode
     stops at the first t <= q_max that passes ``pve_converged`` (the test comes
     before the shift update; sigma-hat starts at zero, so t = 1 passes only for
-    an unbounded tol). shift "none" keeps alpha at zero.
+    an unbounded tol). shift "none" keeps alpha at zero. variant "t" is the
+    T-HOSVD form the paper names Algorithm 2-v3 (details omitted there): every
+    mode from A, the core A x_1 U_1^T ... x_d U_d^T at the end.
 
     Readings: the printed test's right-hand side is garbled; it is read as tol
     times sigma_t(r_k + 1), the first discarded estimate, and sigma_t(l_k) stands
     in when l_k = r_k. q_max >= 1."""
-    if shift not in ("adaptive", "none"):
-        raise ValueError("bad shift")
+    if shift not in ("adaptive", "none") or variant not in ("t", "st"):
+        raise ValueError("bad shift or variant")
     if q_max < 1:
         raise ValueError("q_max must be at least 1")
     a = np.asarray(a, dtype=np.float64)
@@ -200,21 +202,22 @@ def randomized_sthosvd_pve(a: np.ndarray, ranks: Sequence[int], p: int, q_max: i
     logs: List[ModeLog] = []
     qs: List[int] = []
     for k in range(a.ndim):
-        n_k = g.shape[k]
-        m_k = g.size // n_k
+        x = a if variant == "t" else g
+        n_k = x.shape[k]
+        m_k = x.size // n_k
         r_k = int(ranks[k])
         if not (1 <= r_k <= n_k and r_k <= m_k):
             raise ValueError("infeasible rank at mode %d" % k)
         l_k = sketch_width(r_k, p, n_k, m_k)
         om = omega(k, m_k, l_k) if omega is not None else gaussian_omega(seed, k, m_k, l_k)
-        qm, s = svd_econ(sketch(g, k, om))
+        qm, s = svd_econ(sketch(x, k, om))
         alpha = 0.0
         sig_hat = np.zeros(l_k)
         alphas, sigmas = [alpha], [s]
         q_k = 0
         for _t in range(q_max):
             q_k += 1
-            qm, s = svd_econ(shifted_power(g, k, qm, alpha))
+            qm, s = svd_econ(shifted_power(x, k, qm, alpha))
             sig_t = s + alpha
             sigmas.append(s)
             if pve_converged(sig_t, sig_hat, r_k, tol):
@@ -226,7 +229,7 @@ def randomized_sthosvd_pve(a: np.ndarray, ranks: Sequence[int], p: int, q_max: i
             sig_hat = sig_t
         u_k = sign_fix(qm[:, :r_k])
         factors.append(u_k)
-        g = core_step(g, k, u_k)
+        g = core_step(g, k, u_k)   # T-HOSVD: the same contractions of A, in mode order
         logs.append(ModeLog(l_k, m_k, alphas, sigmas))
         qs.append(q_k)
     return PveResult(g, factors, logs, qs)

@@ -267,13 +267,15 @@ def test_pve_stopping_test_by_hand():
     assert pve_converged(sig_t, np.zeros(4), 2, 10.0)
 
 
+@pytest.mark.parametrize("variant", ["st", "t"])
 @pytest.mark.parametrize("shift", ["adaptive", "none"])
-def test_pve_tol_zero_is_algorithm_3_with_q_max(shift):
+def test_pve_tol_zero_is_algorithm_3_with_q_max(shift, variant):
     """tol = 0 never stops early (the estimates of a noisy tensor keep moving):
-    q_k = q_max and every result equals Algorithm 3 with q = q_max."""
+    q_k = q_max and every result equals Algorithm 3 (the T form: Algorithm 2)
+    with q = q_max."""
     a, _, _ = random_tucker((24, 22, 20), (4, 5, 3), 1e-2, seed=31)
-    res = randomized_sthosvd_pve(a, (4, 5, 3), 4, 4, 0.0, shift=shift, seed=2)
-    ref = randomized_hosvd(a, (4, 5, 3), 4, 4, shift=shift, variant="st", seed=2)
+    res = randomized_sthosvd_pve(a, (4, 5, 3), 4, 4, 0.0, shift=shift, seed=2, variant=variant)
+    ref = randomized_hosvd(a, (4, 5, 3), 4, 4, shift=shift, variant=variant, seed=2)
     assert res.qs == [4, 4, 4]
     assert np.array_equal(res.core, ref.core)
     for u, v in zip(res.factors, ref.factors):
@@ -282,12 +284,13 @@ def test_pve_tol_zero_is_algorithm_3_with_q_max(shift):
         assert lp.alphas == lr.alphas
 
 
-def test_pve_unbounded_tol_is_algorithm_3_with_one_step():
+@pytest.mark.parametrize("variant", ["st", "t"])
+def test_pve_unbounded_tol_is_algorithm_3_with_one_step(variant):
     """tol = inf stops after the first power step: q_k = 1 and the result
-    equals Algorithm 3 with q = 1."""
+    equals Algorithm 3 (Algorithm 2) with q = 1."""
     a, _, _ = random_tucker((24, 22, 20), (4, 5, 3), 1e-2, seed=32)
-    res = randomized_sthosvd_pve(a, (4, 5, 3), 4, 6, np.inf, seed=2)
-    ref = randomized_hosvd(a, (4, 5, 3), 4, 1, variant="st", seed=2)
+    res = randomized_sthosvd_pve(a, (4, 5, 3), 4, 6, np.inf, seed=2, variant=variant)
+    ref = randomized_hosvd(a, (4, 5, 3), 4, 1, variant=variant, seed=2)
     assert res.qs == [1, 1, 1]
     assert np.array_equal(res.core, ref.core)
 
@@ -304,6 +307,20 @@ def test_pve_first_mode_steps_fall_with_tol():
             assert res.qs[0] <= prev
         prev = res.qs[0]
         assert 1 <= min(res.qs) and max(res.qs) <= 40
+
+
+def test_pve_t_form_modes_are_independent():
+    """In the T form every mode reads A: mode 3's power count and factor are the
+    same whatever ranks the other modes ask for (in the ST form they are not,
+    since mode 3 then works on a tensor the other factors contracted)."""
+    a, _, _ = random_tucker((20, 18, 16), (4, 3, 5), 5e-2, seed=35)
+    r1 = randomized_sthosvd_pve(a, (4, 3, 5), 3, 30, 0.05, seed=9, variant="t")
+    r2 = randomized_sthosvd_pve(a, (2, 6, 5), 3, 30, 0.05, seed=9, variant="t")
+    assert r1.qs[2] == r2.qs[2]
+    assert np.array_equal(r1.factors[2], r2.factors[2])
+    s1 = randomized_sthosvd_pve(a, (4, 3, 5), 3, 30, 0.05, seed=9, variant="st")
+    s2 = randomized_sthosvd_pve(a, (2, 6, 5), 3, 30, 0.05, seed=9, variant="st")
+    assert not np.array_equal(s1.factors[2], s2.factors[2])
 
 
 def test_pve_reaches_the_q_max_error():
