@@ -175,7 +175,8 @@ def cpu_baseline(workload, cfg, a_host, shift, q, pve=None, omega="gaussian", or
     oo = orc.decreasing_order(a_host.shape) if order == "decreasing" else order
     t0 = time.perf_counter()
     if pve is not None:
-        res = orc.randomized_sthosvd_pve(a64, cfg["ranks"], cfg["p"], q, pve, shift=shift, seed=1)
+        res = orc.randomized_sthosvd_pve(a64, cfg["ranks"], cfg["p"], q, pve, shift=shift, seed=1,
+                                         variant=cfg["variant"])
     else:
         om = None
         if omega != "gaussian":
@@ -239,13 +240,11 @@ def main():
         a_host_store = None
 
     if args.pve is not None:
-        if cfg["variant"] != "st":
-            raise SystemExit("--pve applies to ST-HOSVD workloads")
         if order is not None or args.holistic:
             raise SystemExit("--pve runs Algorithm 3 in the natural order")
         q = 20 if args.q is None else args.q
         solver = T.PveSolver(A.shape, cfg["ranks"], cfg["p"], q, args.pve, args.shift, seed=w.sketch_seed,
-                             precision=prec, device=dev)
+                             precision=prec, device=dev, sequential=(cfg["variant"] == "st"))
     else:
         solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
                           sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega, order=order,
@@ -346,7 +345,8 @@ def main():
         line["config"]["algorithm"] = "holistic (Appendix B.1 / A.2 form)"
     line["config"]["launch"] = "HIP graph replay of the whole solve" if use_graph else "eager"
     if args.pve is not None:
-        line["config"].update({"algorithm": "4 (per-vector-error q)", "tol": args.pve, "q_max": q,
+        line["config"].update({"algorithm": "4 (per-vector-error q)" if cfg["variant"] == "st" else
+                               "2-v3 (Algorithm 4's test in T-HOSVD)", "tol": args.pve, "q_max": q,
                                "q_used": solver.q_used})
     print(json.dumps(line), flush=True)
 

@@ -50,7 +50,7 @@ extern "C" {
 
 #define TUCKER_MAX_ORDER 8
 #define TUCKER_MAX_Q 16 /* largest power count q */
-#define TUCKER_MAX_Q_PVE 1000 /* largest q_max of tucker_rsthosvd_pve */
+#define TUCKER_MAX_Q_PVE 1000 /* largest q_max of tucker_rsthosvd_pve / tucker_rthosvd_pve */
 #define TUCKER_MAX_L 64 /* largest sketch width l_k = min(r_k + p, n_k, m_k) */
 
 typedef enum {
@@ -297,6 +297,17 @@ int tucker_rsthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* 
 int tucker_rsthosvd_pve(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q_max,
                         double tol, tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                         tucker_info* info, int32_t* q_used, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* The T-HOSVD form of Algorithm 4, which the paper names Algorithm 2-v3 (in
+ * the remark after Algorithm 4; details omitted there): every mode from A, with
+ * the power count of each mode chosen by the same test, and the core
+ * A x_1 U_1^T ... x_d U_d^T at the end. The modes run one after the other on
+ * `stream` (each reads its flag on the host). Arguments, synchronisation and
+ * errors as tucker_rsthosvd_pve; workspace tucker_workspace_bytes(...,
+ * min(q_max, 16), prec, 0). */
+int tucker_rthosvd_pve(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q_max,
+                       double tol, tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                       tucker_info* info, int32_t* q_used, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* ---- Launch timing (measurement only) ---------------------------------------
  * When a kernel class is enabled, every launch of that class records a pair

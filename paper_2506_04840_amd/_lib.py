@@ -119,6 +119,8 @@ SIGNATURES = {
                                          _P, _P, _SZ, _P]),
     "tucker_rsthosvd_ex": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P,
                                           _P, _P, _SZ, _P]),
+    "tucker_rthosvd_pve": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, _D, ctypes.c_int, _U64, ctypes.c_int, _P, _P,
+                                          _P, _P, _P, _SZ, _P]),
     "tucker_rsthosvd_pve": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, _D, ctypes.c_int, _U64, ctypes.c_int, _P, _P,
                                            _P, _P, _P, _SZ, _P]),
     "tucker_timing_enable": (ctypes.c_int, [_I32, _I32]),
@@ -317,14 +319,15 @@ class Solver:
 
 class PveSolver(Solver):
     """Algorithm 4 (power count per mode by the per-vector-error test): q is
-    the largest power count q_max. run() returns after the solve (the library
-    synchronises the stream once per power step); q_used holds each q_k."""
+    the largest power count q_max; sequential=False gives its T-HOSVD form
+    (Algorithm 2-v3). run() returns after the solve (the library synchronises
+    the stream once per power step); q_used holds each q_k."""
 
     def __init__(self, dims, ranks, p=10, q_max=20, tol=0.5, shift="adaptive", seed=1, precision="fp32",
-                 device="cuda"):
+                 device="cuda", sequential=True):
         if not 1 <= int(q_max) <= MAX_Q_PVE:
             raise ValueError("q_max outside 1..%d" % MAX_Q_PVE)
-        super().__init__(dims, ranks, p, min(int(q_max), MAX_Q), shift, seed, precision, True, device)
+        super().__init__(dims, ranks, p, min(int(q_max), MAX_Q), shift, seed, precision, sequential, device)
         self.q_max, self.tol = int(q_max), float(tol)
         self._qused = (ctypes.c_int32 * len(self.dims))()
 
@@ -334,12 +337,11 @@ class PveSolver(Solver):
     def _call(self, A: Optional[torch.Tensor] = None, dry: bool = False):
         if dry:
             return super()._call(A, dry)
-        _check(lib.tucker_rsthosvd_pve(ctypes.byref(self._shape), ctypes.c_void_p(A.data_ptr()), self._ranks, self.p,
-                                       self.q_max, ctypes.c_double(self.tol), self.shift, ctypes.c_uint64(self.seed),
-                                       self.prec, ctypes.c_void_p(self.G.data_ptr()), self._uptr,
-                                       ctypes.c_void_p(self.info.data_ptr()), self._qused,
-                                       ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws.numel()),
-                                       _stream(self.device)))
+        fn = lib.tucker_rsthosvd_pve if self.sequential else lib.tucker_rthosvd_pve
+        _check(fn(ctypes.byref(self._shape), ctypes.c_void_p(A.data_ptr()), self._ranks, self.p, self.q_max,
+                  ctypes.c_double(self.tol), self.shift, ctypes.c_uint64(self.seed), self.prec,
+                  ctypes.c_void_p(self.G.data_ptr()), self._uptr, ctypes.c_void_p(self.info.data_ptr()), self._qused,
+                  ctypes.c_void_p(self.ws.data_ptr()), ctypes.c_size_t(self.ws.numel()), _stream(self.device)))
 
     @property
     def q_used(self):
@@ -352,6 +354,16 @@ def rsthosvd_pve(A: torch.Tensor, ranks, p=10, q_max=20, tol=0.5, shift="adaptiv
     prec = precision_of(A, precision)
     s = PveSolver(A.shape, ranks, p, q_max, tol, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec],
                   A.device)
+    s.run(A.contiguous())
+    return s.G, s.U, read_info(s.info), s.q_used
+
+
+def rthosvd_pve(A: torch.Tensor, ranks, p=10, q_max=20, tol=0.5, shift="adaptive", seed=1,
+                precision: Optional[str] = None):
+    """Algorithm 4 in the T-HOSVD form (Algorithm 2-v3). Returns (G, [U_k], info dict, [q_k])."""
+    prec = precision_of(A, precision)
+    s = PveSolver(A.shape, ranks, p, q_max, tol, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec],
+                  A.device, sequential=False)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info), s.q_used
 

@@ -1239,6 +1239,16 @@ int tucker_rsthosvd_pve(const tucker_shape* shape, const void* A, const int64_t*
   return solve(true, shape, A, ranks, p, q_max, shift, seed, prec, G, U, info, ws, ws_bytes, stream, tol, q_used);
 }
 
+int tucker_rthosvd_pve(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q_max,
+                       double tol, tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                       tucker_info* info, int32_t* q_used, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (q_max < 1 || q_max > TUCKER_MAX_Q_PVE)
+    return fail(TUCKER_EINVAL, "q_max = %d outside 1..%d", q_max, TUCKER_MAX_Q_PVE);
+  if (!(tol >= 0.0)) return fail(TUCKER_EINVAL, "tol must be >= 0 (got %g)", tol);
+  if (q_used == nullptr) return fail(TUCKER_EINVAL, "q_used is null");
+  return solve(false, shape, A, ranks, p, q_max, shift, seed, prec, G, U, info, ws, ws_bytes, stream, tol, q_used);
+}
+
 size_t tucker_batch_plan_bytes(int32_t capacity, int32_t order, int32_t q) {
   if (capacity < 1 || capacity > 4096 || order < 1 || order > TUCKER_MAX_ORDER || q < 0 || q > TUCKER_MAX_Q) return 0;
   return batch_plan_bytes(capacity, order, q);

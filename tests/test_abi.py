@@ -102,6 +102,10 @@ def test_pve_entry_point_validates_on_the_host():
     assert L.tucker_rsthosvd_pve(*args(5, math.nan, qu)) == -1
     assert L.tucker_rsthosvd_pve(*args(5, 0.5, None)) == -1
     assert "q_max" in L.tucker_status_string(L.tucker_rsthosvd_pve(*args(0, 0.5, qu))).decode()
+    # the T-HOSVD form checks the same
+    assert L.tucker_rthosvd_pve(*args(0, 0.5, qu)) == -1
+    assert L.tucker_rthosvd_pve(*args(5, math.nan, qu)) == -1
+    assert L.tucker_rthosvd_pve(*args(5, 0.5, None)) == -1
 
 
 def test_processing_order_options_on_the_host():

@@ -408,11 +408,13 @@ def _pve_ratios(res, ranks):
     return out
 
 
+@pytest.mark.parametrize("variant", ["st", "t"])
 @pytest.mark.parametrize("target", ["zero", "mid", "inf"])
-def test_solve_pve_fp64_matches_oracle(T, target):
-    """Algorithm 4 in FP64 against the oracle: the same power counts q_k (tol
-    chosen away from every step's threshold, where rounding could flip the
-    decision) and the reconstruction within 1e-10."""
+def test_solve_pve_fp64_matches_oracle(T, target, variant):
+    """Algorithm 4 in FP64 against the oracle (and its T-HOSVD form, the
+    paper's Algorithm 2-v3): the same power counts q_k (tol chosen away from
+    every step's threshold, where rounding could flip the decision) and the
+    reconstruction within 1e-10."""
     a, _, _ = gen.random_tucker((33, 45, 28), (5, 6, 4), 0.05, seed=21)
     ranks, p, qmax = (5, 6, 4), 6, 12
     if target == "zero":
@@ -420,17 +422,17 @@ def test_solve_pve_fp64_matches_oracle(T, target):
     elif target == "inf":
         tol = float("inf")
     else:
-        probe = orc.randomized_sthosvd_pve(a, ranks, p, qmax, 0.0, seed=1)
+        probe = orc.randomized_sthosvd_pve(a, ranks, p, qmax, 0.0, seed=1, variant=variant)
         rats = _pve_ratios(probe, ranks)
         tol = float(np.sqrt(rats[0][1] * rats[0][2]))  # mode 1 stops at its third step
         for _ in range(20):
-            res = orc.randomized_sthosvd_pve(a, ranks, p, qmax, tol, seed=1)
+            res = orc.randomized_sthosvd_pve(a, ranks, p, qmax, tol, seed=1, variant=variant)
             if all(abs(x / tol - 1.0) > 1e-6 for rr in _pve_ratios(res, ranks) for x in rr):
                 break
             tol *= 1.37
-    res = orc.randomized_sthosvd_pve(a, ranks, p, qmax, tol, seed=1)
-    G, U, info, qs = T.rsthosvd_pve(_dev(a, torch.float64), ranks, p=p, q_max=qmax, tol=tol, seed=1,
-                                    precision="fp64")
+    res = orc.randomized_sthosvd_pve(a, ranks, p, qmax, tol, seed=1, variant=variant)
+    fn = T.rsthosvd_pve if variant == "st" else T.rthosvd_pve
+    G, U, info, qs = fn(_dev(a, torch.float64), ranks, p=p, q_max=qmax, tol=tol, seed=1, precision="fp64")
     torch.cuda.synchronize()
     assert qs == res.qs, (qs, res.qs, tol)
     na = np.linalg.norm(a)
