@@ -661,3 +661,41 @@ def test_concurrent_t_hosvd_capture_is_refused(T):
     s = T.Solver((20, 18, 16), (3, 3, 3), 4, 1, "adaptive", 1, "fp32", False, torch.device("cuda:0"))
     with pytest.raises(NotImplementedError):
         s.capture(torch.zeros((20, 18, 16), device="cuda:0"))
+
+
+# --------------------------------------------------------------- degenerate inputs
+
+@pytest.mark.parametrize("variant", ["st", "t"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_tensor(T, variant, prec):
+    """A = 0: every column of every iterate is dependent. The core is exactly
+    zero, the factors are orthonormal (completed by the fixed pseudo-random
+    directions), the shift stays at 0 and the deficiency flag is raised."""
+    x = torch.zeros((30, 28, 26), dtype=DT[prec], device="cuda")
+    fn = T.rsthosvd if variant == "st" else T.rthosvd
+    G, U, info = fn(x, (4, 5, 3), p=5, q=2, precision=prec)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(G).item() == 0
+    for u in U:
+        uu = _np(u)
+        assert np.all(np.isfinite(uu))
+        assert np.max(np.abs(uu.T @ uu - np.eye(uu.shape[1]))) < (1e-12 if prec == "fp64" else 1e-6)
+    assert all(a == 0.0 for row in info["alpha"][:3] for a in row)
+    assert info["flags"] & T.INFO_DEFICIENT
+
+
+def test_ranks_above_the_true_rank_and_unit_modes(T):
+    """Ranks above the tensor's exact Tucker rank (the extra columns are
+    completion directions: orthonormal, the reconstruction still exact), and a
+    mode of size 1, against the oracle."""
+    a, _, _ = gen.random_tucker((24, 22, 20), (2, 3, 2), 0.0, seed=43)
+    G, U, info = T.rsthosvd(_dev(a, torch.float64), (5, 6, 4), p=4, q=1, precision="fp64")
+    torch.cuda.synchronize()
+    rec = reconstruct(_np(G), [_np(u) for u in U])
+    assert np.linalg.norm(a - rec) / np.linalg.norm(a) < 1e-12
+    for u in U:
+        uu = _np(u)
+        assert np.max(np.abs(uu.T @ uu - np.eye(uu.shape[1]))) < 1e-12
+    b, _, _ = gen.random_tucker((1, 30, 40), (1, 5, 5), 0.05, seed=44)
+    for variant in ("st", "t"):
+        _compare_solve(_dev(b, torch.float64), b, (1, 5, 5), 4, 1, "adaptive", variant, "fp64", check_core=False)
