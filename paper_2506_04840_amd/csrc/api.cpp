@@ -841,7 +841,7 @@ int batch_colreduce_splits(const View3& v, int l) {
 
 // Fills one phase's descriptor for item b (returns its work items).
 int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const SolveWs& w,
-                   const tucker_batch_item& it, tucker_shift shift, int d, void* dst) {
+                   const tucker_batch_item& it, tucker_shift shift, int d, int q, void* dst) {
   const View3 v = pl.v[k];
   const int l = pl.l[k], r = (int)pl.r[k];
   const int64_t n = v.n, m = pl.m[k];
@@ -989,6 +989,10 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
       return nblk;
     }
     case BK_SVD: {
+      // with power steps to follow, the sketch's SVD feeds nothing (alpha_0 = 0
+      // and step 1 factors the unrotated iterate): it only logs, so it runs for
+      // the items that keep a log
+      if (t == 0 && q > 0 && it.info == nullptr) return 0;
       BSvd* b = (BSvd*)dst;
       b->Rg = ows.R;
       b->status = ows.status;
@@ -1324,7 +1328,8 @@ int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t n
     int64_t acc = 0;
     for (int b = 0; b < nitems; ++b) {
       hdr[1 + b] = (int)acc;
-      acc += batch_desc((BatchKind)r.kind, k, t, role, pls[b], wss[b], items[b], shift, d, desc + (size_t)b * dsz);
+      acc += batch_desc((BatchKind)r.kind, k, t, role, pls[b], wss[b], items[b], shift, d, q,
+                        desc + (size_t)b * dsz);
       batch_phase_work((BatchKind)r.kind, k, role, pls[b], &r.bytes, &r.flops);
     }
     hdr[1 + nitems] = (int)acc;
