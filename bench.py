@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--pve", type=float, default=None, metavar="TOL",
                     help="Algorithm 4: power count per mode by the per-vector-error test with this tol "
                          "(--q is then q_max, default 20)")
-    ap.add_argument("--kernel", default="auto", choices=["auto", "colreduce", "rowcontract"],
+    ap.add_argument("--kernel", default="auto", choices=["auto", "colreduce", "rowcontract", "powerstep"],
                     help="kernel class reported in the roofline object (auto: the larger summed launch time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -280,10 +280,10 @@ def main():
 
     roof = None
     if not args.no_kernel_timing:
-        # both product classes, one timing pass each; the roofline object is the
+        # the product classes, one timing pass each; the roofline object is the
         # class with the larger summed launch time (or the one named by --kernel)
         timed = {}
-        for kern in ("colreduce", "rowcontract"):
+        for kern in ("colreduce", "rowcontract", "powerstep"):
             T.timing_enable(kern, capacity=65536)
             torch.cuda.synchronize()
             for _ in range(args.steps):

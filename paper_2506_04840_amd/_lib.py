@@ -136,7 +136,7 @@ SIGNATURES = {
     "tucker_batch_step": (ctypes.c_int, [_P, _P]),
 }
 
-KC = {"colreduce": 0, "rowcontract": 1, "orth": 2, "fill": 3, "reduce": 4}
+KC = {"colreduce": 0, "rowcontract": 1, "orth": 2, "fill": 3, "reduce": 4, "powerstep": 5}
 
 
 def _load() -> ctypes.CDLL:

@@ -418,16 +418,16 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
       e = launch_orth_svd(l, step_prec(t - 1), orth_step_set(ows, t - 1), w.sigma, t == 1 ? nullptr : alpha_upd,
                           info, k, t - 1, side->s);
     if (e == hipSuccess) e = hipEventRecord(side->svd_done, side->s);
-    // Z = X_(k)^T Q3 (j-major), Y' = X_(k) Z
-    if (e == hipSuccess) e = launch_rowcontract(tp, v, X, w.qt, 1, n, l, w.omz, true, st);
-    if (e == hipSuccess) e = launch_colreduce(tp, v, X, w.omz, l, w.part, nsplit, st);
+    // Z = X_(k)^T Q3, Y' = X_(k) Z (one pass over X where the fused kernel applies)
+    int ns_used = nsplit;
+    if (e == hipSuccess) e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, &ns_used, st);
     // Y = (Y' - alpha Q3) J, then its CholeskyQR. Step 1 needs nothing from
     // the sketch's SVD: alpha_0 = 0, and J_0 only turns the basis inside the
     // span, which leaves the iterate's left singular vectors and values as
     // they are; step 1 factors Y' itself and its own SVD absorbs J_0.
     if (e == hipSuccess && t > 1) e = hipStreamWaitEvent(st, side->svd_done, 0);
     if (e == hipSuccess)
-      e = launch_reduce_splits(tp, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
+      e = launch_reduce_splits(tp, w.part, ns_used, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
     if (e == hipSuccess)
       e = launch_orth_qr(n, l, w.y64, t > 1 ? ows.Wm : nullptr, tp, w.qt, orth_step_set(ows, t), cseed, t, st);
   }
@@ -472,9 +472,9 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
   while (e == hipSuccess && t < q_max) {
     ++t;
     // Z = X_(k)^T Q3, Y' = X_(k) Z, Y = (Y' - alpha Q3) J (reading R1), CholeskyQR, small SVD + test
-    e = launch_rowcontract(tp, v, X, w.qt, 1, n, l, w.omz, true, st);
-    if (e == hipSuccess) e = launch_colreduce(tp, v, X, w.omz, l, w.part, nsplit, st);
-    if (e == hipSuccess) e = launch_reduce_splits(tp, w.part, nsplit, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
+    int ns_used = nsplit;
+    e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, &ns_used, st);
+    if (e == hipSuccess) e = launch_reduce_splits(tp, w.part, ns_used, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
     if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, tp, w.qt, ows, cseed, t, st);
     if (e == hipSuccess) e = launch_orth_svd(l, tp, ows, w.sigma, alpha_upd, info, k, t, st, &pve);
     int halt = 0;
@@ -1112,10 +1112,19 @@ int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X,
   op_ws_layout(v, m, (int)l, prec, (char*)ws, &w);
   const int nsplit = colreduce_splits(v, (int)l);
   double* y = raw ? (double*)out : w.y64;
-  hipError_t e = launch_rowcontract(prec, v, X, Q, l, 1, (int)l, w.omz, true, stream);
-  if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
+  hipError_t e;
+  int ns_used = nsplit;
+  if (power_fused_splits(v, (int)l, prec) > 0 && v.n <= m) {
+    // the fused pass reads Q j-major: transposed into the space of Z, which it does not use
+    e = launch_transpose_f32((const float*)Q, v.n, (int)l, (float*)w.omz, stream);
+    if (e == hipSuccess)
+      e = launch_power_products(prec, v, X, w.omz, (int)l, nullptr, w.part, nsplit, &ns_used, stream);
+  } else {
+    e = launch_rowcontract(prec, v, X, Q, l, 1, (int)l, w.omz, true, stream);
+    if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
+  }
   if (e == hipSuccess)
-    e = launch_reduce_splits(prec, w.part, nsplit, v.n * l, Q, prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32,
+    e = launch_reduce_splits(prec, w.part, ns_used, v.n * l, Q, prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32,
                              alpha, y, stream);
   if (e == hipSuccess && !raw) {
     const OrthWs ows = carve_orth(w.orth, v.n, (int)l);

@@ -17,7 +17,15 @@ struct View3 {
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Kernel classes of the opt-in launch timing (values of TUCKER_KC_*).
-enum KernelClass { KC_COLREDUCE = 0, KC_ROWCONTRACT = 1, KC_ORTH = 2, KC_FILL = 3, KC_REDUCE = 4, KC_COUNT = 5 };
+enum KernelClass {
+  KC_COLREDUCE = 0,
+  KC_ROWCONTRACT = 1,
+  KC_ORTH = 2,
+  KC_FILL = 3,
+  KC_REDUCE = 4,
+  KC_POWERSTEP = 5,
+  KC_COUNT = 6
+};
 
 // Records a HIP event pair around the launches in its scope when `cls` is the
 // enabled class; bytes and flops are the launch's algorithmic traffic and work.
@@ -88,6 +96,20 @@ int colreduce_splits(const View3& v, int l);
 size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec);
 hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* B, int l,
                             void* part, int nsplit, hipStream_t st);
+
+// Both products of a power step, Y' = X_(k) (X_(k)^T Q) as split partials
+// (part[split][i][j], FP32 or FP64 as the column reduction's), from Q given
+// j-major in the storage precision (qt[j * n + i]). FP32 steps with S >= 64,
+// n <= 512 and l <= 48 run one fused pass over X (power_fused_splits > 0
+// splits, part needs power_fused_part_bytes); the others run the row
+// contraction into z (j-major, P S x l) and the column reduction with nsplit
+// splits. *nsplit_used: the split count to reduce.
+int power_fused_splits(const View3& v, int l, tucker_precision prec);
+size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec);
+hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
+                                 void* z, void* part, int nsplit, int* nsplit_used, hipStream_t st);
+// Qt[j n + i] = Q[i l + j], FP32.
+hipError_t launch_transpose_f32(const float* Q, int64_t n, int l, float* Qt, hipStream_t st);
 
 // Y[e] = sum_s part[s][e] - (qsub ? alpha * qsub[e] : 0), FP64 out.
 // qsub_prec gives qsub's element type (FP64 or FP32 storage).

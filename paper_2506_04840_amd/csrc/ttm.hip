@@ -1,6 +1,7 @@
 // Mode-k products on the in-place unfolding X_(k)[i, p*S + s] = X[p, i, s].
 //
-// Two contractions cover the method's three products:
+// Two contractions cover the method's three products (and a fused kernel
+// runs both products of an FP32 power step in one pass, further below):
 //  * column reduction  part = X_(k) B   (sketch Y = X_(k) Omega_k and the
 //    second half of the power step Y = X_(k) Z): a long reduction over the
 //    m_k columns, split over workgroups, summed in a fixed order later;
@@ -466,7 +467,9 @@ int colreduce_splits(const View3& v, int l) {
 
 size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec) {
   const int ns = std::max(colreduce_splits_prec(v, prec), colreduce_splits_prec(v, TUCKER_FP32));
-  return (size_t)ns * (size_t)v.n * (size_t)l * elem_bytes(prec);
+  const size_t b = (size_t)ns * (size_t)v.n * (size_t)l * elem_bytes(prec);
+  // FP32 and BF16 plans (whose last step runs on FP32 operands) may take the fused power step
+  return prec == TUCKER_FP64 ? b : std::max(b, power_fused_part_bytes(v, l, TUCKER_FP32));
 }
 
 template <int MK, int NJ>
@@ -931,6 +934,262 @@ hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X
     case TUCKER_BF16: return rc_dispatch<MF_BF16>(v, X, W, wsi, wsj, lw, out, out_jmajor, st);
   }
   return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Both products of a power step in one pass over X (FP32, S > 1):
+//   part[g][i][j] = sum over the column blocks b dealt to workgroup g of
+//                   sum_{c in b} X_(k)[i, c] Z[c, j],
+//   Z[c, j] = sum_i X_(k)[i, c] Q[i, j]   (Q given j-major, Qt[j n + i]).
+// A block is 64 consecutive columns s of one p, all n rows (at most
+// PF_NMAX). It crosses HBM once and is staged in LDS: rows of 16 float4
+// slots, the slot index XOR-ed with the row's low 4 bits so that the lanes
+// of a fragment read hit distinct banks; rows past n are zero. Eight waves,
+// two per SIMD, so that one wave's LDS and L2 waits are covered by the
+// other's matrix-core work:
+//  * Z_b = X_b^T Q: wave w forms the 16 columns 16 (w % 4) .. + 15 over the
+//    row groups of half w / 4 (A from LDS, Q's rows from L2, two groups
+//    ahead); the two halves go to LDS j-major and are added in that order;
+//  * Y += X_b Z_b: wave w owns the 16-row groups w, w + 8, ... and keeps
+//    their Y tiles in matrix-core registers across the workgroup's blocks.
+// The loads of the next block are issued after the first product (whose Q
+// loads would otherwise wait behind them) and are in flight through the
+// second; the barriers order LDS only. Loads take clamped addresses with
+// no branch (a branch around a load made the compiler wait for every load
+// in flight); values from clamped rows or columns are replaced by zeros or
+// feed only outputs that are never written. The block fills most of the
+// LDS: one workgroup per CU.
+// Requires n % 4 == 0 (a 4-row group of Q is whole, or lies past n where
+// the staged X rows are zero) and S % 4 == 0 (a 4-column group of X is
+// whole or absent).
+// ---------------------------------------------------------------------------
+constexpr int PF_NMAX = 512;  // rows: 32 groups of 16, 4 per wave
+
+__device__ __forceinline__ int pf_swz(int row, int slot) { return row * 16 + (slot ^ (row & 15)); }
+
+template <int JT, int GW>
+__global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X, const float* __restrict__ Qt,
+                                                     int64_t n, int64_t S, int l, int64_t nbs, int64_t nblocks,
+                                                     float* __restrict__ part) {
+  constexpr int XROWS = 8 * GW * 16;
+  constexpr int ZH = 16 * JT * 16;  // one half's Z_b (float4 slots)
+  static_assert(XROWS <= PF_NMAX, "row groups");
+  __shared__ floatx4 lds[XROWS * 16 + 2 * ZH];
+  floatx4* Xs = lds;               // [XROWS rows i][16 slots of c]
+  floatx4* Zs = lds + XROWS * 16;  // [2 halves][16 JT rows j][16 slots of c]
+  const float* Xsf = reinterpret_cast<const float*>(Xs);
+
+  const int lane = threadIdx.x & 63, w = wave_id();
+  const int g = lane >> 4, f = lane & 15;
+  const int ng = (int)((n + 15) >> 4);
+  const int ngw = (ng - w + 7) >> 3;  // this wave's row groups: w + 8 gg, gg < ngw
+  const int ct = w & 3, h = w >> 2;   // first product: column tile and row half
+  const int th = (ng + 1) >> 1;
+  const int t0 = h * th, t1 = min(ng, t0 + th);
+  const int64_t G = gridDim.x;
+
+  // lane (g, f) loads rows 16 (w + 8 gg) + 4 g + q, columns s0 + 4 f .. + 3
+  floatx4 xr[GW][4];
+  auto load_block = [&](int64_t b) {
+    const int64_t p = b / nbs, s = (b - p * nbs) * 64 + 4 * f;
+    const bool in = s < S;
+    const float* base = X + p * n * S + (in ? s : S - 4);
+#pragma unroll
+    for (int gg = 0; gg < GW; ++gg)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t i = min<int64_t>(16 * (w + 8 * gg) + 4 * g + q, n - 1);
+        const f4u_t v = *reinterpret_cast<const f4u_t*>(base + i * S);
+        xr[gg][q] = in ? floatx4{v[0], v[1], v[2], v[3]} : floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  // Q rows 16 t + 4 g .. + 3 of column j = 16 jt + f (clamped to valid rows
+  // and columns: past n they meet zero X rows, past l they feed unused Z)
+  int64_t qcol[JT];
+#pragma unroll
+  for (int jt = 0; jt < JT; ++jt) qcol[jt] = (int64_t)min(16 * jt + f, l - 1) * n;
+  auto load_q = [&](int t, floatx4* qv) {
+    const int64_t i0 = min<int64_t>(16 * t + 4 * g, n - 4);
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) {
+      const f4u_t v = *reinterpret_cast<const f4u_t*>(Qt + qcol[jt] + i0);
+      qv[jt] = floatx4{v[0], v[1], v[2], v[3]};
+    }
+  };
+
+  floatx4 yacc[GW][JT];
+#pragma unroll
+  for (int gg = 0; gg < GW; ++gg)
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) yacc[gg][jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  int64_t b = blockIdx.x;
+  load_block(b);
+  for (; b < nblocks; b += G) {
+    // Q's first row groups of this wave's half, in flight while the block is
+    // staged (issued in buffer order, as in the loop below: the wait before
+    // a buffer's use counts the loads issued after it on every path). The
+    // empty asm keeps these loads in the loop: hoisted, their values would
+    // hold 12 JT registers through the second product.
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) __asm__ volatile("" : "+v"(qcol[jt]));
+    floatx4 qa[JT], qb[JT], qc[JT];
+    load_q(min(t0, ng - 1), qa);
+    __builtin_amdgcn_sched_barrier(0);
+    load_q(min(t0 + 1, ng - 1), qb);
+    __builtin_amdgcn_sched_barrier(0);
+    load_q(min(t0 + 2, ng - 1), qc);
+    __builtin_amdgcn_sched_barrier(0);
+    // 1. stage the block (the previous block's second product is done with the LDS)
+    lds_barrier();
+#pragma unroll
+    for (int gg = 0; gg < GW; ++gg)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * (w + 8 * gg) + 4 * g + q;
+        Xs[pf_swz(r, f)] = r < n ? xr[gg][q] : floatx4{0.f, 0.f, 0.f, 0.f};
+      }
+    lds_barrier();
+    // 2. Z_b columns 16 ct + r (tile row r = f for the A operand), all j,
+    //    over row groups t0 .. t1 - 1: k-slot g at step q of group t is row
+    //    16 t + 4 g + q. Three Q buffers, each refilled right after its last
+    //    use and consumed three groups later (a copy between buffers would
+    //    wait for its load).
+    floatx4 zacc[JT];
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) zacc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int aslot = 4 * ct + (f >> 2), ael = f & 3;
+    auto zstep = [&](int t, const floatx4* qv) {
+      float a[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * t + 4 * g + q;
+        a[q] = Xsf[4 * (16 * r + (aslot ^ (r & 15))) + ael];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) zacc[jt] = mfma_f32(a[q], qv[jt][q], zacc[jt]);
+    };
+    for (int t = t0; t < t1; t += 3) {
+      zstep(t, qa);
+      load_q(min(t + 3, ng - 1), qa);
+      if (t + 1 < t1) zstep(t + 1, qb);
+      load_q(min(t + 4, ng - 1), qb);
+      if (t + 2 < t1) zstep(t + 2, qc);
+      load_q(min(t + 5, ng - 1), qc);
+    }
+    // lane holds rows 4 g + e of tile jt: column c = 16 ct + 4 g + e, j = 16 jt + f
+#pragma unroll
+    for (int jt = 0; jt < JT; ++jt) Zs[h * ZH + pf_swz(16 * jt + f, 4 * ct + g)] = zacc[jt];
+    // 3. the next block's loads, in flight through the second product
+    load_block(b + G < nblocks ? b + G : b);
+    lds_barrier();
+    // 4. Y += X_b Z_b: tile (gg, jt) row r is row 16 G' + r, k-slot g at
+    //    step q is column 16 cc + 4 g + q (column chunks outermost: one
+    //    chunk of Z_b is held at a time)
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      floatx4 zb[JT];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        const int o = pf_swz(16 * jt + f, 4 * cc + g);
+        zb[jt] = Zs[o] + Zs[ZH + o];
+      }
+#pragma unroll
+      for (int gg = 0; gg < GW; ++gg)
+        if (gg < ngw) {
+          const floatx4 a = Xs[pf_swz(16 * (w + 8 * gg) + f, 4 * cc + g)];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int jt = 0; jt < JT; ++jt) yacc[gg][jt] = mfma_f32(a[q], zb[jt][q], yacc[gg][jt]);
+        }
+    }
+  }
+  // lane holds rows 4 g + e of tile (gg, jt): i = 16 G' + 4 g + e, j = 16 jt + f
+  float* dst = part + (int64_t)blockIdx.x * n * l;
+#pragma unroll
+  for (int gg = 0; gg < GW; ++gg)
+    if (gg < ngw) {
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        const int j = 16 * jt + f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t i = 16 * (w + 8 * gg) + 4 * g + e;
+          if (i < n && j < l) dst[i * l + j] = yacc[gg][jt][e];
+        }
+      }
+    }
+}
+
+// Qt[j n + i] = Q[i l + j] (FP32).
+__global__ __launch_bounds__(256) void k_transpose_f32(const float* __restrict__ Q, int64_t n, int l,
+                                                       float* __restrict__ Qt) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n * l) return;
+  const int64_t j = e / n, i = e - j * n;
+  Qt[e] = Q[i * l + j];
+}
+
+hipError_t launch_transpose_f32(const float* Q, int64_t n, int l, float* Qt, hipStream_t st) {
+  const int64_t cnt = n * l;
+  if (cnt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, Q, n, l, Qt);
+  return hipGetLastError();
+}
+
+// Workgroups of the fused power step: the fewest rounds over the blocks with
+// at most 252 workgroups (one per CU of the 256; four CUs stay free for the
+// small SVD that runs beside it), then as few workgroups as give that many
+// rounds. A function of the shape only, so the plan that sizes the partials
+// and the launch agree. 0 when the fused kernel does not apply.
+int power_fused_splits(const View3& v, int l, tucker_precision prec) {
+  if (prec != TUCKER_FP32 || v.S < 64 || v.S % 4 != 0 || v.n % 4 != 0 || v.n > PF_NMAX || l > 48 || l < 1)
+    return 0;
+  constexpr int64_t kMaxGroups = 256 - 4;
+  const int64_t nblocks = v.P * ((v.S + 63) / 64);
+  const int64_t rounds = (nblocks + kMaxGroups - 1) / kMaxGroups;
+  return (int)((nblocks + rounds - 1) / rounds);
+}
+
+size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec) {
+  return (size_t)power_fused_splits(v, l, prec) * v.n * l * sizeof(float);
+}
+
+template <int JT, int GW>
+static void pf_launch(const View3& v, const float* X, const float* Qt, int l, float* part, int G, hipStream_t st) {
+  const int64_t nbs = (v.S + 63) / 64;
+  TK_LAUNCH((k_power_fused<JT, GW>), dim3(G), dim3(512), 0, st, X, Qt, v.n, v.S, l, nbs, v.P * nbs, part);
+}
+
+template <int JT>
+static void pf_dispatch(const View3& v, const float* X, const float* Qt, int l, float* part, int G, hipStream_t st) {
+  const int gw = (int)(((v.n + 15) / 16 + 7) / 8);  // row groups per wave
+  if (gw <= 1) pf_launch<JT, 1>(v, X, Qt, l, part, G, st);
+  else if (gw <= 2) pf_launch<JT, 2>(v, X, Qt, l, part, G, st);
+  else pf_launch<JT, 4>(v, X, Qt, l, part, G, st);
+}
+
+hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
+                                 void* z, void* part, int nsplit, int* nsplit_used, hipStream_t st) {
+  const int G = power_fused_splits(v, l, prec);
+  if (G == 0) {
+    *nsplit_used = nsplit;
+    hipError_t e = launch_rowcontract(prec, v, X, qt, 1, v.n, l, z, true, st);
+    if (e == hipSuccess) e = launch_colreduce(prec, v, X, z, l, part, nsplit, st);
+    return e;
+  }
+  *nsplit_used = G;
+  const double N = (double)v.P * v.n * v.S;
+  TimingScope ts(KC_POWERSTEP, st, 4.0 * (N + (double)v.n * l), 4.0 * N * l, true);
+  switch ((l + 15) / 16) {
+    case 1: pf_dispatch<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, st); break;
+    case 2: pf_dispatch<2>(v, (const float*)X, (const float*)qt, l, (float*)part, G, st); break;
+    default: pf_dispatch<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, st); break;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -115,6 +115,56 @@ def test_power_step_raw_matches_oracle(T, prec, dims, mode, l):
     assert np.max(np.abs(m - ref)) <= TOL[prec] * scale
 
 
+# Shapes that take the fused one-pass power step in FP32 (S >= 64, n and S
+# multiples of 4, n <= 512, l <= 48): several rounds of blocks per workgroup
+# (400 x 16640 columns: 260 blocks), ragged row groups (n = 100, 44, 260),
+# ragged last blocks (S = 1800, 100, 204), P > 1 (modes in the middle), the
+# largest n (512, 4 row groups per wave), a row half with no group (n = 16)
+# and widths of one to three 16-column tiles.
+FUSED = [((400, 130, 128), 0, 40), ((100, 36, 50), 0, 17), ((30, 400, 100), 1, 48), ((8, 44, 68, 3), 1, 1),
+         ((8, 44, 68, 3), 1, 44), ((512, 70, 40), 0, 48), ((16, 12, 64), 0, 16), ((260, 24, 20), 0, 33)]
+
+
+@pytest.mark.parametrize("dims,mode,l", FUSED)
+def test_fused_power_step_matches_oracle(T, dims, mode, l):
+    """The one-pass power step against the oracle's X_(k)(X_(k)^T Q) - alpha Q,
+    element by element (FP32 operands, FP32 accumulation over at most the
+    columns of one workgroup's blocks, FP64 sum of the workgroups)."""
+    g = gen.rng(23)
+    a = g.standard_normal(dims)
+    x = _dev(a, torch.float32)
+    xa = _np(x)
+    q0 = np.linalg.qr(g.standard_normal((dims[mode], l)))[0]
+    q = _dev(q0, torch.float32)
+    qa = _np(q)
+    alpha = 0.37 * float(np.linalg.norm(a) ** 2) / dims[mode]
+    al = torch.tensor([alpha], dtype=torch.float64, device="cuda")
+    print("fused power step", dims, mode, l, flush=True)
+    m = _np(T.shifted_power(x, mode, q, al, raw=True, precision="fp32"))
+    ref = orc.shifted_power(xa, mode, qa, alpha)
+    # each entry sums m products of size |X_i| |Z_j| / m; FP32 rounding of Z
+    # and of the sums: a few 2^-24 relative to the row and column scales
+    xk = unfold(xa, mode)
+    z = xk.T @ qa
+    scale = np.sqrt(np.sum(xk ** 2, axis=1))[:, None] * np.sqrt(np.sum(z ** 2, axis=0))[None, :]
+    assert np.all(np.abs(m - ref) <= 1e-5 * scale + 1e-5 * alpha * np.abs(qa)), np.max(np.abs(m - ref) / scale)
+
+
+def test_fused_power_step_at_an_unaligned_address(T):
+    """X and Q one element past an aligned address on the fused path."""
+    dims, mode, l = (20, 64, 36), 0, 20
+    g = gen.rng(29)
+    a = g.standard_normal(dims)
+    x = _dev_offset(a, torch.float32)
+    assert x.data_ptr() % 16 != 0
+    q = _dev_offset(np.linalg.qr(g.standard_normal((dims[mode], l)))[0], torch.float32)
+    al = torch.tensor([0.5], dtype=torch.float64, device="cuda")
+    m = _np(T.shifted_power(x, mode, q, al, raw=True, precision="fp32"))
+    xa = _np(x)
+    ref = orc.shifted_power(xa, mode, _np(q), 0.5)
+    assert np.max(np.abs(m - ref)) <= 1e-5 * np.linalg.norm(xa) ** 2
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("dims,mode,r", [((60, 60, 60), 0, 10), ((37, 130, 29), 1, 20), ((37, 130, 29), 2, 5),
                                          ((5, 6, 7, 8), 1, 3), ((9, 10, 11, 12), 3, 12), ((300, 40), 1, 33),
