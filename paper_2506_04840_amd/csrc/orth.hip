@@ -63,6 +63,7 @@ OrthWs carve_orth(void* base, int64_t n, int l) {
   w.Wm = (double*)p; p += align_up((size_t)kMaxL * kMaxL * sizeof(double));
   w.defic = (int*)p; p += align_up(3 * kMaxL * sizeof(int));
   w.status = (int*)p; p += align_up(4 * sizeof(int));
+  w.pf_ctr = w.status + 8;  // in the same 256-byte block, past the 4 status words
   w.R_odd = (double*)p; p += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
   w.defic_odd = (int*)p; p += align_up(3 * kMaxL * sizeof(int));
   w.status_odd = (int*)p; p += align_up(4 * sizeof(int));
@@ -1130,12 +1131,15 @@ hipError_t launch_info_init(tucker_info* info, const int32_t* l, int d, int32_t 
   return hipGetLastError();
 }
 
-__global__ void k_set_double(double* dst, double v) {
-  if (threadIdx.x == 0) *dst = v;
+__global__ void k_mode_start(double* alpha, int* ctr) {
+  if (threadIdx.x != 0) return;
+  if (alpha != nullptr) *alpha = 0.0;
+  ctr[0] = 0;
+  ctr[1] = 0;
 }
 
-hipError_t launch_set_double(double* dst, double v, hipStream_t st) {
-  hipLaunchKernelGGL(k_set_double, dim3(1), dim3(1), 0, st, dst, v);
+hipError_t launch_mode_start(double* alpha, int* ctr, hipStream_t st) {
+  hipLaunchKernelGGL(k_mode_start, dim3(1), dim3(1), 0, st, alpha, ctr);
   return hipGetLastError();
 }
 

@@ -952,6 +952,13 @@ hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X
 //    ahead); the two halves go to LDS j-major and are added in that order;
 //  * Y += X_b Z_b: wave w owns the 16-row groups w, w + 8, ... and keeps
 //    their Y tiles in matrix-core registers across the workgroup's blocks.
+// The blocks form NC chunks, chunk c holding blocks c, c + NC, ...; a
+// workgroup takes chunks from a counter (ctr[0]) and writes chunk c's Y as
+// split partial c, so the result does not depend on which workgroup took a
+// chunk. A workgroup that starts late (its CU held by a kernel of another
+// stream) finds the chunks taken and leaves, instead of delaying the whole
+// launch. The last workgroup to finish (ctr[1] counts them) sets both
+// counters back to zero for the next launch.
 // The loads of the next block are issued after the first product (whose Q
 // loads would otherwise wait behind them) and are in flight through the
 // second; the barriers order LDS only. Loads take clamped addresses with
@@ -970,11 +977,12 @@ __device__ __forceinline__ int pf_swz(int row, int slot) { return row * 16 + (sl
 template <int JT, int GW>
 __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X, const float* __restrict__ Qt,
                                                      int64_t n, int64_t S, int l, int64_t nbs, int64_t nblocks,
-                                                     float* __restrict__ part) {
+                                                     int nchunks, int* __restrict__ ctr, float* __restrict__ part) {
   constexpr int XROWS = 8 * GW * 16;
   constexpr int ZH = 16 * JT * 16;  // one half's Z_b (float4 slots)
   static_assert(XROWS <= PF_NMAX, "row groups");
   __shared__ floatx4 lds[XROWS * 16 + 2 * ZH];
+  __shared__ int chunk_s;
   floatx4* Xs = lds;               // [XROWS rows i][16 slots of c]
   floatx4* Zs = lds + XROWS * 16;  // [2 halves][16 JT rows j][16 slots of c]
   const float* Xsf = reinterpret_cast<const float*>(Xs);
@@ -986,7 +994,7 @@ __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X
   const int ct = w & 3, h = w >> 2;   // first product: column tile and row half
   const int th = (ng + 1) >> 1;
   const int t0 = h * th, t1 = min(ng, t0 + th);
-  const int64_t G = gridDim.x;
+  const int64_t NC = nchunks;
 
   // lane (g, f) loads rows 16 (w + 8 gg) + 4 g + q, columns s0 + 4 f .. + 3
   floatx4 xr[GW][4];
@@ -1017,111 +1025,132 @@ __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X
     }
   };
 
-  floatx4 yacc[GW][JT];
-#pragma unroll
-  for (int gg = 0; gg < GW; ++gg)
-#pragma unroll
-    for (int jt = 0; jt < JT; ++jt) yacc[gg][jt] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  int64_t b = blockIdx.x;
-  load_block(b);
-  for (; b < nblocks; b += G) {
-    // Q's first row groups of this wave's half, in flight while the block is
-    // staged (issued in buffer order, as in the loop below: the wait before
-    // a buffer's use counts the loads issued after it on every path). The
-    // empty asm keeps these loads in the loop: hoisted, their values would
-    // hold 12 JT registers through the second product.
-#pragma unroll
-    for (int jt = 0; jt < JT; ++jt) __asm__ volatile("" : "+v"(qcol[jt]));
-    floatx4 qa[JT], qb[JT], qc[JT];
-    load_q(min(t0, ng - 1), qa);
-    __builtin_amdgcn_sched_barrier(0);
-    load_q(min(t0 + 1, ng - 1), qb);
-    __builtin_amdgcn_sched_barrier(0);
-    load_q(min(t0 + 2, ng - 1), qc);
-    __builtin_amdgcn_sched_barrier(0);
-    // 1. stage the block (the previous block's second product is done with the LDS)
+  // A chunk number is fetched only when the previous chunk is done: fetched
+  // one chunk ahead, the first workgroups to start took second chunks before
+  // the last ones had started, and the launch took up to twice as long.
+  for (;;) {
+    // the next chunk (the previous chunk ended with a barrier after every
+    // wave's last read of chunk_s)
+    if (threadIdx.x == 0) chunk_s = atomicAdd(ctr, 1);
     lds_barrier();
+    const int chunk = __builtin_amdgcn_readfirstlane(chunk_s);
+    if (chunk < 0 || chunk >= nchunks) break;
+    floatx4 yacc[GW][JT];
 #pragma unroll
     for (int gg = 0; gg < GW; ++gg)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 16 * (w + 8 * gg) + 4 * g + q;
-        Xs[pf_swz(r, f)] = r < n ? xr[gg][q] : floatx4{0.f, 0.f, 0.f, 0.f};
-      }
-    lds_barrier();
-    // 2. Z_b columns 16 ct + r (tile row r = f for the A operand), all j,
-    //    over row groups t0 .. t1 - 1: k-slot g at step q of group t is row
-    //    16 t + 4 g + q. Three Q buffers, each refilled right after its last
-    //    use and consumed three groups later (a copy between buffers would
-    //    wait for its load).
-    floatx4 zacc[JT];
+      for (int jt = 0; jt < JT; ++jt) yacc[gg][jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    int64_t b = chunk;
+    load_block(b);
+    for (; b < nblocks; b += NC) {
+      // Q's first row groups of this wave's half, in flight while the block is
+      // staged (issued in buffer order, as in the loop below: the wait before
+      // a buffer's use counts the loads issued after it on every path). The
+      // empty asm keeps these loads in the loop: hoisted, their values would
+      // hold 12 JT registers through the second product.
 #pragma unroll
-    for (int jt = 0; jt < JT; ++jt) zacc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int aslot = 4 * ct + (f >> 2), ael = f & 3;
-    auto zstep = [&](int t, const floatx4* qv) {
-      float a[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 16 * t + 4 * g + q;
-        a[q] = Xsf[4 * (16 * r + (aslot ^ (r & 15))) + ael];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int jt = 0; jt < JT; ++jt) zacc[jt] = mfma_f32(a[q], qv[jt][q], zacc[jt]);
-    };
-    for (int t = t0; t < t1; t += 3) {
-      zstep(t, qa);
-      load_q(min(t + 3, ng - 1), qa);
-      if (t + 1 < t1) zstep(t + 1, qb);
-      load_q(min(t + 4, ng - 1), qb);
-      if (t + 2 < t1) zstep(t + 2, qc);
-      load_q(min(t + 5, ng - 1), qc);
-    }
-    // lane holds rows 4 g + e of tile jt: column c = 16 ct + 4 g + e, j = 16 jt + f
-#pragma unroll
-    for (int jt = 0; jt < JT; ++jt) Zs[h * ZH + pf_swz(16 * jt + f, 4 * ct + g)] = zacc[jt];
-    // 3. the next block's loads, in flight through the second product
-    load_block(b + G < nblocks ? b + G : b);
-    lds_barrier();
-    // 4. Y += X_b Z_b: tile (gg, jt) row r is row 16 G' + r, k-slot g at
-    //    step q is column 16 cc + 4 g + q (column chunks outermost: one
-    //    chunk of Z_b is held at a time)
-#pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      floatx4 zb[JT];
-#pragma unroll
-      for (int jt = 0; jt < JT; ++jt) {
-        const int o = pf_swz(16 * jt + f, 4 * cc + g);
-        zb[jt] = Zs[o] + Zs[ZH + o];
-      }
+      for (int jt = 0; jt < JT; ++jt) __asm__ volatile("" : "+v"(qcol[jt]));
+      floatx4 qa[JT], qb[JT], qc[JT];
+      load_q(min(t0, ng - 1), qa);
+      __builtin_amdgcn_sched_barrier(0);
+      load_q(min(t0 + 1, ng - 1), qb);
+      __builtin_amdgcn_sched_barrier(0);
+      load_q(min(t0 + 2, ng - 1), qc);
+      __builtin_amdgcn_sched_barrier(0);
+      // 1. stage the block (the previous block's second product is done with the LDS)
+      lds_barrier();
 #pragma unroll
       for (int gg = 0; gg < GW; ++gg)
-        if (gg < ngw) {
-          const floatx4 a = Xs[pf_swz(16 * (w + 8 * gg) + f, 4 * cc + g)];
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int jt = 0; jt < JT; ++jt) yacc[gg][jt] = mfma_f32(a[q], zb[jt][q], yacc[gg][jt]);
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * (w + 8 * gg) + 4 * g + q;
+          Xs[pf_swz(r, f)] = r < n ? xr[gg][q] : floatx4{0.f, 0.f, 0.f, 0.f};
         }
-    }
-  }
-  // lane holds rows 4 g + e of tile (gg, jt): i = 16 G' + 4 g + e, j = 16 jt + f
-  float* dst = part + (int64_t)blockIdx.x * n * l;
+      lds_barrier();
+      // 2. Z_b columns 16 ct + r (tile row r = f for the A operand), all j,
+      //    over row groups t0 .. t1 - 1: k-slot g at step q of group t is row
+      //    16 t + 4 g + q. Three Q buffers, each refilled right after its last
+      //    use and consumed three groups later (a copy between buffers would
+      //    wait for its load).
+      floatx4 zacc[JT];
 #pragma unroll
-  for (int gg = 0; gg < GW; ++gg)
-    if (gg < ngw) {
+      for (int jt = 0; jt < JT; ++jt) zacc[jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+      const int aslot = 4 * ct + (f >> 2), ael = f & 3;
+      auto zstep = [&](int t, const floatx4* qv) {
+        float a[4];
 #pragma unroll
-      for (int jt = 0; jt < JT; ++jt) {
-        const int j = 16 * jt + f;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t i = 16 * (w + 8 * gg) + 4 * g + e;
-          if (i < n && j < l) dst[i * l + j] = yacc[gg][jt][e];
+        for (int q = 0; q < 4; ++q) {
+          const int r = 16 * t + 4 * g + q;
+          a[q] = Xsf[4 * (16 * r + (aslot ^ (r & 15))) + ael];
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int jt = 0; jt < JT; ++jt) zacc[jt] = mfma_f32(a[q], qv[jt][q], zacc[jt]);
+      };
+      for (int t = t0; t < t1; t += 3) {
+        zstep(t, qa);
+        load_q(min(t + 3, ng - 1), qa);
+        if (t + 1 < t1) zstep(t + 1, qb);
+        load_q(min(t + 4, ng - 1), qb);
+        if (t + 2 < t1) zstep(t + 2, qc);
+        load_q(min(t + 5, ng - 1), qc);
+      }
+      // lane holds rows 4 g + e of tile jt: column c = 16 ct + 4 g + e, j = 16 jt + f
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) Zs[h * ZH + pf_swz(16 * jt + f, 4 * ct + g)] = zacc[jt];
+      // 3. the next block's loads, in flight through the second product
+      load_block(b + NC < nblocks ? b + NC : b);
+      lds_barrier();
+      // 4. Y += X_b Z_b: tile (gg, jt) row r is row 16 G' + r, k-slot g at
+      //    step q is column 16 cc + 4 g + q (column chunks outermost: one
+      //    chunk of Z_b is held at a time)
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        floatx4 zb[JT];
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          const int o = pf_swz(16 * jt + f, 4 * cc + g);
+          zb[jt] = Zs[o] + Zs[ZH + o];
+        }
+#pragma unroll
+        for (int gg = 0; gg < GW; ++gg)
+          if (gg < ngw) {
+            const floatx4 a = Xs[pf_swz(16 * (w + 8 * gg) + f, 4 * cc + g)];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int jt = 0; jt < JT; ++jt) yacc[gg][jt] = mfma_f32(a[q], zb[jt][q], yacc[gg][jt]);
+          }
       }
     }
+    // lane holds rows 4 g + e of tile (gg, jt): i = 16 G' + 4 g + e, j = 16 jt + f
+    float* dst = part + (int64_t)chunk * n * l;
+#pragma unroll
+    for (int gg = 0; gg < GW; ++gg)
+      if (gg < ngw) {
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) {
+          const int j = 16 * jt + f;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int64_t i = 16 * (w + 8 * gg) + 4 * g + e;
+            if (i < n && j < l) dst[i * l + j] = yacc[gg][jt][e];
+          }
+        }
+      }
+    lds_barrier();  // chunk_s is rewritten next
+  }
+  // every workgroup has taken its last chunk number before it counts itself
+  // done; the last one resets the counters for the next launch
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(ctr + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(ctr, 0);
+      atomicExch(ctr + 1, 0);
+    }
+  }
 }
 
 // Qt[j n + i] = Q[i l + j] (FP32).
@@ -1140,11 +1169,11 @@ hipError_t launch_transpose_f32(const float* Q, int64_t n, int l, float* Qt, hip
   return hipGetLastError();
 }
 
-// Workgroups of the fused power step: the fewest rounds over the blocks with
-// at most 252 workgroups (one per CU of the 256; four CUs stay free for the
-// small SVD that runs beside it), then as few workgroups as give that many
-// rounds. A function of the shape only, so the plan that sizes the partials
-// and the launch agree. 0 when the fused kernel does not apply.
+// Chunks (split partials) of the fused power step: the fewest rounds over the
+// blocks with at most 252 chunks (one workgroup per CU of the 256), then as
+// few chunks as give that many rounds. A function of the shape only, so the
+// plan that sizes the partials and the launch agree. 0 when the fused kernel
+// does not apply.
 int power_fused_splits(const View3& v, int l, tucker_precision prec) {
   if (prec != TUCKER_FP32 || v.S < 64 || v.S % 4 != 0 || v.n % 4 != 0 || v.n > PF_NMAX || l > 48 || l < 1)
     return 0;
@@ -1158,22 +1187,28 @@ size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec) {
   return (size_t)power_fused_splits(v, l, prec) * v.n * l * sizeof(float);
 }
 
+// Grid: the chunks plus four spare workgroups (at most one per CU), which
+// take the chunks of workgroups that start late.
 template <int JT, int GW>
-static void pf_launch(const View3& v, const float* X, const float* Qt, int l, float* part, int G, hipStream_t st) {
+static void pf_launch(const View3& v, const float* X, const float* Qt, int l, float* part, int NC, int* ctr,
+                      hipStream_t st) {
   const int64_t nbs = (v.S + 63) / 64;
-  TK_LAUNCH((k_power_fused<JT, GW>), dim3(G), dim3(512), 0, st, X, Qt, v.n, v.S, l, nbs, v.P * nbs, part);
+  const unsigned grid = (unsigned)std::min(256, NC + 4);
+  TK_LAUNCH((k_power_fused<JT, GW>), dim3(grid), dim3(512), 0, st, X, Qt, v.n, v.S, l, nbs, v.P * nbs, NC, ctr,
+            part);
 }
 
 template <int JT>
-static void pf_dispatch(const View3& v, const float* X, const float* Qt, int l, float* part, int G, hipStream_t st) {
+static void pf_dispatch(const View3& v, const float* X, const float* Qt, int l, float* part, int NC, int* ctr,
+                        hipStream_t st) {
   const int gw = (int)(((v.n + 15) / 16 + 7) / 8);  // row groups per wave
-  if (gw <= 1) pf_launch<JT, 1>(v, X, Qt, l, part, G, st);
-  else if (gw <= 2) pf_launch<JT, 2>(v, X, Qt, l, part, G, st);
-  else pf_launch<JT, 4>(v, X, Qt, l, part, G, st);
+  if (gw <= 1) pf_launch<JT, 1>(v, X, Qt, l, part, NC, ctr, st);
+  else if (gw <= 2) pf_launch<JT, 2>(v, X, Qt, l, part, NC, ctr, st);
+  else pf_launch<JT, 4>(v, X, Qt, l, part, NC, ctr, st);
 }
 
 hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
-                                 void* z, void* part, int nsplit, int* nsplit_used, hipStream_t st) {
+                                 void* z, void* part, int nsplit, int* ctr, int* nsplit_used, hipStream_t st) {
   const int G = power_fused_splits(v, l, prec);
   if (G == 0) {
     *nsplit_used = nsplit;
@@ -1185,9 +1220,9 @@ hipError_t launch_power_products(tucker_precision prec, const View3& v, const vo
   const double N = (double)v.P * v.n * v.S;
   TimingScope ts(KC_POWERSTEP, st, 4.0 * (N + (double)v.n * l), 4.0 * N * l, true);
   switch ((l + 15) / 16) {
-    case 1: pf_dispatch<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, st); break;
-    case 2: pf_dispatch<2>(v, (const float*)X, (const float*)qt, l, (float*)part, G, st); break;
-    default: pf_dispatch<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, st); break;
+    case 1: pf_dispatch<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, st); break;
+    case 2: pf_dispatch<2>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, st); break;
+    default: pf_dispatch<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, st); break;
   }
   return hipGetLastError();
 }
