@@ -408,6 +408,19 @@ def test_edge_shapes(T):
         _compare_solve(_dev(a, torch.float64), a, ranks, p, q, "adaptive", "st", "fp64", check_core=False)
 
 
+def test_fp32_t_hosvd_with_concurrent_fused_power_steps(T):
+    """FP32 T-HOSVD where modes 0 (S = 68 * 72) and 1 (P = 64, S = 72) both take
+    the one-pass power step, on their own streams at the same time (each with
+    its own chunk counters), two power steps each, against the FP64 oracle;
+    mode 2 (S = 1) runs the two-kernel products. Then the same solve again:
+    the counters that each launch leaves at zero serve the next call."""
+    a, _, _ = gen.random_tucker((64, 68, 72), (8, 9, 10), 1e-2, seed=43)
+    a32 = a.astype(np.float32)
+    x = _dev(a32, torch.float32)
+    for _ in range(2):
+        _compare_solve(x, a32.astype(np.float64), (8, 9, 10), 10, 2, "adaptive", "t", "fp32")
+
+
 @pytest.mark.parametrize("variant", ["t", "st"])
 def test_solve_largest_order_and_width(T, variant):
     """The limits: order 8 (TUCKER_MAX_ORDER), and a mode whose sketch width is
