@@ -406,6 +406,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   if (e == hipSuccess)
     e = launch_reduce_splits(step_prec(0), w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_mode_start(alpha, ows.pf_ctr, st);
+  int nfused = 0;  // fused power steps launched since the counter was zeroed
   if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, step_prec(0), w.qt, ows, cseed, 0, st);
   for (int t = 1; t <= q && e == hipSuccess; ++t) {
     const tucker_precision tp = step_prec(t);
@@ -421,7 +422,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     // Z = X_(k)^T Q3, Y' = X_(k) Z (one pass over X where the fused kernel applies)
     int ns_used = nsplit;
     if (e == hipSuccess)
-      e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &ns_used, st);
+      e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used, st);
     // Y = (Y' - alpha Q3) J, then its CholeskyQR. Step 1 needs nothing from
     // the sketch's SVD: alpha_0 = 0, and J_0 only turns the basis inside the
     // span, which leaves the iterate's left singular vectors and values as
@@ -467,6 +468,7 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
   if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
   if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_mode_start(alpha, ows.pf_ctr, st);
+  int nfused = 0;  // fused power steps launched since the counter was zeroed
   if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, prec, w.qt, ows, cseed, 0, st);
   if (e == hipSuccess) e = launch_orth_svd(l, prec, ows, w.sigma, nullptr, info, k, 0, st, &pve);
   int t = 0;
@@ -474,7 +476,7 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
     ++t;
     // Z = X_(k)^T Q3, Y' = X_(k) Z, Y = (Y' - alpha Q3) J (reading R1), CholeskyQR, small SVD + test
     int ns_used = nsplit;
-    e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &ns_used, st);
+    e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used, st);
     if (e == hipSuccess) e = launch_reduce_splits(tp, w.part, ns_used, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
     if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, tp, w.qt, ows, cseed, t, st);
     if (e == hipSuccess) e = launch_orth_svd(l, tp, ows, w.sigma, alpha_upd, info, k, t, st, &pve);
@@ -1120,8 +1122,10 @@ int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X,
     const OrthWs ows = carve_orth(w.orth, v.n, (int)l);
     e = launch_transpose_f32((const float*)Q, v.n, (int)l, (float*)w.omz, stream);
     if (e == hipSuccess) e = launch_mode_start(nullptr, ows.pf_ctr, stream);
+    int nfused = 0;
     if (e == hipSuccess)
-      e = launch_power_products(prec, v, X, w.omz, (int)l, nullptr, w.part, nsplit, ows.pf_ctr, &ns_used, stream);
+      e = launch_power_products(prec, v, X, w.omz, (int)l, nullptr, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used,
+                                stream);
   } else {
     e = launch_rowcontract(prec, v, X, Q, l, 1, (int)l, w.omz, true, stream);
     if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);

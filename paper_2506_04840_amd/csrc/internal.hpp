@@ -101,14 +101,16 @@ hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X
 // (part[split][i][j], FP32 or FP64 as the column reduction's), from Q given
 // j-major in the storage precision (qt[j * n + i]). FP32 steps with S >= 64,
 // n <= 512 and l <= 48 run one fused pass over X (power_fused_splits > 0
-// splits, part needs power_fused_part_bytes; ctr: two ints that are zero
-// before the first launch and that each launch leaves at zero); the others
-// run the row contraction into z (j-major, P S x l) and the column reduction
-// with nsplit splits. *nsplit_used: the split count to reduce.
+// splits, part needs power_fused_part_bytes; ctr: a chunk counter, zeroed
+// together with *fused_count = 0 before a series of launches on this (v, l);
+// each fused launch counts itself in *fused_count); the others run the row
+// contraction into z (j-major, P S x l) and the column reduction with nsplit
+// splits. *nsplit_used: the split count to reduce.
 int power_fused_splits(const View3& v, int l, tucker_precision prec);
 size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec);
 hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
-                                 void* z, void* part, int nsplit, int* ctr, int* nsplit_used, hipStream_t st);
+                                 void* z, void* part, int nsplit, int* ctr, int* fused_count, int* nsplit_used,
+                                 hipStream_t st);
 // Qt[j n + i] = Q[i l + j], FP32.
 hipError_t launch_transpose_f32(const float* Q, int64_t n, int l, float* Qt, hipStream_t st);
 
@@ -140,7 +142,7 @@ struct OrthWs {
   double* Wm;     // l x l left singular vectors of R (columns, descending)
   int* defic;     // 3 x 64
   int* status;    // [0] flags, [1] deficient count, [2] 1 when pass 3 was skipped
-  int* pf_ctr;    // 2 ints: chunk counters of the fused power step (not part of either set)
+  int* pf_ctr;    // chunk counter of the fused power step (not part of either set)
   // a second R / flags / status set, so that the factorisation of step t + 1
   // can run while the small SVD of step t still reads its own
   double* R_odd;
@@ -217,8 +219,8 @@ hipError_t launch_assemble(tucker_precision prec, const double* Q, int64_t n, in
 hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t count, double* dst,
                                  hipStream_t st);
 hipError_t launch_info_init(tucker_info* info, const int32_t* l, int d, int32_t flags, hipStream_t st);
-// *alpha = 0 (alpha may be null) and ctr[0] = ctr[1] = 0: a mode's start,
-// before its first fused power step.
+// *alpha = 0 (alpha may be null) and *ctr = 0: a mode's start, before its
+// first fused power step.
 hipError_t launch_mode_start(double* alpha, int* ctr, hipStream_t st);
 
 // ---- batched persistent launches (many small solves at once) --------------

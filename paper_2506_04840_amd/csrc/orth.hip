@@ -1134,8 +1134,7 @@ hipError_t launch_info_init(tucker_info* info, const int32_t* l, int d, int32_t 
 __global__ void k_mode_start(double* alpha, int* ctr) {
   if (threadIdx.x != 0) return;
   if (alpha != nullptr) *alpha = 0.0;
-  ctr[0] = 0;
-  ctr[1] = 0;
+  *ctr = 0;
 }
 
 hipError_t launch_mode_start(double* alpha, int* ctr, hipStream_t st) {

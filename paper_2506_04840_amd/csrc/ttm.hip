@@ -953,12 +953,14 @@ hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X
 //  * Y += X_b Z_b: wave w owns the 16-row groups w, w + 8, ... and keeps
 //    their Y tiles in matrix-core registers across the workgroup's blocks.
 // The blocks form NC chunks, chunk c holding blocks c, c + NC, ...; a
-// workgroup takes chunks from a counter (ctr[0]) and writes chunk c's Y as
-// split partial c, so the result does not depend on which workgroup took a
-// chunk. A workgroup that starts late (its CU held by a kernel of another
-// stream) finds the chunks taken and leaves, instead of delaying the whole
-// launch. The last workgroup to finish (ctr[1] counts them) sets both
-// counters back to zero for the next launch.
+// workgroup takes chunks from a counter (chunk = fetched value - base) and
+// writes chunk c's Y as split partial c, so the result does not depend on
+// which workgroup took a chunk. A workgroup that starts late (its CU held by
+// a kernel of another stream) finds the chunks taken and leaves, instead of
+// delaying the whole launch. Every workgroup stops at its first fetch past
+// the chunks, so a launch advances the counter by exactly NC + gridDim.x:
+// the caller passes the base (the launches since the counter was zeroed
+// times that).
 // The loads of the next block are issued after the first product (whose Q
 // loads would otherwise wait behind them) and are in flight through the
 // second; the barriers order LDS only. Loads take clamped addresses with
@@ -977,7 +979,8 @@ __device__ __forceinline__ int pf_swz(int row, int slot) { return row * 16 + (sl
 template <int JT, int GW>
 __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X, const float* __restrict__ Qt,
                                                      int64_t n, int64_t S, int l, int64_t nbs, int64_t nblocks,
-                                                     int nchunks, int* __restrict__ ctr, float* __restrict__ part) {
+                                                     int nchunks, int* __restrict__ ctr, int base,
+                                                     float* __restrict__ part) {
   constexpr int XROWS = 8 * GW * 16;
   constexpr int ZH = 16 * JT * 16;  // one half's Z_b (float4 slots)
   static_assert(XROWS <= PF_NMAX, "row groups");
@@ -1031,7 +1034,7 @@ __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X
   for (;;) {
     // the next chunk (the previous chunk ended with a barrier after every
     // wave's last read of chunk_s)
-    if (threadIdx.x == 0) chunk_s = atomicAdd(ctr, 1);
+    if (threadIdx.x == 0) chunk_s = atomicAdd(ctr, 1) - base;
     lds_barrier();
     const int chunk = __builtin_amdgcn_readfirstlane(chunk_s);
     if (chunk < 0 || chunk >= nchunks) break;
@@ -1142,15 +1145,6 @@ __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X
       }
     lds_barrier();  // chunk_s is rewritten next
   }
-  // every workgroup has taken its last chunk number before it counts itself
-  // done; the last one resets the counters for the next launch
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(ctr + 1, 1) == (int)gridDim.x - 1) {
-      atomicExch(ctr, 0);
-      atomicExch(ctr + 1, 0);
-    }
-  }
 }
 
 // Qt[j n + i] = Q[i l + j] (FP32).
@@ -1189,26 +1183,28 @@ size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec) {
 
 // Grid: the chunks plus four spare workgroups (at most one per CU), which
 // take the chunks of workgroups that start late.
+static int pf_grid(int NC) { return std::min(256, NC + 4); }
+
 template <int JT, int GW>
 static void pf_launch(const View3& v, const float* X, const float* Qt, int l, float* part, int NC, int* ctr,
-                      hipStream_t st) {
+                      int base, hipStream_t st) {
   const int64_t nbs = (v.S + 63) / 64;
-  const unsigned grid = (unsigned)std::min(256, NC + 4);
-  TK_LAUNCH((k_power_fused<JT, GW>), dim3(grid), dim3(512), 0, st, X, Qt, v.n, v.S, l, nbs, v.P * nbs, NC, ctr,
-            part);
+  TK_LAUNCH((k_power_fused<JT, GW>), dim3(pf_grid(NC)), dim3(512), 0, st, X, Qt, v.n, v.S, l, nbs, v.P * nbs, NC,
+            ctr, base, part);
 }
 
 template <int JT>
 static void pf_dispatch(const View3& v, const float* X, const float* Qt, int l, float* part, int NC, int* ctr,
-                        hipStream_t st) {
+                        int base, hipStream_t st) {
   const int gw = (int)(((v.n + 15) / 16 + 7) / 8);  // row groups per wave
-  if (gw <= 1) pf_launch<JT, 1>(v, X, Qt, l, part, NC, ctr, st);
-  else if (gw <= 2) pf_launch<JT, 2>(v, X, Qt, l, part, NC, ctr, st);
-  else pf_launch<JT, 4>(v, X, Qt, l, part, NC, ctr, st);
+  if (gw <= 1) pf_launch<JT, 1>(v, X, Qt, l, part, NC, ctr, base, st);
+  else if (gw <= 2) pf_launch<JT, 2>(v, X, Qt, l, part, NC, ctr, base, st);
+  else pf_launch<JT, 4>(v, X, Qt, l, part, NC, ctr, base, st);
 }
 
 hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
-                                 void* z, void* part, int nsplit, int* ctr, int* nsplit_used, hipStream_t st) {
+                                 void* z, void* part, int nsplit, int* ctr, int* fused_count, int* nsplit_used,
+                                 hipStream_t st) {
   const int G = power_fused_splits(v, l, prec);
   if (G == 0) {
     *nsplit_used = nsplit;
@@ -1219,10 +1215,11 @@ hipError_t launch_power_products(tucker_precision prec, const View3& v, const vo
   *nsplit_used = G;
   const double N = (double)v.P * v.n * v.S;
   TimingScope ts(KC_POWERSTEP, st, 4.0 * (N + (double)v.n * l), 4.0 * N * l, true);
+  const int base = (*fused_count)++ * (G + pf_grid(G));
   switch ((l + 15) / 16) {
-    case 1: pf_dispatch<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, st); break;
-    case 2: pf_dispatch<2>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, st); break;
-    default: pf_dispatch<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, st); break;
+    case 1: pf_dispatch<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, st); break;
+    case 2: pf_dispatch<2>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, st); break;
+    default: pf_dispatch<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, st); break;
   }
   return hipGetLastError();
 }
