@@ -79,6 +79,8 @@ typedef struct {
 #define TUCKER_INFO_DEFICIENT 2  /* an iterate was numerically rank deficient; the basis
                                     was completed with random orthonormal directions */
 #define TUCKER_INFO_L_CLAMPED 4  /* some l_k < r_k + p because n_k or m_k is smaller */
+#define TUCKER_INFO_INTERNAL 8   /* an internal consistency check failed (a one-pass power step
+                                    found its chunk counter out of step); the results are invalid */
 
 /* Device-resident report of one solve (caller allocates sizeof(tucker_info)
  * bytes of device memory). Written by the solve's kernels. */
@@ -91,6 +93,11 @@ typedef struct {
   double sigma_1[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1]; /* Sigma_k(1,1) after svd t (t=0: sketch) */
   double sigma_l[TUCKER_MAX_ORDER][TUCKER_MAX_Q + 1]; /* Sigma_k(l,l) after svd t */
   double normG2;                                /* ||G||_F^2 of the returned core (FP64 sum) */
+  double normA2;                                /* ||A||_F^2 of the input tensor (FP64 sum) */
+  double rel_error;                             /* sqrt(max(normA2 - normG2, 0) / normA2), 0 for a zero A */
+  int32_t deficient_steps[TUCKER_MAX_ORDER];    /* bit t: the factorisation of iterate t of mode k found
+                                                   numerically dependent columns (TUCKER_INFO_DEFICIENT) */
+  int32_t reserved[6];
 } tucker_info;
 
 /* Flags of tucker_shifted_power. */
@@ -166,11 +173,13 @@ typedef struct {
 /* Sketch Y = X_(mode) Omega_mode (Algorithms 2 and 3: the first product of
  * each mode). X has `shape` (FP64 for TUCKER_FP64, FP32 otherwise). Omega
  * is the m x l matrix of tucker_fill_gaussian(seed, mode, 0, m, l) with
- * m = numel(X) / n_mode. Y: n_mode x l, FP64, overwritten.
+ * m = numel(X) / n_mode. Y: n_mode x l row-major in the storage precision
+ * (FP64 for TUCKER_FP64, FP32 otherwise: the split sums are added in FP64
+ * in a fixed order, then rounded once), overwritten.
  * EINVAL: bad shape, mode, l < 1 or l > min(TUCKER_MAX_L, n_mode, m), null X/Y.
  * EWORKSPACE: ws_bytes < tucker_op_workspace_bytes(shape, mode, l, prec). */
 int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_t l, uint64_t seed,
-                  tucker_precision prec, double* Y, void* ws, size_t ws_bytes, hipStream_t stream);
+                  tucker_precision prec, void* Y, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /* One shifted power step (Algorithms 2 and 3, the inner loop):
  * M = X_(mode) (X_(mode)^T Q) - alpha Q with Q n_mode x l in the storage

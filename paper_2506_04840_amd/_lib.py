@@ -23,7 +23,7 @@ NORM2_WS_BYTES = 8192
 FP64, FP32, BF16 = 0, 1, 2
 SHIFT_ADAPTIVE, SHIFT_NONE = 0, 1
 POWER_RAW = 1
-INFO_NONFINITE, INFO_DEFICIENT, INFO_L_CLAMPED = 1, 2, 4
+INFO_NONFINITE, INFO_DEFICIENT, INFO_L_CLAMPED, INFO_INTERNAL = 1, 2, 4, 8
 
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 _SHIFT = {"adaptive": SHIFT_ADAPTIVE, "none": SHIFT_NONE}
@@ -47,6 +47,10 @@ class Info(ctypes.Structure):
         ("sigma_1", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
         ("sigma_l", (ctypes.c_double * (MAX_Q + 1)) * MAX_ORDER),
         ("normG2", ctypes.c_double),
+        ("normA2", ctypes.c_double),
+        ("rel_error", ctypes.c_double),
+        ("deficient_steps", ctypes.c_int32 * MAX_ORDER),
+        ("reserved", ctypes.c_int32 * 6),
     ]
 
 
@@ -222,6 +226,9 @@ def read_info(info: torch.Tensor) -> dict:
         "sigma_1": [[float(x) for x in row] for row in st.sigma_1],
         "sigma_l": [[float(x) for x in row] for row in st.sigma_l],
         "normG2": float(st.normG2),
+        "normA2": float(st.normA2),
+        "rel_error": float(st.rel_error),
+        "deficient_steps": [int(x) for x in st.deficient_steps],
     }
 
 
@@ -409,10 +416,10 @@ def fill_gaussian(seed: int, mode: int, rows: int, cols: int, precision: str = "
 
 
 def sketch(X: torch.Tensor, mode: int, l: int, seed: int = 1, precision: Optional[str] = None) -> torch.Tensor:
-    """Y = X_(mode) Omega_mode, FP64 n x l."""
+    """Y = X_(mode) Omega_mode, n x l in the storage dtype (FP64 or FP32)."""
     prec = precision_of(X, precision)
     s = _shape(X.shape)
-    Y = torch.empty((X.shape[mode], l), dtype=torch.float64, device=X.device)
+    Y = torch.empty((X.shape[mode], l), dtype=storage_dtype(prec), device=X.device)
     nbytes = op_workspace_bytes(X.shape, mode, l, prec)
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=X.device)
     _check(lib.tucker_sketch(ctypes.byref(s), mode, ctypes.c_void_p(_dev(X, "X")), l, ctypes.c_uint64(seed), prec,

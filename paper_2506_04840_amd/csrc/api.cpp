@@ -83,6 +83,7 @@ struct Plan {
   // holistic variants: the small tensor B (sizes l_k) and its deterministic HOSVD
   int64_t b_elems;      // numel(B)
   size_t orth2_bytes;   // largest orthonormalisation workspace of phase 2
+  int64_t napart_elems; // ||A||^2 partial sums of the first mode's sketch (or of the plain norm pass)
 };
 
 // Processing order of an options struct (nullptr: natural) into ord[0..d-1].
@@ -177,6 +178,13 @@ int make_plan(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_
     for (int j = 0; j < d; ++j) e *= chain[j];
     pl->xbuf_elems = std::max(pl->xbuf_elems, e);
   }
+  // ||A||^2 rides on the sketch of the first mode processed (every element of
+  // A is staged once there), or takes its own pass when that mode has S == 1
+  {
+    const int k0 = pl->ord[0];
+    const int64_t slots = colreduce_norm_slots(pl->v[k0], colreduce_splits(pl->v[k0], pl->l[k0]));
+    pl->napart_elems = std::max<int64_t>(std::max<int64_t>(slots, norm2_blocks(numel)), 1);
+  }
   pl->b_elems = 1;
   pl->orth2_bytes = 256;
   if (pl->holistic && d < 2) return fail(TUCKER_EUNSUPPORTED, "the holistic variants need order d >= 2");
@@ -231,6 +239,8 @@ struct SolveWs {
   void* orth;
   double* sig_hat;  // per-vector-error estimates of the previous step (Algorithm 4)
   int* stop;        // its stopping flag
+  double* napart;   // ||A||^2 partial sums
+  double* na2;      // where the mode that carries ||A||^2 writes it (nullptr in the other modes)
   ModeWs mode_store[TUCKER_MAX_ORDER];
   ModeWs* mode[TUCKER_MAX_ORDER];  // T-HOSVD: own scratch of modes 1..d-1 (else nullptr)
   // holistic variants
@@ -285,6 +295,8 @@ size_t solve_ws_layout(const Plan& pl, tucker_precision prec, char* base, SolveW
   w->orth = take(pl.orth_bytes);
   w->sig_hat = (double*)take(TUCKER_MAX_L * 8);
   w->stop = (int*)take(64);
+  w->napart = (double*)take((size_t)pl.napart_elems * 8);
+  w->na2 = nullptr;
   // T-HOSVD: the modes are independent and run concurrently; modes 1..d-1
   // get their own copy of the per-mode scratch (mode 0 uses the one above)
   for (int k = 0; k < TUCKER_MAX_ORDER; ++k) {
@@ -366,6 +378,15 @@ int side_ctx(SideCtx** out, int lane = 0) {
   return TUCKER_OK;
 }
 
+// ||A||^2 into *w.na2 for the mode that carries it, right after its sketch:
+// the fixed-order sum of the partials that sketch wrote (S > 1), or a pass of
+// its own over X (S == 1, whose column reduction stages no rows).
+hipError_t launch_norm_of_input(tucker_precision prec, const View3& v, const void* X, int nsplit, const SolveWs& w,
+                                hipStream_t st) {
+  if (v.S > 1) return launch_norm2_final(w.napart, colreduce_norm_slots(v, nsplit), w.na2, st);
+  return launch_norm2(prec, X, v.P * v.n * v.S, w.napart, w.na2, st);
+}
+
 // One mode of Algorithm 2 / 3 up to U_k (before truncation):
 //   Y = X_(k) Omega_k; [Q, Sigma] = svd(Y); alpha_0 = 0;
 //   q times: Y = X_(k) (X_(k)^T Q) - alpha Q; [Q, Sigma] = svd(Y); shift update.
@@ -402,7 +423,9 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   // sketch: Y = X_(k) Omega_k, then its CholeskyQR
   e = launch_fill_omega(om, prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l, true, w.omz,
                         st);
-  if (e == hipSuccess) e = launch_colreduce(step_prec(0), v, X, w.omz, l, w.part, nsplit, st);
+  if (e == hipSuccess)
+    e = launch_colreduce(step_prec(0), v, X, w.omz, l, w.part, nsplit, st, w.na2 != nullptr ? w.napart : nullptr);
+  if (e == hipSuccess && w.na2 != nullptr) e = launch_norm_of_input(prec, v, X, nsplit, w, st);
   if (e == hipSuccess)
     e = launch_reduce_splits(step_prec(0), w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_mode_start(alpha, ows.pf_ctr, st);
@@ -422,7 +445,8 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     // Z = X_(k)^T Q3, Y' = X_(k) Z (one pass over X where the fused kernel applies)
     int ns_used = nsplit;
     if (e == hipSuccess)
-      e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used, st);
+      e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used, st,
+                                info != nullptr ? &info->flags : nullptr);
     // Y = (Y' - alpha Q3) J, then its CholeskyQR. Step 1 needs nothing from
     // the sketch's SVD: alpha_0 = 0, and J_0 only turns the basis inside the
     // span, which leaves the iterate's left singular vectors and values as
@@ -465,7 +489,9 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
   const SvdPve pve{(int)pl.r[k], tol, tp == TUCKER_FP64 ? 0.0 : 1e-6, alpha, w.sig_hat, w.stop};
   hipError_t e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)k, 0, m, l,
                                       true, w.omz, st);
-  if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st);
+  if (e == hipSuccess)
+    e = launch_colreduce(prec, v, X, w.omz, l, w.part, nsplit, st, w.na2 != nullptr ? w.napart : nullptr);
+  if (e == hipSuccess && w.na2 != nullptr) e = launch_norm_of_input(prec, v, X, nsplit, w, st);
   if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_mode_start(alpha, ows.pf_ctr, st);
   int nfused = 0;  // fused power steps launched since the counter was zeroed
@@ -476,7 +502,8 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
     ++t;
     // Z = X_(k)^T Q3, Y' = X_(k) Z, Y = (Y' - alpha Q3) J (reading R1), CholeskyQR, small SVD + test
     int ns_used = nsplit;
-    e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used, st);
+    e = launch_power_products(tp, v, X, w.qt, l, w.omz, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used, st,
+                              info != nullptr ? &info->flags : nullptr);
     if (e == hipSuccess) e = launch_reduce_splits(tp, w.part, ns_used, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
     if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, ows.Wm, tp, w.qt, ows, cseed, t, st);
     if (e == hipSuccess) e = launch_orth_svd(l, tp, ows, w.sigma, alpha_upd, info, k, t, st, &pve);
@@ -537,6 +564,7 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
     int64_t gn = 1;
     for (int k = 0; k < pl.d; ++k) gn *= pl.r[k];
     e = launch_norm2(prec, G, gn, w.normpart, &info->normG2, st);
+    if (e == hipSuccess) e = launch_info_rel_error(info, st);
     if (e != hipSuccess) return dev_check(e, "norm launch");
   }
   return TUCKER_OK;
@@ -574,7 +602,8 @@ int solve_modes(const Plan& pl, const void* A, tucker_shift shift, int32_t q, ui
     const int k = pl.ord[i];
     const void* Xk = st_variant ? X : A;
     const hipStream_t sk = concurrent && k > 0 ? lanes[k]->ms : st;
-    const SolveWs wk = w.for_mode(k);
+    SolveWs wk = w.for_mode(k);
+    wk.na2 = (i == 0 && info != nullptr) ? &info->normA2 : nullptr;
     // the tensor mode k works on: A (T-HOSVD), or A with the modes processed
     // before k contracted (ST-HOSVD)
     int64_t curk[TUCKER_MAX_ORDER];
@@ -638,6 +667,7 @@ int solve_holistic(const Plan& pl, const void* A, tucker_shift shift, int32_t q,
     const OmegaSpec om = omega_spec(omega_kind, d, curk, k);
     SolveWs wk = w;
     wk.q64 = w.hq64[k];
+    wk.na2 = (i == 0 && info != nullptr) ? &info->normA2 : nullptr;
     rc = mode_factor(pl, k, pl.st ? X : A, q, shift, seed, prec, info, wk, st, om);
     if (rc) return rc;
     // Q_k with the sign rule (its basis fixes the coordinates the next mode's
@@ -1080,7 +1110,7 @@ int tucker_fill_gaussian(uint64_t seed, int32_t mode, int64_t row0, int64_t rows
 }
 
 int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_t l, uint64_t seed,
-                  tucker_precision prec, double* Y, void* ws, size_t ws_bytes, hipStream_t stream) {
+                  tucker_precision prec, void* Y, void* ws, size_t ws_bytes, hipStream_t stream) {
   View3 v;
   int64_t m;
   int rc = check_op(shape, mode, l, prec, &v, &m);
@@ -1094,7 +1124,10 @@ int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_
   hipError_t e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)mode, 0, m,
                                       (int)l, true, w.omz, stream);
   if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
-  if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, v.n * l, nullptr, prec, nullptr, Y, stream);
+  // the fixed-order sum is FP64; FP32 and BF16 calls store it in FP32
+  double* y64 = prec == TUCKER_FP64 ? (double*)Y : w.y64;
+  if (e == hipSuccess) e = launch_reduce_splits(prec, w.part, nsplit, v.n * l, nullptr, prec, nullptr, y64, stream);
+  if (e == hipSuccess && prec != TUCKER_FP64) e = launch_convert_from_f64(TUCKER_FP32, y64, v.n * l, Y, stream);
   return dev_check(e, "sketch launch");
 }
 

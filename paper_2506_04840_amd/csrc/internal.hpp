@@ -94,8 +94,12 @@ hipError_t launch_fill_omega(const OmegaSpec& sp, tucker_precision prec, uint64_
 // Output type: double for FP64, float otherwise.
 int colreduce_splits(const View3& v, int l);
 size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec);
+// npart (S > 1 only; ignored for S == 1): also ||X||_F^2 as colreduce_norm_slots
+// FP64 partial sums, one per workgroup, each over the elements that workgroup
+// staged; launch_norm2_final adds them in a fixed order.
 hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* B, int l,
-                            void* part, int nsplit, hipStream_t st);
+                            void* part, int nsplit, hipStream_t st, double* npart = nullptr);
+int colreduce_norm_slots(const View3& v, int nsplit);
 
 // Both products of a power step, Y' = X_(k) (X_(k)^T Q) as split partials
 // (part[split][i][j], FP32 or FP64 as the column reduction's), from Q given
@@ -105,12 +109,13 @@ hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X
 // together with *fused_count = 0 before a series of launches on this (v, l);
 // each fused launch counts itself in *fused_count); the others run the row
 // contraction into z (j-major, P S x l) and the column reduction with nsplit
-// splits. *nsplit_used: the split count to reduce.
+// splits. *nsplit_used: the split count to reduce. err (may be null): a fused
+// launch whose counter disagrees with the base ors TUCKER_INFO_INTERNAL into it.
 int power_fused_splits(const View3& v, int l, tucker_precision prec);
 size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec);
 hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
                                  void* z, void* part, int nsplit, int* ctr, int* fused_count, int* nsplit_used,
-                                 hipStream_t st);
+                                 hipStream_t st, int* err = nullptr);
 // Qt[j n + i] = Q[i l + j], FP32.
 hipError_t launch_transpose_f32(const float* Q, int64_t n, int l, float* Qt, hipStream_t st);
 
@@ -133,6 +138,10 @@ hipError_t launch_rowcontract(tucker_precision mk, const View3& v, const void* X
 int norm2_blocks(int64_t numel);
 hipError_t launch_norm2(tucker_precision prec, const void* X, int64_t numel, double* part, double* out,
                         hipStream_t st);
+// *out = sum of part[0 .. nb) in a fixed order.
+hipError_t launch_norm2_final(const double* part, int nb, double* out, hipStream_t st);
+// info->rel_error = sqrt(max(normA2 - normG2, 0) / normA2) (0 when normA2 is 0).
+hipError_t launch_info_rel_error(tucker_info* info, hipStream_t st);
 
 // ---- orthonormalisation (FP64) --------------------------------------------
 struct OrthWs {
@@ -218,6 +227,9 @@ hipError_t launch_assemble(tucker_precision prec, const double* Q, int64_t n, in
 // Small helpers.
 hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t count, double* dst,
                                  hipStream_t st);
+// dst (FP64, or FP32 for the other precisions) = src rounded to nearest.
+hipError_t launch_convert_from_f64(tucker_precision prec, const double* src, int64_t count, void* dst,
+                                   hipStream_t st);
 hipError_t launch_info_init(tucker_info* info, const int32_t* l, int d, int32_t flags, hipStream_t st);
 // *alpha = 0 (alpha may be null) and *ctr = 0: a mode's start, before its
 // first fused power step.

@@ -773,6 +773,7 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
       info->alpha[mode][step] = al;
       atomicOr(&info->flags, status[0]);  // modes of a T-HOSVD may run concurrently
       info->deficient[mode] = status[1];
+      if (status[0] & TUCKER_INFO_DEFICIENT) info->deficient_steps[mode] |= 1 << step;
       atomicMax(&info->jacobi_sweeps, sweeps);
     }
   }

@@ -170,7 +170,8 @@ template <int MK, int NJ, int EDGE>
 __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restrict__ X,
                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
                                                 int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
-                                                typename Pol<MK>::part_t* __restrict__ part, int split, int rb) {
+                                                typename Pol<MK>::part_t* __restrict__ part, int split, int rb,
+                                                double* __restrict__ nslot = nullptr) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   using LT = typename LdsPol<MK>::LT;
@@ -270,6 +271,31 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
     }
   };
 
+  // With nslot != nullptr the workgroup also sums the squares of the X
+  // elements it stages (FP64, in stage order; rows past n and stages past the
+  // split excluded), for ||X||_F^2 at no extra pass over X. Every element of
+  // X is staged by exactly one workgroup once.
+  double nacc = 0.0;
+  auto nsum = [&](const V4 (&xr)[XU], bool live) {
+    if (nslot == nullptr || !live) return;
+#pragma unroll
+    for (int q = 0; q < XU; ++q) {
+      const int L = q * 256 + tid, row = L / UPR;
+      if (r0 + row < n) {
+        if constexpr (sizeof(T) == 8) {
+          typedef double d2_t __attribute__((ext_vector_type(2)));
+          const d2_t d = __builtin_bit_cast(d2_t, xr[q]);
+          nacc = fma(d[0], d[0], nacc);
+          nacc = fma(d[1], d[1], nacc);
+        } else {
+          const float e[4] = {xr[q].x, xr[q].y, xr[q].z, xr[q].w};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) nacc = fma((double)e[c], (double)e[c], nacc);
+        }
+      }
+    }
+  };
+
   typename Po::acc_t acc[NJ];
 #pragma unroll
   for (int u = 0; u < NJ; ++u) acc[u] = typename Po::acc_t{0, 0, 0, 0};
@@ -300,6 +326,7 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
     gload(t0, xa, ba);
     gload(t0 + 1, xb, bb);
     lstore(0, xa, ba);
+    nsum(xa, true);
     lds_barrier();
     // pairs of stages with no exit inside the body (an exit would let the
     // compiler sink the stage t + 2 loads below it, after the t + 3 loads)
@@ -310,14 +337,26 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
       __builtin_amdgcn_sched_barrier(0);
       compute(0);
       lstore(1, xb, bb);
+      nsum(xb, true);
       lds_barrier();
       gload(t + 3, xb, bb);
       __builtin_amdgcn_sched_barrier(0);
       compute(1);
       lstore(0, xa, ba);
+      nsum(xa, t + 2 < t1);
       lds_barrier();
     }
     if (t < t1) compute(0);  // odd stage count: the last stage is in buffer 0
+  }
+  if (nslot != nullptr) {
+    // fixed order: a butterfly over the lanes (every lane ends with the same
+    // sum), then the four waves in index order
+    __shared__ double nred[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, 64);
+    if (lane == 0) nred[wave] = nacc;
+    __syncthreads();
+    if (tid == 0) *nslot = (nred[0] + nred[1]) + (nred[2] + nred[3]);
   }
 #pragma unroll
   for (int u = 0; u < NJ; ++u)
@@ -333,10 +372,12 @@ template <int MK, int NJ, int EDGE>
 __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __restrict__ X,
                                                 const typename Pol<MK>::T* __restrict__ Bt, int64_t n, int64_t S,
                                                 int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
-                                                int nrblocks, typename Pol<MK>::part_t* __restrict__ part) {
+                                                int nrblocks, typename Pol<MK>::part_t* __restrict__ part,
+                                                double* __restrict__ npart) {
   int split, rb;
   if (!xcd_decode((int)blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
-  cr_lds_body<MK, NJ, EDGE>(X, Bt, n, S, l, m, spp, nsteps, nsplit, part, split, rb);
+  cr_lds_body<MK, NJ, EDGE>(X, Bt, n, S, l, m, spp, nsteps, nsplit, part, split, rb,
+                            npart != nullptr ? npart + (int64_t)split * nrblocks + rb : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -474,7 +515,7 @@ size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec) {
 
 template <int MK, int NJ>
 static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l, void* part, int nsplit,
-                            hipStream_t st) {
+                            double* npart, hipStream_t st) {
   using Po = Pol<MK>;
   using T = typename Po::T;
   using PT = typename Po::part_t;
@@ -492,7 +533,7 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
     const int edge = v.S % LdsPol<MK>::KT == 0 ? 0 : (v.S % VE == 0 ? 1 : 2);
 #define TK_CR_LDS(E)                                                                                       \
   TK_LAUNCH((k_cr_lds<MK, NJ, E>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.n, v.S, l, \
-                     m, spp, nsteps, nsplit, nrb, (PT*)part)
+                     m, spp, nsteps, nsplit, nrb, (PT*)part, npart)
     if (edge == 0) TK_CR_LDS(0);
     else if (edge == 1) TK_CR_LDS(1);
     else TK_CR_LDS(2);
@@ -503,24 +544,29 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
 
 template <int MK>
 static hipError_t cr_dispatch(const View3& v, const void* X, const void* Bt, int l, void* part, int nsplit,
-                              hipStream_t st) {
+                              double* npart, hipStream_t st) {
   switch ((l + 15) / 16) {
-    case 1: return cr_launch<MK, 1>(v, X, Bt, l, part, nsplit, st);
-    case 2: return cr_launch<MK, 2>(v, X, Bt, l, part, nsplit, st);
-    case 3: return cr_launch<MK, 3>(v, X, Bt, l, part, nsplit, st);
-    case 4: return cr_launch<MK, 4>(v, X, Bt, l, part, nsplit, st);
+    case 1: return cr_launch<MK, 1>(v, X, Bt, l, part, nsplit, npart, st);
+    case 2: return cr_launch<MK, 2>(v, X, Bt, l, part, nsplit, npart, st);
+    case 3: return cr_launch<MK, 3>(v, X, Bt, l, part, nsplit, npart, st);
+    case 4: return cr_launch<MK, 4>(v, X, Bt, l, part, nsplit, npart, st);
     default: return hipErrorInvalidValue;
   }
 }
 
+int colreduce_norm_slots(const View3& v, int nsplit) {
+  return v.S > 1 ? nsplit * (int)((v.n + 63) / 64) : 0;
+}
+
 hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X, const void* Bt, int l,
-                            void* part, int nsplit, hipStream_t st) {
+                            void* part, int nsplit, hipStream_t st, double* npart) {
   const double N = (double)v.P * v.n * v.S, es = (double)elem_bytes(prec);
+  if (v.S == 1) npart = nullptr;
   TimingScope ts(KC_COLREDUCE, st, N * es + N / v.n * l * es, 2.0 * N * l, true);
   switch (prec) {
-    case TUCKER_FP64: return cr_dispatch<MF_F64>(v, X, Bt, l, part, nsplit, st);
-    case TUCKER_FP32: return cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, st);
-    case TUCKER_BF16: return cr_dispatch<MF_BF16>(v, X, Bt, l, part, nsplit, st);
+    case TUCKER_FP64: return cr_dispatch<MF_F64>(v, X, Bt, l, part, nsplit, npart, st);
+    case TUCKER_FP32: return cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, npart, st);
+    case TUCKER_BF16: return cr_dispatch<MF_BF16>(v, X, Bt, l, part, nsplit, npart, st);
   }
   return hipErrorInvalidValue;
 }
@@ -980,7 +1026,7 @@ template <int JT, int GW>
 __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X, const float* __restrict__ Qt,
                                                      int64_t n, int64_t S, int l, int64_t nbs, int64_t nblocks,
                                                      int nchunks, int* __restrict__ ctr, int base,
-                                                     float* __restrict__ part) {
+                                                     float* __restrict__ part, int* __restrict__ err) {
   constexpr int XROWS = 8 * GW * 16;
   constexpr int ZH = 16 * JT * 16;  // one half's Z_b (float4 slots)
   static_assert(XROWS <= PF_NMAX, "row groups");
@@ -1037,7 +1083,14 @@ __global__ __launch_bounds__(512) void k_power_fused(const float* __restrict__ X
     if (threadIdx.x == 0) chunk_s = atomicAdd(ctr, 1) - base;
     lds_barrier();
     const int chunk = __builtin_amdgcn_readfirstlane(chunk_s);
-    if (chunk < 0 || chunk >= nchunks) break;
+    if (chunk < 0 || chunk >= nchunks) {
+      // a launch fetches exactly nchunks + gridDim.x numbers from base on; a
+      // value outside that range means the counter and the host's base
+      // disagree (some chunks would keep stale partials): flag it
+      if ((chunk < 0 || chunk >= nchunks + (int)gridDim.x) && err != nullptr && threadIdx.x == 0)
+        atomicOr(err, TUCKER_INFO_INTERNAL);
+      break;
+    }
     floatx4 yacc[GW][JT];
 #pragma unroll
     for (int gg = 0; gg < GW; ++gg)
@@ -1187,24 +1240,24 @@ static int pf_grid(int NC) { return std::min(256, NC + 4); }
 
 template <int JT, int GW>
 static void pf_launch(const View3& v, const float* X, const float* Qt, int l, float* part, int NC, int* ctr,
-                      int base, hipStream_t st) {
+                      int base, int* err, hipStream_t st) {
   const int64_t nbs = (v.S + 63) / 64;
   TK_LAUNCH((k_power_fused<JT, GW>), dim3(pf_grid(NC)), dim3(512), 0, st, X, Qt, v.n, v.S, l, nbs, v.P * nbs, NC,
-            ctr, base, part);
+            ctr, base, part, err);
 }
 
 template <int JT>
 static void pf_dispatch(const View3& v, const float* X, const float* Qt, int l, float* part, int NC, int* ctr,
-                        int base, hipStream_t st) {
+                        int base, int* err, hipStream_t st) {
   const int gw = (int)(((v.n + 15) / 16 + 7) / 8);  // row groups per wave
-  if (gw <= 1) pf_launch<JT, 1>(v, X, Qt, l, part, NC, ctr, base, st);
-  else if (gw <= 2) pf_launch<JT, 2>(v, X, Qt, l, part, NC, ctr, base, st);
-  else pf_launch<JT, 4>(v, X, Qt, l, part, NC, ctr, base, st);
+  if (gw <= 1) pf_launch<JT, 1>(v, X, Qt, l, part, NC, ctr, base, err, st);
+  else if (gw <= 2) pf_launch<JT, 2>(v, X, Qt, l, part, NC, ctr, base, err, st);
+  else pf_launch<JT, 4>(v, X, Qt, l, part, NC, ctr, base, err, st);
 }
 
 hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
                                  void* z, void* part, int nsplit, int* ctr, int* fused_count, int* nsplit_used,
-                                 hipStream_t st) {
+                                 hipStream_t st, int* err) {
   const int G = power_fused_splits(v, l, prec);
   if (G == 0) {
     *nsplit_used = nsplit;
@@ -1217,9 +1270,9 @@ hipError_t launch_power_products(tucker_precision prec, const View3& v, const vo
   TimingScope ts(KC_POWERSTEP, st, 4.0 * (N + (double)v.n * l), 4.0 * N * l, true);
   const int base = (*fused_count)++ * (G + pf_grid(G));
   switch ((l + 15) / 16) {
-    case 1: pf_dispatch<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, st); break;
-    case 2: pf_dispatch<2>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, st); break;
-    default: pf_dispatch<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, st); break;
+    case 1: pf_dispatch<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, err, st); break;
+    case 2: pf_dispatch<2>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, err, st); break;
+    default: pf_dispatch<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, err, st); break;
   }
   return hipGetLastError();
 }
@@ -1386,6 +1439,24 @@ __global__ __launch_bounds__(256) void k_norm2_final(const double* part, int nb,
   if (threadIdx.x == 0) *out = red[0];
 }
 
+hipError_t launch_norm2_final(const double* part, int nb, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm2_final, dim3(1), dim3(256), 0, st, part, nb, out);
+  return hipGetLastError();
+}
+
+// The relative error of section 5 through the orthogonal-projection identity
+// ||A - Ahat||^2 = ||A||^2 - ||G||^2 (orthonormal factors, section 2.2).
+__global__ void k_info_rel_error(tucker_info* info) {
+  if (threadIdx.x != 0) return;
+  const double a = info->normA2, gsq = info->normG2;
+  info->rel_error = a > 0.0 ? sqrt(fmax(a - gsq, 0.0) / a) : 0.0;
+}
+
+hipError_t launch_info_rel_error(tucker_info* info, hipStream_t st) {
+  hipLaunchKernelGGL(k_info_rel_error, dim3(1), dim3(64), 0, st, info);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm2(tucker_precision prec, const void* X, int64_t numel, double* part, double* out,
                         hipStream_t st) {
   const int nb = norm2_blocks(numel);
@@ -1411,6 +1482,23 @@ hipError_t launch_convert_to_f64(tucker_precision prec, const void* src, int64_t
     hipLaunchKernelGGL((k_to_f64<double>), dim3(blocks), dim3(256), 0, st, (const double*)src, count, dst);
   else
     hipLaunchKernelGGL((k_to_f64<float>), dim3(blocks), dim3(256), 0, st, (const float*)src, count, dst);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_from_f64(const double* __restrict__ src, int64_t count, T* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < count) dst[e] = (T)src[e];
+}
+
+hipError_t launch_convert_from_f64(tucker_precision prec, const double* src, int64_t count, void* dst,
+                                   hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((count + 255) / 256);
+  if (prec == TUCKER_FP64)
+    hipLaunchKernelGGL((k_from_f64<double>), dim3(blocks), dim3(256), 0, st, src, count, (double*)dst);
+  else
+    hipLaunchKernelGGL((k_from_f64<float>), dim3(blocks), dim3(256), 0, st, src, count, (float*)dst);
   return hipGetLastError();
 }
 

@@ -29,9 +29,25 @@ def test_library_exports_every_declared_symbol():
         assert name in _lib.SIGNATURES, name
 
 
-def test_info_struct_layout():
+def test_info_struct_layout(tmp_path):
+    """The binding's tucker_info matches the C header's: size and the offset of
+    every field, as gcc lays the struct out."""
+    import subprocess
     from paper_2506_04840_amd import _lib
-    assert _lib.INFO_BYTES == 4 + 4 * 8 + 4 * 8 + 4 + 3 * 8 * 17 * 8 + 8
+    fields = [f[0] for f in _lib.Info._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "tucker.h"\nint main(void) {\n'
+                   '  printf("%zu\\n", sizeof(tucker_info));\n'
+                   + "".join('  printf("%%zu\\n", offsetof(tucker_info, %s));\n' % f for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(root, "include"), "-I/opt/rocm/include",
+                        str(src), "-o", str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got[0] == _lib.INFO_BYTES
+    assert got[1:] == [getattr(_lib.Info, f).offset for f in fields]
 
 
 def _ws(dims, ranks, p, q, prec, seq):

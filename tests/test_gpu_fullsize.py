@@ -52,6 +52,11 @@ def _orthonormal(n, r, seed, dtype):
     return torch.from_numpy(q).to(device="cuda", dtype=dtype)
 
 
+def _row_col_scale(xr, b):
+    """Cauchy-Schwarz scale of the entries of xr @ b: row norms times column norms."""
+    return np.sqrt(np.sum(xr ** 2, axis=1))[:, None] * np.sqrt(np.sum(b ** 2, axis=0))[None, :]
+
+
 def _sampled_products(T, A, l, rows, cols, prec, tol, om_full=None):
     """Mode-0 sketch and core of A (device, row-major) on sampled outputs."""
     n = A.shape[0]
@@ -92,9 +97,10 @@ def test_hilbert3_400_products_sampled(T):
     m = _np(T.shifted_power(A, 0, Q, al, raw=True, precision="fp32"))
     xk = A.reshape(400, -1).double().cpu().numpy()
     qa = _np(Q)
-    ref = xk[rows] @ (xk.T @ qa) - alpha * qa[rows]
-    scale = float(np.linalg.norm(xk)) ** 2
-    assert np.max(np.abs(m[rows] - ref)) <= 1e-5 * scale
+    z = xk.T @ qa
+    ref = xk[rows] @ z - alpha * qa[rows]
+    scale = _row_col_scale(xk[rows], z) + alpha * np.abs(qa[rows])
+    assert np.all(np.abs(m[rows] - ref) <= 1e-5 * scale), np.max(np.abs(m[rows] - ref) / scale)
 
 
 def test_hilbert3_400_solve_matches_oracle(T):
@@ -114,17 +120,9 @@ def test_hilbert3_400_solve_matches_oracle(T):
         assert np.max(np.abs(u.T @ u - np.eye(30))) < 1e-5
 
 
-def _noise_level_solve(T, name, ranks, p, q, prec, eta, re_tol):
-    A = gen.build_on_device(name, torch.device("cuda:0"))
-    _say("solve", name, prec)
-    s = T.Solver(A.shape, ranks, p, q, "adaptive", 1, prec, True, A.device)
-    G, U = s.run(A)
-    torch.cuda.synchronize()
-    for u in U:
-        ud = u.double()
-        assert float(torch.max(torch.abs(ud.T @ ud - torch.eye(ud.shape[1], device=ud.device, dtype=ud.dtype)))) < 1e-5
-    assert bool(torch.isfinite(G).all())
-    # relative error, formed explicitly on the device in FP64 slabs of mode 0
+def _explicit_rel_error(A, G, U):
+    """||A - G x_1 U_1 ... x_d U_d|| / ||A||, formed explicitly on the device in
+    FP64 slabs of mode 0 (measurement of a result, not part of the oracle)."""
     Gd, Ud = G.double(), [u.double() for u in U]
     core12 = Gd
     for k in range(1, len(Ud)):
@@ -136,7 +134,20 @@ def _noise_level_solve(T, name, ranks, p, q, prec, eta, re_tol):
         slab = A[i0:i1].double()
         num += float(torch.sum((slab - ahat) ** 2))
         den += float(torch.sum(slab ** 2))
-    re = (num / den) ** 0.5
+    return (num / den) ** 0.5
+
+
+def _noise_level_solve(T, name, ranks, p, q, prec, eta, re_tol):
+    A = gen.build_on_device(name, torch.device("cuda:0"))
+    _say("solve", name, prec)
+    s = T.Solver(A.shape, ranks, p, q, "adaptive", 1, prec, True, A.device)
+    G, U = s.run(A)
+    torch.cuda.synchronize()
+    for u in U:
+        ud = u.double()
+        assert float(torch.max(torch.abs(ud.T @ ud - torch.eye(ud.shape[1], device=ud.device, dtype=ud.dtype)))) < 1e-5
+    assert bool(torch.isfinite(G).all())
+    re = _explicit_rel_error(A, G, U)
     _say(name, "RE", re)
     assert abs(re - eta) <= re_tol * eta, re
 
@@ -167,6 +178,77 @@ def test_tucker4_120_products_sampled_bf16(T):
     ref = x_rows @ om
     scale = np.sqrt(np.sum(x_rows ** 2, axis=1))[:, None] * np.sqrt(np.sum(om ** 2, axis=0))[None, :]
     assert np.all(np.abs(y[np.ix_(rows, cols)] - ref) <= 2 * 2.0 ** -8 * scale)
+
+
+def test_tucker3_1000_power_step_sampled(T):
+    """1000^3 FP32, mode 0, l = 60: the raw shifted power step the solve runs
+    at n = 1000, on sampled rows, against the oracle's definition
+    X_(0)(X_(0)^T Q) - alpha Q with X_(0)^T Q formed in full (FP64, in column
+    slabs), per entry within 1e-5 of the row norm of X_(0) times the column
+    norm of X_(0)^T Q."""
+    A = gen.build_on_device("tucker3_1000", torch.device("cuda:0"))
+    n, l, alpha = 1000, 60, 3e-3
+    Q = _orthonormal(n, l, 9, torch.float32)
+    al = torch.tensor([alpha], dtype=torch.float64, device="cuda")
+    _say("power step 1000^3")
+    got = _np(T.shifted_power(A, 0, Q, al, raw=True, precision="fp32"))
+    qa = _np(Q)
+    rows = np.array([0, 1, 333, 500, 998, 999])
+    X = A.reshape(n, -1)
+    m = X.shape[1]
+    xr = X[torch.from_numpy(rows).to("cuda")].double().cpu().numpy()
+    acc = np.zeros((len(rows), l))
+    zn2 = np.zeros(l)
+    for c0 in range(0, m, 100000):
+        xs = X[:, c0:c0 + 100000].double().cpu().numpy()
+        z = xs.T @ qa
+        acc += xr[:, c0:c0 + 100000] @ z
+        zn2 += np.sum(z ** 2, axis=0)
+    ref = acc - alpha * qa[rows]
+    scale = np.sqrt(np.sum(xr ** 2, axis=1))[:, None] * np.sqrt(zn2)[None, :] + alpha * np.abs(qa[rows])
+    err = np.abs(got[rows] - ref)
+    assert np.all(err <= 1e-5 * scale), np.max(err / scale)
+
+
+def _recon_distance(g1, u1, g2, u2):
+    """||G1 x_k U1_k - G2 x_k U2_k||_F from the cores and factors (FP64): the
+    squared norms and the inner product are contractions in the core space,
+    <A1, A2> = <G1, G2 x_k (U1_k^T U2_k)>."""
+    def inner(ga, ua, gb, ub):
+        t = gb
+        for k in range(len(ua)):
+            t = np.moveaxis(np.tensordot(ua[k].T @ ub[k], t, axes=([1], [k])), 0, k)
+        return float(np.sum(ga * t))
+    d2 = inner(g1, u1, g1, u1) + inner(g2, u2, g2, u2) - 2.0 * inner(g1, u1, g2, u2)
+    return max(d2, 0.0) ** 0.5
+
+
+def test_tucker4_120_bf16_solve_matches_oracle(T):
+    """120^4 with BF16 operands (r = 20, p = 10, q = 2): the FP64 oracle's solve
+    of the same stored tensor and test matrices. The last step runs on FP32
+    operands, so the approximation matches the oracle's to the FP32
+    tolerance: reconstruction within 1e-5 of ||A||, relative error within 1e-6,
+    and the solve's own norms and identity-form error match the oracle's."""
+    A = gen.build_on_device("tucker4_120", torch.device("cuda:0"))
+    ranks = (20, 20, 20, 20)
+    _say("solve tucker4_120 bf16")
+    G, U, info = T.rsthosvd(A, ranks, p=10, q=2, seed=1, precision="bf16")
+    torch.cuda.synchronize()
+    a = A.double().cpu().numpy()
+    _say("oracle tucker4_120")
+    res = orc.randomized_hosvd(a, ranks, 10, 2, shift="adaptive", variant="st", seed=1)
+    g, us = _np(G), [_np(u) for u in U]
+    na2 = orc.frob2(a)
+    d = _recon_distance(g, us, res.core, res.factors) / na2 ** 0.5
+    _say("reconstruction distance", d)
+    assert d <= 1e-5, d
+    re_o = orc.rel_error(a, res)
+    del a
+    re_g = _explicit_rel_error(A, G, U)
+    _say("RE gpu", re_g, "oracle", re_o, "info", info["rel_error"])
+    assert abs(re_g - re_o) <= 1e-6, (re_g, re_o)
+    assert abs(info["normA2"] - na2) <= 1e-12 * na2
+    assert abs(info["rel_error"] ** 2 - (1.0 - orc.frob2(res.core) / na2)) <= 4e-5
 
 
 def test_tucker4_120_solve_reaches_the_noise_level(T):

@@ -73,6 +73,13 @@ def _row_col_scale(xk, b):
     return np.sqrt(np.sum(xk ** 2, axis=1))[:, None] * np.sqrt(np.sum(b ** 2, axis=0))[None, :]
 
 
+def _power_scale(xk, qa, alpha):
+    """Per-entry scale of M = X_(k)(X_(k)^T Q) - alpha Q: entry (i, j) sums
+    X_ic Z_cj over c with Z = X_(k)^T Q, so Cauchy-Schwarz bounds its rounding
+    by the row norm of X_(k) times the column norm of Z, plus the shift term."""
+    return _row_col_scale(xk, xk.T @ qa) + abs(alpha) * np.abs(qa)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("dims,mode,l", SHAPES)
 def test_sketch_matches_oracle(T, prec, dims, mode, l):
@@ -111,8 +118,8 @@ def test_power_step_raw_matches_oracle(T, prec, dims, mode, l):
     al = torch.tensor([alpha], dtype=torch.float64, device="cuda")
     m = _np(T.shifted_power(x, mode, q, al, raw=True, precision=prec))
     ref = orc.shifted_power(xa, mode, qa, alpha)
-    scale = np.linalg.norm(xa) ** 2
-    assert np.max(np.abs(m - ref)) <= TOL[prec] * scale
+    scale = _power_scale(unfold(xa, mode), qa, alpha)
+    assert np.all(np.abs(m - ref) <= TOL[prec] * scale), np.max(np.abs(m - ref) / scale)
 
 
 # Shapes that take the fused one-pass power step in FP32 (S >= 64, n and S
@@ -162,7 +169,7 @@ def test_fused_power_step_at_an_unaligned_address(T):
     m = _np(T.shifted_power(x, mode, q, al, raw=True, precision="fp32"))
     xa = _np(x)
     ref = orc.shifted_power(xa, mode, _np(q), 0.5)
-    assert np.max(np.abs(m - ref)) <= 1e-5 * np.linalg.norm(xa) ** 2
+    assert np.all(np.abs(m - ref) <= 1e-5 * _power_scale(unfold(xa, mode), _np(q), 0.5))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -214,7 +221,7 @@ def test_products_at_unaligned_addresses(T, prec, dims, mode, l):
     al = torch.tensor([0.25], dtype=torch.float64, device="cuda")
     m = _np(T.shifted_power(x, mode, q, al, raw=True, precision=prec))
     ref = orc.shifted_power(xa, mode, _np(q), 0.25)
-    assert np.max(np.abs(m - ref)) <= TOL[prec] * np.linalg.norm(xa) ** 2
+    assert np.all(np.abs(m - ref) <= TOL[prec] * _power_scale(xk, _np(q), 0.25))
     # core step with U and the output at odd addresses
     r = min(l, dims[mode])
     u = _dev_offset(np.linalg.qr(g.standard_normal((dims[mode], r)))[0], dt)
@@ -274,10 +281,33 @@ def test_orth_matches_lapack(T, n, l, kind):
 
 # --------------------------------------------------------------- whole solves
 
-def _align_signs(ug, uo):
-    d = np.sign(np.sum(ug * uo, axis=0))
-    d[d == 0] = 1.0
-    return d
+SIGN_TOL = {"fp64": 1e-8, "fp32": 1e-4}
+
+
+def _check_signed_factors(us, res, ranks, prec, gap_need):
+    """The factors as returned, column by column, against the oracle's: both
+    sides apply the sign rule of reading A5 (each column's largest-magnitude
+    entry positive, the lowest row on ties), and nothing is aligned here, so a
+    wrong sign on either side puts that column 2 away. Checked where the
+    column's singular value is separated from its neighbours (else any
+    rotation is correct) and where the rule's pick is not within rounding of
+    the runner-up entry (else either sign is). Returns (columns checked, every
+    column of every mode checked)."""
+    stol = SIGN_TOL["fp64" if prec == "fp64" else "fp32"]
+    checked, complete = 0, True
+    for k, lg in enumerate(res.logs):
+        s, r, uo = lg.sigmas[-1], ranks[k], res.factors[k]
+        for j in range(r):
+            lo = abs(s[j] - s[j + 1]) if j + 1 < len(s) else np.inf
+            hi = abs(s[j - 1] - s[j]) if j > 0 else np.inf
+            a = np.sort(np.abs(uo[:, j]))[::-1]
+            if min(lo, hi) < gap_need * s[0] or (len(a) > 1 and a[0] - a[1] <= 10 * stol):
+                complete = False
+                continue
+            err = np.max(np.abs(us[k][:, j] - uo[:, j]))
+            assert err <= stol, (k, j, err)
+            checked += 1
+    return checked, complete
 
 
 def _compare_solve(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, check_core=True, order=None):
@@ -311,20 +341,33 @@ def _compare_solve(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, check_
             uo = res.factors[k]
             sin = np.linalg.norm(us[k] - uo @ (uo.T @ us[k]), 2)
             assert sin <= 1e-4, (k, sin)
-    # (iv) core entrywise after sign alignment, when every mode is separated
-    if check_core:
-        gg = g.copy()
-        ok = True
-        for k, lg in enumerate(res.logs):
-            s = lg.sigmas[-1]
-            r = ranks[k]
-            sep = np.all(np.abs(np.diff(s[:r + 1 if r < len(s) else r])) >= gap_need * s[0])
-            ok = ok and sep
-            d = _align_signs(us[k], res.factors[k])
-            gg = np.moveaxis(np.moveaxis(gg, k, -1) * d, -1, k)
-        if ok:
-            assert np.max(np.abs(gg - res.core)) <= 10 * tol * np.linalg.norm(res.core)
+    # (iv) the factors column by column and the core entrywise with the signs
+    # both sides chose (the sign rule, nothing aligned), where they are unique
+    checked, complete = _check_signed_factors(us, res, ranks, prec, gap_need)
+    if check_core and complete:
+        assert np.max(np.abs(g - res.core)) <= 10 * tol * np.linalg.norm(res.core)
+    # the norms and the identity-based relative error the solve reports (section 5,
+    # and the orthogonal-projection identity of section 2.2)
+    _check_info_norms(info, a64 if prec == "fp64" else _np(a_dev), g, res, prec)
     return G, U, info, res
+
+
+def _check_info_norms(info, a_stored, g, res, prec):
+    """info.normA2 is ||A||^2 of the stored tensor (FP64 sums of exactly
+    representable squares: a few units of FP64 rounding); info.normG2 is the
+    returned core's ||G||^2 (summed here from the core as returned), and within the
+    solve's tolerance of the oracle core's; info.rel_error is the identity form
+    sqrt(1 - ||G||^2/||A||^2) of both reported norms, and matches the oracle's
+    identity-form error within the tolerance in RE^2."""
+    tol = TOL["fp64" if prec == "fp64" else "fp32"]
+    na2 = orc.frob2(a_stored)
+    assert abs(info["normA2"] - na2) <= 1e-12 * na2, (info["normA2"], na2)
+    assert abs(info["normG2"] - float(np.dot(g.ravel(), g.ravel()))) <= 1e-12 * na2
+    assert abs(info["normG2"] - orc.frob2(res.core)) <= 4 * tol * na2
+    re_id = np.sqrt(max(info["normA2"] - info["normG2"], 0.0) / info["normA2"]) if na2 > 0 else 0.0
+    assert abs(info["rel_error"] - re_id) <= 1e-15 + 1e-12 * re_id
+    re_o = orc.rel_error_identity(a_stored, res.core)
+    assert abs(info["rel_error"] ** 2 - re_o ** 2) <= 4 * tol, (info["rel_error"], re_o)
 
 
 def test_solve_tucker3_60_fp64_thosvd(T):
@@ -413,7 +456,8 @@ def test_fp32_t_hosvd_with_concurrent_fused_power_steps(T):
     the one-pass power step, on their own streams at the same time (each with
     its own chunk counters), two power steps each, against the FP64 oracle;
     mode 2 (S = 1) runs the two-kernel products. Then the same solve again:
-    the counters that each launch leaves at zero serve the next call."""
+    each mode zeroes its counter at its start, and every launch takes its base
+    (the fetches of the launches before it) from the host."""
     a, _, _ = gen.random_tucker((64, 68, 72), (8, 9, 10), 1e-2, seed=43)
     a32 = a.astype(np.float32)
     x = _dev(a32, torch.float32)
@@ -762,3 +806,120 @@ def test_ranks_above_the_true_rank_and_unit_modes(T):
     b, _, _ = gen.random_tucker((1, 30, 40), (1, 5, 5), 0.05, seed=44)
     for variant in ("st", "t"):
         _compare_solve(_dev(b, torch.float64), b, (1, 5, 5), 4, 1, "adaptive", variant, "fp64", check_core=False)
+
+
+# --------------------------------------------------------------- norms, relative error, sign rule
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("numel", [1, 7, 4096, 100003, 3 * 1024 * 1024 + 5])
+def test_norm2_matches_oracle(T, prec, numel):
+    """tucker_norm2: ||X||_F^2 with FP64 accumulation against the oracle's frob2
+    of the same stored values (a sum of exactly representable squares)."""
+    x = _dev(gen.rng(numel).standard_normal(numel), DT[prec])
+    got = float(T.norm2(x).item())
+    ref = orc.frob2(_np(x))
+    assert abs(got - ref) <= 1e-13 * ref, (got, ref)
+
+
+@pytest.mark.parametrize("case", ["st_first_mode_s1", "order1", "t_concurrent", "bf16", "holistic", "pve",
+                                  "fp64_odd_stage"])
+def test_info_norms_on_every_path(T, case):
+    """info.normA2 / normG2 / rel_error on the paths that carry ||A||^2 in the
+    first sketch (S > 1 and each edge form) and on those that take a pass of
+    their own (the first mode processed has S == 1): normA2 is the oracle's
+    frob2 of the stored tensor, rel_error the identity form of section 2.2,
+    matching the oracle's identity-form error in RE^2 within the tolerance."""
+    a, _, _ = gen.random_tucker((33, 45, 28), (5, 6, 4), 0.05, seed=51)
+    ranks, p, q = (5, 6, 4), 6, 2
+    kw = {}
+    prec, variant = "fp32", "st"
+    if case == "st_first_mode_s1":
+        kw["order"] = (2, 0, 1)
+    elif case == "order1":
+        a = gen.rng(52).standard_normal(300)
+        ranks, p, q = (1,), 3, 1
+    elif case == "t_concurrent":
+        variant = "t"
+    elif case == "bf16":
+        prec = "bf16"
+    elif case == "holistic":
+        kw["holistic"] = True
+    elif case == "fp64_odd_stage":
+        prec = "fp64"
+        a, _, _ = gen.random_tucker((21, 19, 23), (4, 4, 4), 0.05, seed=53)  # S = 437 and 23: odd edge stages
+        ranks = (4, 4, 4)
+    x = _dev(a, DT[prec])
+    xa = _np(x)
+    if case == "pve":
+        G, U, info, qs = T.rsthosvd_pve(x, ranks, p=p, q_max=6, tol=0.5, seed=1)
+        res = orc.randomized_sthosvd_pve(xa, ranks, p, 6, 0.5, seed=1)
+    else:
+        fn = T.rsthosvd if variant == "st" else T.rthosvd
+        G, U, info = fn(x, ranks, p=p, q=q, seed=1, precision=prec, **kw)
+        oo = kw.get("order")
+        if kw.get("holistic"):
+            res = orc.randomized_hosvd_holistic(xa, ranks, p, q, variant=variant, seed=1)
+        else:
+            res = orc.randomized_hosvd(xa, ranks, p, q, variant=variant, seed=1, order=oo)
+    torch.cuda.synchronize()
+    print("norms", case, info["normA2"], info["normG2"], info["rel_error"], flush=True)
+    _check_info_norms(info, xa, _np(G), res, "fp64" if prec == "fp64" else "fp32")
+    assert not info["flags"] & T.INFO_INTERNAL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", ["t", "st"])
+def test_sign_rule_factors_and_core(T, prec, variant):
+    """Every factor column and the core against the oracle with no sign
+    alignment at all, on a tensor whose unfoldings have well separated
+    singular values (superdiagonal core 4, 3.2, 2.5, ... times Haar factors,
+    plus noise): every column is unique up to its sign, and the sign rule
+    fixes the sign, so both sides must return the same vectors."""
+    g = gen.rng(61)
+    v = 4.0 * 0.8 ** np.arange(6)
+    dims, r = (40, 36, 32), 6
+    core = gen.superdiagonal(v, (r, r, r))
+    a, _, _ = gen.random_tucker(dims, (r, r, r), 1e-3, seed=62, core=core)
+    x = _dev(a, DT[prec])
+    G, U, info, res = _compare_solve(x, _np(x), (r, r, r), 6, 2, "adaptive", variant, prec)
+    checked, complete = _check_signed_factors([_np(u) for u in U], res, (r, r, r), prec,
+                                              1e-6 if prec == "fp64" else 1e-2)
+    assert complete and checked == 3 * r, (checked, complete)
+    assert np.max(np.abs(_np(G) - res.core)) <= 10 * TOL[prec] * np.linalg.norm(res.core)
+
+
+def test_nonfinite_input_is_flagged(T):
+    """A NaN in the tensor: every iterate's Gram is non-finite, the
+    orthonormalisation takes every column as dependent (bounded loops, no
+    hang), the solve completes with TUCKER_INFO_NONFINITE set, orthonormal
+    finite factors and a core that carries the NaN."""
+    a, _, _ = gen.random_tucker((30, 28, 26), (4, 4, 4), 0.05, seed=63)
+    a[3, 4, 5] = np.nan
+    for prec in ("fp64", "fp32"):
+        G, U, info = T.rsthosvd(_dev(a, DT[prec]), (4, 4, 4), p=4, q=2, precision=prec)
+        torch.cuda.synchronize()
+        assert info["flags"] & T.INFO_NONFINITE, info["flags"]
+        for u in U:
+            uu = _np(u)
+            assert np.all(np.isfinite(uu))
+            assert np.max(np.abs(uu.T @ uu - np.eye(uu.shape[1]))) < 1e-5
+        assert not bool(torch.isfinite(G).all())
+
+
+def test_fused_power_steps_without_rezeroing(T):
+    """Four FP32 power steps through the one-pass kernel in one mode: the
+    chunk counter is zeroed once at the mode's start and every later launch
+    takes its base from the host. Each step's iterate (its Sigma(1,1),
+    Sigma(l,l) and shift) matches the oracle's, on a tensor whose unfolding
+    spectra decay as 0.9^i (slowly enough that the steps' iterates differ),
+    and no launch flags its counter out of step."""
+    core = gen.superdiagonal(0.9 ** np.arange(40), (40, 40, 40))
+    a, _, _ = gen.random_tucker((96, 80, 72), (40, 40, 40), 1e-2, seed=64, core=core)
+    a32 = a.astype(np.float32)
+    x = _dev(a32, torch.float32)
+    G, U, info, res = _compare_solve(x, a32.astype(np.float64), (12, 12, 12), 8, 4, "adaptive", "st", "fp32",
+                                     check_core=False)
+    assert not info["flags"] & T.INFO_INTERNAL
+    lg = res.logs[0]
+    # the iterates of consecutive steps really differ (a stale partial would repeat one)
+    assert len({round(s[-1] / s[0], 6) for s in lg.sigmas[1:]}) == len(lg.sigmas) - 1
