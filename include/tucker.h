@@ -250,6 +250,28 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
                     tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                     tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/* tucker_rsthosvd for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, with its scratch taken from a static device array of
+ * TUCKER_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends, instead of a caller workspace. The caller still
+ * passes A, G, U and info. Arguments, layouts, results and errors as
+ * tucker_rsthosvd, plus EWORKSPACE when tucker_workspace_bytes(shape, ranks,
+ * p, q, prec, 1) exceeds TUCKER_NOALLOC_SCRATCH_BYTES (checked on the host
+ * before anything is enqueued). The call allocates nothing and creates no
+ * stream or event: every launch goes to `stream`, so the small SVDs do not
+ * overlap the products as they do in tucker_rsthosvd (same results).
+ * The first call on a device resolves that device's copy of the array
+ * (hipGetSymbolAddress, with the device current). Every call on one device
+ * shares its array and finds the previous call's contents there (the solve
+ * initialises what it reads): two calls on one device that may overlap in
+ * time, on different streams or from different threads, race and give
+ * undefined results. Order them on one stream. */
+#define TUCKER_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int tucker_rsthosvd_noalloc(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                            tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                            tucker_info* info, hipStream_t stream);
+
 /* tucker_rthosvd / tucker_rsthosvd with options (opt may be NULL: the plain
  * call). Mode k draws its test matrix of kind opt->omega as
  * tucker_fill_test_matrix(kind, seed, k, d, current sizes), the current sizes

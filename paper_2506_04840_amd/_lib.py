@@ -19,6 +19,7 @@ MAX_Q = 16
 MAX_Q_PVE = 1000
 MAX_L = 64
 NORM2_WS_BYTES = 8192
+NOALLOC_SCRATCH_BYTES = 128 << 20  # TUCKER_NOALLOC_SCRATCH_BYTES
 
 FP64, FP32, BF16 = 0, 1, 2
 SHIFT_ADAPTIVE, SHIFT_NONE = 0, 1
@@ -118,6 +119,8 @@ SIGNATURES = {
                                       _SZ, _P]),
     "tucker_rsthosvd": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P, _P,
                                        _SZ, _P]),
+    "tucker_rsthosvd_noalloc": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P,
+                                               _P, _P, _P]),
     "tucker_fill_test_matrix": (ctypes.c_int, [_I32, _U64, _I32, _I32, _P, _I64, _I64, _I64, ctypes.c_int, _P, _P]),
     "tucker_rthosvd_ex": (ctypes.c_int, [_SHAPE_P, _P, _P, _I32, _I32, ctypes.c_int, _U64, ctypes.c_int, _P, _P, _P,
                                          _P, _P, _SZ, _P]),
@@ -383,6 +386,25 @@ def rsthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precis
                omega, order, holistic)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
+
+
+def rsthosvd_noalloc(A: torch.Tensor, G: torch.Tensor, U: Sequence[torch.Tensor], info: torch.Tensor, ranks, p=10,
+                     q=1, shift="adaptive", seed=1, precision: Optional[str] = None) -> None:
+    """tucker_rsthosvd_noalloc: Algorithm 3 into caller-allocated G, U_k and
+    info, with the library's static device scratch (no workspace)."""
+    prec = precision_of(A, precision)
+    if not A.is_contiguous():
+        raise ValueError("A must be contiguous")
+    for t, name in [(A, "A"), (G, "G"), (info, "info")] + [(u, "U[%d]" % k) for k, u in enumerate(U)]:
+        _dev(t, name)
+    if len(U) != A.dim():
+        raise ValueError("one factor per mode")
+    uptr = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+    r = (ctypes.c_int64 * len(ranks))(*[int(x) for x in ranks])
+    s = _shape(A.shape)
+    _check(lib.tucker_rsthosvd_noalloc(ctypes.byref(s), ctypes.c_void_p(A.data_ptr()), r, int(p), int(q),
+                                       _SHIFT[shift], ctypes.c_uint64(seed), prec, ctypes.c_void_p(G.data_ptr()),
+                                       uptr, ctypes.c_void_p(info.data_ptr()), _stream(A.device)))
 
 
 def rthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,

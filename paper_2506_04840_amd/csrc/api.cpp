@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -72,6 +73,7 @@ struct Plan {
   View3 v[TUCKER_MAX_ORDER];  // view of the tensor each mode's products read
   bool st;
   bool holistic;        // Appendix A / B variants: modes keep width l_k, then a small HOSVD
+  bool one_stream = false;  // every launch on the caller's stream (no side stream for the small SVDs)
   int32_t flags;
   int64_t xbuf_elems;   // largest intermediate of the core chain
   int64_t omz_elems;    // largest m_k * l_k (Omega / Z)
@@ -378,6 +380,32 @@ int side_ctx(SideCtx** out, int lane = 0) {
   return TUCKER_OK;
 }
 
+// Scratch of tucker_rsthosvd_noalloc: one array per device, part of the
+// library's code object, so that entry point never allocates. In host code
+// `scratch` names a host-side stand-in, not the device array: the device
+// address comes from hipGetSymbolAddress, once per device with that device
+// current, and only that address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[TUCKER_NOALLOC_SCRATCH_BYTES];
+void* g_scratch_addr[16] = {};
+std::mutex g_scratch_mu;
+
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return dev_check(e, "hipGetDevice");
+  if (dev < 0 || dev >= 16) return fail(TUCKER_EDEVICE, "device ordinal %d outside 0..15", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return dev_check(e, "hipGetSymbolAddress(scratch)");
+    if (p == nullptr) return fail(TUCKER_EDEVICE, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return TUCKER_OK;
+}
+
 // ||A||^2 into *w.na2 for the mode that carries it, right after its sketch:
 // the fixed-order sum of the partials that sketch wrote (S > 1), or a pass of
 // its own over X (S == 1, whose column reduction stages no rows).
@@ -411,10 +439,14 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   double* alpha = w.alpha + k;
   double* alpha_upd = shift == TUCKER_SHIFT_ADAPTIVE ? alpha : nullptr;
   SideCtx* side = nullptr;
-  if (q > 0) {
+  if (q > 0 && !pl.one_stream) {
     const int rc = side_ctx(&side, lane);
     if (rc) return rc;
   }
+  // the small SVDs of steps 0..q-1 run on the side stream, or in line on the
+  // caller's stream when the plan asks for one stream (same kernels, same order
+  // of dependent work, so the same results)
+  const hipStream_t svd_s = side != nullptr ? side->s : st;
   // BF16 operands: the products of the last step (the sketch when q = 0) run
   // on FP32 operands, with FP32 orthonormalisation settings, so the final
   // subspace carries FP32 rather than BF16 rounding (storage is FP32 either way)
@@ -436,12 +468,14 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     // small SVD of step t - 1 beside the products of step t (each step's R,
     // flags and status in the set of its parity, so step t factors while the
     // SVD of step t - 1 still reads its own)
-    e = hipEventRecord(side->qr_done, st);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->qr_done, 0);
+    if (side != nullptr) {
+      e = hipEventRecord(side->qr_done, st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->qr_done, 0);
+    }
     if (e == hipSuccess)
       e = launch_orth_svd(l, step_prec(t - 1), orth_step_set(ows, t - 1), w.sigma, t == 1 ? nullptr : alpha_upd,
-                          info, k, t - 1, side->s);
-    if (e == hipSuccess) e = hipEventRecord(side->svd_done, side->s);
+                          info, k, t - 1, svd_s);
+    if (e == hipSuccess && side != nullptr) e = hipEventRecord(side->svd_done, side->s);
     // Z = X_(k)^T Q3, Y' = X_(k) Z (one pass over X where the fused kernel applies)
     int ns_used = nsplit;
     if (e == hipSuccess)
@@ -451,7 +485,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     // the sketch's SVD: alpha_0 = 0, and J_0 only turns the basis inside the
     // span, which leaves the iterate's left singular vectors and values as
     // they are; step 1 factors Y' itself and its own SVD absorbs J_0.
-    if (e == hipSuccess && t > 1) e = hipStreamWaitEvent(st, side->svd_done, 0);
+    if (e == hipSuccess && t > 1 && side != nullptr) e = hipStreamWaitEvent(st, side->svd_done, 0);
     if (e == hipSuccess)
       e = launch_reduce_splits(tp, w.part, ns_used, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
     if (e == hipSuccess)
@@ -459,7 +493,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   }
   // last small SVD on the caller's stream, after the side SVDs (they share Wm
   // and sigma); then Q = Q3 J (also as Q^T j-major when asked)
-  if (e == hipSuccess && q == 1) e = hipStreamWaitEvent(st, side->svd_done, 0);
+  if (e == hipSuccess && q == 1 && side != nullptr) e = hipStreamWaitEvent(st, side->svd_done, 0);
   if (e == hipSuccess)
     e = launch_orth_svd(l, step_prec(q), orth_step_set(ows, q), w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q,
                         st);
@@ -527,13 +561,14 @@ int solve_modes(const Plan& pl, const void* A, tucker_shift shift, int32_t q, ui
 int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
           tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
           void* ws, size_t ws_bytes, hipStream_t st, double pve_tol = -1.0, int32_t* q_used = nullptr,
-          const tucker_options* opt = nullptr) {
+          const tucker_options* opt = nullptr, bool one_stream = false) {
   Plan pl;
   // with the per-vector-error test q is the largest power count; the plan (and
   // the per-step logs) cover the first TUCKER_MAX_Q steps
   int rc = make_plan(shape, ranks, p, pve_tol >= 0.0 ? std::min<int32_t>(q, TUCKER_MAX_Q) : q, prec, st_variant, &pl,
                      opt);
   if (rc) return rc;
+  pl.one_stream = one_stream;
   if (shift != TUCKER_SHIFT_ADAPTIVE && shift != TUCKER_SHIFT_NONE) return fail(TUCKER_EINVAL, "bad shift mode");
   if (A == nullptr || G == nullptr || U == nullptr) return fail(TUCKER_EINVAL, "null tensor, core or factor array");
   for (int k = 0; k < pl.d; ++k)
@@ -586,7 +621,7 @@ int solve_modes(const Plan& pl, const void* A, tucker_shift shift, int32_t q, ui
   // and modes 1..d-1 on their own streams (each with its own scratch and SVD
   // side stream), forked from the caller's stream here and joined back before
   // the core chain.
-  const bool concurrent = !st_variant && pl.d > 1 && pve_tol < 0.0;
+  const bool concurrent = !st_variant && pl.d > 1 && pve_tol < 0.0 && !pl.one_stream;
   SideCtx* lanes[TUCKER_MAX_ORDER] = {};
   if (concurrent) {
     for (int k = 1; k < pl.d; ++k) {
@@ -1221,6 +1256,24 @@ int tucker_rsthosvd(const tucker_shape* shape, const void* A, const int64_t* ran
                     tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
                     tucker_info* info, void* ws, size_t ws_bytes, hipStream_t stream) {
   return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, ws_bytes, stream);
+}
+
+int tucker_rsthosvd_noalloc(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,
+                            tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U,
+                            tucker_info* info, hipStream_t stream) {
+  Plan pl;
+  int rc = make_plan(shape, ranks, p, q, prec, true, &pl);
+  if (rc) return rc;
+  SolveWs w;
+  const size_t need = solve_ws_layout(pl, prec, nullptr, &w);
+  if (need > TUCKER_NOALLOC_SCRATCH_BYTES)
+    return fail(TUCKER_EWORKSPACE, "this solve needs %zu bytes of scratch; the static scratch holds %zu", need,
+                (size_t)TUCKER_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  return solve(true, shape, A, ranks, p, q, shift, seed, prec, G, U, info, ws, TUCKER_NOALLOC_SCRATCH_BYTES, stream,
+               -1.0, nullptr, nullptr, /*one_stream=*/true);
 }
 
 // Field checks of an options struct (the order itself is checked against

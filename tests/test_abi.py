@@ -99,6 +99,29 @@ def test_error_codes_before_any_launch():
     assert rc == -1
 
 
+def test_noalloc_entry_point_rejects_on_the_host():
+    """tucker_rsthosvd_noalloc checks its arguments and the static scratch's
+    size before it touches a device (nothing here needs a GPU)."""
+    from paper_2506_04840_amd import _lib
+    hdr = open(HEADER).read()
+    m = re.search(r"#define TUCKER_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.NOALLOC_SCRATCH_BYTES
+    s = _lib._shape((1000, 1000, 1000))
+    r = (ctypes.c_int64 * 3)(50, 50, 50)
+    assert _lib.workspace_bytes((1000,) * 3, (50,) * 3, 10, 3, _lib.FP32, True) > _lib.NOALLOC_SCRATCH_BYTES
+    u = (ctypes.c_void_p * 3)(16, 16, 16)
+    rc = _lib.lib.tucker_rsthosvd_noalloc(ctypes.byref(s), ctypes.c_void_p(16), r, 10, 3, 0, 1, _lib.FP32,
+                                          ctypes.c_void_p(16), u, None, None)
+    assert rc == -2
+    assert "static scratch" in _lib.lib.tucker_status_string(rc).decode()
+    bad = (ctypes.c_int64 * 3)(50, 50, 1001)
+    rc = _lib.lib.tucker_rsthosvd_noalloc(ctypes.byref(s), ctypes.c_void_p(16), bad, 10, 3, 0, 1, _lib.FP32,
+                                          ctypes.c_void_p(16), u, None, None)
+    assert rc == -1
+    rc = _lib.lib.tucker_rsthosvd_noalloc(None, None, r, 10, 3, 0, 1, _lib.FP32, None, None, None, None)
+    assert rc == -1
+
+
 def test_pve_entry_point_validates_on_the_host():
     """Algorithm 4's entry point rejects a bad q_max, tol or q_used before any
     device work."""
