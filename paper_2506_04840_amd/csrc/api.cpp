@@ -354,6 +354,9 @@ struct SideCtx {
   hipEvent_t qr_done = nullptr, svd_done = nullptr;
   hipStream_t ms = nullptr;  // the mode's own stream (concurrent T-HOSVD modes 1..d-1)
   hipEvent_t fork = nullptr, join = nullptr;
+  // the sketch's small SVD when power steps follow (it only feeds the logs)
+  hipStream_t ls = nullptr;
+  hipEvent_t log_fork = nullptr, log_done = nullptr;
 };
 thread_local SideCtx g_side[16][TUCKER_MAX_ORDER];
 
@@ -373,6 +376,9 @@ int side_ctx(SideCtx** out, int lane = 0) {
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c.ms, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c.fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c.join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c.ls, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.log_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c.log_done, hipEventDisableTiming);
     if (e != hipSuccess) return dev_check(e, "side stream setup");
     c.dev = dev;
   }
@@ -462,20 +468,34 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     e = launch_reduce_splits(step_prec(0), w.part, nsplit, n * l, nullptr, prec, nullptr, w.y64, st);
   if (e == hipSuccess) e = launch_mode_start(alpha, ows.pf_ctr, st);
   int nfused = 0;  // fused power steps launched since the counter was zeroed
-  if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, step_prec(0), w.qt, ows, cseed, 0, st);
+  // With power steps to follow, the sketch's small SVD feeds only the logs
+  // (alpha_0 = 0, and step 1 factors the unrotated iterate): on a stream of
+  // its own, with its own R set and Wm, it runs beside the whole power
+  // iteration and is joined back at the end of the mode.
+  const bool log_sketch = q > 0 && side != nullptr;
+  const OrthWs ows0 = log_sketch ? orth_log_set(ows) : orth_step_set(ows, 0);
+  if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, step_prec(0), w.qt, ows0, cseed, 0, st);
+  if (e == hipSuccess && log_sketch) {
+    e = hipEventRecord(side->log_fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side->ls, side->log_fork, 0);
+    if (e == hipSuccess) e = launch_orth_svd(l, step_prec(0), ows0, nullptr, nullptr, info, k, 0, side->ls, nullptr,
+                                             nullptr, /*last=*/false);
+    if (e == hipSuccess) e = hipEventRecord(side->log_done, side->ls);
+  }
   for (int t = 1; t <= q && e == hipSuccess; ++t) {
     const tucker_precision tp = step_prec(t);
     // small SVD of step t - 1 beside the products of step t (each step's R,
     // flags and status in the set of its parity, so step t factors while the
     // SVD of step t - 1 still reads its own)
-    if (side != nullptr) {
+    const bool svd_prev = !(t == 1 && log_sketch);
+    if (svd_prev && side != nullptr) {
       e = hipEventRecord(side->qr_done, st);
       if (e == hipSuccess) e = hipStreamWaitEvent(side->s, side->qr_done, 0);
     }
-    if (e == hipSuccess)
-      e = launch_orth_svd(l, step_prec(t - 1), orth_step_set(ows, t - 1), w.sigma, t == 1 ? nullptr : alpha_upd,
-                          info, k, t - 1, svd_s);
-    if (e == hipSuccess && side != nullptr) e = hipEventRecord(side->svd_done, side->s);
+    if (e == hipSuccess && svd_prev)
+      e = launch_orth_svd(l, step_prec(t - 1), t == 1 ? ows0 : orth_step_set(ows, t - 1), w.sigma,
+                          t == 1 ? nullptr : alpha_upd, info, k, t - 1, svd_s);
+    if (e == hipSuccess && svd_prev && side != nullptr) e = hipEventRecord(side->svd_done, side->s);
     // Z = X_(k)^T Q3, Y' = X_(k) Z (one pass over X where the fused kernel applies)
     int ns_used = nsplit;
     if (e == hipSuccess)
@@ -493,11 +513,14 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   }
   // last small SVD on the caller's stream, after the side SVDs (they share Wm
   // and sigma); then Q = Q3 J (also as Q^T j-major when asked)
-  if (e == hipSuccess && q == 1 && side != nullptr) e = hipStreamWaitEvent(st, side->svd_done, 0);
+  if (e == hipSuccess && q == 1 && side != nullptr && !log_sketch) e = hipStreamWaitEvent(st, side->svd_done, 0);
   if (e == hipSuccess)
-    e = launch_orth_svd(l, step_prec(q), orth_step_set(ows, q), w.sigma, q == 0 ? nullptr : alpha_upd, info, k, q,
-                        st);
+    e = launch_orth_svd(l, step_prec(q), q == 0 ? ows0 : orth_step_set(ows, q), w.sigma, q == 0 ? nullptr : alpha_upd,
+                        info, k, q, st);
   if (e == hipSuccess) e = launch_orth_rotate(n, l, ows, prec, nullptr, qt_out, w.q64, st);
+  // the logging SVD of the sketch joins back before the mode ends (the next
+  // mode's sketch reuses its set)
+  if (e == hipSuccess && log_sketch) e = hipStreamWaitEvent(st, side->log_done, 0);
   return e == hipSuccess ? TUCKER_OK : dev_check(e, "mode launch");
 }
 

@@ -157,12 +157,21 @@ struct OrthWs {
   double* R_odd;
   int* defic_odd;
   int* status_odd;
+  // the sketch's set when power steps follow: its small SVD only feeds the
+  // info logs, so it reads and writes nothing the power steps use
+  double* R_log;
+  int* defic_log;
+  int* status_log;
+  double* Wm_log;
 };
 size_t orth_ws_bytes(int64_t n, int l);
 OrthWs carve_orth(void* base, int64_t n, int l);
 // The workspace of power step `step`: R, flags and status of its parity (odd
 // steps use the second set), the rest shared.
 OrthWs orth_step_set(const OrthWs& w, int step);
+// The sketch's own set (R, flags, status and Wm), for a sketch whose small SVD
+// only feeds the logs.
+OrthWs orth_log_set(const OrthWs& w);
 
 // CholeskyQR part of svd(Y): Y (FP64 n x l) = Q3 R with Q3 in ws.Qa and the R
 // factors in ws.R. With Wrot != nullptr, Y is first replaced in place by
@@ -194,9 +203,11 @@ struct SvdPve {
 };
 // vright (when not nullptr): the right singular vectors of R (l x l, columns,
 // descending), unit columns of the rotated R^T (zero where Sigma is zero).
+// last: this is the mode's last small SVD, whose deficient-column count goes
+// to info->deficient[mode] (the others only set their step's bit).
 hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
                            tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve = nullptr,
-                           double* vright = nullptr);
+                           double* vright = nullptr, bool last = true);
 // Q = Q3 Wm to q_out (n x l, `prec` storage), qt (j-major l x n, `prec`
 // storage) and q64 (n x l, FP64), each when not nullptr.
 hipError_t launch_orth_rotate(int64_t n, int l, const OrthWs& ws, tucker_precision prec, void* q_out, void* qt,

@@ -49,6 +49,12 @@ size_t orth_ws_bytes(int64_t n, int l) {
   b += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
   b += align_up(3 * kMaxL * sizeof(int));
   b += align_up(4 * sizeof(int));
+  // the set of the sketch's factorisation when power steps follow (its small
+  // SVD only feeds the logs and runs beside the power steps), with its own Wm
+  b += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
+  b += align_up(3 * kMaxL * sizeof(int));
+  b += align_up(4 * sizeof(int));
+  b += align_up((size_t)kMaxL * kMaxL * sizeof(double));
   return b;
 }
 
@@ -67,7 +73,20 @@ OrthWs carve_orth(void* base, int64_t n, int l) {
   w.R_odd = (double*)p; p += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
   w.defic_odd = (int*)p; p += align_up(3 * kMaxL * sizeof(int));
   w.status_odd = (int*)p; p += align_up(4 * sizeof(int));
+  w.R_log = (double*)p; p += align_up(3 * (size_t)kMaxL * kMaxL * sizeof(double));
+  w.defic_log = (int*)p; p += align_up(3 * kMaxL * sizeof(int));
+  w.status_log = (int*)p; p += align_up(4 * sizeof(int));
+  w.Wm_log = (double*)p; p += align_up((size_t)kMaxL * kMaxL * sizeof(double));
   return w;
+}
+
+OrthWs orth_log_set(const OrthWs& w) {
+  OrthWs o = w;
+  o.R = w.R_log;
+  o.defic = w.defic_log;
+  o.status = w.status_log;
+  o.Wm = w.Wm_log;
+  return o;
 }
 
 OrthWs orth_step_set(const OrthWs& w, int step) {
@@ -604,7 +623,8 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
                                                    int mode, int step, int pve_r, double pve_tol, double pve_floor,
                                                    const double* __restrict__ alpha_prev, double* __restrict__ sig_hat,
-                                                   int* __restrict__ stop, double* __restrict__ vright, int bid) {
+                                                   int* __restrict__ stop, double* __restrict__ vright, int bid,
+                                                   bool last = true) {
   __shared__ double A[kMaxL][OR_LS];  // A[a][x] = column a of R^T = row a of R
   __shared__ double J[kMaxL][OR_LS];  // J[a][x] = column a of the rotation
   __shared__ double sv[kMaxL];
@@ -772,8 +792,9 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
       info->sigma_l[mode][step] = sl;
       info->alpha[mode][step] = al;
       atomicOr(&info->flags, status[0]);  // modes of a T-HOSVD may run concurrently
-      info->deficient[mode] = status[1];
-      if (status[0] & TUCKER_INFO_DEFICIENT) info->deficient_steps[mode] |= 1 << step;
+      if (last) info->deficient[mode] = status[1];
+      // atomic: the sketch's SVD of a mode may run beside that mode's later ones
+      if (status[0] & TUCKER_INFO_DEFICIENT) atomicOr(&info->deficient_steps[mode], 1 << step);
       atomicMax(&info->jacobi_sweeps, sweeps);
     }
   }
@@ -786,9 +807,9 @@ __global__ __launch_bounds__(256) void k_small_svd(const double* __restrict__ Rg
                                                    double* __restrict__ alpha, tucker_info* __restrict__ info,
                                                    int mode, int step, int pve_r, double pve_tol, double pve_floor,
                                                    const double* __restrict__ alpha_prev, double* __restrict__ sig_hat,
-                                                   int* __restrict__ stop, double* __restrict__ vright) {
+                                                   int* __restrict__ stop, double* __restrict__ vright, int last) {
   small_svd_body<RPT>(Rg, l, status, tol, negl, Wm, sigma, alpha, info, mode, step, pve_r, pve_tol, pve_floor,
-                      alpha_prev, sig_hat, stop, vright, (int)blockIdx.x);
+                      alpha_prev, sig_hat, stop, vright, (int)blockIdx.x, last != 0);
 }
 
 // Q = Q3 Wm, written in the storage precision (and optionally in FP64).
@@ -866,15 +887,16 @@ hipError_t launch_orth_qr(int64_t n, int l, double* Y, const double* Wrot, tucke
 
 template <int RPT>
 static void svd_launch(int l, const OrthWs& ws, double tol, double negl, double* sigma, double* alpha,
-                       tucker_info* info, int mode, int step, const SvdPve& pv, double* vright, hipStream_t st) {
+                       tucker_info* info, int mode, int step, const SvdPve& pv, double* vright, bool last,
+                       hipStream_t st) {
   hipLaunchKernelGGL((k_small_svd<RPT>), dim3(1), dim3(256), 0, st, (const double*)ws.R, l, (const int*)ws.status,
                      tol, negl, ws.Wm, sigma, alpha, info, mode, step, pv.r, pv.tol, pv.floor, pv.alpha_prev,
-                     pv.sig_hat, pv.stop, vright);
+                     pv.sig_hat, pv.stop, vright, last ? 1 : 0);
 }
 
 hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, double* sigma, double* alpha,
                            tucker_info* info, int mode, int step, hipStream_t st, const SvdPve* pve,
-                           double* vright) {
+                           double* vright, bool last) {
   const SvdPve off{0, -1.0, 0.0, nullptr, nullptr, nullptr};
   const SvdPve& pv = pve != nullptr ? *pve : off;
   // Rotation thresholds by the precision the iterate was formed in: FP64
@@ -885,14 +907,14 @@ hipError_t launch_orth_svd(int l, tucker_precision prec, const OrthWs& ws, doubl
   const double tol = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-8 : 1e-7;
   const double negl = prec == TUCKER_FP64 ? u * l : prec == TUCKER_FP32 ? 1e-6 : 1e-4;
   switch ((l + 7) / 8) {
-    case 1: svd_launch<1>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
-    case 2: svd_launch<2>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
-    case 3: svd_launch<3>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
-    case 4: svd_launch<4>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
-    case 5: svd_launch<5>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
-    case 6: svd_launch<6>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
-    case 7: svd_launch<7>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
-    case 8: svd_launch<8>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, st); break;
+    case 1: svd_launch<1>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
+    case 2: svd_launch<2>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
+    case 3: svd_launch<3>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
+    case 4: svd_launch<4>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
+    case 5: svd_launch<5>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
+    case 6: svd_launch<6>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
+    case 7: svd_launch<7>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
+    case 8: svd_launch<8>(l, ws, tol, negl, sigma, alpha, info, mode, step, pv, vright, last, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

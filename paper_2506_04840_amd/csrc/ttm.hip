@@ -633,12 +633,13 @@ hipError_t launch_reduce_splits(tucker_precision part_prec, const void* part, in
 // (4 interleaved 16-row MFMA tiles), 4 waves per workgroup, all n rows per
 // wave, in batches of 4 * KB rows: k-slot g takes i = i0 + KB g + q, q < KB.
 // ---------------------------------------------------------------------------
-template <int MK, int NJ, bool WVEC>
+template <int MK, int NJ, bool WVEC, bool KSPLIT>
 __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
                                                  int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
-                                                 int64_t ntiles, int ksplit, typename Pol<MK>::T* __restrict__ out,
+                                                 int64_t ntiles, typename Pol<MK>::T* __restrict__ out,
                                                  int64_t osp, int64_t osj, int bid) {
+  constexpr bool ksplit = KSPLIT;
   using Po = Pol<MK>;
   using T = typename Po::T;
   constexpr int KL = Po::KL, MV = Po::MV, NH = 4 / MV;
@@ -732,8 +733,14 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
   int64_t ig = iw0;  // first row of the guarded remainder
   if (npair > 0) {
     const int64_t last = iw0 + (2 * npair - 2) * ROWS;
+    // the fence keeps the prologue's loads in the loop's order (batch 0, then
+    // batch 1): the wait-count pass merges the orders of both paths into the
+    // loop head, and interleaved prologue loads made every iteration wait for
+    // nearly all loads in flight, the batch just issued included
     ffetch(iw0, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     ffetch(iw0 + ROWS, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
     for (int64_t k = 0; k < npair; ++k) {
       const int64_t nx = min<int64_t>(iw0 + (2 * k + 2) * ROWS, last);
       // scheduling fences keep the pipeline order: a batch's loads are issued
@@ -759,7 +766,9 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
       fetch(i0 + 3 * ROWS, a1, b1);
     }
   }
-  if (ksplit) {
+  if constexpr (KSPLIT) {
+    // (only this instantiation reserves the LDS: without it the row
+    // contraction's occupancy is bounded by registers alone)
     using AE = typename Po::part_t;
     __shared__ AE red[3][16 * NJ][64];
     if (wave > 0) {
@@ -812,13 +821,13 @@ __device__ __forceinline__ void rc_rows_body(const typename Pol<MK>::T* __restri
   }
 }
 
-template <int MK, int NJ, bool WVEC>
+template <int MK, int NJ, bool WVEC, bool KSPLIT>
 __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __restrict__ X,
                                                  const typename Pol<MK>::T* __restrict__ W, int64_t n, int64_t S,
                                                  int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
-                                                 int64_t ntiles, int ksplit, typename Pol<MK>::T* __restrict__ out,
+                                                 int64_t ntiles, typename Pol<MK>::T* __restrict__ out,
                                                  int64_t osp, int64_t osj) {
-  rc_rows_body<MK, NJ, WVEC>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, ksplit, out, osp, osj, (int)blockIdx.x);
+  rc_rows_body<MK, NJ, WVEC, KSPLIT>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, out, osp, osj, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,11 +957,13 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     // resident waves (one partial round would leave most of the chip idle)
     const int ksplit = ntiles < 4096 ? 1 : 0;
     const unsigned blocks = (unsigned)(ksplit ? ntiles : (ntiles + 3) / 4);
-#define TK_RC_ROWS(WV)                                                                                            \
-  TK_LAUNCH((k_rc_rows<MK, NJ, WV>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
-                     lw, wsi, wsj, tpp, ntiles, ksplit, (T*)out, osp, osj)
-    if (wvec) TK_RC_ROWS(true);
-    else TK_RC_ROWS(false);
+#define TK_RC_ROWS(WV, KS)                                                                                        \
+  TK_LAUNCH((k_rc_rows<MK, NJ, WV, KS>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \
+                     lw, wsi, wsj, tpp, ntiles, (T*)out, osp, osj)
+    if (wvec && ksplit) TK_RC_ROWS(true, true);
+    else if (wvec) TK_RC_ROWS(true, false);
+    else if (ksplit) TK_RC_ROWS(false, true);
+    else TK_RC_ROWS(false, false);
 #undef TK_RC_ROWS
   }
   return hipGetLastError();
@@ -1553,8 +1564,9 @@ __device__ __forceinline__ void b_reduce(const BReduce& d, int bid) {
 }
 template <int NJ>
 __device__ __forceinline__ void b_rc_rows(const BRcRows& d, int bid) {
-  rc_rows_body<MF_F32, NJ, true>(d.X, d.W, d.n, d.S, d.lw, d.wsi, d.wsj, d.tpp, d.ntiles, d.ksplit, d.out,
-                                         d.osp, d.osj, bid);
+  // a batch always gives each wave a tile and all n rows (d.ksplit is 0)
+  rc_rows_body<MF_F32, NJ, true, false>(d.X, d.W, d.n, d.S, d.lw, d.wsi, d.wsj, d.tpp, d.ntiles, d.out, d.osp,
+                                        d.osj, bid);
 }
 template <int NJ>
 __device__ __forceinline__ void b_rc_cols(const BRcCols& d, int bid) {
