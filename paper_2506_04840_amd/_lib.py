@@ -308,11 +308,9 @@ class Solver:
         replay() then reruns the whole solve on whatever A holds, into the same
         G, U and info. One eager solve first creates the side streams.
 
-        Not for the concurrent T-HOSVD (its d - 1 mode streams fork from one
-        event): capturing it ended in a host segmentation fault inside the
-        capture, whose cause is not known, so it is refused."""
-        if not self.sequential and not self.opt.holistic and len(self.dims) > 1:
-            raise NotImplementedError("graph capture of the concurrent T-HOSVD modes is not supported")
+        A T-HOSVD captured this way runs its modes one after another (the
+        library does not fork its d - 1 mode streams under capture), with the
+        same results as the eager call, whose modes run concurrently."""
         self.run(A)
         torch.cuda.synchronize(self.device)
         g = torch.cuda.CUDAGraph()

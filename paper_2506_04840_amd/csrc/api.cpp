@@ -644,7 +644,16 @@ int solve_modes(const Plan& pl, const void* A, tucker_shift shift, int32_t q, ui
   // and modes 1..d-1 on their own streams (each with its own scratch and SVD
   // side stream), forked from the caller's stream here and joined back before
   // the core chain.
-  const bool concurrent = !st_variant && pl.d > 1 && pve_tol < 0.0 && !pl.one_stream;
+  // Under stream capture the modes run one after another on the caller's
+  // stream (each with its side streams, the pattern of the captured ST-HOSVD):
+  // the fork of the d - 1 mode streams from one event is not captured.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (!st_variant) {
+    const hipError_t ce = hipStreamIsCapturing(st, &cap);
+    if (ce != hipSuccess) return dev_check(ce, "hipStreamIsCapturing");
+  }
+  const bool concurrent =
+      !st_variant && pl.d > 1 && pve_tol < 0.0 && !pl.one_stream && cap == hipStreamCaptureStatusNone;
   SideCtx* lanes[TUCKER_MAX_ORDER] = {};
   if (concurrent) {
     for (int k = 1; k < pl.d; ++k) {

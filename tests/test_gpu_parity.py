@@ -729,13 +729,7 @@ def test_holistic_exact_rank_and_wide_small_unfolding(T, variant):
 
 # --------------------------------------------------------------- graph replay of whole solves
 
-_T_CAPTURE_SKIP = pytest.mark.skip(reason="capturing the concurrent T-HOSVD modes ended in a host segmentation "
-                                          "fault inside graph capture; Solver.capture refuses it until the cause is "
-                                          "shown")
-
-
-@pytest.mark.parametrize("variant,q,holistic", [("st", 2, False), pytest.param("t", 1, False, marks=_T_CAPTURE_SKIP),
-                                                ("st", 1, True), ("t", 1, True)])
+@pytest.mark.parametrize("variant,q,holistic", [("st", 2, False), ("t", 1, False), ("st", 1, True), ("t", 1, True)])
 def test_solve_graph_replay_equals_eager(T, variant, q, holistic):
     """A captured solve (side streams joined through events) replayed three
     times, with eager work and new tensor contents between replays, gives the
@@ -764,10 +758,31 @@ def test_solve_graph_replay_equals_eager(T, variant, q, holistic):
             assert torch.equal(u, v)
 
 
-def test_concurrent_t_hosvd_capture_is_refused(T):
-    s = T.Solver((20, 18, 16), (3, 3, 3), 4, 1, "adaptive", 1, "fp32", False, torch.device("cuda:0"))
-    with pytest.raises(NotImplementedError):
-        s.capture(torch.zeros((20, 18, 16), device="cuda:0"))
+def test_t_hosvd_capture_runs_modes_in_sequence(T):
+    """Under stream capture a T-HOSVD runs its modes one after another on the
+    capturing stream (the eager call runs them on concurrent streams): an
+    order-4 FP64 solve with q = 2, captured and replayed twice, equals the
+    eager concurrent solve bitwise, and the eager call after the capture still
+    does."""
+    a, _, _ = gen.random_tucker((18, 16, 14, 12), (3, 4, 3, 2), 0.02, seed=41)
+    dev = torch.device("cuda:0")
+    s = T.Solver(a.shape, (3, 4, 3, 2), 4, 2, "adaptive", 5, "fp64", False, dev)
+    A = torch.from_numpy(a).to(dev)
+    G, U = s.run(A)
+    torch.cuda.synchronize()
+    ref = (G.clone(), [u.clone() for u in U])
+    s.capture(A)
+    for rep in range(2):
+        G.zero_()
+        G, U = s.replay()
+        torch.cuda.synchronize()
+        print("replay", rep, flush=True)
+        assert torch.equal(G, ref[0])
+        for u, v in zip(U, ref[1]):
+            assert torch.equal(u, v)
+    G, U = s.run(A)
+    torch.cuda.synchronize()
+    assert torch.equal(G, ref[0])
 
 
 # --------------------------------------------------------------- degenerate inputs
