@@ -44,7 +44,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+# fp32-split: FP32 products formed as six BF16 matrix-core products of
+# three-piece BF16 splits, i.e. a sixth of the dense BF16 rate per FP32 flop
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp32-split": 2500.0 / 6}
 METRIC = "Tucker approximations/sec at fixed rel. error; TTM HBM GB/s; p99 latency"
 
 CONFIGS = {
@@ -77,6 +79,9 @@ def parse():
                     help="time K eager solves; by default one solve is captured into a HIP graph and K replays are "
                          "timed (each replay is a whole solve), where capture is supported (not for Algorithm 4, "
                          "which reads a flag on the host every step, nor the concurrent T-HOSVD)")
+    ap.add_argument("--fp32-products", default="split", choices=["split", "native"],
+                    help="how FP32 solves form their mode products: three-piece BF16 splits on the BF16 matrix cores "
+                         "(default) or FP32 matrix-core instructions only")
     ap.add_argument("--holistic", action="store_true",
                     help="the holistic variants of Appendices A / B (range finders at width l, then a small HOSVD)")
     ap.add_argument("--pve", type=float, default=None, metavar="TOL",
@@ -253,7 +258,7 @@ def main():
     else:
         solver = T.Solver(A.shape, cfg["ranks"], cfg["p"], q, args.shift, seed=w.sketch_seed, precision=prec,
                           sequential=(cfg["variant"] == "st"), device=dev, omega=args.omega, order=order,
-                          holistic=args.holistic)
+                          holistic=args.holistic, fp32_products=args.fp32_products)
     use_graph = not args.eager and args.pve is None and (cfg["variant"] == "st" or args.holistic)
     if use_graph:
         solver.capture(A)
@@ -299,6 +304,8 @@ def main():
         kern = args.kernel if args.kernel != "auto" else max(timed, key=lambda k: timed[k]["ms"])
         tk = timed[kern]
         mk = "fp32" if (prec == "bf16" and kern == "rowcontract") else prec
+        if mk == "fp32" and args.fp32_products == "split" and kern in ("colreduce", "rowcontract"):
+            mk = "fp32-split"  # the large products of this class run as six BF16 products per pair
         roof = _roof_from_timing(tk, mk)
         same = prec == CONFIGS[args.workload]["precision"] and cfg["ranks"] == CONFIGS[args.workload]["ranks"]
         traffic = measured_traffic(kern, args.workload) \
@@ -334,7 +341,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16-operands/f32-acc"}[prec],
+        "dtype": {"fp64": "f64", "fp32": "f32" if args.fp32_products == "native" else
+                  "f32 (large products as bf16x3-split pairs, f32 accumulation)",
+                  "bf16": "bf16-operands/f32-acc"}[prec],
         "data": "synthetic",
         "config": {"workload": args.workload, "dims": list(A.shape), "ranks": list(cfg["ranks"]), "p": cfg["p"],
                    "q": q, "shift": args.shift, "variant": cfg["variant"], "precision": prec,
@@ -342,6 +351,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if prec == "fp32":
+        line["config"]["fp32_products"] = args.fp32_products
     if args.omega != "gaussian":
         line["config"]["omega"] = args.omega
     if order is not None:

@@ -29,8 +29,15 @@
  *  - Calls are reentrant given distinct workspaces. Two calls that share a
  *    workspace must be ordered on one stream.
  *  - Precision: TUCKER_FP64 keeps tensors, factors and products in FP64.
- *    TUCKER_FP32 stores tensors and factors in FP32 and runs the mode
- *    products in FP32 on the matrix cores. TUCKER_BF16 stores tensors and
+ *    TUCKER_FP32 stores tensors and factors in FP32 and forms the mode
+ *    products to FP32 accuracy on the matrix cores: by default the large
+ *    products split each FP32 operand into three BF16 pieces and sum six
+ *    BF16 products per pair in FP32 accumulators (the pieces carry 24
+ *    significant bits; the terms left out are below 3 * 2^-24 of each
+ *    product), which gfx950 runs at its BF16 rate; the FP32 instructions
+ *    throughout with tucker_options.fp32_products = TUCKER_FP32_NATIVE
+ *    (the other products, and sizes the split kernels do not cover, always
+ *    use them). TUCKER_BF16 stores tensors and
  *    factors in FP32, runs the sketch and power products with BF16 operands
  *    and FP32 accumulation, and runs the core contraction in FP32. In every
  *    precision the Gram matrices, Cholesky factors, small SVD and shift are
@@ -161,13 +168,20 @@ typedef enum {
   TUCKER_ORDER_DECREASING = 2  /* by decreasing n_k; equal sizes in increasing mode */
 } tucker_order;
 
+/* How TUCKER_FP32 forms its mode products (the default first). */
+typedef enum {
+  TUCKER_FP32_SPLIT = 0,  /* three-piece BF16 split, six BF16 products, FP32 accumulation */
+  TUCKER_FP32_NATIVE = 1  /* FP32 matrix-core instructions only */
+} tucker_fp32_products;
+
 /* Options of the _ex solves. A zeroed struct gives the plain solves. */
 typedef struct {
   int32_t omega;                    /* tucker_omega */
   int32_t order_kind;               /* tucker_order */
   int32_t order[TUCKER_MAX_ORDER];  /* TUCKER_ORDER_GIVEN: processing order, first d entries */
   int32_t holistic;                 /* 0: Algorithms 2 / 3; 1: the holistic variants (below) */
-  int32_t reserved[5];              /* zero */
+  int32_t fp32_products;            /* tucker_fp32_products (TUCKER_FP32 only) */
+  int32_t reserved[4];              /* zero */
 } tucker_options;
 
 /* Sketch Y = X_(mode) Omega_mode (Algorithms 2 and 3: the first product of
@@ -299,9 +313,12 @@ int tucker_rsthosvd_noalloc(const tucker_shape* shape, const void* A, const int6
  * in phase 2 (no unfolding of the small tensor has that rank); EUNSUPPORTED
  * for order d = 1.
  *
+ * opt->fp32_products chooses how TUCKER_FP32 forms its products (see the
+ * precision conventions at the top); other precisions ignore it.
+ *
  * EINVAL for an unknown kind, an order that is not a permutation of 0..d-1,
- * holistic outside 0..1 or nonzero reserved fields; otherwise as the plain
- * calls. */
+ * holistic or fp32_products outside 0..1 or nonzero reserved fields;
+ * otherwise as the plain calls. */
 size_t tucker_workspace_bytes_ex(const tucker_shape* shape, const int64_t* ranks, int32_t p, int32_t q,
                                  tucker_precision prec, int32_t sequential, const tucker_options* opt);
 int tucker_rthosvd_ex(const tucker_shape* shape, const void* A, const int64_t* ranks, int32_t p, int32_t q,

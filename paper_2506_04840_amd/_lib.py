@@ -60,20 +60,27 @@ INFO_BYTES = ctypes.sizeof(Info)
 
 class Options(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_int32), ("order_kind", ctypes.c_int32), ("order", ctypes.c_int32 * 8),
-                ("holistic", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("holistic", ctypes.c_int32), ("fp32_products", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 OMEGA = {"gaussian": 0, "uniform": 1, "kr_gaussian": 2, "kr_uniform": 3}
 ORDER_NATURAL, ORDER_GIVEN, ORDER_DECREASING = 0, 1, 2
 
 
-def make_options(omega: str = "gaussian", order=None, holistic: bool = False) -> Options:
+FP32_PRODUCTS = {"split": 0, "native": 1}
+
+
+def make_options(omega: str = "gaussian", order=None, holistic: bool = False,
+                 fp32_products: str = "split") -> Options:
     """Options struct: test-matrix kind, processing order (None: 0..d-1,
-    "decreasing": by decreasing mode size, or a permutation of the modes) and
-    the holistic variants of Appendices A / B."""
+    "decreasing": by decreasing mode size, or a permutation of the modes), the
+    holistic variants of Appendices A / B, and how FP32 solves form their
+    products ("split": three-piece BF16 splits on the BF16 matrix cores, the
+    default; "native": FP32 matrix-core instructions only)."""
     opt = Options()
     opt.omega = OMEGA[omega]
     opt.holistic = 1 if holistic else 0
+    opt.fp32_products = FP32_PRODUCTS[fp32_products]
     if order is None or order == "natural":
         opt.order_kind = ORDER_NATURAL
     elif order == "decreasing":
@@ -243,9 +250,10 @@ class Solver:
     """
 
     def __init__(self, dims, ranks, p=10, q=1, shift="adaptive", seed=1, precision="fp32", sequential=True,
-                 device="cuda", omega="gaussian", order=None, holistic=False):
-        self.opt = make_options(omega, order, holistic)
-        self.plain = self.opt.omega == 0 and self.opt.order_kind == ORDER_NATURAL and not holistic
+                 device="cuda", omega="gaussian", order=None, holistic=False, fp32_products="split"):
+        self.opt = make_options(omega, order, holistic, fp32_products)
+        self.plain = (self.opt.omega == 0 and self.opt.order_kind == ORDER_NATURAL and not holistic
+                      and self.opt.fp32_products == 0)
         self.dims = tuple(int(x) for x in dims)
         self.ranks = tuple(int(x) for x in ranks)
         self.p, self.q, self.seed = int(p), int(q), int(seed)
@@ -377,11 +385,12 @@ def rthosvd_pve(A: torch.Tensor, ranks, p=10, q_max=20, tol=0.5, shift="adaptive
 
 
 def rsthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
-             omega: str = "gaussian", order=None, holistic: bool = False):
+             omega: str = "gaussian", order=None, holistic: bool = False,
+             fp32_products: str = "split"):
     """Shifted randomized ST-HOSVD (Algorithm 3). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
     s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], True, A.device,
-               omega, order, holistic)
+               omega, order, holistic, fp32_products)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
 
@@ -406,11 +415,12 @@ def rsthosvd_noalloc(A: torch.Tensor, G: torch.Tensor, U: Sequence[torch.Tensor]
 
 
 def rthosvd(A: torch.Tensor, ranks, p=10, q=1, shift="adaptive", seed=1, precision: Optional[str] = None,
-            omega: str = "gaussian", order=None, holistic: bool = False):
+            omega: str = "gaussian", order=None, holistic: bool = False,
+            fp32_products: str = "split"):
     """Shifted randomized T-HOSVD (Algorithm 2). Returns (G, [U_k], info dict)."""
     prec = precision_of(A, precision)
     s = Solver(A.shape, ranks, p, q, shift, seed, {FP64: "fp64", FP32: "fp32", BF16: "bf16"}[prec], False, A.device,
-               omega, order, holistic)
+               omega, order, holistic, fp32_products)
     s.run(A.contiguous())
     return s.G, s.U, read_info(s.info)
 

@@ -585,6 +585,7 @@ int solve(bool st_variant, const tucker_shape* shape, const void* A, const int64
           tucker_shift shift, uint64_t seed, tucker_precision prec, void* G, void* const* U, tucker_info* info,
           void* ws, size_t ws_bytes, hipStream_t st, double pve_tol = -1.0, int32_t* q_used = nullptr,
           const tucker_options* opt = nullptr, bool one_stream = false) {
+  const ProductScope products(opt != nullptr ? opt->fp32_products : TUCKER_FP32_SPLIT);
   Plan pl;
   // with the per-vector-error test q is the largest power count; the plan (and
   // the per-step logs) cover the first TUCKER_MAX_Q steps
@@ -828,6 +829,7 @@ struct OpWs {
   void* part;
   double* y64;
   void* orth;
+  void* qt;  // Q^T (l x n, storage precision): the j-major operand the solve's products read
 };
 
 size_t op_ws_layout(const View3& v, int64_t m, int l, tucker_precision prec, char* base, OpWs* w) {
@@ -841,6 +843,7 @@ size_t op_ws_layout(const View3& v, int64_t m, int l, tucker_precision prec, cha
   w->part = take(colreduce_part_bytes(v, l, prec));
   w->y64 = (double*)take((size_t)v.n * l * 8);
   w->orth = take(orth_ws_bytes(v.n, l));
+  w->qt = take((size_t)v.n * l * elem_bytes(prec));
   return off;
 }
 
@@ -1226,6 +1229,11 @@ int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X,
     if (e == hipSuccess)
       e = launch_power_products(prec, v, X, w.omz, (int)l, nullptr, w.part, nsplit, ows.pf_ctr, &nfused, &ns_used,
                                 stream);
+  } else if (prec != TUCKER_FP64) {
+    // Q^T j-major, as the solve's power steps read it (the same kernels run)
+    e = launch_transpose_f32((const float*)Q, v.n, (int)l, (float*)w.qt, stream);
+    if (e == hipSuccess) e = launch_rowcontract(prec, v, X, w.qt, 1, v.n, (int)l, w.omz, true, stream);
+    if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
   } else {
     e = launch_rowcontract(prec, v, X, Q, l, 1, (int)l, w.omz, true, stream);
     if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
@@ -1317,7 +1325,9 @@ static int check_options(const tucker_options* opt) {
   if (opt->order_kind < TUCKER_ORDER_NATURAL || opt->order_kind > TUCKER_ORDER_DECREASING)
     return fail(TUCKER_EINVAL, "unknown order kind %d", opt->order_kind);
   if (opt->holistic != 0 && opt->holistic != 1) return fail(TUCKER_EINVAL, "holistic = %d is not 0 or 1", opt->holistic);
-  for (int i = 0; i < 5; ++i)
+  if (opt->fp32_products != TUCKER_FP32_SPLIT && opt->fp32_products != TUCKER_FP32_NATIVE)
+    return fail(TUCKER_EINVAL, "fp32_products = %d is not 0 or 1", opt->fp32_products);
+  for (int i = 0; i < 4; ++i)
     if (opt->reserved[i] != 0) return fail(TUCKER_EINVAL, "tucker_options.reserved[%d] is not zero", i);
   return TUCKER_OK;
 }

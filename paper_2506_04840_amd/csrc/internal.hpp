@@ -68,6 +68,18 @@ class TimingScope {
   } while (0)
 inline size_t elem_bytes(tucker_precision p) { return p == TUCKER_FP64 ? 8 : 4; }
 
+// How the FP32 launches of the calling host thread form their products
+// (tucker_fp32_products), for the duration of one entry-point call: the
+// launch functions read it when they choose a kernel.
+class ProductScope {
+ public:
+  explicit ProductScope(int fp32_products);
+  ~ProductScope();
+ private:
+  int prev_;
+};
+bool fp32_split_products();
+
 // ---- Gaussian test matrix -------------------------------------------------
 // Writes Omega[row0 + c, j] for c < rows, j < cols: jmajor -> out[j * rows + c]
 // (the [cols, rows] layout the column reduction reads), else out[c * cols + j].

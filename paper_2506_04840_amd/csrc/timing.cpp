@@ -35,6 +35,11 @@ Timing& state() {
 
 thread_local TimingScope* g_scope = nullptr;  // innermost active scope of this host thread
 
+thread_local int g_fp32_products = TUCKER_FP32_SPLIT;
+ProductScope::ProductScope(int fp32_products) : prev_(g_fp32_products) { g_fp32_products = fp32_products; }
+ProductScope::~ProductScope() { g_fp32_products = prev_; }
+bool fp32_split_products() { return g_fp32_products == TUCKER_FP32_SPLIT; }
+
 TimingScope::TimingScope(int cls, hipStream_t st, double bytes, double flops, bool stamped)
     : slot_(-1), st_(st), stamped_(stamped), attached_(false), prev_(nullptr) {
   Timing& t = state();

@@ -54,6 +54,15 @@ struct Pol<MF_BF16> {
   static constexpr int KC = 8;
   static constexpr int MV = 4;
 };
+template <>
+struct Pol<MF_S3> {
+  using T = float;
+  using acc_t = floatx4;
+  using part_t = float;
+  static constexpr int KL = 8;
+  static constexpr int KC = 8;
+  static constexpr int MV = 4;
+};
 
 // Row of the 16x16 result held by (lane, element v): the FP32 and BF16
 // instructions return 4 consecutive rows per lane group, the FP64 one
@@ -136,6 +145,35 @@ __device__ __forceinline__ void copy_frag(T* dst, const T* src) {
 }
 
 // ---------------------------------------------------------------------------
+// FP32 products on the BF16 matrix cores. An FP32 value splits into three
+// BF16 pieces, x = x0 + x1 + x2 + e with |e| <= 2^-24 |x| (each piece the
+// round-to-nearest BF16 of what the previous ones leave; each product of two
+// pieces is exact in FP32). A product a b is taken as the six partial
+// products whose pieces' orders sum to at most 2 (a0 b0, a0 b1, a1 b0, a0 b2,
+// a1 b1, a2 b0); the three left out are below 3 2^-24 |a b| together. The
+// sums run in the FP32 accumulators of v_mfma_f32_16x16x32_bf16, whose BF16
+// rate on gfx950 is about 15 times its FP32 one, so six of them cost less
+// than half of one FP32 16x16x4 step of the same work.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split1(float x, __bf16& a, __bf16& b, __bf16& c) {
+  a = (__bf16)x;
+  const float r1 = x - (float)a;
+  b = (__bf16)r1;
+  c = (__bf16)(r1 - (float)b);
+}
+__device__ __forceinline__ void split3(const float (&x)[8], bf16x8 (&p)[3]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 a = (__bf16)x[e];
+    const float r1 = x[e] - (float)a;
+    const __bf16 b = (__bf16)r1;
+    p[0][e] = a;
+    p[1][e] = b;
+    p[2][e] = (__bf16)(r1 - (float)b);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Column reduction, S > 1, staged through LDS: part[split][i][j] = sum over
 // the split's columns c of X_(k)[i, c] Bt[j, c]. A workgroup owns 64 rows
 // (16 per wave) and one split; a stage is KT consecutive columns of one p
@@ -163,6 +201,13 @@ struct LdsPol<MF_BF16> {
   using LT = __bf16;
   static constexpr int KT = 64, RV = 8;
 };
+// split: X stays FP32 in LDS (each wave splits its own rows after reading
+// them); the skinny operand is split once at staging into three BF16 tiles
+template <>
+struct LdsPol<MF_S3> {
+  using LT = float;
+  static constexpr int KT = 32, RV = 8;
+};
 
 // EDGE: 0 when KT divides S (no edge stage), 1 when the 16-byte group
 // divides S (an edge-stage group is whole or absent), 2 otherwise.
@@ -179,9 +224,14 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
   constexpr int VE = 16 / (int)sizeof(T);          // elements of T per 16-byte global load
   constexpr int UPR = KT / VE;                     // 16-byte units per row per stage (16)
   constexpr int LS = KT + 16 / (int)sizeof(LT);    // padded LDS row (elements)
-  constexpr int XU = 64 * UPR / 256, BU = 16 * NJ * UPR / 256;  // units per thread: X tile, Bt tile
+  constexpr bool S3 = MK == MF_S3;
+  // rows of the skinny operand staged per stage (the split stages whole 32-row units)
+  constexpr int NJB = S3 ? ((NJ + 1) & ~1) : NJ;
+  constexpr int XU = 64 * UPR / 256, BU = 16 * NJB * UPR / 256;  // units per thread: X tile, Bt tile
   __shared__ __align__(16) LT xs[2][64][LS];
-  __shared__ __align__(16) LT bs[2][16 * NJ][LS];
+  __shared__ __align__(16) LT bs[2][S3 ? 1 : 16 * NJ][LS];
+  // the split's skinny operand: three BF16 pieces, rows padded by 16 bytes
+  __shared__ __align__(16) __bf16 bs3[S3 ? 2 : 1][3][S3 ? 16 * NJB : 1][KT + 8];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
@@ -267,7 +317,23 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
 #pragma unroll
     for (int q = 0; q < BU; ++q) {
       const int L = q * 256 + tid, j = L / UPR, u = L % UPR;
-      sput(&bs[buf][j][u * VE], br[q]);
+      if constexpr (S3) {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        const float f[4] = {br[q].x, br[q].y, br[q].z, br[q].w};
+        bf16x4 pc[3];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          __bf16 a, b, c;
+          split1(f[e], a, b, c);
+          pc[0][e] = a;
+          pc[1][e] = b;
+          pc[2][e] = c;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x4*>(&bs3[buf][c][j][u * VE]) = pc[c];
+      } else {
+        sput(&bs[buf][j][u * VE], br[q]);
+      }
     }
   };
 
@@ -300,6 +366,28 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
 #pragma unroll
   for (int u = 0; u < NJ; ++u) acc[u] = typename Po::acc_t{0, 0, 0, 0};
   auto compute = [&](int buf) {
+    if constexpr (S3) {
+      // k index 8 g + e of a 32-column step, the same in X and the pieces
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 32) {
+        float xa[8];
+        *reinterpret_cast<V4*>(&xa[0]) = *reinterpret_cast<const V4*>(&xs[buf][16 * wave + mm][kk + 8 * g]);
+        *reinterpret_cast<V4*>(&xa[4]) = *reinterpret_cast<const V4*>(&xs[buf][16 * wave + mm][kk + 8 * g + 4]);
+        bf16x8 ap[3];
+        split3(xa, ap);
+        bf16x8 bp[NJ][3];
+#pragma unroll
+        for (int u = 0; u < NJ; ++u)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) bp[u][c] = *reinterpret_cast<const bf16x8*>(&bs3[buf][c][16 * u + mm][kk + 8 * g]);
+        constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+          for (int u = 0; u < NJ; ++u) acc[u] = mfma_bf16(ap[PA[k]], bp[u][PB[k]], acc[u]);
+      }
+      return;
+    }
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4 * RV) {
       LT a[RV];
@@ -523,12 +611,18 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
   int64_t nsteps, spp;
   int nrb;
   cr_geom(prec, v, &nsteps, &spp, &nrb);
+  if (MK == MF_S3 && v.S > 1) {  // stages of the split's own width
+    spp = (v.S + LdsPol<MK>::KT - 1) / LdsPol<MK>::KT;
+    nsteps = v.P * spp;
+  }
   const unsigned blocks = (unsigned)(((nsplit + 7) / 8) * 8 * nrb);
   const int64_t m = v.P * v.S;
-  if (v.S == 1)
-    TK_LAUNCH((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l,
-                       nsteps, nsplit, nrb, (PT*)part);
-  else {
+  if (v.S == 1) {
+    if constexpr (MK == MF_S3) return hipErrorInvalidValue;  // the split runs the staged kernel only
+    else
+      TK_LAUNCH((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l,
+                nsteps, nsplit, nrb, (PT*)part);
+  } else {
     constexpr int VE = 16 / (int)sizeof(T);
     const int edge = v.S % LdsPol<MK>::KT == 0 ? 0 : (v.S % VE == 0 ? 1 : 2);
 #define TK_CR_LDS(E)                                                                                       \
@@ -565,7 +659,9 @@ hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X
   TimingScope ts(KC_COLREDUCE, st, N * es + N / v.n * l * es, 2.0 * N * l, true);
   switch (prec) {
     case TUCKER_FP64: return cr_dispatch<MF_F64>(v, X, Bt, l, part, nsplit, npart, st);
-    case TUCKER_FP32: return cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, npart, st);
+    case TUCKER_FP32:
+      return v.S > 1 && fp32_split_products() ? cr_dispatch<MF_S3>(v, X, Bt, l, part, nsplit, npart, st)
+                                        : cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, npart, st);
     case TUCKER_BF16: return cr_dispatch<MF_BF16>(v, X, Bt, l, part, nsplit, npart, st);
   }
   return hipErrorInvalidValue;
@@ -830,6 +926,149 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
   rc_rows_body<MK, NJ, WVEC, KSPLIT>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, out, osp, osj, (int)blockIdx.x);
 }
 
+// Row contraction, S > 1, FP32 storage through the split (W j-major, whole
+// tiles of rows): the layout of k_rc_rows (64 output columns per wave as 4
+// interleaved 16-row tiles, NJ j tiles), with batches of 32 rows: k index
+// 8 g + q (lane group g, q < 8) is row i0 + 8 g + q for X and W alike. A
+// batch is split into pieces as soon as it arrives, which frees its raw
+// registers for the next batch's loads, issued before this batch's MFMAs.
+// WVEC: W j-major (wsi = 1), a lane's 8 rows are two 16-byte loads; otherwise
+// element loads at stride wsi.
+template <int NJ, bool WVEC>
+__global__ __launch_bounds__(256) void k_rc_rows_s3(const float* __restrict__ X, const float* __restrict__ W,
+                                                    int64_t n, int64_t S, int lw, int64_t wsi, int64_t wsj,
+                                                    int64_t tiles_per_p, int64_t ntiles, float* __restrict__ out,
+                                                    int64_t osp, int64_t osj) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int mm = lane & 15, g = lane >> 4;
+  const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  if (tile >= ntiles) return;  // whole waves; no barrier follows
+  const int64_t p = tile / tiles_per_p;
+  const int64_t s0 = (tile - p * tiles_per_p) * 64;
+  const float* xp = X + p * n * S + s0 + 4 * mm;
+  const float* wr[NJ];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) wr[u] = W + (int64_t)min(16 * u + mm, lw - 1) * wsj + 8 * g * wsi;
+  floatx4 acc[4][NJ];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  float xa[8][4], wa[NJ][8];
+  // interior batch: unconditional 16-byte loads
+  auto ffetch = [&](int64_t i0) {
+    const float* xr = xp + (i0 + 8 * g) * S;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const f4u_t v = *reinterpret_cast<const f4u_t*>(xr + q * S);
+      xa[q][0] = v[0];
+      xa[q][1] = v[1];
+      xa[q][2] = v[2];
+      xa[q][3] = v[3];
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      if constexpr (WVEC) {
+        const f4u_t v0 = *reinterpret_cast<const f4u_t*>(wr[u] + i0);
+        const f4u_t v1 = *reinterpret_cast<const f4u_t*>(wr[u] + i0 + 4);
+        wa[u][0] = v0[0];
+        wa[u][1] = v0[1];
+        wa[u][2] = v0[2];
+        wa[u][3] = v0[3];
+        wa[u][4] = v1[0];
+        wa[u][5] = v1[1];
+        wa[u][6] = v1[2];
+        wa[u][7] = v1[3];
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) wa[u][q] = wr[u][(i0 + q) * wsi];
+      }
+    }
+  };
+  // guarded batch: rows at or past n and columns at or past S read as zero
+  const int scnt = (int)max<int64_t>(0, min<int64_t>(4, S - (s0 + 4 * mm)));
+  auto gfetch = [&](int64_t i0) {
+    const int64_t ib = i0 + 8 * g;
+    const int icnt = (int)max<int64_t>(0, min<int64_t>(8, n - ib));
+#pragma unroll
+    for (int q = 0; q < 8; ++q) load_n<float, 4>(xp + (ib + q) * S, q < icnt ? scnt : 0, xa[q]);
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      if constexpr (WVEC) {
+        load_n<float, 8>(wr[u] + i0, icnt, wa[u]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) wa[u][q] = q < icnt ? wr[u][(i0 + q) * wsi] : 0.f;
+      }
+    }
+  };
+  bf16x8 ap[4][3], bp[NJ][3];
+  auto split_batch = [&]() {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float col[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) col[q] = xa[q][t];
+      split3(col, ap[t]);
+    }
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) split3(wa[u], bp[u]);
+  };
+  // the six products, each pass over all tiles before the next (16 MFMAs
+  // between two that share an accumulator)
+  auto compute = [&]() {
+    constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < NJ; ++u) acc[t][u] = mfma_bf16(ap[t][PA[k]], bp[u][PB[k]], acc[t][u]);
+  };
+
+  const bool wide = s0 + 64 <= S;
+  const int64_t nb = wide ? n / 32 : 0;  // interior batches
+  if (nb > 0) {
+    const int64_t last = (nb - 1) * 32;
+    ffetch(0);
+    for (int64_t b = 0; b < nb; ++b) {
+      split_batch();
+      __builtin_amdgcn_sched_barrier(0);
+      // the next batch (the last one again past the end: never split)
+      ffetch(min<int64_t>((b + 1) * 32, last));
+      __builtin_amdgcn_sched_barrier(0);
+      compute();
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  for (int64_t i0 = nb * 32; i0 < n; i0 += 32) {
+    gfetch(i0);
+    split_batch();
+    compute();
+  }
+  // tile t, result row dr = 4 g + v -> column s0 + 4 dr + t, output row j
+  float* op = out + p * osp;
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int j = 16 * u + mm;
+    if (j >= lw) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t c = s0 + 4 * (4 * g + v);
+      float* dst = op + (int64_t)j * osj + c;
+      if (c + 3 < S) {
+        const f4u_t o = {acc[0][u][v], acc[1][u][v], acc[2][u][v], acc[3][u][v]};
+        *reinterpret_cast<f4u_t*>(dst) = o;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (c + t < S) dst[t] = acc[t][u][v];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Row contraction, S == 1: X is [P, n] (rows p contiguous along i, the
 // reduction index); out(p, j) = out[p * osp + j * osj]; each wave owns 64
@@ -956,6 +1195,18 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     // split the rows while the tiles fill fewer than two rounds of the ~2048
     // resident waves (one partial round would leave most of the chip idle)
     const int ksplit = ntiles < 4096 ? 1 : 0;
+    if constexpr (MK == MF_F32) {
+      if (!ksplit && fp32_split_products()) {
+        const unsigned b = (unsigned)((ntiles + 3) / 4);
+#define TK_RC_S3(WV)                                                                                       \
+  TK_LAUNCH((k_rc_rows_s3<NJ, WV>), dim3(b), dim3(256), 0, st, (const float*)X, (const float*)W, v.n, v.S, \
+            lw, wsi, wsj, tpp, ntiles, (float*)out, osp, osj)
+        if (wvec) TK_RC_S3(true);
+        else TK_RC_S3(false);
+#undef TK_RC_S3
+        return hipGetLastError();
+      }
+    }
     const unsigned blocks = (unsigned)(ksplit ? ntiles : (ntiles + 3) / 4);
 #define TK_RC_ROWS(WV, KS)                                                                                        \
   TK_LAUNCH((k_rc_rows<MK, NJ, WV, KS>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)W, v.n, v.S, \

@@ -166,8 +166,13 @@ def test_processing_order_options_on_the_host():
     bad.order_kind = 7
     assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, bad) == 0
     bad = _lib.make_options()
-    bad.reserved[4] = 1
+    bad.reserved[3] = 1
     assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, bad) == 0
+    bad = _lib.make_options()
+    bad.fp32_products = 2
+    assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, bad) == 0
+    native = _lib.make_options(fp32_products="native")
+    assert _lib.workspace_bytes((60, 12, 40), (5, 6, 4), 4, 1, _lib.FP32, True, native) == nat
     L = _lib.lib
     s = _lib._shape((60, 12, 40))
     r = (ctypes.c_int64 * 3)(5, 6, 4)

@@ -310,10 +310,12 @@ def _check_signed_factors(us, res, ranks, prec, gap_need):
     return checked, complete
 
 
-def _compare_solve(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, check_core=True, order=None):
+def _compare_solve(a_dev, a64, ranks, p, q, shift, variant, prec, seed=1, check_core=True, order=None,
+                   fp32_products="split"):
     from paper_2506_04840_amd import _lib as T
     fn = T.rsthosvd if variant == "st" else T.rthosvd
-    G, U, info = fn(a_dev, ranks, p=p, q=q, shift=shift, seed=seed, precision=prec, order=order)
+    G, U, info = fn(a_dev, ranks, p=p, q=q, shift=shift, seed=seed, precision=prec, order=order,
+                    fp32_products=fp32_products)
     torch.cuda.synchronize()
     g, us = _np(G), [_np(u) for u in U]
     oo = orc.decreasing_order(a64.shape) if order == "decreasing" else order
@@ -938,3 +940,47 @@ def test_fused_power_steps_without_rezeroing(T):
     lg = res.logs[0]
     # the iterates of consecutive steps really differ (a stale partial would repeat one)
     assert len({round(s[-1] / s[0], 6) for s in lg.sigmas[1:]}) == len(lg.sigmas) - 1
+
+
+# --------------------------------------------------------------- FP32 products through BF16 splits
+
+def test_split_products_match_their_definitions(T):
+    """FP32 power step and core contraction at a size where both product
+    kernels take the three-piece BF16 split (mode 0 of 64 x 300000: 4688 tiles
+    of 64 columns): every entry within 1e-5 of its Cauchy-Schwarz scale of
+    the FP64 definitions X_(0)(X_(0)^T Q) and U^T X_(0) (the split keeps 24
+    significant bits of each operand; measured about 3e-8 and 2e-7), and
+    within the same bound of the FP32-instruction path's result."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(3)
+    X = torch.randn((64, 300000), generator=g, device=dev, dtype=torch.float32)
+    Q = torch.linalg.qr(torch.randn((64, 40), generator=g, device=dev, dtype=torch.float64))[0].float().contiguous()
+    alpha = torch.zeros(1, dtype=torch.float64, device=dev)
+    M = T.shifted_power(X, 0, Q, alpha, raw=True)
+    U = Q[:, :30].contiguous()
+    C = T.core(X, 0, U).double()
+    X64 = X.double()
+    Z = X64.T @ Q.double()
+    sc = torch.linalg.vector_norm(X64, dim=1)[:, None] * torch.linalg.vector_norm(Z, dim=0)[None, :]
+    err = ((M - X64 @ Z).abs() / sc).max().item()
+    print("split power step: max error / scale %.3e" % err, flush=True)
+    assert err <= 1e-5
+    Cref = U.double().T @ X64
+    sc2 = torch.linalg.vector_norm(U.double(), dim=0)[:, None] * torch.linalg.vector_norm(X64, dim=0)[None, :]
+    err2 = ((C - Cref).abs() / sc2).max().item()
+    print("split core: max error / scale %.3e" % err2, flush=True)
+    assert err2 <= 1e-5
+
+
+@pytest.mark.parametrize("fp32_products", ["split", "native"])
+def test_fp32_solve_at_split_sizes_matches_oracle(T, fp32_products):
+    """A whole FP32 ST-HOSVD whose mode-0 products run through the BF16 split
+    (48 x 96 x 3000: 4500 tiles of 64 columns), and the same solve on the FP32
+    instructions only, each against the FP64 oracle on the same tensor and
+    test matrices: reconstruction within 1e-5, shifts and singular values,
+    subspaces, signed factors and core (the checks of every solve test)."""
+    a, _, _ = gen.random_tucker((48, 96, 3000), (6, 8, 10), 1e-3, seed=51)
+    a32 = a.astype(np.float32)
+    _compare_solve(_dev(a32, torch.float32), a32.astype(np.float64), (6, 8, 10), 6, 2, "adaptive", "st", "fp32",
+                   seed=4, fp32_products=fp32_products)
