@@ -22,7 +22,7 @@ import re
 
 CLASSES = {
     "colreduce": r"tk::k_cr_(lds|cols)<",
-    "rowcontract": r"tk::k_rc_(rows|cols)<",
+    "rowcontract": r"tk::k_rc_(rows|cols)(_s3)?<",
     "powerstep": r"tk::k_power_fused<",
     # persistent batched kernels: the profiler may print them mangled
     "batched_colreduce": r"k_persist<tk::BCr(Lds|Cols),|k_persistINS_\d+BCr(Lds|Cols)E",
