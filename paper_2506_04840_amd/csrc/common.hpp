@@ -17,9 +17,7 @@ constexpr int kWave = 64;
 constexpr int kMaxL = TUCKER_MAX_L;   // widest sketch handled by the kernels
 
 // Which matrix-core instruction a product runs on.
-// MF_S3: FP32 operands split into three BF16 pieces, six BF16 products with
-// FP32 accumulation (FP32-level accuracy at the BF16 instruction rate).
-enum MfmaKind { MF_F32 = 0, MF_F64 = 1, MF_BF16 = 2, MF_S3 = 3 };
+enum MfmaKind { MF_F32 = 0, MF_F64 = 1, MF_BF16 = 2 };
 
 // Tensor X viewed as row-major [P, n, S]; the mode-k unfolding is
 // X_(k)[i, p*S + s] = X[p, i, s] (columns in row-major order of the other modes).

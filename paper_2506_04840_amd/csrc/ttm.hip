@@ -20,6 +20,8 @@
 //    go to MV interleaved 16-row tiles.
 // Instructions: v_mfma_f32_16x16x4_f32 (FP32), v_mfma_f64_16x16x4_f64 (FP64),
 // v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation).
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -47,15 +49,6 @@ struct Pol<MF_F64> {
 };
 template <>
 struct Pol<MF_BF16> {
-  using T = float;
-  using acc_t = floatx4;
-  using part_t = float;
-  static constexpr int KL = 8;
-  static constexpr int KC = 8;
-  static constexpr int MV = 4;
-};
-template <>
-struct Pol<MF_S3> {
   using T = float;
   using acc_t = floatx4;
   using part_t = float;
@@ -145,35 +138,6 @@ __device__ __forceinline__ void copy_frag(T* dst, const T* src) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 products on the BF16 matrix cores. An FP32 value splits into three
-// BF16 pieces, x = x0 + x1 + x2 + e with |e| <= 2^-24 |x| (each piece the
-// round-to-nearest BF16 of what the previous ones leave; each product of two
-// pieces is exact in FP32). A product a b is taken as the six partial
-// products whose pieces' orders sum to at most 2 (a0 b0, a0 b1, a1 b0, a0 b2,
-// a1 b1, a2 b0); the three left out are below 3 2^-24 |a b| together. The
-// sums run in the FP32 accumulators of v_mfma_f32_16x16x32_bf16, whose BF16
-// rate on gfx950 is about 15 times its FP32 one, so six of them cost less
-// than half of one FP32 16x16x4 step of the same work.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void split1(float x, __bf16& a, __bf16& b, __bf16& c) {
-  a = (__bf16)x;
-  const float r1 = x - (float)a;
-  b = (__bf16)r1;
-  c = (__bf16)(r1 - (float)b);
-}
-__device__ __forceinline__ void split3(const float (&x)[8], bf16x8 (&p)[3]) {
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const __bf16 a = (__bf16)x[e];
-    const float r1 = x[e] - (float)a;
-    const __bf16 b = (__bf16)r1;
-    p[0][e] = a;
-    p[1][e] = b;
-    p[2][e] = (__bf16)(r1 - (float)b);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Column reduction, S > 1, staged through LDS: part[split][i][j] = sum over
 // the split's columns c of X_(k)[i, c] Bt[j, c]. A workgroup owns 64 rows
 // (16 per wave) and one split; a stage is KT consecutive columns of one p
@@ -201,13 +165,6 @@ struct LdsPol<MF_BF16> {
   using LT = __bf16;
   static constexpr int KT = 64, RV = 8;
 };
-// split: X stays FP32 in LDS (each wave splits its own rows after reading
-// them); the skinny operand is split once at staging into three BF16 tiles
-template <>
-struct LdsPol<MF_S3> {
-  using LT = float;
-  static constexpr int KT = 32, RV = 8;
-};
 
 // EDGE: 0 when KT divides S (no edge stage), 1 when the 16-byte group
 // divides S (an edge-stage group is whole or absent), 2 otherwise.
@@ -224,14 +181,9 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
   constexpr int VE = 16 / (int)sizeof(T);          // elements of T per 16-byte global load
   constexpr int UPR = KT / VE;                     // 16-byte units per row per stage (16)
   constexpr int LS = KT + 16 / (int)sizeof(LT);    // padded LDS row (elements)
-  constexpr bool S3 = MK == MF_S3;
-  // rows of the skinny operand staged per stage (the split stages whole 32-row units)
-  constexpr int NJB = S3 ? ((NJ + 1) & ~1) : NJ;
-  constexpr int XU = 64 * UPR / 256, BU = 16 * NJB * UPR / 256;  // units per thread: X tile, Bt tile
+  constexpr int XU = 64 * UPR / 256, BU = 16 * NJ * UPR / 256;  // units per thread: X tile, Bt tile
   __shared__ __align__(16) LT xs[2][64][LS];
-  __shared__ __align__(16) LT bs[2][S3 ? 1 : 16 * NJ][LS];
-  // the split's skinny operand: three BF16 pieces, rows padded by 16 bytes
-  __shared__ __align__(16) __bf16 bs3[S3 ? 2 : 1][3][S3 ? 16 * NJB : 1][KT + 8];
+  __shared__ __align__(16) LT bs[2][16 * NJ][LS];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
@@ -317,23 +269,7 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
 #pragma unroll
     for (int q = 0; q < BU; ++q) {
       const int L = q * 256 + tid, j = L / UPR, u = L % UPR;
-      if constexpr (S3) {
-        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-        const float f[4] = {br[q].x, br[q].y, br[q].z, br[q].w};
-        bf16x4 pc[3];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          __bf16 a, b, c;
-          split1(f[e], a, b, c);
-          pc[0][e] = a;
-          pc[1][e] = b;
-          pc[2][e] = c;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) *reinterpret_cast<bf16x4*>(&bs3[buf][c][j][u * VE]) = pc[c];
-      } else {
-        sput(&bs[buf][j][u * VE], br[q]);
-      }
+      sput(&bs[buf][j][u * VE], br[q]);
     }
   };
 
@@ -366,28 +302,6 @@ __device__ __forceinline__ void cr_lds_body(const typename Pol<MK>::T* __restric
 #pragma unroll
   for (int u = 0; u < NJ; ++u) acc[u] = typename Po::acc_t{0, 0, 0, 0};
   auto compute = [&](int buf) {
-    if constexpr (S3) {
-      // k index 8 g + e of a 32-column step, the same in X and the pieces
-#pragma unroll
-      for (int kk = 0; kk < KT; kk += 32) {
-        float xa[8];
-        *reinterpret_cast<V4*>(&xa[0]) = *reinterpret_cast<const V4*>(&xs[buf][16 * wave + mm][kk + 8 * g]);
-        *reinterpret_cast<V4*>(&xa[4]) = *reinterpret_cast<const V4*>(&xs[buf][16 * wave + mm][kk + 8 * g + 4]);
-        bf16x8 ap[3];
-        split3(xa, ap);
-        bf16x8 bp[NJ][3];
-#pragma unroll
-        for (int u = 0; u < NJ; ++u)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) bp[u][c] = *reinterpret_cast<const bf16x8*>(&bs3[buf][c][16 * u + mm][kk + 8 * g]);
-        constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
-#pragma unroll
-        for (int k = 0; k < 6; ++k)
-#pragma unroll
-          for (int u = 0; u < NJ; ++u) acc[u] = mfma_bf16(ap[PA[k]], bp[u][PB[k]], acc[u]);
-      }
-      return;
-    }
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 4 * RV) {
       LT a[RV];
@@ -466,6 +380,333 @@ __global__ __launch_bounds__(256) void k_cr_lds(const typename Pol<MK>::T* __res
   if (!xcd_decode((int)blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
   cr_lds_body<MK, NJ, EDGE>(X, Bt, n, S, l, m, spp, nsteps, nsplit, part, split, rb,
                             npart != nullptr ? npart + (int64_t)split * nrblocks + rb : nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Column reduction, S > 1, FP32 storage on the BF16 matrix cores: NP = 3
+// forms FP32 products through the three-piece split, NP = 1 rounds both
+// operands to BF16 once. part[split][i][j] as for k_cr_lds. A workgroup owns
+// 128 rows (32 per wave, two 16-row tiles) and one split; a stage is 32
+// columns of one p. X goes from HBM straight into each wave's registers in
+// the operand layout of v_mfma_f32_16x16x32_bf16: lane (mm, g) of tile h
+// holds row 32 w + 16 h + mm at stage columns 4 g .. 4 g + 3 (k slots 8 g ..
+// 8 g + 3) and 16 + 4 g .. 16 + 4 g + 3 (k slots 8 g + 4 .. 8 g + 7), so a
+// row's 128 bytes are two 64-byte runs, each read by one instruction, and X
+// never passes through LDS. The stage's Bt tile (FP32) is read by the whole
+// workgroup, converted once into BF16 pieces in the same k order and kept in
+// LDS (rows padded by 16 bytes), where every wave reads it for its two tiles.
+// X and Bt are kept two stages ahead in registers; one barrier per stage.
+// With NORM (npart given), the workgroup also sums the squares of the X elements it
+// reads (FP64, stage order, rows past n and stages past the split excluded)
+// into the slots of its two 64-row halves (slot split * nslots + 64-row
+// block), the layout colreduce_norm_slots describes.
+// EDGE as for k_cr_lds (0: 32 divides S; 1: 4 divides S; 2: otherwise).
+// ---------------------------------------------------------------------------
+// FP32 products on the BF16 matrix cores. An FP32 value splits into three
+// BF16 pieces, x = x0 + x1 + x2 + e with |e| <= 2^-24 |x| (each piece the
+// round-to-nearest BF16 of what the previous ones leave; each product of two
+// pieces is exact in FP32). A product a b is taken as the six partial
+// products whose pieces' orders sum to at most 2 (a0 b0, a0 b1, a1 b0, a0 b2,
+// a1 b1, a2 b0); the three left out are below 3 2^-24 |a b| together. The
+// sums run in the FP32 accumulators of v_mfma_f32_16x16x32_bf16, whose BF16
+// rate on gfx950 is about 15 times its FP32 one, so six of them cost less
+// than half of one FP32 16x16x4 step of the same work. With one piece (NP =
+// 1) the same kernels take BF16 operands.
+// Pieces of pairs of FP32 values: fptrunc and fpext of two-element vectors
+// become one v_cvt_pk_bf16_f32 per pair and one shift or mask per element.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+
+template <int NP>
+__device__ __forceinline__ void pair_pieces(f32x2_t v, bf16x2_t (&p)[NP]) {
+  const bf16x2_t a = __builtin_convertvector(v, bf16x2_t);
+  p[0] = a;
+  if constexpr (NP == 3) {
+    const f32x2_t r1 = v - __builtin_convertvector(a, f32x2_t);
+    const bf16x2_t b = __builtin_convertvector(r1, bf16x2_t);
+    p[1] = b;
+    p[2] = __builtin_convertvector(r1 - __builtin_convertvector(b, f32x2_t), bf16x2_t);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void bf_pieces(const float (&x)[8], bf16x8 (&p)[NP]) {
+  bf16x2_t q[4][NP];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) pair_pieces<NP>(f32x2_t{x[2 * e], x[2 * e + 1]}, q[e]);
+#pragma unroll
+  for (int c = 0; c < NP; ++c) {
+    const bf16x4_t lo = __builtin_shufflevector(q[0][c], q[1][c], 0, 1, 2, 3);
+    const bf16x4_t hi = __builtin_shufflevector(q[2][c], q[3][c], 0, 1, 2, 3);
+    p[c] = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ void bf_pieces4(const float (&x)[4], bf16x4_t (&p)[NP]) {
+  bf16x2_t q[2][NP];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) pair_pieces<NP>(f32x2_t{x[2 * e], x[2 * e + 1]}, q[e]);
+#pragma unroll
+  for (int c = 0; c < NP; ++c) p[c] = __builtin_shufflevector(q[0][c], q[1][c], 0, 1, 2, 3);
+}
+
+// The products of a pair of pieced operands, smallest first: (piece of A,
+// piece of B) with orders summing to at most 2 for the split, (0, 0) for BF16.
+template <int NP>
+struct BfProducts;
+template <>
+struct BfProducts<1> {
+  static constexpr int N = 1;
+  static constexpr int A[1] = {0}, B[1] = {0};
+};
+template <>
+struct BfProducts<3> {
+  static constexpr int N = 6;
+  static constexpr int A[6] = {2, 1, 0, 1, 0, 0}, B[6] = {0, 1, 2, 0, 1, 0};
+};
+
+template <int NP, int NJ, int EDGE, bool NORM>
+__global__ __launch_bounds__(256, 2) void k_cr_split(const float* __restrict__ X, const float* __restrict__ Bt, int64_t n,
+                                                  int64_t S, int l, int64_t m, int64_t spp, int64_t nsteps,
+                                                  int nsplit, int nrblocks, int nslots, float* __restrict__ part,
+                                                  double* __restrict__ npart) {
+  constexpr int KT = 32;
+  constexpr int NJB = (NJ + 1) & ~1;       // Bt rows staged per stage: whole 32-row units
+  constexpr int BU = NJB / 2;              // 16-byte Bt units per thread per stage
+  constexpr int LS = KT + 8;               // padded LDS row (BF16 elements)
+  using PR = BfProducts<NP>;
+  __shared__ __align__(16) __bf16 bs[2][NP][16 * NJB][LS];
+  __shared__ double nred[4];
+  int split, rb;
+  if (!xcd_decode((int)blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  const int mm = lane & 15, g = lane >> 4;
+  const int64_t r0 = (int64_t)rb * 128 + 32 * wave;
+  const int64_t t0 = nsteps * split / nsplit, t1 = nsteps * (split + 1) / nsplit;
+  // the lane's rows in the two tiles, clamped (rows past n feed only outputs
+  // that are never written)
+  const int64_t ia = min<int64_t>(r0 + mm, n - 1), ib = min<int64_t>(r0 + 16 + mm, n - 1);
+  const bool rowa = r0 + mm < n, rowb = r0 + 16 + mm < n;
+  typedef float fv4 __attribute__((ext_vector_type(4)));
+
+  // stage cursors as in k_cr_lds, one for X and one for Bt (their loads run
+  // at different distances): (p, s0) of the next stage to load; a cursor
+  // stays on the split's last stage, so loads past the split re-read that stage
+  struct Cursor {
+    int64_t p, s, left;
+  };
+  const int64_t rowlen = spp * KT;
+  Cursor xc{t0 / spp, (t0 - (t0 / spp) * spp) * KT, t1 - t0}, bc = xc;
+  auto advance = [&](Cursor& c, int64_t& p, int64_t& s0) {
+    p = c.p;
+    s0 = c.s;
+    const bool adv = c.left > 1;
+    const int64_t ns = c.s + KT;
+    const bool wrap = ns == rowlen;
+    c.s = adv ? (wrap ? 0 : ns) : c.s;
+    c.p = adv && wrap ? c.p + 1 : c.p;
+    c.left = adv ? c.left - 1 : c.left;
+  };
+  // X of stage t: [tile a cols 4g.., tile a cols 16+4g.., tile b .., tile b ..]
+  auto xload = [&](int64_t t, fv4 (&xr)[4]) {
+    int64_t p, s0;
+    advance(xc, p, s0);
+    const float* xa = X + (p * n + ia) * S;
+    const float* xb = X + (p * n + ib) * S;
+    const int64_t c0 = s0 + 4 * g, c1 = s0 + 16 + 4 * g;
+    if (EDGE != 2 || s0 + KT <= S) {
+      const bool in0 = EDGE == 0 || c0 < S, in1 = EDGE == 0 || c1 < S;
+      const int64_t a0 = in0 ? c0 : S - 4, a1 = in1 ? c1 : S - 4;
+      f4u_t v[4] = {*reinterpret_cast<const f4u_t*>(xa + a0), *reinterpret_cast<const f4u_t*>(xa + a1),
+                    *reinterpret_cast<const f4u_t*>(xb + a0), *reinterpret_cast<const f4u_t*>(xb + a1)};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool in = (q & 1) ? in1 : in0;
+        xr[q] = (EDGE == 0 || in) ? fv4{v[q][0], v[q][1], v[q][2], v[q][3]} : fv4{0.f, 0.f, 0.f, 0.f};
+      }
+      return;
+    }
+    // EDGE 2 edge stage: element loads, counted
+    const bool live = t < t1;
+    const int n0 = live ? (int)max<int64_t>(0, min<int64_t>(4, S - c0)) : 0;
+    const int n1 = live ? (int)max<int64_t>(0, min<int64_t>(4, S - c1)) : 0;
+    float v[4][4];
+    load_n<float, 4>(xa + c0, n0, v[0]);
+    load_n<float, 4>(xa + c1, n1, v[1]);
+    load_n<float, 4>(xb + c0, n0, v[2]);
+    load_n<float, 4>(xb + c1, n1, v[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xr[q] = fv4{v[q][0], v[q][1], v[q][2], v[q][3]};
+  };
+  // Bt tile of stage t: unit q * 256 + tid is row j, columns 4 u .. 4 u + 3
+  auto bload = [&](int64_t t, fv4 (&br)[BU]) {
+    int64_t p, s0;
+    advance(bc, p, s0);
+    if (EDGE != 2 || s0 + KT <= S) {
+#pragma unroll
+      for (int q = 0; q < BU; ++q) {
+        const int L = q * 256 + tid, j = min(L / 8, l - 1), u = L % 8;
+        const int64_t sg = s0 + 4 * u;
+        const f4u_t b = *reinterpret_cast<const f4u_t*>(Bt + (int64_t)j * m + p * S + (EDGE == 0 || sg < S ? sg : S - 4));
+        br[q] = fv4{b[0], b[1], b[2], b[3]};
+      }
+      return;
+    }
+    const bool live = t < t1;
+#pragma unroll
+    for (int q = 0; q < BU; ++q) {
+      const int L = q * 256 + tid, j = L / 8, u = L % 8;
+      const int64_t sg = s0 + 4 * u;
+      const int cnt = (live && j < l) ? (int)max<int64_t>(0, min<int64_t>(4, S - sg)) : 0;
+      float b[4];
+      load_n<float, 4>(Bt + (int64_t)j * m + p * S + sg, cnt, b);
+      br[q] = fv4{b[0], b[1], b[2], b[3]};
+    }
+  };
+  // Bt units -> LDS pieces: unit u of row j holds stage columns 4 u .. 4 u + 3,
+  // k slots 8 u .. 8 u + 3 (u < 4) or 8 (u - 4) + 4 .. + 3
+  auto lstore = [&](int buf, const fv4 (&br)[BU]) {
+#pragma unroll
+    for (int q = 0; q < BU; ++q) {
+      const int L = q * 256 + tid, j = L / 8, u = L % 8;
+      const int kk = u < 4 ? 8 * u : 8 * (u - 4) + 4;
+      const float f[4] = {br[q][0], br[q][1], br[q][2], br[q][3]};
+      bf16x4_t pc[NP];
+      bf_pieces4<NP>(f, pc);
+#pragma unroll
+      for (int c = 0; c < NP; ++c) *reinterpret_cast<bf16x4_t*>(&bs[buf][c][j][kk]) = pc[c];
+    }
+  };
+
+  floatx4 acc[2][NJ];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) acc[h][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  double nacc = 0.0;
+  // X of a stage into pieces (and, for a stage of the split, its squares
+  // into the norm sum)
+  auto prep = [&](const fv4 (&xr)[4], bf16x8 (&ap)[2][NP], bool counted) {
+    if constexpr (NORM) {  // no branch: a branch would end the block the products share
+      double sq = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double v = (q < 2 ? rowa : rowb) ? (double)xr[q][e] : 0.0;
+          sq = fma(v, v, sq);
+        }
+      nacc += counted ? sq : 0.0;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const float f[8] = {xr[2 * h][0],     xr[2 * h][1],     xr[2 * h][2],     xr[2 * h][3],
+                          xr[2 * h + 1][0], xr[2 * h + 1][1], xr[2 * h + 1][2], xr[2 * h + 1][3]};
+      bf_pieces<NP>(f, ap[h]);
+    }
+  };
+  // the stage's products, two j tiles at a time (four independent chains)
+  auto mma = [&](int buf, const bf16x8 (&ap)[2][NP]) {
+#pragma unroll
+    for (int u0 = 0; u0 < NJ; u0 += 2) {
+      constexpr int W2 = 2;
+      bf16x8 bp[W2][NP];
+#pragma unroll
+      for (int uu = 0; uu < W2; ++uu)
+        if (u0 + uu < NJ)
+#pragma unroll
+          for (int c = 0; c < NP; ++c)
+            bp[uu][c] = *reinterpret_cast<const bf16x8*>(&bs[buf][c][16 * (u0 + uu) + mm][8 * g]);
+#pragma unroll
+      for (int k = 0; k < PR::N; ++k)
+#pragma unroll
+        for (int uu = 0; uu < W2; ++uu)
+          if (u0 + uu < NJ)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+              acc[h][u0 + uu] = mfma_bf16(ap[h][PR::A[k]], bp[uu][PR::B[k]], acc[h][u0 + uu]);
+    }
+  };
+
+  // Software pipeline over the split's K stages, stage k = t0 + k. X loads
+  // run four stages ahead through a ring of four register slots (slot
+  // k % 4), Bt loads (mostly L2 hits: the row blocks of a split share them)
+  // two ahead through two; while the matrix cores take stage k (pieces from
+  // the previous step, Bt pieces in LDS buffer k % 2), the vector unit splits
+  // stage k + 1's X and stages its Bt into the other buffer. The loop is
+  // unrolled by four so that every slot index is a constant.
+  const int64_t K = t1 - t0;
+  fv4 xs[4][4], bsl[2][BU];
+  bf16x8 apc[2][2][NP];
+  auto step = [&](int64_t k, auto sc) {
+    constexpr int sl = decltype(sc)::value, cur = sl & 1, nxt = cur ^ 1;
+    xload(t0 + k + 4, xs[sl]);
+    bload(t0 + k + 2, bsl[cur]);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(cur, apc[cur]);
+    prep(xs[(sl + 1) & 3], apc[nxt], k + 1 < K);
+    lstore(nxt, bsl[nxt]);
+    // issue order: the first pair of j tiles' piece reads, then the stage's
+    // products, each followed by two vector instructions (the next stage's
+    // split); the later piece reads go where their products need them
+    constexpr int FIRST_READS = NP * (NJ < 2 ? NJ : 2), NMFMA = PR::N * 2 * NJ;
+    __builtin_amdgcn_sched_group_barrier(0x100, FIRST_READS, 0);
+#pragma unroll
+    for (int i = 0; i < NMFMA; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
+    }
+    lds_barrier();
+  };
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
+  using S2 = std::integral_constant<int, 2>;
+  using S3 = std::integral_constant<int, 3>;
+  if (K > 0) {
+    xload(t0, xs[0]);
+    bload(t0, bsl[0]);
+    xload(t0 + 1, xs[1]);
+    bload(t0 + 1, bsl[1]);
+    xload(t0 + 2, xs[2]);
+    xload(t0 + 3, xs[3]);
+    prep(xs[0], apc[0], true);
+    lstore(0, bsl[0]);
+    lds_barrier();
+    int64_t k = 0;
+    for (; k + 4 <= K; k += 4) {
+      step(k, S0{});
+      step(k + 1, S1{});
+      step(k + 2, S2{});
+      step(k + 3, S3{});
+    }
+    if (k < K) step(k, S0{});
+    if (k + 1 < K) step(k + 1, S1{});
+    if (k + 2 < K) step(k + 2, S2{});
+  }
+  if constexpr (NORM) {
+    // fixed order: a butterfly over the lanes, then the two waves of each
+    // 64-row half in index order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nacc += __shfl_xor(nacc, o, 64);
+    if (lane == 0) nred[wave] = nacc;
+    __syncthreads();
+    if (tid < 2) {
+      const int64_t b64 = 2 * (int64_t)rb + tid;
+      if (b64 < nslots) npart[(int64_t)split * nslots + b64] = nred[2 * tid] + nred[2 * tid + 1];
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < NJ; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = r0 + 16 * h + 4 * g + v;
+        const int col = 16 * u + mm;
+        if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[h][u][v];
+      }
 }
 
 // ---------------------------------------------------------------------------
@@ -611,17 +852,11 @@ static hipError_t cr_launch(const View3& v, const void* X, const void* Bt, int l
   int64_t nsteps, spp;
   int nrb;
   cr_geom(prec, v, &nsteps, &spp, &nrb);
-  if (MK == MF_S3 && v.S > 1) {  // stages of the split's own width
-    spp = (v.S + LdsPol<MK>::KT - 1) / LdsPol<MK>::KT;
-    nsteps = v.P * spp;
-  }
   const unsigned blocks = (unsigned)(((nsplit + 7) / 8) * 8 * nrb);
   const int64_t m = v.P * v.S;
   if (v.S == 1) {
-    if constexpr (MK == MF_S3) return hipErrorInvalidValue;  // the split runs the staged kernel only
-    else
-      TK_LAUNCH((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l,
-                nsteps, nsplit, nrb, (PT*)part);
+    TK_LAUNCH((k_cr_cols<MK, NJ>), dim3(blocks), dim3(256), 0, st, (const T*)X, (const T*)Bt, v.P, v.n, l, nsteps,
+              nsplit, nrb, (PT*)part);
   } else {
     constexpr int VE = 16 / (int)sizeof(T);
     const int edge = v.S % LdsPol<MK>::KT == 0 ? 0 : (v.S % VE == 0 ? 1 : 2);
@@ -648,6 +883,46 @@ static hipError_t cr_dispatch(const View3& v, const void* X, const void* Bt, int
   }
 }
 
+// FP32 storage through k_cr_split (S > 1): NP = 3 pieces (FP32 products) or
+// 1 (BF16 operands). Stages of 32 columns, 128-row workgroups; the split
+// count (and so the partial layout) is the one colreduce_splits_prec gives.
+template <int NP, int NJ>
+static hipError_t crs_launch(const View3& v, const void* X, const void* Bt, int l, void* part, int nsplit,
+                             double* npart, hipStream_t st) {
+  constexpr int KT = 32;
+  const int64_t spp = (v.S + KT - 1) / KT, nsteps = v.P * spp;
+  const int nrb = (int)((v.n + 127) / 128), nslots = (int)((v.n + 63) / 64);
+  const unsigned blocks = (unsigned)(((nsplit + 7) / 8) * 8 * nrb);
+  const int64_t m = v.P * v.S;
+  const int edge = v.S % KT == 0 ? 0 : (v.S % 4 == 0 ? 1 : 2);
+#define TK_CRS(E, NM)                                                                                              \
+  TK_LAUNCH((k_cr_split<NP, NJ, E, NM>), dim3(blocks), dim3(256), 0, st, (const float*)X, (const float*)Bt, v.n, \
+            v.S, l, m, spp, nsteps, nsplit, nrb, nslots, (float*)part, npart)
+  if (npart != nullptr) {
+    if (edge == 0) TK_CRS(0, true);
+    else if (edge == 1) TK_CRS(1, true);
+    else TK_CRS(2, true);
+  } else {
+    if (edge == 0) TK_CRS(0, false);
+    else if (edge == 1) TK_CRS(1, false);
+    else TK_CRS(2, false);
+  }
+#undef TK_CRS
+  return hipGetLastError();
+}
+
+template <int NP>
+static hipError_t crs_dispatch(const View3& v, const void* X, const void* Bt, int l, void* part, int nsplit,
+                               double* npart, hipStream_t st) {
+  switch ((l + 15) / 16) {
+    case 1: return crs_launch<NP, 1>(v, X, Bt, l, part, nsplit, npart, st);
+    case 2: return crs_launch<NP, 2>(v, X, Bt, l, part, nsplit, npart, st);
+    case 3: return crs_launch<NP, 3>(v, X, Bt, l, part, nsplit, npart, st);
+    case 4: return crs_launch<NP, 4>(v, X, Bt, l, part, nsplit, npart, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 int colreduce_norm_slots(const View3& v, int nsplit) {
   return v.S > 1 ? nsplit * (int)((v.n + 63) / 64) : 0;
 }
@@ -660,9 +935,10 @@ hipError_t launch_colreduce(tucker_precision prec, const View3& v, const void* X
   switch (prec) {
     case TUCKER_FP64: return cr_dispatch<MF_F64>(v, X, Bt, l, part, nsplit, npart, st);
     case TUCKER_FP32:
-      return v.S > 1 && fp32_split_products() ? cr_dispatch<MF_S3>(v, X, Bt, l, part, nsplit, npart, st)
-                                        : cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, npart, st);
-    case TUCKER_BF16: return cr_dispatch<MF_BF16>(v, X, Bt, l, part, nsplit, npart, st);
+      return v.S > 1 && fp32_split_products() ? crs_dispatch<3>(v, X, Bt, l, part, nsplit, npart, st)
+                                              : cr_dispatch<MF_F32>(v, X, Bt, l, part, nsplit, npart, st);
+    case TUCKER_BF16:  // the LDS-staged kernel: its 256-byte row runs read HBM faster here
+      return cr_dispatch<MF_BF16>(v, X, Bt, l, part, nsplit, npart, st);
   }
   return hipErrorInvalidValue;
 }
@@ -926,128 +1202,184 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
   rc_rows_body<MK, NJ, WVEC, KSPLIT>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, out, osp, osj, (int)blockIdx.x);
 }
 
-// Row contraction, S > 1, FP32 storage through the split (W j-major, whole
-// tiles of rows): the layout of k_rc_rows (64 output columns per wave as 4
-// interleaved 16-row tiles, NJ j tiles), with batches of 32 rows: k index
-// 8 g + q (lane group g, q < 8) is row i0 + 8 g + q for X and W alike. A
-// batch is split into pieces as soon as it arrives, which frees its raw
-// registers for the next batch's loads, issued before this batch's MFMAs.
-// WVEC: W j-major (wsi = 1), a lane's 8 rows are two 16-byte loads; otherwise
-// element loads at stride wsi.
-template <int NJ, bool WVEC>
-__global__ __launch_bounds__(256) void k_rc_rows_s3(const float* __restrict__ X, const float* __restrict__ W,
-                                                    int64_t n, int64_t S, int lw, int64_t wsi, int64_t wsj,
-                                                    int64_t tiles_per_p, int64_t ntiles, float* __restrict__ out,
-                                                    int64_t osp, int64_t osj) {
-  const int lane = threadIdx.x & 63, wave = wave_id();
+// ---------------------------------------------------------------------------
+// Row contraction, S > 1, FP32 storage on the BF16 matrix cores (NP as for
+// k_cr_split): out(p, j, s) = sum_i X[p, i, s] W(i, j), W(i, j) =
+// W[i * wsi + j * wsj]. Each wave owns a 32-column tile of one p (2
+// interleaved 16-row tiles: tile t, result row dr -> column s0 + 2 dr + t;
+// a lane reads 8 bytes of each row, a row's 128 bytes per instruction), 4
+// waves per workgroup, all n rows in batches of 32: k slot 8 g + q is row
+// i0 + 8 g + q for X and W alike. A batch of W (32 rows x 16 NJ columns) is
+// read by the whole workgroup, converted once into BF16 pieces and kept in
+// LDS (double buffered), where all four waves read it; each wave converts
+// its own X. The next batch's loads go out before the current batch's
+// products. A partial batch (n not a multiple of 32) is taken first, with
+// guarded loads; the full batches follow with unconditional ones. Waves past
+// the last tile work on the last tile (their loads stay in bounds and they
+// take part in the barriers) and write nothing. The small per-wave state
+// (two tiles) keeps three waves on each SIMD.
+// WVEC: W contiguous along i (wsi = 1), a unit's 8 rows are two 16-byte loads.
+// ---------------------------------------------------------------------------
+constexpr int RCS_COLS = 32;  // output columns s per wave
+
+typedef float f2u_t __attribute__((ext_vector_type(2), aligned(4)));
+
+template <int NP, int NJ, bool WVEC>
+__global__ __launch_bounds__(256) void k_rc_split(const float* __restrict__ X, const float* __restrict__ W, int64_t n,
+                                                  int64_t S, int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
+                                                  int64_t ntiles, float* __restrict__ out, int64_t osp, int64_t osj) {
+  constexpr int LS = 32 + 8;  // padded LDS row (BF16 elements)
+  using PR = BfProducts<NP>;
+  __shared__ __align__(16) __bf16 ws[2][NP][16 * NJ][LS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
-  const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
-  if (tile >= ntiles) return;  // whole waves; no barrier follows
+  const int64_t traw = (int64_t)blockIdx.x * 4 + wave;
+  const bool live = traw < ntiles;
+  const int64_t tile = live ? traw : ntiles - 1;
   const int64_t p = tile / tiles_per_p;
-  const int64_t s0 = (tile - p * tiles_per_p) * 64;
-  const float* xp = X + p * n * S + s0 + 4 * mm;
-  const float* wr[NJ];
+  const int64_t s0 = (tile - p * tiles_per_p) * RCS_COLS;
+  const float* xp = X + p * n * S;
+  const int64_t sc = s0 + 2 * mm;  // the lane's 2 columns
+  // this thread's W unit: column tid / 4 (clamped: columns past lw feed only
+  // outputs that are never written), rows 8 (tid % 4) .. + 7 of the batch;
+  // threads past 64 NJ load a clamped unit and store nothing
+  const int wj = tid >> 2, wq = tid & 3;
+  const bool wunit = wj < 16 * NJ;
+  const float* wcol = W + (int64_t)min(wj, lw - 1) * wsj;
+  const int64_t nfull = n / 32;
+  const bool tail = n % 32 != 0;
+
+  floatx4 acc[2][NJ];
 #pragma unroll
-  for (int u = 0; u < NJ; ++u) wr[u] = W + (int64_t)min(16 * u + mm, lw - 1) * wsj + 8 * g * wsi;
-  floatx4 acc[4][NJ];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int u = 0; u < NJ; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  float xr[8][2];  // X of a batch: rows i0 + 8 g + q, columns sc, sc + 1
+  float wr[8];     // the W unit of a batch
 
-  float xa[8][4], wa[NJ][8];
-  // interior batch: unconditional 16-byte loads
-  auto ffetch = [&](int64_t i0) {
-    const float* xr = xp + (i0 + 8 * g) * S;
+  // GUARD: rows at or past n read as zero (the partial batch)
+  auto wload = [&](int64_t i0, auto guard_c) {
+    constexpr bool GUARD = decltype(guard_c)::value;
+    const int64_t ib = i0 + 8 * wq;
+    if constexpr (WVEC && !GUARD) {
+      const f4u_t v0 = *reinterpret_cast<const f4u_t*>(wcol + ib);
+      const f4u_t v1 = *reinterpret_cast<const f4u_t*>(wcol + ib + 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        wr[e] = v0[e];
+        wr[4 + e] = v1[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t i = ib + e;
+        const float v = wcol[(GUARD ? min<int64_t>(i, n - 1) : i) * wsi];
+        wr[e] = (!GUARD || i < n) ? v : 0.f;
+      }
+    }
+  };
+  auto wstore = [&](int buf) {
+    if (!wunit) return;
+    bf16x8 pc[NP];
+    bf_pieces<NP>(wr, pc);
+#pragma unroll
+    for (int c = 0; c < NP; ++c) *reinterpret_cast<bf16x8*>(&ws[buf][c][wj][8 * wq]) = pc[c];
+  };
+  // WIDE: the tile's columns lie inside the row (else columns at or past S
+  // read as zero, element by element)
+  auto xload = [&](int64_t i0, auto guard_c, auto wide_c) {
+    constexpr bool GUARD = decltype(guard_c)::value, WIDE = decltype(wide_c)::value;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const f4u_t v = *reinterpret_cast<const f4u_t*>(xr + q * S);
-      xa[q][0] = v[0];
-      xa[q][1] = v[1];
-      xa[q][2] = v[2];
-      xa[q][3] = v[3];
-    }
-#pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      if constexpr (WVEC) {
-        const f4u_t v0 = *reinterpret_cast<const f4u_t*>(wr[u] + i0);
-        const f4u_t v1 = *reinterpret_cast<const f4u_t*>(wr[u] + i0 + 4);
-        wa[u][0] = v0[0];
-        wa[u][1] = v0[1];
-        wa[u][2] = v0[2];
-        wa[u][3] = v0[3];
-        wa[u][4] = v1[0];
-        wa[u][5] = v1[1];
-        wa[u][6] = v1[2];
-        wa[u][7] = v1[3];
+      const int64_t i = i0 + 8 * g + q;
+      const int64_t ir = GUARD ? min<int64_t>(i, n - 1) : i;
+      const bool rin = !GUARD || i < n;
+      const float* rp = xp + ir * S;
+      if constexpr (WIDE) {
+        const f2u_t v = *reinterpret_cast<const f2u_t*>(rp + sc);
+        xr[q][0] = rin ? v[0] : 0.f;
+        xr[q][1] = rin ? v[1] : 0.f;
       } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) wa[u][q] = wr[u][(i0 + q) * wsi];
+        for (int e = 0; e < 2; ++e) {
+          const int64_t c = sc + e;
+          const float v = rp[min<int64_t>(c, S - 1)];
+          xr[q][e] = (rin && c < S) ? v : 0.f;
+        }
       }
     }
   };
-  // guarded batch: rows at or past n and columns at or past S read as zero
-  const int scnt = (int)max<int64_t>(0, min<int64_t>(4, S - (s0 + 4 * mm)));
-  auto gfetch = [&](int64_t i0) {
-    const int64_t ib = i0 + 8 * g;
-    const int icnt = (int)max<int64_t>(0, min<int64_t>(8, n - ib));
+  auto prep = [&](bf16x8 (&ap)[2][NP]) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) load_n<float, 4>(xp + (ib + q) * S, q < icnt ? scnt : 0, xa[q]);
-#pragma unroll
-    for (int u = 0; u < NJ; ++u) {
-      if constexpr (WVEC) {
-        load_n<float, 8>(wr[u] + i0, icnt, wa[u]);
-      } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) wa[u][q] = q < icnt ? wr[u][(i0 + q) * wsi] : 0.f;
-      }
-    }
-  };
-  bf16x8 ap[4][3], bp[NJ][3];
-  auto split_batch = [&]() {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < 2; ++t) {
       float col[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) col[q] = xa[q][t];
-      split3(col, ap[t]);
+      for (int q = 0; q < 8; ++q) col[q] = xr[q][t];
+      bf_pieces<NP>(col, ap[t]);
     }
-#pragma unroll
-    for (int u = 0; u < NJ; ++u) split3(wa[u], bp[u]);
   };
-  // the six products, each pass over all tiles before the next (16 MFMAs
-  // between two that share an accumulator)
-  auto compute = [&]() {
-    constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+  // the batch's products, two j tiles at a time (four independent chains)
+  auto mma = [&](int buf, const bf16x8 (&ap)[2][NP]) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k)
+    for (int u0 = 0; u0 < NJ; u0 += 2) {
+      bf16x8 bp[2][NP];
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
+      for (int uu = 0; uu < 2; ++uu)
+        if (u0 + uu < NJ)
 #pragma unroll
-        for (int u = 0; u < NJ; ++u) acc[t][u] = mfma_bf16(ap[t][PA[k]], bp[u][PB[k]], acc[t][u]);
-  };
-
-  const bool wide = s0 + 64 <= S;
-  const int64_t nb = wide ? n / 32 : 0;  // interior batches
-  if (nb > 0) {
-    const int64_t last = (nb - 1) * 32;
-    ffetch(0);
-    for (int64_t b = 0; b < nb; ++b) {
-      split_batch();
-      __builtin_amdgcn_sched_barrier(0);
-      // the next batch (the last one again past the end: never split)
-      ffetch(min<int64_t>((b + 1) * 32, last));
-      __builtin_amdgcn_sched_barrier(0);
-      compute();
-      __builtin_amdgcn_sched_barrier(0);
+          for (int c = 0; c < NP; ++c)
+            bp[uu][c] = *reinterpret_cast<const bf16x8*>(&ws[buf][c][16 * (u0 + uu) + mm][8 * g]);
+#pragma unroll
+      for (int k = 0; k < PR::N; ++k)
+#pragma unroll
+        for (int uu = 0; uu < 2; ++uu)
+          if (u0 + uu < NJ)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+              acc[t][u0 + uu] = mfma_bf16(ap[t][PR::A[k]], bp[uu][PR::B[k]], acc[t][u0 + uu]);
     }
-  }
-  for (int64_t i0 = nb * 32; i0 < n; i0 += 32) {
-    gfetch(i0);
-    split_batch();
-    compute();
-  }
-  // tile t, result row dr = 4 g + v -> column s0 + 4 dr + t, output row j
+  };
+  using tru = std::integral_constant<bool, true>;
+  using fal = std::integral_constant<bool, false>;
+  auto run = [&](auto wide_c) {
+    bf16x8 ap[2][NP];
+    if (nfull == 0) {  // n < 32: one partial batch
+      wload(0, tru{});
+      wstore(0);
+      xload(0, tru{}, wide_c);
+      lds_barrier();
+      prep(ap);
+      mma(0, ap);
+      return;
+    }
+    // batch 0: the partial one when there is one, else full batch 0; batch
+    // k > 0: full batch k - 1 or k
+    if (tail) {
+      wload(32 * nfull, tru{});
+      xload(32 * nfull, tru{}, wide_c);
+    } else {
+      wload(0, fal{});
+      xload(0, fal{}, wide_c);
+    }
+    wstore(0);
+    lds_barrier();
+    const int64_t nb = nfull + (tail ? 1 : 0);
+    for (int64_t k = 0; k < nb; ++k) {
+      prep(ap);
+      // the next full batch (the last one again past the end: staged, never used)
+      const int64_t f = min<int64_t>(k + 1 - (tail ? 1 : 0), nfull - 1);
+      wload(32 * f, fal{});
+      xload(32 * f, fal{}, wide_c);
+      __builtin_amdgcn_sched_barrier(0);
+      mma((int)(k & 1), ap);
+      wstore((int)((k + 1) & 1));
+      lds_barrier();
+    }
+  };
+  if (s0 + RCS_COLS <= S) run(tru{});
+  else run(fal{});
+  if (!live) return;
+  // tile t, result row dr = 4 g + v -> column s0 + 2 dr + t, output row j
   float* op = out + p * osp;
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
@@ -1055,15 +1387,13 @@ __global__ __launch_bounds__(256) void k_rc_rows_s3(const float* __restrict__ X,
     if (j >= lw) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int64_t c = s0 + 4 * (4 * g + v);
+      const int64_t c = s0 + 2 * (4 * g + v);
       float* dst = op + (int64_t)j * osj + c;
-      if (c + 3 < S) {
-        const f4u_t o = {acc[0][u][v], acc[1][u][v], acc[2][u][v], acc[3][u][v]};
-        *reinterpret_cast<f4u_t*>(dst) = o;
-      } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (c + t < S) dst[t] = acc[t][u][v];
+      if (c + 1 < S) {
+        const f2u_t o = {acc[0][u][v], acc[1][u][v]};
+        *reinterpret_cast<f2u_t*>(dst) = o;
+      } else if (c < S) {
+        dst[0] = acc[0][u][v];
       }
     }
   }
@@ -1195,15 +1525,18 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     // split the rows while the tiles fill fewer than two rounds of the ~2048
     // resident waves (one partial round would leave most of the chip idle)
     const int ksplit = ntiles < 4096 ? 1 : 0;
-    if constexpr (MK == MF_F32) {
-      if (!ksplit && fp32_split_products()) {
-        const unsigned b = (unsigned)((ntiles + 3) / 4);
-#define TK_RC_S3(WV)                                                                                       \
-  TK_LAUNCH((k_rc_rows_s3<NJ, WV>), dim3(b), dim3(256), 0, st, (const float*)X, (const float*)W, v.n, v.S, \
-            lw, wsi, wsj, tpp, ntiles, (float*)out, osp, osj)
-        if (wvec) TK_RC_S3(true);
-        else TK_RC_S3(false);
-#undef TK_RC_S3
+    // FP32 storage on the BF16 matrix cores: split FP32 products, or BF16 operands
+    if constexpr (MK == MF_F32 || MK == MF_BF16) {
+      if (!ksplit && (MK == MF_BF16 || fp32_split_products())) {
+        constexpr int NP = MK == MF_BF16 ? 1 : 3;
+        const int64_t tpp2 = (v.S + RCS_COLS - 1) / RCS_COLS, nt2 = v.P * tpp2;
+        const unsigned b = (unsigned)((nt2 + 3) / 4);
+#define TK_RCS(WV)                                                                                          \
+  TK_LAUNCH((k_rc_split<NP, NJ, WV>), dim3(b), dim3(256), 0, st, (const float*)X, (const float*)W, v.n, v.S, \
+            lw, wsi, wsj, tpp2, nt2, (float*)out, osp, osj)
+        if (wvec) TK_RCS(true);
+        else TK_RCS(false);
+#undef TK_RCS
         return hipGetLastError();
       }
     }

@@ -21,8 +21,8 @@ import os
 import re
 
 CLASSES = {
-    "colreduce": r"tk::k_cr_(lds|cols)<",
-    "rowcontract": r"tk::k_rc_(rows|cols)(_s3)?<",
+    "colreduce": r"tk::k_cr_(lds|cols|split)<",
+    "rowcontract": r"tk::k_rc_(rows|cols|split)<",
     "powerstep": r"tk::k_power_fused<",
     # persistent batched kernels: the profiler may print them mangled
     "batched_colreduce": r"k_persist<tk::BCr(Lds|Cols),|k_persistINS_\d+BCr(Lds|Cols)E",

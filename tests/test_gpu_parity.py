@@ -984,3 +984,61 @@ def test_fp32_solve_at_split_sizes_matches_oracle(T, fp32_products):
     a32 = a.astype(np.float32)
     _compare_solve(_dev(a32, torch.float32), a32.astype(np.float64), (6, 8, 10), 6, 2, "adaptive", "st", "fp32",
                    seed=4, fp32_products=fp32_products)
+
+
+# Shapes that reach the BF16-matrix-core product kernels (FP32 split pieces and
+# BF16 operands) on their awkward paths: mode-k views [P, n, S] with a partial
+# 32-row batch or n < 32, 32-column tiles cut by S, S a multiple of 32, of 4
+# but not 32, and odd; sketch widths of one to four 16-column tiles. Each view
+# has at least 4096 tiles of 64 columns, so the row contraction takes the
+# split kernel (the column reduction takes it for any S > 1).
+_AWKWARD = [
+    ((4096, 33, 40), 1, 8), ((4096, 33, 40), 1, 33),
+    ((2048, 70, 67), 1, 24), ((2048, 70, 67), 1, 60),
+    ((1, 20, 270000), 1, 17),
+    ((100, 262208), 0, 60),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("dims,mode,l", _AWKWARD)
+def test_product_kernels_at_awkward_shapes(T, prec, dims, mode, l):
+    """Sketch, raw power step and core contraction against the oracle entry by
+    entry, each within its Cauchy-Schwarz scale: FP32 split pieces at the
+    FP32 tolerance; BF16 operands (each rounded with relative error at most
+    2^-9) within 2^-8 for one product, and for the power step within
+    2^-8 (2 + sqrt(n)), the bound for its second product run on a rounded
+    first one when X is Gaussian and Q has unit columns."""
+    g = gen.rng(21)
+    a = g.standard_normal(dims).astype(np.float32)
+    x = _dev(a, torch.float32)
+    xa = _np(x)
+    xk = unfold(xa, mode)
+    n = dims[mode]
+    one = TOL["fp32"] if prec == "fp32" else 2.0 ** -8
+    two = TOL["fp32"] if prec == "fp32" else 2.0 ** -8 * (2.0 + np.sqrt(n))
+    print("case", prec, dims, mode, l, flush=True)
+    # sketch
+    y = _np(T.sketch(x, mode, l, seed=9, precision=prec))
+    om = orc_rng.gaussian_omega(9, mode, xk.shape[1], l)
+    err = np.abs(y - orc.sketch(xa, mode, om)) / _row_col_scale(xk, om)
+    print("  sketch max err/scale %.3e" % err.max(), flush=True)
+    assert err.max() <= one
+    # raw power step (no shift)
+    q0 = np.linalg.qr(g.standard_normal((n, l)))[0]
+    q = _dev(q0, torch.float32)
+    qa = _np(q)
+    al = torch.zeros(1, dtype=torch.float64, device="cuda")
+    m = _np(T.shifted_power(x, mode, q, al, raw=True, precision=prec))
+    err = np.abs(m - orc.shifted_power(xa, mode, qa, 0.0)) / _power_scale(xk, qa, 0.0)
+    print("  power max err/scale %.3e" % err.max(), flush=True)
+    assert err.max() <= two
+    # core contraction (FP32 products for both: the BF16 path contracts on FP32 operands)
+    r = min(l, n)
+    u = _dev(q0[:, :r], torch.float32)
+    out = _np(T.core(x, mode, u, precision=prec))
+    ref = orc.core_step(xa, mode, _np(u))
+    ck = unfold(out, mode)
+    err = np.abs(ck - unfold(ref, mode)) / _row_col_scale(_np(u).T, xk)
+    print("  core max err/scale %.3e" % err.max(), flush=True)
+    assert err.max() <= TOL["fp32"]
