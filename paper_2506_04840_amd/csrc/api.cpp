@@ -1075,7 +1075,7 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
       b->Qin = role == 0 ? w.y64 : ows.Qa;
       b->part_in = role == 1 ? p1 : p0;
       b->Qout = ows.Qa;
-      b->qt = role == 0 ? nullptr : w.qt;
+      b->qt = w.qt;
       b->part_out = role == 0 ? p1 : (role == 1 ? p0 : nullptr);
       b->Rg = ows.R + (size_t)role * TUCKER_MAX_L * TUCKER_MAX_L;
       b->defic = ows.defic + role * TUCKER_MAX_L;
@@ -1220,7 +1220,7 @@ int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X,
   double* y = raw ? (double*)out : w.y64;
   hipError_t e;
   int ns_used = nsplit;
-  if (power_fused_splits(v, (int)l, prec) > 0 && v.n <= m) {
+  if (power_fused_launch_splits(v, (int)l, prec) > 0 && v.n <= m) {
     // the fused pass reads Q j-major: transposed into the space of Z, which it does not use
     const OrthWs ows = carve_orth(w.orth, v.n, (int)l);
     e = launch_transpose_f32((const float*)Q, v.n, (int)l, (float*)w.omz, stream);

@@ -9,9 +9,12 @@
 //           CholeskyQR on Y D^-1 (s = 11 (n l + l (l+1)) u ||Y D^-1||_F^2,
 //           Fukaya et al. 2020). For FP32 / BF16 products there is no shift;
 //           a pivot below their rounding level marks the column dependent.
-//   pass 2  R2 = chol(Q1^T Q1), Q2 = Q1 R2^-1
+//   pass 2  R2 = chol(Q1^T Q1), Q2 = Q1 R2^-1, skipped (R2 = I) when Q1^T Q1
+//           is already I to 1e-13 (FP64) / 1e-10 (FP32, BF16): the common
+//           case for a power step's iterate, whose columns arrive turned to
+//           the previous step's singular vectors, nearly orthogonal
 //   pass 3  R3 = chol(Q2^T Q2), Q3 = Q2 R3^-1, skipped (R3 = I) when Q2^T Q2
-//           is already I to 1e-13 (FP64) / 1e-10 (FP32, BF16)
+//           is already I to the same level, or when pass 2 was skipped
 //   R = R3 R2 R1 (so Y = Q3 R); one-sided Jacobi on R^T: R^T J = B with
 //   orthogonal columns, hence R = J diag(|B_j|) (B/|B|)^T and the left
 //   singular vectors of Y are Q3 J. Columns sorted by descending Sigma.
@@ -234,15 +237,17 @@ __global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n,
 }
 
 // One CholeskyQR pass over 64 rows per block (role 0: pass 1, scaled and
-// shifted by shift_scale * trace; role 1: pass 2; role 2: pass 3, which
-// leaves at once when W is I to eps3).
+// shifted by shift_scale * trace; role 1: pass 2 and role 2: pass 3, each of
+// which leaves at once when W is I to eps3, recording that in status[3] and
+// status[2]; pass 3 also leaves when pass 2 did, since then its partials
+// were never written).
 //   W = sum_b part_in[b] (scaled and shifted for role 0); R = chol(W) with
 //   deficiency flags; Qout rows = Qin rows R^-1 (deficient columns: random
 //   direction / sqrt(n)); part_out[blk] = Gram of this block's Qout rows.
 // Qout may alias Qin (each block reads its rows before writing them).
 // Block 0 writes R (role 0: R~ D) and the flags for the small SVD.
-// Passes 2 and 3 also write Q j-major in the storage precision to qt (when
-// not null).
+// Every pass that runs also writes Q j-major in the storage precision to qt
+// (when not null): the last one that runs leaves the result.
 template <int LP>
 __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, const double* __restrict__ part_in,
                                               int nblk, int role, double tau, double shift_scale, double eps3,
@@ -262,6 +267,10 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
 
   const int tid = threadIdx.x;
   const int ta = tid >> 4, tb = tid & 15;
+  if (role == 2 && status[3] != 0) {  // pass 2 left: Q1 is the result
+    if (bid == 0 && tid == 0) status[2] = 1;
+    return;
+  }
   if (tid == 0) {
     flag_s = 0;
     far_s = 0;
@@ -315,10 +324,10 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
   }
   __syncthreads();
   const bool anybad = flag_s != 0;
-  // pass 3: when Q2^T Q2 is already I to eps3, Q2 is the result (R3 = I);
-  // every block sees the same sums and leaves together
-  if (role == 2 && far_s == 0 && !anybad) {
-    if (bid == 0 && tid == 0) status[2] = 1;
+  // passes 2 and 3: when the input's Gram is already I to eps3, the input is
+  // the result (R = I); every block sees the same sums and leaves together
+  if (role >= 1 && far_s == 0 && !anybad) {
+    if (bid == 0 && tid == 0) status[role == 1 ? 3 : 2] = 1;
     return;
   }
   if (role == 0) {
@@ -485,9 +494,9 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
       }
     }
   }
-  // passes 2 and 3 write Q in the storage precision (pass 3, when it runs,
-  // overwrites what pass 2 wrote)
-  const bool emit = role >= 1;
+  // every pass that runs writes Q in the storage precision (a later pass
+  // overwrites what an earlier one wrote)
+  const bool emit = true;
 
   // 3. solve z R = y for the block's 64 rows: 4 lanes per row (one quad), lane
   //    t holds columns t + 4 m in registers; column j's value comes from its
@@ -636,8 +645,9 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
   const int tid = threadIdx.x;
   const int ta = tid >> 4, tb = tid & 15;
   const int lp = (l + 1) & ~1;
-  const bool three = status[2] == 0;
-  // J <- R1, A <- R2; c = A J; then (pass 3 ran) J <- c, A <- R3, c = A J
+  const bool two = status[3] == 0, three = status[2] == 0;  // pass 3 runs only after pass 2
+  // J <- R1, A <- R2; c = A J (R1 when pass 2 was skipped); then (pass 3
+  // ran) J <- c, A <- R3, c = A J
   for (int e = tid; e < kMaxL * kMaxL; e += 256) {
     const int r = e >> 6, x = e & 63;
     J[r][x] = (r < l && x < l) ? Rg[r * l + x] : 0.0;
@@ -645,7 +655,14 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
   }
   __syncthreads();
   double c[4][4];
-  tile_matmul(A, J, l, c);
+  if (two) {
+    tile_matmul(A, J, l, c);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c[i][j] = J[ta + 16 * i][tb + 16 * j];
+  }
   if (three) {
     __syncthreads();
 #pragma unroll
@@ -857,14 +874,15 @@ static void orth_passes(int64_t n, int l, double* Y, const double* Wrot, tucker_
   // the shift of pass 1 (FP64 only; the FP32 / BF16 threshold already keeps
   // every accepted pivot far above rounding)
   const double shift1 = prec == TUCKER_FP64 ? 11.0 * ((double)n * l + (double)l * (l + 1)) * 1.1102230246251565e-16 : 0.0;
-  // pass 3 is skipped when Q2 is orthonormal to this (it only re-orthogonalises)
+  // passes 2 and 3 are skipped when their input is orthonormal to this (they
+  // only re-orthogonalise)
   const double eps3 = prec == TUCKER_FP64 ? 1e-13 : 1e-10;
   const uint32_t tag = 0x100u + 16u * (uint32_t)step;
   hipLaunchKernelGGL((k_gram<LP>), dim3(nblk), dim3(256), 0, st, Y, n, l, Wrot, p0, ws.status);
   hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)Y, n, l, (const double*)p0, nblk, 0,
-                     tau1, shift1, 0.0, cseed, tag + 1, ws.Qa, (void*)nullptr, 0, p1, ws.R, ws.defic, ws.status);
+                     tau1, shift1, 0.0, cseed, tag + 1, ws.Qa, qt, qt_f64, p1, ws.R, ws.defic, ws.status);
   hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)ws.Qa, n, l, (const double*)p1, nblk,
-                     1, tau, 0.0, 0.0, cseed, tag + 2, ws.Qa, qt, qt_f64, p0, ws.R + kMaxL * kMaxL, ws.defic + kMaxL,
+                     1, tau, 0.0, eps3, cseed, tag + 2, ws.Qa, qt, qt_f64, p0, ws.R + kMaxL * kMaxL, ws.defic + kMaxL,
                      ws.status);
   hipLaunchKernelGGL((k_pass<LP>), dim3(nblk), dim3(256), 0, st, (const double*)ws.Qa, n, l, (const double*)p0, nblk,
                      2, tau, 0.0, eps3, cseed, tag + 3, ws.Qa, qt, qt_f64, (double*)nullptr, ws.R + 2 * kMaxL * kMaxL,

@@ -1825,6 +1825,17 @@ int power_fused_splits(const View3& v, int l, tucker_precision prec) {
   return (int)((nblocks + rounds - 1) / rounds);
 }
 
+// The one-pass kernel forms its products with FP32 instructions. Where FP32
+// products go through the BF16 split and n <= 256 (one row group per wave,
+// blocks too small to keep the FP32 matrix cores busy; measured at n = 120:
+// 3.36 -> 3.23 ms per 120^4 solve), the two split kernels are faster despite
+// their second pass over X; at n = 400 the one-pass kernel still wins (2.23
+// against 2.40 ms per 400^3 solve). The partial layout is sized for both
+// (power_fused_part_bytes does not depend on this choice).
+int power_fused_launch_splits(const View3& v, int l, tucker_precision prec) {
+  return (fp32_split_products() && v.n <= 256) ? 0 : power_fused_splits(v, l, prec);
+}
+
 size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec) {
   return (size_t)power_fused_splits(v, l, prec) * v.n * l * sizeof(float);
 }
@@ -1853,8 +1864,9 @@ static void pf_dispatch(const View3& v, const float* X, const float* Qt, int l, 
 hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
                                  void* z, void* part, int nsplit, int* ctr, int* fused_count, int* nsplit_used,
                                  hipStream_t st, int* err) {
-  const int G = power_fused_splits(v, l, prec);
+  const int G = power_fused_launch_splits(v, l, prec);
   if (G == 0) {
+    if (z == nullptr) return hipErrorInvalidValue;  // the two-kernel path needs Z's space
     *nsplit_used = nsplit;
     hipError_t e = launch_rowcontract(prec, v, X, qt, 1, v.n, l, z, true, st);
     if (e == hipSuccess) e = launch_colreduce(prec, v, X, z, l, part, nsplit, st);

@@ -239,18 +239,24 @@ def test_products_at_unaligned_addresses(T, prec, dims, mode, l):
 
 # --------------------------------------------------------------- svd econ
 
-def _matrix_with_spectrum(n, l, s, seed):
+def _matrix_with_spectrum(n, l, s, seed, turn=True):
     g = gen.rng(seed)
     u = np.linalg.qr(g.standard_normal((n, l)))[0]
-    v = np.linalg.qr(g.standard_normal((l, l)))[0]
+    v = np.linalg.qr(g.standard_normal((l, l)))[0] if turn else np.eye(l)
     return (u * s[None, :]) @ v.T
 
 
+# "orthogonal": columns already orthogonal with graded lengths (the shape of a
+# power step's turned iterate without a shift), so the scaled first pass is
+# orthonormal to rounding and the second and third passes leave at once
 @pytest.mark.parametrize("n,l,kind", [(60, 15, "flat"), (400, 40, "graded"), (1000, 60, "graded"), (130, 64, "flat"),
                                       (77, 33, "severe"), (256, 40, "deficient"), (50, 50, "graded"),
-                                      (90, 20, "zero_tail")])
+                                      (90, 20, "zero_tail"), (400, 40, "orthogonal"), (1000, 60, "orthogonal"),
+                                      (60, 15, "orthogonal")])
 def test_orth_matches_lapack(T, n, l, kind):
-    if kind == "flat":
+    if kind == "orthogonal":
+        s = np.logspace(0, -6, l)
+    elif kind == "flat":
         s = np.linspace(2.0, 1.0, l)
     elif kind == "graded":
         s = np.logspace(0, -6, l)
@@ -260,7 +266,7 @@ def test_orth_matches_lapack(T, n, l, kind):
         s = np.concatenate([np.logspace(0, -3, l - 7), np.zeros(7)])
     else:
         s = np.concatenate([np.logspace(0, -2, l - 3), np.zeros(3)])
-    y = _matrix_with_spectrum(n, l, s, seed=n + l)
+    y = _matrix_with_spectrum(n, l, s, seed=n + l, turn=kind != "orthogonal")
     q, sig = T.orth(_dev(y, torch.float64), "fp64")
     q, sig = _np(q), _np(sig)
     s_ref = np.linalg.svd(y, compute_uv=False)
