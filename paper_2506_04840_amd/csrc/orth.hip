@@ -245,7 +245,8 @@ __global__ __launch_bounds__(256) void k_gram(double* __restrict__ Y, int64_t n,
 //   deficiency flags; Qout rows = Qin rows R^-1 (deficient columns: random
 //   direction / sqrt(n)); part_out[blk] = Gram of this block's Qout rows.
 // Qout may alias Qin (each block reads its rows before writing them).
-// Block 0 writes R (role 0: R~ D) and the flags for the small SVD.
+// The blocks write R between them (role 0: R~ D); block 0 the flags for the
+// small SVD.
 // Every pass that runs also writes Q j-major in the storage precision to qt
 // (when not null): the last one that runs leaves the result.
 template <int LP>
@@ -274,6 +275,19 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
   if (tid == 0) {
     flag_s = 0;
     far_s = 0;
+  }
+  // the block's rows of Qin, loaded first so that they arrive while W is
+  // summed and factored: 4 lanes per row (one quad), lane t holds columns
+  // t + 4 m (role 0 scales them once the exponents are known)
+  const int r = tid >> 2, t = tid & 3;
+  const int64_t r0 = (int64_t)bid * OR_RB;
+  const int64_t row = r0 + r;
+  double y[MW], z[MW];
+#pragma unroll
+  for (int m = 0; m < MW; ++m) {
+    const int b = t + 4 * m;
+    y[m] = (row < n && b < l) ? Qin[row * l + b] : 0.0;
+    z[m] = 0.0;
   }
 
   // 1. W in registers: thread owns W[ta + 16 i][tb + 16 j]; the partials are
@@ -362,12 +376,17 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
   }
 
   // 2. blocked right-looking Cholesky W = R^T R (R upper), panels of 4 rows
-  //    and one barrier per panel: the panel's rows of the trailing matrix are
-  //    published by their owners before the previous barrier (double
-  //    buffered); every thread factors the 4 x 4 diagonal block itself (the
-  //    same arithmetic everywhere), forms the panel rows of R at the columns
-  //    it owns and applies the rank-4 update.
+  //    and two barriers per panel. The panel's rows of the trailing matrix are
+  //    published by their owners before the panel starts (double buffered).
+  //    Phase A: the lanes of wave 0 (lane c < LP owns column c) factor the
+  //    4 x 4 diagonal block (the same arithmetic in every lane) and form the
+  //    panel rows of R at their column, into LDS. Phase B: every thread reads
+  //    the panel rows at its rows and columns and applies the rank-4 update
+  //    to the entries it owns, then publishes the next panel's rows.
   constexpr int PW = 4;
+  __shared__ double rpan[PW][LP];  // the panel's rows of R (zero at and left of the diagonal)
+  __shared__ unsigned long long dmask_s;
+  __shared__ int ndef_s;
   if (ta < PW) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) pbuf[0][ta][tb + 16 * j] = W[0][j];
@@ -379,82 +398,71 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
   }
   if (tid >= l && tid < LP) inv_diag[tid] = 0.0;
   __syncthreads();
-  uint64_t dmask = 0;
+  uint64_t dmask = 0;  // kept by the lanes of phase A
   int ndef = 0;
   const int npan = (l + PW - 1) / PW;
   for (int pn = 0; pn < npan; ++pn) {
     const int k0 = PW * pn;
     const double (*buf)[LP] = pbuf[pn & 1];
-    // all loads of the panel first (one LDS round trip)
-    double xa[PW][NB], xb[PW][NB], dg[PW][PW], bv[PW];
-#pragma unroll
-    for (int q = 0; q < PW; ++q) {
-#pragma unroll
-      for (int i = 0; i < NB; ++i) xa[q][i] = buf[q][ta + 16 * i];
-#pragma unroll
-      for (int j = 0; j < NB; ++j) xb[q][j] = buf[q][tb + 16 * j];
-#pragma unroll
-      for (int c = 0; c < PW; ++c) dg[q][c] = buf[q][k0 + c];
-      bv[q] = buf[q][tid < LP ? tid : 0];
-    }
-    // diagonal block: pivots, inverse square roots, R[k0+q][k0+c]
-    double inv[PW], piv[PW], rd[PW][PW];
-#pragma unroll
-    for (int q = 0; q < PW; ++q) {
-      double pv = dg[q][q];
-#pragma unroll
-      for (int pp = 0; pp < q; ++pp) pv = fma(-rd[pp][q], rd[pp][q], pv);
-      const bool dep = !(pv > tau * maxdiag) || anybad;
-      inv[q] = dep ? 0.0 : rsq_nr(fmax(pv, 1e-300));
-      piv[q] = pv;
-      if (dep && k0 + q < l) {
-        dmask |= 1ull << (k0 + q);
-        ++ndef;
-      }
-#pragma unroll
-      for (int c = 0; c < PW; ++c) {
-        double v = dg[q][c];
-#pragma unroll
-        for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rd[pp][c], v);
-        rd[q][c] = c > q ? v * inv[q] : 0.0;
-      }
-    }
-    // panel rows of R at this thread's columns (zero at or left of the diagonal)
-    double ra[PW][NB], rb[PW][NB], rc[PW];
-#pragma unroll
-    for (int q = 0; q < PW; ++q) {
-      const int k = k0 + q;
-#pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        double v = xa[q][i];
-#pragma unroll
-        for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], ra[pp][i], v);
-        ra[q][i] = v * (ta + 16 * i > k ? inv[q] : 0.0);
-      }
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        double v = xb[q][j];
-#pragma unroll
-        for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rb[pp][j], v);
-        rb[q][j] = v * (tb + 16 * j > k ? inv[q] : 0.0);
-      }
-      double v = bv[q];
-#pragma unroll
-      for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rc[pp], v);
-      rc[q] = v * (tid > k && tid < l ? inv[q] : 0.0);
-    }
     if (tid < LP) {
+      // phase A, column c = tid
+      double dg[PW][PW], col[PW];
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c) dg[q][c] = buf[q][k0 + c];
+        col[q] = buf[q][tid];
+      }
+      // diagonal block: pivots, inverse square roots, R[k0+q][k0+c]
+      double inv[PW], piv[PW], rd[PW][PW];
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        double pv = dg[q][q];
+#pragma unroll
+        for (int pp = 0; pp < q; ++pp) pv = fma(-rd[pp][q], rd[pp][q], pv);
+        const bool dep = !(pv > tau * maxdiag) || anybad;
+        inv[q] = dep ? 0.0 : rsq_nr(fmax(pv, 1e-300));
+        piv[q] = pv;
+        const bool cnt = dep && k0 + q < l;
+        dmask |= cnt ? (1ull << (k0 + q)) : 0ull;
+        ndef += cnt ? 1 : 0;
+#pragma unroll
+        for (int c = 0; c < PW; ++c) {
+          double v = dg[q][c];
+#pragma unroll
+          for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rd[pp][c], v);
+          rd[q][c] = c > q ? v * inv[q] : 0.0;
+        }
+      }
+      // the panel rows of R at this column: R[k][c] for c > k, the diagonal
+      // R[k][k] = pv^(1/2) (0 when dependent), zero left of it
+      double rc[PW];
 #pragma unroll
       for (int q = 0; q < PW; ++q) {
         const int k = k0 + q;
+        double v = col[q];
+#pragma unroll
+        for (int pp = 0; pp < q; ++pp) v = fma(-rd[pp][q], rc[pp], v);
+        rc[q] = v * (tid > k && tid < l ? inv[q] : 0.0);
+        rpan[q][tid] = rc[q];
         Rp[k][tid & 3][tid >> 2] = tid == k ? piv[q] * inv[q] : rc[q];  // inv = 0 when dep
       }
-    }
-    if (tid < PW) {
-      double v = inv[0];
+      if (tid < PW) {
+        double v = inv[0];
 #pragma unroll
-      for (int q = 1; q < PW; ++q) v = tid == q ? inv[q] : v;
-      inv_diag[k0 + tid] = v;
+        for (int q = 1; q < PW; ++q) v = tid == q ? inv[q] : v;
+        inv_diag[k0 + tid] = v;
+      }
+    }
+    __syncthreads();
+    // phase B: rank-4 update of the entries this thread owns
+    double ra[PW][NB], rb[PW][NB];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) ra[q][i] = rpan[q][ta + 16 * i];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) rb[q][j] = rpan[q][tb + 16 * j];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i)
@@ -479,12 +487,21 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
     }
     __syncthreads();
   }
+  // the deficiency record of phase A, for every thread
+  if (tid == 0) {
+    dmask_s = dmask;
+    ndef_s = ndef;
+  }
+  __syncthreads();
+  dmask = dmask_s;
+  ndef = ndef_s;
+  // R to Rg: every block holds the same R, so the blocks share the copy
+  for (int e = tid + 256 * bid; e < l * l; e += 256 * nblk) {
+    const int a = e / l, b = e % l;
+    const double v = Rp[a][b & 3][b >> 2];
+    Rg[e] = role == 0 ? ldexp(v, esc[b]) : v;
+  }
   if (bid == 0) {
-    for (int e = tid; e < l * l; e += 256) {
-      const int a = e / l, b = e % l;
-      const double v = Rp[a][b & 3][b >> 2];
-      Rg[e] = role == 0 ? ldexp(v, esc[b]) : v;
-    }
     if (tid < l) defic_g[tid] = (int)((dmask >> tid) & 1ull);
     if (tid == 0) {
       if (anybad) atomicOr(&status[0], TUCKER_INFO_NONFINITE);
@@ -498,20 +515,12 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
   // overwrites what an earlier one wrote)
   const bool emit = true;
 
-  // 3. solve z R = y for the block's 64 rows: 4 lanes per row (one quad), lane
-  //    t holds columns t + 4 m in registers; column j's value comes from its
-  //    owner lane by a quad broadcast and updates the rest right-looking.
-  const int r = tid >> 2, t = tid & 3;
-  const int64_t r0 = (int64_t)bid * OR_RB;
-  const int64_t row = r0 + r;
-  double y[MW], z[MW];
+  // 3. solve z R = y for the block's 64 rows (the rows loaded at the start):
+  //    column j's value comes from its owner lane by a quad broadcast and
+  //    updates the rest right-looking.
+  if (role == 0) {
 #pragma unroll
-  for (int m = 0; m < MW; ++m) {
-    const int b = t + 4 * m;
-    double v = (row < n && b < l) ? Qin[row * l + b] : 0.0;
-    if (role == 0) v = ldexp(v, -esc[b]);
-    y[m] = v;
-    z[m] = 0.0;
+    for (int m = 0; m < MW; ++m) y[m] = ldexp(y[m], -esc[t + 4 * m]);
   }
   // A deficient column j has a zero row j in R (and inv_diag[j] = 0), so its
   // value never reaches later columns: the loop carries zero for it and the

@@ -958,7 +958,16 @@ __device__ __forceinline__ void reduce_splits_body(const PT* __restrict__ part, 
   double s = 0.0;
   if (e < nl) {
     const int s0 = (int)((int64_t)nsplit * sub / 8), s1 = (int)((int64_t)nsplit * (sub + 1) / 8);
-    for (int sp = s0; sp < s1; ++sp) s += (double)part[(int64_t)sp * nl + e];
+    // eight loads in flight, added in split order (the same sum as one by one)
+    int sp = s0;
+    for (; sp + 8 <= s1; sp += 8) {
+      PT v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = part[(int64_t)(sp + q) * nl + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += (double)v[q];
+    }
+    for (; sp < s1; ++sp) s += (double)part[(int64_t)sp * nl + e];
   }
   double t[8];
 #pragma unroll
