@@ -257,7 +257,7 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
                                               double* __restrict__ part_out, double* __restrict__ Rg,
                                               int* __restrict__ defic_g, int* __restrict__ status, int bid) {
   constexpr int NB = LP / 16, MW = LP / 4;
-  constexpr int PF = NB <= 3 ? 8 : 4;  // Gram partials in flight per thread
+  constexpr int PF = 8;  // Gram partials in flight per thread (one round trip per 8 blocks)
   __shared__ double Zs[OR_RB][OR_LS];
   __shared__ double Rp[LP][4][MW];     // Rp[j][t][m] = R[j][t + 4 m]
   __shared__ double pbuf[2][4][LP];    // panel rows of the trailing matrix
@@ -525,13 +525,28 @@ __device__ __forceinline__ void pass_body(const double* Qin, int64_t n, int l, c
   // A deficient column j has a zero row j in R (and inv_diag[j] = 0), so its
   // value never reaches later columns: the loop carries zero for it and the
   // completion direction is put in afterwards, off the dependency chain.
+  // Row j + 1 of R (this lane's columns) and its pivot inverse are read
+  // from LDS while step j runs, so no step waits for its own reads.
+  double rrow[MW], rnext[MW], inv_j = inv_diag[0], inv_n;
+#pragma unroll
+  for (int m = 0; m < MW; ++m) rrow[m] = Rp[0][t][m];
 #pragma unroll
   for (int j = 0; j < LP; ++j) {
     const int jt = j & 3, jm = j >> 2;
-    double zj = quad_bcast(y[jm] * inv_diag[j], jt);
+    if (j + 1 < LP) {
+      inv_n = inv_diag[j + 1];
+#pragma unroll
+      for (int m = (j + 1) >> 2; m < MW; ++m) rnext[m] = Rp[j + 1][t][m];
+    }
+    double zj = quad_bcast(y[jm] * inv_j, jt);
     z[jm] = t == jt ? zj : z[jm];
 #pragma unroll
-    for (int m = jm; m < MW; ++m) y[m] = fma(-zj, Rp[j][t][m], y[m]);
+    for (int m = jm; m < MW; ++m) y[m] = fma(-zj, rrow[m], y[m]);
+    if (j + 1 < LP) {
+      inv_j = inv_n;
+#pragma unroll
+      for (int m = (j + 1) >> 2; m < MW; ++m) rrow[m] = rnext[m];
+    }
   }
 #pragma unroll
   for (int m = 0; m < MW; ++m) Zs[r][t + 4 * m] = z[m];
