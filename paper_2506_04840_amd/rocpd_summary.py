@@ -1,12 +1,13 @@
 """Kernel summary (calls, total/avg/min/max us, share) of a rocprofv3 kernel trace.
 
-Reads a rocpd database (run_results.db) or a kernel-trace CSV
-(run_kernel_trace.csv). Persistent batched kernels are listed as
+Reads a rocpd database (run_results.db), a kernel-trace CSV
+(run_kernel_trace.csv) or the per-kernel statistics CSV that --stats writes
+(run_kernel_stats.csv: calls, total, min and max per kernel, no dispatches). Persistent batched kernels are listed as
 k_persist<Desc> (the profiler prints them mangled). The last block gives the
 product kernel classes (launch count and average duration), the figures the
 benchmark's launch-timing hooks report for the same classes.
 
-usage: python -m paper_2506_04840_amd.rocpd_summary <run_results.db | run_kernel_trace.csv> [top_n]
+usage: python -m paper_2506_04840_amd.rocpd_summary <run_results.db | run_kernel_trace.csv | run_kernel_stats.csv> [top_n]
 """
 import collections
 import csv
@@ -37,25 +38,44 @@ def _short(name):
     return name.split("(")[0]
 
 
+def _stats(path):
+    """(name, calls, total_ns, min_ns, max_ns) per kernel: aggregated from the
+    dispatches of a trace or database, or read from a --stats CSV."""
+    if path.endswith("kernel_stats.csv"):
+        for r in csv.DictReader(open(path)):
+            yield r["Name"], int(r["Calls"]), int(r["TotalDurationNs"]), int(r["MinNs"]), int(r["MaxNs"])
+        return
+    per = collections.defaultdict(list)
+    for name, dur in _rows(path):
+        per[name].append(dur)
+    for name, v in per.items():
+        yield name, len(v), sum(v), min(v), max(v)
+
+
 def main():
     path = sys.argv[1]
     top = int(sys.argv[2]) if len(sys.argv) > 2 else 30
-    agg = collections.defaultdict(list)
-    cls = collections.defaultdict(list)
-    for name, dur in _rows(path):
-        agg[_short(name)].append(dur)
+    agg = {}  # short name -> [calls, total, min, max]
+    cls = collections.defaultdict(lambda: [0, 0])
+    for name, calls, tot, lo, hi in _stats(path):
+        a = agg.setdefault(_short(name), [0, 0, lo, hi])
+        a[0] += calls
+        a[1] += tot
+        a[2] = min(a[2], lo)
+        a[3] = max(a[3], hi)
         for k, rx in CLASSES.items():
             if re.search(rx, name):
-                cls[k].append(dur)
-    total = sum(sum(v) for v in agg.values())
+                cls[k][0] += calls
+                cls[k][1] += tot
+    total = sum(v[1] for v in agg.values())
     print("%-70s %7s %12s %10s %10s %10s %6s" % ("kernel", "calls", "total_us", "avg_us", "min_us", "max_us", "pct"))
-    for name, v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
-        print("%-70s %7d %12.1f %10.2f %10.2f %10.2f %6.2f" % (name[:70], len(v), sum(v) / 1e3, sum(v) / len(v) / 1e3,
-                                                              min(v) / 1e3, max(v) / 1e3, 100.0 * sum(v) / total))
+    for name, (n, tot, lo, hi) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        print("%-70s %7d %12.1f %10.2f %10.2f %10.2f %6.2f" % (name[:70], n, tot / 1e3, tot / n / 1e3, lo / 1e3,
+                                                              hi / 1e3, 100.0 * tot / total))
     print()
     print("%-24s %7s %12s %10s" % ("kernel class", "calls", "total_us", "avg_us"))
-    for k, v in cls.items():
-        print("%-24s %7d %12.1f %10.2f" % (k, len(v), sum(v) / 1e3, sum(v) / len(v) / 1e3))
+    for k, (n, tot) in cls.items():
+        print("%-24s %7d %12.1f %10.2f" % (k, n, tot / 1e3, tot / n / 1e3))
 
 
 if __name__ == "__main__":
