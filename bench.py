@@ -307,7 +307,10 @@ def main():
         if mk == "fp32" and args.fp32_products == "split" and kern in ("colreduce", "rowcontract"):
             mk = "fp32-split"  # the large products of this class run as six BF16 products per pair
         roof = _roof_from_timing(tk, mk)
-        same = prec == CONFIGS[args.workload]["precision"] and cfg["ranks"] == CONFIGS[args.workload]["ranks"]
+        # the committed counters were taken on the workload's default command
+        # (default precision, ranks, q, order, test matrix and FP32 product mode)
+        same = prec == CONFIGS[args.workload]["precision"] and cfg["ranks"] == CONFIGS[args.workload]["ranks"] \
+            and args.fp32_products == "split" and args.omega == "gaussian"
         traffic = measured_traffic(kern, args.workload) \
             if same and order is None and not args.holistic and q == CONFIGS[args.workload]["q"] else None
         roof["traffic"] = traffic
