@@ -1213,7 +1213,7 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
 
 // ---------------------------------------------------------------------------
 // Row contraction, S > 1, FP32 storage on the BF16 matrix cores (NP as for
-// k_cr_split): out(p, j, s) = sum_i X[p, i, s] W(i, j), W(i, j) =
+// k_cr_split; taken from 1024 tiles of 32 columns): out(p, j, s) = sum_i X[p, i, s] W(i, j), W(i, j) =
 // W[i * wsi + j * wsj]. Each wave owns a 32-column tile of one p (2
 // interleaved 16-row tiles: tile t, result row dr -> column s0 + 2 dr + t;
 // a lane reads 8 bytes of each row, a row's 128 bytes per instruction), 4
@@ -1534,11 +1534,14 @@ static hipError_t rc_launch(const View3& v, const void* X, const void* W, int64_
     // split the rows while the tiles fill fewer than two rounds of the ~2048
     // resident waves (one partial round would leave most of the chip idle)
     const int ksplit = ntiles < 4096 ? 1 : 0;
-    // FP32 storage on the BF16 matrix cores: split FP32 products, or BF16 operands
+    // FP32 storage on the BF16 matrix cores: split FP32 products, or BF16
+    // operands. Its 32-column tiles keep the chip busy down to about 1024 tiles
+    // (50 x 1000 x 1000, mode 1: 1600 tiles, 135 -> 62 us against the FP32
+    // row-split kernel), where the 64-column kernels split the rows
     if constexpr (MK == MF_F32 || MK == MF_BF16) {
-      if (!ksplit && (MK == MF_BF16 || fp32_split_products())) {
+      const int64_t tpp2 = (v.S + RCS_COLS - 1) / RCS_COLS, nt2 = v.P * tpp2;
+      if ((!ksplit || nt2 >= 1024) && (MK == MF_BF16 || fp32_split_products())) {
         constexpr int NP = MK == MF_BF16 ? 1 : 3;
-        const int64_t tpp2 = (v.S + RCS_COLS - 1) / RCS_COLS, nt2 = v.P * tpp2;
         const unsigned b = (unsigned)((nt2 + 3) / 4);
 #define TK_RCS(WV)                                                                                          \
   TK_LAUNCH((k_rc_split<NP, NJ, WV>), dim3(b), dim3(256), 0, st, (const float*)X, (const float*)W, v.n, v.S, \
