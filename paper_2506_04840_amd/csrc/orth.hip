@@ -740,13 +740,11 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
     if (pair < np) {
       const int pa = pair == 0 ? 0 : 1 + posa;
       const int pb = 1 + posb;
-      double u[RPT], v[RPT], ju[RPT], jv[RPT];
+      double u[RPT], v[RPT];
 #pragma unroll
       for (int q = 0; q < RPT; ++q) {
         u[q] = A[pa][sub + 8 * q];
         v[q] = A[pb][sub + 8 * q];
-        ju[q] = J[pa][sub + 8 * q];
-        jv[q] = J[pb][sub + 8 * q];
       }
       double al0 = 0.0, be0 = 0.0, ga0 = 0.0, al1 = 0.0, be1 = 0.0, ga1 = 0.0;
 #pragma unroll
@@ -763,6 +761,14 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
       const double al = octet_sum(al0 + al1), be = octet_sum(be0 + be1), ga = octet_sum(ga0 + ga1);
       const bool rot = ga * ga > tol2 * al * be && fmin(al, be) > nu2;
       if (rot) {  // the same decision in all 8 lanes of the pair
+        // J's columns only for a pair that turns (the rounds are bound by LDS
+        // traffic); their reads go out before the rotation is formed
+        double ju[RPT], jv[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          ju[q] = J[pa][sub + 8 * q];
+          jv[q] = J[pb][sub + 8 * q];
+        }
         double cs, sn;
         jacobi_rotation(al, be, ga, cs, sn);
 #pragma unroll
