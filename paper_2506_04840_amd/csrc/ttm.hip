@@ -1837,19 +1837,406 @@ int power_fused_splits(const View3& v, int l, tucker_precision prec) {
   return (int)((nblocks + rounds - 1) / rounds);
 }
 
-// The one-pass kernel forms its products with FP32 instructions. Where FP32
-// products go through the BF16 split and n <= 256 (one row group per wave,
-// blocks too small to keep the FP32 matrix cores busy; measured at n = 120:
-// 3.36 -> 3.23 ms per 120^4 solve), the two split kernels are faster despite
-// their second pass over X; at n = 400 the one-pass kernel still wins (2.23
-// against 2.40 ms per 400^3 solve). The partial layout is sized for both
-// (power_fused_part_bytes does not depend on this choice).
+// ---------------------------------------------------------------------------
+// Both products of a power step in one pass over X on the BF16 matrix cores:
+// FP32 products through the three-piece split (NP = 3) or BF16 operands
+// (NP = 1), n <= PS_NMAX. The partial layout and the chunk protocol are those
+// of k_power_fused:
+//   part[g][i][j] = sum over the column blocks b of chunk g of
+//                   sum_{c in b} X_(k)[i, c] W[c, j],
+//   W[c, j] = sum_i X_(k)[i, c] Q[i, j].
+// A block is 32 consecutive columns s of one p, all n rows. It crosses HBM
+// once and is staged in LDS in FP32: rows of 8 float4 slots, the slot index
+// XOR-ed with bits 1..3 of the row (both read patterns below then spread over
+// the banks); rows past n are zero. Four waves, one per SIMD: the Y tiles of
+// all rows take 256 registers of every lane, kept in the accumulation
+// registers across the chunk's blocks.
+//  * W_b^T = Q^T X_b: wave h takes the 32-row k-steps of its quarter of the
+//    rows, all j tiles and both 16-column tiles. k slot 8 g + e is row
+//    32 ks + 4 e + g; column tile t holds columns 2 mm + t, so one 8-byte LDS
+//    read per row serves both tiles. Q arrives as pieces already in that k
+//    order (k_q_pieces), 16 bytes per lane, two k-steps ahead. The four
+//    quarters' partials meet in LDS and are added in quarter order, split
+//    once and shared as B-operand pieces.
+//  * Y += X_b W_b: wave w owns the 16-row tiles w, w + 4, ... (k slot 8 g + e
+//    is column 8 g + e: two 16-byte LDS reads per lane and tile).
+// The next block's loads are issued when the second product starts and are
+// in flight through it (128 registers). Loads take clamped addresses with no
+// branch; clamped values are replaced by zeros or meet zero Q pieces.
+// Requires S % 4 == 0 (a 4-column group of X is whole or absent).
+// ---------------------------------------------------------------------------
+constexpr int PS_NMAX = 1024;
+
+__device__ __forceinline__ int ps_slot(int r, int s) { return s ^ ((r >> 1) & 7); }
+
+template <int NP, int JT, int QN>
+__global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict__ X, const __bf16* __restrict__ Qp,
+                                                        int64_t n, int64_t S, int l, int64_t nbs,
+                                                        int64_t nblocks, int nchunks, int* __restrict__ ctr, int base,
+                                                        float* __restrict__ part, int* __restrict__ err) {
+  constexpr int NR = 32 * QN;  // staged rows
+  constexpr int KW = QN / 4;   // k-steps per wave in the first product
+  constexpr int UR = QN / 2;   // row tiles per wave in the second
+  static_assert(QN % 4 == 0 && NR <= PS_NMAX && JT >= 1 && JT <= 4, "shape");
+  using PR = BfProducts<NP>;
+  typedef float fv4 __attribute__((ext_vector_type(4)));
+  typedef float fv2 __attribute__((ext_vector_type(2)));
+  // the block, then the quarter partials of W^T (whose space later holds W's
+  // pieces and, between chunks, the chunk number)
+  __shared__ __align__(16) float lds[NR * 32 + 4 * 64 * 32];
+  float* Xs = lds;
+  float* Pt = lds + NR * 32;
+  bf16x8* Wp = reinterpret_cast<bf16x8*>(Pt);
+  int* chunk_s = reinterpret_cast<int*>(Pt);
+
+  const int tid = threadIdx.x, lane = tid & 63, w = wave_id();
+  const int mm = lane & 15, g = lane >> 4;
+  const int nks = (int)((n + 31) >> 5);
+  const int64_t NC = nchunks;
+
+  // thread (lf, lr) loads rows lr + 32 q, columns s0 + 4 lf .. + 3; its LDS
+  // slot in those rows is the same for every q (bits 1..3 of lr + 32 q are
+  // lr's). Rows past n take row n - 1 (they meet zero Q pieces in the first
+  // product and feed unwritten rows in the second), columns past S the last
+  // four (their W columns are set to zero before the second product).
+  const int lf = tid & 7, lr = tid >> 3, nlast = (int)n - 1;
+  float* const xst = Xs + 32 * lr + 4 * ps_slot(lr, lf);
+  constexpr int QH = QN / 2;  // row groups per half block
+  fv4 xr[QH];
+  // half hh of block b: rows lr + 32 q for q in [QH hh, QH hh + QH)
+  auto load_half = [&](int64_t b, int hh) {
+    const int64_t p = b / nbs, s = (b - p * nbs) * 32 + 4 * lf;
+    const float* src = X + p * n * S + (s < S ? s : S - 4);
+    // the row stride, the last row and the lane's row made opaque here: the
+    // row offsets are then formed at the loads (hoisted out of the block loop,
+    // they would hold registers through the whole loop)
+    int64_t rs = S;
+    int il = nlast, ir = lr + 32 * QH * hh;
+    __asm__ volatile("" : "+s"(rs), "+s"(il), "+v"(ir));
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const int i = min(ir + 32 * q, il);
+      const f4u_t v = *reinterpret_cast<const f4u_t*>(src + (int64_t)i * rs);
+      xr[q] = fv4{v[0], v[1], v[2], v[3]};
+      if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  auto stage_half = [&](int hh) {
+#pragma unroll
+    for (int q = 0; q < QH; ++q) *reinterpret_cast<fv4*>(xst + 1024 * (QH * hh + q)) = xr[q];
+  };
+  // Q pieces of k-step ks (k-steps past the rows read the zero pieces of
+  // k-step nks, so the staged copies of row n - 1 there add nothing): NP JT
+  // 16-byte units per lane, one per (piece,
+  // j tile), consecutive for a k-step. The lane offset is rewritten opaquely
+  // for every block so that the unit addresses are formed where the loads are
+  // issued (hoisted out of the block loop, they would hold two registers per load).
+  const bf16x8* const qp8 = reinterpret_cast<const bf16x8*>(Qp);
+  int qlane = lane;
+  auto qload = [&](int ks, int jt0, int jt1, bf16x8 (&qv)[JT][NP]) {
+    const bf16x8* src = qp8 + (int64_t)min(ks, nks) * (NP * JT * 64) + qlane;
+#pragma unroll
+    for (int jt = jt0; jt < jt1; ++jt)
+#pragma unroll
+      for (int c = 0; c < NP; ++c) qv[jt][c] = src[(c * JT + jt) * 64];
+  };
+  // first product's B operand: rows 32 ks + 4 e + g, columns 2 mm and 2 mm + 1
+  // (bits 1..3 of the row are those of 4 e + g)
+  auto xread = [&](int ks, fv2 (&xb)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = 4 * e + g;
+      xb[e] = *reinterpret_cast<const fv2*>(Xs + 32 * (32 * ks + r) + 4 * ps_slot(r, mm >> 1) + 2 * (mm & 1));
+    }
+  };
+  auto bsplit = [&](const fv2 (&xb)[8], bf16x8 (&bp)[2][NP]) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const float f[8] = {xb[0][t], xb[1][t], xb[2][t], xb[3][t], xb[4][t], xb[5][t], xb[6][t], xb[7][t]};
+      bf_pieces<NP>(f, bp[t]);
+    }
+  };
+  // second product's A operand: row 16 rt + mm, columns 8 g .. 8 g + 7 (bits
+  // 1..3 of the row are those of mm)
+  const float* const xal = Xs + 32 * mm;
+  const int sa0 = 4 * ps_slot(mm, 2 * g), sa1 = 4 * ps_slot(mm, 2 * g + 1);
+  auto aread = [&](int rt, fv4 (&a)[2]) {
+    a[0] = *reinterpret_cast<const fv4*>(xal + 512 * rt + sa0);
+    a[1] = *reinterpret_cast<const fv4*>(xal + 512 * rt + sa1);
+  };
+  auto asplit = [&](const fv4 (&a)[2], bf16x8 (&ap)[NP]) {
+    const float f[8] = {a[0][0], a[0][1], a[0][2], a[0][3], a[1][0], a[1][1], a[1][2], a[1][3]};
+    bf_pieces<NP>(f, ap);
+  };
+  // issue order inside a pipeline step: the step's LDS reads, then each
+  // product followed by VX vector instructions (the next step's split)
+  auto interleave = [&](auto nreads, auto nmfma, auto vx) {
+    constexpr int NRD = decltype(nreads)::value, NMF = decltype(nmfma)::value, VX = decltype(vx)::value;
+    __builtin_amdgcn_sched_group_barrier(0x100, NRD, 0);
+#pragma unroll
+    for (int i = 0; i < NMF; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x002, VX, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  for (;;) {
+    if (threadIdx.x == 0) *chunk_s = atomicAdd(ctr, 1) - base;
+    lds_barrier();
+    const int chunk = __builtin_amdgcn_readfirstlane(*chunk_s);
+    if (chunk < 0 || chunk >= nchunks) {
+      // a launch fetches exactly nchunks + gridDim.x numbers from base on; a
+      // value outside that range means the counter and the host's base disagree
+      if ((chunk < 0 || chunk >= nchunks + (int)gridDim.x) && err != nullptr && threadIdx.x == 0)
+        atomicOr(err, TUCKER_INFO_INTERNAL);
+      break;
+    }
+    // the Y tiles live in the accumulation registers (empty statements that
+    // require them there, here and after every block: without them the
+    // allocator moves some into vector registers and spills at n near 1024)
+    floatx4 yacc[UR][JT];
+#pragma unroll
+    for (int u = 0; u < UR; ++u)
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) {
+        yacc[u][jt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        __asm__ volatile("" : "+a"(yacc[u][jt]));
+      }
+
+    // the chunk's first block: its first half staged here, its second half in
+    // flight into the loop
+    int64_t b = chunk;
+    load_half(b, 0);
+    stage_half(0);
+    load_half(b, 1);
+    for (; b < nblocks; b += NC) {
+      // Q pieces of this wave's first k-step, in flight while the block is staged
+      const int ks0 = w * KW;
+      __asm__ volatile("" : "+v"(qlane));
+      bf16x8 qv[JT][NP];
+      qload(ks0, 0, JT, qv);
+      // 1. stage the block's second half (its first half was staged during the
+      //    previous block's second product; that product and the chunk
+      //    number's readers are done with the LDS)
+      const int64_t scol = (b - (b / nbs) * nbs) * 32;  // the block's first column within its p
+      lds_barrier();
+      stage_half(1);
+      lds_barrier();
+      // 2. W_b^T over this wave's k-steps: step kk reads k-step kk + 1 from
+      //    LDS and splits it while the matrix cores take k-step kk's pieces,
+      //    two j tiles at a time (four independent chains); a pair's Q pieces
+      //    are reloaded with k-step kk + 1's as soon as its products are
+      //    issued (one register set for Q, each load a whole step ahead)
+      floatx4 acc1[JT][2];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) acc1[jt][0] = acc1[jt][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+      fv2 xb[8];
+      bf16x8 bp[2][2][NP];
+      xread(ks0, xb);
+      bsplit(xb, bp[0]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int kk = 0; kk < KW; ++kk) {
+        const int cur = kk & 1, nxt = cur ^ 1;
+        if (kk + 1 < KW) {
+          xread(ks0 + kk + 1, xb);
+          bsplit(xb, bp[nxt]);
+        }
+#pragma unroll
+        for (int j0 = 0; j0 < JT; j0 += 2) {
+          const int j1 = j0 + 2 < JT ? j0 + 2 : JT;
+#pragma unroll
+          for (int k = 0; k < PR::N; ++k)
+#pragma unroll
+            for (int jt = j0; jt < j1; ++jt)
+#pragma unroll
+              for (int t = 0; t < 2; ++t)
+                acc1[jt][t] = mfma_bf16(qv[jt][PR::A[k]], bp[cur][t][PR::B[k]], acc1[jt][t]);
+          if (kk + 1 < KW) qload(ks0 + kk + 1, j0, j1, qv);
+        }
+        interleave(std::integral_constant<int, 8>{}, std::integral_constant<int, PR::N * JT * 2>{},
+                   std::integral_constant<int, 2>{});
+      }
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt) __asm__ volatile("" : "+v"(acc1[jt][0]), "+v"(acc1[jt][1]));
+      // 3. quarter partials Pt[w][j][c]: lane holds j = 16 jt + 4 g + v, c = 2 mm + t
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          *reinterpret_cast<fv2*>(Pt + (w * 64 + 16 * jt + 4 * g + v) * 32 + 2 * mm) =
+              fv2{acc1[jt][0][v], acc1[jt][1][v]};
+      lds_barrier();
+      // wave w forms j tile w: lane (mm, g) sums W^T[16 w + mm][8 g .. 8 g + 7]
+      // over the quarters in order and splits it (the B operand of the second
+      // product: k slot 8 g + e is column 8 g + e)
+      bf16x8 wown[NP];
+      if (w < JT) {
+        float sum[8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const float* src = Pt + (h * 64 + 16 * w + mm) * 32 + 8 * g;
+          const fv4 a = *reinterpret_cast<const fv4*>(src), c = *reinterpret_cast<const fv4*>(src + 4);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            sum[e] = h == 0 ? a[e] : sum[e] + a[e];
+            sum[4 + e] = h == 0 ? c[e] : sum[4 + e] + c[e];
+          }
+        }
+        // columns past S (the staged copies of the last four) contribute nothing
+        const int64_t cvalid = S - scol - 8 * g;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sum[e] = e < cvalid ? sum[e] : 0.f;
+        bf_pieces<NP>(sum, wown);
+      }
+      lds_barrier();
+      if (w < JT)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) Wp[(w * NP + c) * 64 + lane] = wown[c];
+      lds_barrier();
+      bf16x8 wq[JT][NP];
+#pragma unroll
+      for (int jt = 0; jt < JT; ++jt)
+#pragma unroll
+        for (int c = 0; c < NP; ++c) wq[jt][c] = Wp[(jt * NP + c) * 64 + lane];
+      // 4. Y += X_b W_b over this wave's row tiles w + 4 u (rows past n are
+      //    zero or copies of row n - 1 and feed unwritten rows): step u takes
+      //    tile u's pieces, splits u + 1, reads u + 2. Tiles u < UR / 2 hold
+      //    the first half of the rows: once every wave is past them, the next
+      //    block's first half (its loads issued here) is staged over them and
+      //    its second half's loads go out for the rest of the product.
+      const int64_t bn = b + NC < nblocks ? b + NC : b;
+      load_half(bn, 0);
+      fv4 ar[2][2];
+      bf16x8 ap[2][NP];
+      aread(w, ar[0]);
+      if (UR > 1) aread(w + 4, ar[1]);
+      asplit(ar[0], ap[0]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
+        const int cur = u & 1, nxt = cur ^ 1;
+        if (u == UR / 2) {
+          lds_barrier();
+          stage_half(0);
+          load_half(bn, 1);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        if (u + 2 < UR) aread(w + 4 * (u + 2), ar[cur]);
+        if (u + 1 < UR) asplit(ar[nxt], ap[nxt]);
+#pragma unroll
+        for (int k = 0; k < PR::N; ++k)
+#pragma unroll
+          for (int jt = 0; jt < JT; ++jt) yacc[u][jt] = mfma_bf16(ap[cur][PR::A[k]], wq[jt][PR::B[k]], yacc[u][jt]);
+        interleave(std::integral_constant<int, 2>{}, std::integral_constant<int, PR::N * JT>{},
+                   std::integral_constant<int, 2>{});
+      }
+#pragma unroll
+      for (int u = 0; u < UR; ++u)
+#pragma unroll
+        for (int jt = 0; jt < JT; ++jt) __asm__ volatile("" : "+a"(yacc[u][jt]));
+    }
+    // lane holds rows 4 g + v of tile (u, jt): i = 16 (w + 4 u) + 4 g + v,
+    // j = 16 jt + mm (n and l made opaque so that the row addresses are formed
+    // here, not held from the kernel's start)
+    int nn = (int)n, ll = l, i0 = 16 * w + 4 * g;
+    __asm__ volatile("" : "+s"(nn), "+s"(ll), "+v"(i0));
+    float* drow = part + ((int64_t)chunk * nn + i0) * ll + mm;
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if (i0 + 64 * u + v < nn)
+#pragma unroll
+          for (int jt = 0; jt < JT; ++jt)
+            if (16 * jt + mm < ll) drow[16 * jt] = yacc[u][jt][v];
+        drow += ll;
+      }
+      drow += 60 * (int64_t)ll;  // the wave's next tile: 64 rows on
+    }
+    lds_barrier();  // the chunk number is rewritten next
+  }
+}
+
+// Q's pieces in the first product's k order: 16-byte unit
+// ((ks NP + c) JT + jt) 64 + 16 g + mm holds piece c of Q[32 ks + 4 e + g,
+// 16 jt + mm], e = 0..7 (zero past n and past l), from Qt j-major; nks is the
+// k-step count plus one (the last k-step all zero).
+template <int NP>
+__global__ __launch_bounds__(256) void k_q_pieces(const float* __restrict__ Qt, int64_t n, int l, int JT, int nks,
+                                                  bf16x8* __restrict__ Qp) {
+  const int64_t u = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (u >= (int64_t)nks * JT * 64) return;
+  const int lane = (int)(u & 63), mm = lane & 15, g = lane >> 4;
+  const int64_t r = u >> 6;
+  const int jt = (int)(r % JT), ks = (int)(r / JT);
+  const int64_t j = 16 * jt + mm;
+  float f[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int64_t i = 32 * (int64_t)ks + 4 * e + g;
+    f[e] = (j < l && i < n) ? Qt[j * n + i] : 0.f;
+  }
+  bf16x8 p[NP];
+  bf_pieces<NP>(f, p);
+#pragma unroll
+  for (int c = 0; c < NP; ++c) Qp[(((int64_t)ks * NP + c) * JT + jt) * 64 + lane] = p[c];
+}
+
+// The split one-pass kernel's chunks: the rule of power_fused_splits over
+// 32-column blocks; 0 where the kernel does not apply (precision, S % 4,
+// n > PS_NMAX, l > 64).
+static int power_split_chunks(const View3& v, int l, tucker_precision prec) {
+  if ((prec != TUCKER_FP32 && prec != TUCKER_BF16) || v.S < 32 || v.S % 4 != 0 || v.n > PS_NMAX || l < 1 || l > 64)
+    return 0;
+  constexpr int64_t kMaxGroups = 256 - 4;
+  const int64_t nblocks = v.P * ((v.S + 31) / 32);
+  const int64_t rounds = (nblocks + kMaxGroups - 1) / kMaxGroups;
+  return (int)((nblocks + rounds - 1) / rounds);
+}
+static int64_t ps_nr32(int64_t n) { return (n + 31) / 32 * 32; }
+// Q's pieces follow the partials in the same buffer.
+static size_t ps_qp_offset(const View3& v, int l, int G) {
+  return ((size_t)G * v.n * l * sizeof(float) + 255) / 256 * 256;
+}
+static size_t power_split_part_bytes(const View3& v, int l, tucker_precision prec) {
+  const int G = power_split_chunks(v, l, prec);
+  return G == 0 ? 0 : ps_qp_offset(v, l, G) + (size_t)3 * 64 * (ps_nr32(v.n) + 32) * sizeof(__bf16);
+}
+
+// Which pass a power step takes: the split one-pass kernel where it applies,
+// the step's products run on the BF16 matrix cores (FP32 through the split, or
+// BF16 operands) and n > 256 (below, its 32-column blocks leave the matrix
+// cores idle behind the loads and the two split kernels are faster: 120^4
+// BF16 3.03 against 3.14 ms per solve); else the FP32 one-pass kernel where
+// it applies; else the row contraction and the column reduction.
+enum PowerPass { PP_TWO = 0, PP_FUSED_F32 = 1, PP_SPLIT = 2 };
+static PowerPass power_pass(const View3& v, int l, tucker_precision prec) {
+  if ((prec == TUCKER_BF16 || (prec == TUCKER_FP32 && fp32_split_products())) && v.n > 256 &&
+      power_split_chunks(v, l, prec) > 0)
+    return PP_SPLIT;
+  if (power_fused_splits(v, l, prec) > 0 && !(fp32_split_products() && v.n <= 256)) return PP_FUSED_F32;
+  return PP_TWO;
+}
+
+// The FP32 one-pass kernel forms its products with FP32 instructions; where
+// the split kernel does not apply and FP32 products go through the BF16 split
+// with n <= 256 (one row group per wave, blocks too small to keep the FP32
+// matrix cores busy), the two split kernels are faster despite their second
+// pass over X. The partial layout covers every pass (power_fused_part_bytes
+// does not depend on this choice).
 int power_fused_launch_splits(const View3& v, int l, tucker_precision prec) {
-  return (fp32_split_products() && v.n <= 256) ? 0 : power_fused_splits(v, l, prec);
+  switch (power_pass(v, l, prec)) {
+    case PP_SPLIT: return power_split_chunks(v, l, prec);
+    case PP_FUSED_F32: return power_fused_splits(v, l, prec);
+    default: return 0;
+  }
 }
 
 size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec) {
-  return (size_t)power_fused_splits(v, l, prec) * v.n * l * sizeof(float);
+  return std::max((size_t)power_fused_splits(v, l, prec) * v.n * l * sizeof(float),
+                  power_split_part_bytes(v, l, prec == TUCKER_FP64 ? prec : TUCKER_FP32));
 }
 
 // Grid: the chunks plus four spare workgroups (at most one per CU), which
@@ -1873,17 +2260,64 @@ static void pf_dispatch(const View3& v, const float* X, const float* Qt, int l, 
   else pf_launch<JT, 4>(v, X, Qt, l, part, NC, ctr, base, err, st);
 }
 
+template <int NP, int JT, int QN>
+static void ps_launch(const View3& v, const float* X, const __bf16* Qp, int l, float* part, int NC, int* ctr,
+                      int base, int* err, hipStream_t st) {
+  const int64_t nbs = (v.S + 31) / 32;
+  TK_LAUNCH((k_power_split<NP, JT, QN>), dim3(pf_grid(NC)), dim3(256), 0, st, X, Qp, v.n, v.S, l, nbs,
+            v.P * nbs, NC, ctr, base, part, err);
+}
+
+template <int NP, int JT>
+static void ps_dispatch_q(const View3& v, const float* X, const __bf16* Qp, int l, float* part, int NC, int* ctr,
+                          int base, int* err, hipStream_t st) {
+  const int64_t nq = (v.n + 31) / 32;  // staged 32-row groups: 16, 24 or 32 (n > 256)
+  if (nq <= 16) ps_launch<NP, JT, 16>(v, X, Qp, l, part, NC, ctr, base, err, st);
+  else if (nq <= 24) ps_launch<NP, JT, 24>(v, X, Qp, l, part, NC, ctr, base, err, st);
+  else ps_launch<NP, JT, 32>(v, X, Qp, l, part, NC, ctr, base, err, st);
+}
+
+template <int NP>
+static hipError_t ps_run(const View3& v, const float* X, const float* qt, int l, float* part, int NC, int* ctr,
+                         int base, int* err, hipStream_t st) {
+  const int JT = (l + 15) / 16, nks = (int)((v.n + 31) / 32);
+  __bf16* Qp = reinterpret_cast<__bf16*>(reinterpret_cast<char*>(part) + ps_qp_offset(v, l, NC));
+  const int64_t units = (int64_t)(nks + 1) * JT * 64;
+  hipLaunchKernelGGL(k_q_pieces<NP>, dim3((unsigned)((units + 255) / 256)), dim3(256), 0, st, qt, v.n, l, JT,
+                     nks + 1, reinterpret_cast<bf16x8*>(Qp));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double N = (double)v.P * v.n * v.S;
+  TimingScope ts(KC_POWERSTEP, st, 4.0 * (N + (double)v.n * l), 4.0 * N * l, true);
+  switch (JT) {
+    case 1: ps_dispatch_q<NP, 1>(v, X, Qp, l, part, NC, ctr, base, err, st); break;
+    case 2: ps_dispatch_q<NP, 2>(v, X, Qp, l, part, NC, ctr, base, err, st); break;
+    case 3: ps_dispatch_q<NP, 3>(v, X, Qp, l, part, NC, ctr, base, err, st); break;
+    default: ps_dispatch_q<NP, 4>(v, X, Qp, l, part, NC, ctr, base, err, st); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_power_products(tucker_precision prec, const View3& v, const void* X, const void* qt, int l,
                                  void* z, void* part, int nsplit, int* ctr, int* fused_count, int* nsplit_used,
                                  hipStream_t st, int* err) {
-  const int G = power_fused_launch_splits(v, l, prec);
-  if (G == 0) {
+  const PowerPass pp = power_pass(v, l, prec);
+  if (pp == PP_TWO) {
     if (z == nullptr) return hipErrorInvalidValue;  // the two-kernel path needs Z's space
     *nsplit_used = nsplit;
     hipError_t e = launch_rowcontract(prec, v, X, qt, 1, v.n, l, z, true, st);
     if (e == hipSuccess) e = launch_colreduce(prec, v, X, z, l, part, nsplit, st);
     return e;
   }
+  if (pp == PP_SPLIT) {
+    const int G = power_split_chunks(v, l, prec);
+    *nsplit_used = G;
+    const int base = (*fused_count)++ * (G + pf_grid(G));
+    return prec == TUCKER_BF16
+               ? ps_run<1>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, err, st)
+               : ps_run<3>(v, (const float*)X, (const float*)qt, l, (float*)part, G, ctr, base, err, st);
+  }
+  const int G = power_fused_splits(v, l, prec);
   *nsplit_used = G;
   const double N = (double)v.P * v.n * v.S;
   TimingScope ts(KC_POWERSTEP, st, 4.0 * (N + (double)v.n * l), 4.0 * N * l, true);

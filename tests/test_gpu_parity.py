@@ -122,12 +122,14 @@ def test_power_step_raw_matches_oracle(T, prec, dims, mode, l):
     assert np.all(np.abs(m - ref) <= TOL[prec] * scale), np.max(np.abs(m - ref) / scale)
 
 
-# Shapes that take the fused one-pass power step in FP32 (S >= 64, n and S
-# multiples of 4, n <= 512, l <= 48): several rounds of blocks per workgroup
-# (400 x 16640 columns: 260 blocks), ragged row groups (n = 100, 44, 260),
-# ragged last blocks (S = 1800, 100, 204), P > 1 (modes in the middle), the
-# largest n (512, 4 row groups per wave), a row half with no group (n = 16)
-# and widths of one to three 16-column tiles.
+# Shapes of the one-pass power steps (S a multiple of 4): with FP32 products
+# through the BF16 split, n > 256 takes the split one-pass kernel (32-column
+# blocks) and n <= 256 the row contraction and column reduction; the FP32
+# one-pass kernel (n <= 512, l <= 48) runs them with FP32 instructions in the
+# solves below. Several rounds of blocks per workgroup (400 x 16640 columns),
+# ragged row groups (n = 100, 44, 260), ragged last blocks (S = 1800, 100,
+# 204), P > 1 (modes in the middle), n = 512, a row half with no group
+# (n = 16) and widths of one to three 16-column tiles.
 FUSED = [((400, 130, 128), 0, 40), ((100, 36, 50), 0, 17), ((30, 400, 100), 1, 48), ((8, 44, 68, 3), 1, 1),
          ((8, 44, 68, 3), 1, 44), ((512, 70, 40), 0, 48), ((16, 12, 64), 0, 16), ((260, 24, 20), 0, 33)]
 
@@ -1003,6 +1005,9 @@ _AWKWARD = [
     ((2048, 70, 67), 1, 24), ((2048, 70, 67), 1, 60),
     ((1, 20, 270000), 1, 17),
     ((100, 262208), 0, 60),
+    # n > 256: the one-pass power step on the BF16 matrix cores at each staged
+    # row count (512, 768, 1024 rows), ragged rows and last blocks, P > 1
+    ((300, 40, 36), 0, 24), ((700, 37, 12), 0, 60), ((6, 1000, 44), 1, 40),
 ]
 
 
