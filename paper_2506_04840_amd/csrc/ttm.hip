@@ -1877,6 +1877,7 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
   constexpr int NR = 32 * QN;  // staged rows
   constexpr int KW = QN / 4;   // k-steps per wave in the first product
   constexpr int UR = QN / 2;   // row tiles per wave in the second
+  constexpr int QD = NP == 1 ? 2 : 1;  // register sets for Q's pieces
   static_assert(QN % 4 == 0 && NR <= PS_NMAX && JT >= 1 && JT <= 4, "shape");
   using PR = BfProducts<NP>;
   typedef float fv4 __attribute__((ext_vector_type(4)));
@@ -1921,9 +1922,14 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
       if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
   };
+  // (the half's LDS base made opaque: its rows then sit within the 64 KB
+  // reach of the instructions' immediate offsets, with no address per row)
   auto stage_half = [&](int hh) {
+    int off = 1024 * QH * hh;
+    __asm__ volatile("" : "+v"(off));
+    float* const dst = xst + off;
 #pragma unroll
-    for (int q = 0; q < QH; ++q) *reinterpret_cast<fv4*>(xst + 1024 * (QH * hh + q)) = xr[q];
+    for (int q = 0; q < QH; ++q) *reinterpret_cast<fv4*>(dst + 1024 * q) = xr[q];
   };
   // Q pieces of k-step ks (k-steps past the rows read the zero pieces of
   // k-step nks, so the staged copies of row n - 1 there add nothing): NP JT
@@ -1960,9 +1966,22 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
   // 1..3 of the row are those of mm)
   const float* const xal = Xs + 32 * mm;
   const int sa0 = 4 * ps_slot(mm, 2 * g), sa1 = 4 * ps_slot(mm, 2 * g + 1);
-  auto aread = [&](int rt, fv4 (&a)[2]) {
-    a[0] = *reinterpret_cast<const fv4*>(xal + 512 * rt + sa0);
-    a[1] = *reinterpret_cast<const fv4*>(xal + 512 * rt + sa1);
+  // tile w + 4 u of this wave, read from a base that is made opaque at the
+  // start of each half (u0 = 0, UR / 2), so that the half's tiles sit within
+  // the reach of immediate offsets
+  const float* xa0 = xal;
+  const float* xa1 = xal;
+  int u0 = 0;
+  auto abase = [&](int ub) {
+    int off = 512 * (w + 4 * ub);
+    __asm__ volatile("" : "+v"(off));
+    xa0 = xal + off + sa0;
+    xa1 = xal + off + sa1;
+    u0 = ub;
+  };
+  auto aread = [&](int u, fv4 (&a)[2]) {
+    a[0] = *reinterpret_cast<const fv4*>(xa0 + 2048 * (u - u0));
+    a[1] = *reinterpret_cast<const fv4*>(xa1 + 2048 * (u - u0));
   };
   auto asplit = [&](const fv4 (&a)[2], bf16x8 (&ap)[NP]) {
     const float f[8] = {a[0][0], a[0][1], a[0][2], a[0][3], a[1][0], a[1][1], a[1][2], a[1][3]};
@@ -2014,8 +2033,9 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
       // Q pieces of this wave's first k-step, in flight while the block is staged
       const int ks0 = w * KW;
       __asm__ volatile("" : "+v"(qlane));
-      bf16x8 qv[JT][NP];
-      qload(ks0, 0, JT, qv);
+      bf16x8 qv[QD][JT][NP];
+      qload(ks0, 0, JT, qv[0]);
+      if (QD == 2 && KW > 1) qload(ks0 + 1, 0, JT, qv[QD - 1]);
       // 1. stage the block's second half (its first half was staged during the
       //    previous block's second product; that product and the chunk
       //    number's readers are done with the LDS)
@@ -2024,10 +2044,13 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
       stage_half(1);
       lds_barrier();
       // 2. W_b^T over this wave's k-steps: step kk reads k-step kk + 1 from
-      //    LDS and splits it while the matrix cores take k-step kk's pieces,
-      //    two j tiles at a time (four independent chains); a pair's Q pieces
-      //    are reloaded with k-step kk + 1's as soon as its products are
-      //    issued (one register set for Q, each load a whole step ahead)
+      //    LDS and splits it while the matrix cores take k-step kk's pieces.
+      //    Q's pieces stream from L2 (all of Q for every block: with three
+      //    pieces they, not their latency, bound this product): with one
+      //    piece, two register sets, each refilled two steps ahead; with
+      //    three, one set, refilled by pairs of j tiles as soon as a pair's
+      //    products are issued (each load a step ahead; a second set would
+      //    push the kernel past the register file)
       floatx4 acc1[JT][2];
 #pragma unroll
       for (int jt = 0; jt < JT; ++jt) acc1[jt][0] = acc1[jt][1] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -2038,7 +2061,7 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int kk = 0; kk < KW; ++kk) {
-        const int cur = kk & 1, nxt = cur ^ 1;
+        const int cur = kk & 1, nxt = cur ^ 1, qs = QD == 2 ? cur : 0;
         if (kk + 1 < KW) {
           xread(ks0 + kk + 1, xb);
           bsplit(xb, bp[nxt]);
@@ -2052,9 +2075,10 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
             for (int jt = j0; jt < j1; ++jt)
 #pragma unroll
               for (int t = 0; t < 2; ++t)
-                acc1[jt][t] = mfma_bf16(qv[jt][PR::A[k]], bp[cur][t][PR::B[k]], acc1[jt][t]);
-          if (kk + 1 < KW) qload(ks0 + kk + 1, j0, j1, qv);
+                acc1[jt][t] = mfma_bf16(qv[qs][jt][PR::A[k]], bp[cur][t][PR::B[k]], acc1[jt][t]);
+          if (QD == 1 && kk + 1 < KW) qload(ks0 + kk + 1, j0, j1, qv[0]);
         }
+        if (QD == 2 && kk + 2 < KW) qload(ks0 + kk + 2, 0, JT, qv[qs]);
         interleave(std::integral_constant<int, 8>{}, std::integral_constant<int, PR::N * JT * 2>{},
                    std::integral_constant<int, 2>{});
       }
@@ -2110,8 +2134,9 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
       load_half(bn, 0);
       fv4 ar[2][2];
       bf16x8 ap[2][NP];
-      aread(w, ar[0]);
-      if (UR > 1) aread(w + 4, ar[1]);
+      abase(0);
+      aread(0, ar[0]);
+      if (UR > 1) aread(1, ar[1]);
       asplit(ar[0], ap[0]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -2123,7 +2148,8 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
           load_half(bn, 1);
           __builtin_amdgcn_sched_barrier(0);
         }
-        if (u + 2 < UR) aread(w + 4 * (u + 2), ar[cur]);
+        if (u + 2 == UR / 2) abase(UR / 2);  // the first tile of the second half is read next
+        if (u + 2 < UR) aread(u + 2, ar[cur]);
         if (u + 1 < UR) asplit(ar[nxt], ap[nxt]);
 #pragma unroll
         for (int k = 0; k < PR::N; ++k)
