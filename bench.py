@@ -304,7 +304,7 @@ def main():
         kern = args.kernel if args.kernel != "auto" else max(timed, key=lambda k: timed[k]["ms"])
         tk = timed[kern]
         mk = "fp32" if (prec == "bf16" and kern == "rowcontract") else prec
-        if mk == "fp32" and args.fp32_products == "split" and kern in ("colreduce", "rowcontract"):
+        if mk == "fp32" and args.fp32_products == "split" and kern in ("colreduce", "rowcontract", "powerstep"):
             mk = "fp32-split"  # the large products of this class run as six BF16 products per pair
         roof = _roof_from_timing(tk, mk)
         # the committed counters were taken on the workload's default command

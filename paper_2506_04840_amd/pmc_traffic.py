@@ -23,7 +23,7 @@ import re
 CLASSES = {
     "colreduce": r"tk::k_cr_(lds|cols|split)<",
     "rowcontract": r"tk::k_rc_(rows|cols|split)<",
-    "powerstep": r"tk::k_power_fused<",
+    "powerstep": r"tk::k_power_(fused|split)<",
     # persistent batched kernels: the profiler may print them mangled
     "batched_colreduce": r"k_persist<tk::BCr(Lds|Cols),|k_persistINS_\d+BCr(Lds|Cols)E",
     "batched_rowcontract": r"k_persist<tk::BRc(Rows|Cols),|k_persistINS_\d+BRc(Rows|Cols)E",
