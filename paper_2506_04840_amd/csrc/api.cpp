@@ -421,6 +421,11 @@ hipError_t launch_norm_of_input(tucker_precision prec, const View3& v, const voi
   return launch_norm2(prec, X, v.P * v.n * v.S, w.napart, w.na2, st);
 }
 
+// Element count of a mode's tensor from which step 1 rotates its iterate by
+// the sketch's J (see mode_factor): a power step over 2^28 elements takes
+// about half a millisecond or more, the sketch's small SVD at l <= 64 less.
+constexpr double kRotateStep1Numel = 268435456.0;
+
 // One mode of Algorithm 2 / 3 up to U_k (before truncation):
 //   Y = X_(k) Omega_k; [Q, Sigma] = svd(Y); alpha_0 = 0;
 //   q times: Y = X_(k) (X_(k)^T Q) - alpha Q; [Q, Sigma] = svd(Y); shift update.
@@ -429,10 +434,11 @@ hipError_t launch_norm_of_input(tucker_precision prec, const View3& v, const voi
 // one). Step t + 1 runs its products on Q3 instead of Q = Q3 J; the reduce
 // subtracts alpha_t Q3 and the next Gram kernel applies J: (X X^T Q3 -
 // alpha Q3) J = X X^T Q - alpha Q, the same iterate. Step 1 does not wait
-// for the sketch's SVD at all (alpha_0 = 0 and J_0 does not change the
-// iterate's left singular vectors): in modes whose products are short, that
-// SVD no longer sits on the critical path. On return ws.q64 holds the left
-// singular vectors of the last iterate (FP64, n x l, descending).
+// for the sketch's SVD (alpha_0 = 0 and J_0 does not change the iterate's
+// left singular vectors): in modes whose products are short, that SVD no
+// longer sits on the critical path. In modes of at least kRotateStep1Numel
+// elements it does apply J_0, after the products. On return ws.q64 holds the
+// left singular vectors of the last iterate (FP64, n x l, descending).
 int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift, uint64_t seed, tucker_precision prec,
                 tucker_info* info, const SolveWs& w, hipStream_t st, const OmegaSpec& om, int lane = 0,
                 void* qt_out = nullptr) {
@@ -474,6 +480,14 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   // iteration and is joined back at the end of the mode.
   const bool log_sketch = q > 0 && side != nullptr;
   const OrthWs ows0 = log_sketch ? orth_log_set(ows) : orth_step_set(ows, 0);
+  // Step 1 factors the unrotated iterate, so that it need not wait for the
+  // sketch's SVD; its own SVD then starts from a dense R (at l = 60 it took
+  // 0.8-2.3 ms beside the products, half a millisecond of it on step 2's
+  // path at 1000^3). In a mode whose products take longer than the sketch's
+  // SVD, step 1 waits for that SVD after its products and rotates its
+  // iterate by the sketch's J like every later step (the wait is hidden behind
+  // the products, and step 1's SVD starts from a nearly diagonal R).
+  const bool rot1 = log_sketch && (double)v.P * (double)v.n * (double)v.S >= kRotateStep1Numel;
   if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, step_prec(0), w.qt, ows0, cseed, 0, st);
   if (e == hipSuccess && log_sketch) {
     e = hipEventRecord(side->log_fork, st);
@@ -504,12 +518,15 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
     // Y = (Y' - alpha Q3) J, then its CholeskyQR. Step 1 needs nothing from
     // the sketch's SVD: alpha_0 = 0, and J_0 only turns the basis inside the
     // span, which leaves the iterate's left singular vectors and values as
-    // they are; step 1 factors Y' itself and its own SVD absorbs J_0.
+    // they are; step 1 factors Y' itself and its own SVD absorbs J_0, except
+    // in large modes (rot1), where it waits for J_0 here and applies it.
     if (e == hipSuccess && t > 1 && side != nullptr) e = hipStreamWaitEvent(st, side->svd_done, 0);
     if (e == hipSuccess)
       e = launch_reduce_splits(tp, w.part, ns_used, n * l, ows.Qa, TUCKER_FP64, alpha, w.y64, st);
+    if (e == hipSuccess && t == 1 && rot1) e = hipStreamWaitEvent(st, side->log_done, 0);
     if (e == hipSuccess)
-      e = launch_orth_qr(n, l, w.y64, t > 1 ? ows.Wm : nullptr, tp, w.qt, orth_step_set(ows, t), cseed, t, st);
+      e = launch_orth_qr(n, l, w.y64, t > 1 ? ows.Wm : (rot1 ? ows0.Wm : nullptr), tp, w.qt, orth_step_set(ows, t),
+                         cseed, t, st);
   }
   // last small SVD on the caller's stream, after the side SVDs (they share Wm
   // and sigma); then Q = Q3 J (also as Q^T j-major when asked)
