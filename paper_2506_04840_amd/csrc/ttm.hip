@@ -1917,7 +1917,9 @@ __global__ __launch_bounds__(256, 1) void k_power_split(const float* __restrict_
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
       const int i = min(ir + 32 * q, il);
-      const f4u_t v = *reinterpret_cast<const f4u_t*>(src + (int64_t)i * rs);
+      // streaming (non-temporal): X is read once, and in L2 it would evict
+      // Q's pieces, which every block of the CU's XCD reads again
+      const f4u_t v = __builtin_nontemporal_load(reinterpret_cast<const f4u_t*>(src + (int64_t)i * rs));
       xr[q] = fv4{v[0], v[1], v[2], v[3]};
       if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
