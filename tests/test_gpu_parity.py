@@ -159,9 +159,11 @@ def test_fused_power_step_matches_oracle(T, dims, mode, l):
     assert np.all(np.abs(m - ref) <= 1e-5 * scale + 1e-5 * alpha * np.abs(qa)), np.max(np.abs(m - ref) / scale)
 
 
-def test_fused_power_step_at_an_unaligned_address(T):
-    """X and Q one element past an aligned address on the fused path."""
-    dims, mode, l = (20, 64, 36), 0, 20
+@pytest.mark.parametrize("dims", [(20, 64, 36), (300, 20, 36)])
+def test_fused_power_step_at_an_unaligned_address(T, dims):
+    """X and Q one element past an aligned address on the power-step paths
+    (n = 20: the two split kernels; n = 300: the split one-pass kernel)."""
+    mode, l = 0, 20
     g = gen.rng(29)
     a = g.standard_normal(dims)
     x = _dev_offset(a, torch.float32)
@@ -461,18 +463,22 @@ def test_edge_shapes(T):
         _compare_solve(_dev(a, torch.float64), a, ranks, p, q, "adaptive", "st", "fp64", check_core=False)
 
 
-def test_fp32_t_hosvd_with_concurrent_fused_power_steps(T):
-    """FP32 T-HOSVD where modes 0 (S = 68 * 72) and 1 (P = 64, S = 72) both take
-    the one-pass power step, on their own streams at the same time (each with
+@pytest.mark.parametrize("fp32_products,dims", [("native", (64, 68, 72)), ("split", (300, 264, 32))])
+def test_fp32_t_hosvd_with_concurrent_fused_power_steps(T, fp32_products, dims):
+    """FP32 T-HOSVD where modes 0 (S = n1 n2) and 1 (P = n0, S = n2) both take
+    a one-pass power step, on their own streams at the same time (each with
     its own chunk counters), two power steps each, against the FP64 oracle;
-    mode 2 (S = 1) runs the two-kernel products. Then the same solve again:
+    mode 2 (S = 1) runs the two-kernel products. FP32 instructions take the
+    FP32 one-pass kernel (n <= 512); products through the BF16 split take the
+    split one-pass kernel, which needs n > 256. Then the same solve again:
     each mode zeroes its counter at its start, and every launch takes its base
     (the fetches of the launches before it) from the host."""
-    a, _, _ = gen.random_tucker((64, 68, 72), (8, 9, 10), 1e-2, seed=43)
+    a, _, _ = gen.random_tucker(dims, (8, 9, 10), 1e-2, seed=43)
     a32 = a.astype(np.float32)
     x = _dev(a32, torch.float32)
     for _ in range(2):
-        _compare_solve(x, a32.astype(np.float64), (8, 9, 10), 10, 2, "adaptive", "t", "fp32")
+        _compare_solve(x, a32.astype(np.float64), (8, 9, 10), 10, 2, "adaptive", "t", "fp32",
+                       fp32_products=fp32_products)
 
 
 @pytest.mark.parametrize("variant", ["t", "st"])
@@ -931,19 +937,21 @@ def test_nonfinite_input_is_flagged(T):
         assert not bool(torch.isfinite(G).all())
 
 
-def test_fused_power_steps_without_rezeroing(T):
-    """Four FP32 power steps through the one-pass kernel in one mode: the
-    chunk counter is zeroed once at the mode's start and every later launch
-    takes its base from the host. Each step's iterate (its Sigma(1,1),
-    Sigma(l,l) and shift) matches the oracle's, on a tensor whose unfolding
-    spectra decay as 0.9^i (slowly enough that the steps' iterates differ),
-    and no launch flags its counter out of step."""
+@pytest.mark.parametrize("fp32_products,dims", [("native", (96, 80, 72)), ("split", (288, 48, 40))])
+def test_fused_power_steps_without_rezeroing(T, fp32_products, dims):
+    """Four FP32 power steps through a one-pass kernel in one mode (the FP32
+    one with FP32 instructions, the split one, n > 256, with products through
+    the BF16 split): the chunk counter is zeroed once at the mode's start and
+    every later launch takes its base from the host. Each step's iterate (its
+    Sigma(1,1), Sigma(l,l) and shift) matches the oracle's, on a tensor whose
+    unfolding spectra decay as 0.9^i (slowly enough that the steps' iterates
+    differ), and no launch flags its counter out of step."""
     core = gen.superdiagonal(0.9 ** np.arange(40), (40, 40, 40))
-    a, _, _ = gen.random_tucker((96, 80, 72), (40, 40, 40), 1e-2, seed=64, core=core)
+    a, _, _ = gen.random_tucker(dims, (40, 40, 40), 1e-2, seed=64, core=core)
     a32 = a.astype(np.float32)
     x = _dev(a32, torch.float32)
     G, U, info, res = _compare_solve(x, a32.astype(np.float64), (12, 12, 12), 8, 4, "adaptive", "st", "fp32",
-                                     check_core=False)
+                                     check_core=False, fp32_products=fp32_products)
     assert not info["flags"] & T.INFO_INTERNAL
     lg = res.logs[0]
     # the iterates of consecutive steps really differ (a stale partial would repeat one)
