@@ -2233,15 +2233,16 @@ static size_t power_split_part_bytes(const View3& v, int l, tucker_precision pre
   return G == 0 ? 0 : ps_qp_offset(v, l, G) + (size_t)3 * 64 * (ps_nr32(v.n) + 32) * sizeof(__bf16);
 }
 
-// Which pass a power step takes: the split one-pass kernel where it applies,
-// the step's products run on the BF16 matrix cores (FP32 through the split, or
-// BF16 operands) and n > 256 (below, its 32-column blocks leave the matrix
-// cores idle behind the loads and the two split kernels are faster: 120^4
-// BF16 3.03 against 3.14 ms per solve); else the FP32 one-pass kernel where
-// it applies; else the row contraction and the column reduction.
+// Which pass a power step takes: the split one-pass kernel where it applies
+// and the step's products run on the BF16 matrix cores, with BF16 operands at
+// any n and FP32 products through the split at n > 256 (below, its 32-column
+// blocks leave the matrix cores idle behind Q's stream and the two split
+// kernels are faster: 120^4, 3.03 against 3.14 ms per solve); else the FP32
+// one-pass kernel where it applies; else the row contraction and the column
+// reduction.
 enum PowerPass { PP_TWO = 0, PP_FUSED_F32 = 1, PP_SPLIT = 2 };
 static PowerPass power_pass(const View3& v, int l, tucker_precision prec) {
-  if ((prec == TUCKER_BF16 || (prec == TUCKER_FP32 && fp32_split_products())) && v.n > 256 &&
+  if ((prec == TUCKER_BF16 || (prec == TUCKER_FP32 && fp32_split_products() && v.n > 256)) &&
       power_split_chunks(v, l, prec) > 0)
     return PP_SPLIT;
   if (power_fused_splits(v, l, prec) > 0 && !(fp32_split_products() && v.n <= 256)) return PP_FUSED_F32;
@@ -2299,8 +2300,10 @@ static void ps_launch(const View3& v, const float* X, const __bf16* Qp, int l, f
 template <int NP, int JT>
 static void ps_dispatch_q(const View3& v, const float* X, const __bf16* Qp, int l, float* part, int NC, int* ctr,
                           int base, int* err, hipStream_t st) {
-  const int64_t nq = (v.n + 31) / 32;  // staged 32-row groups: 16, 24 or 32 (n > 256)
-  if (nq <= 16) ps_launch<NP, JT, 16>(v, X, Qp, l, part, NC, ctr, base, err, st);
+  const int64_t nq = (v.n + 31) / 32;  // staged 32-row groups: 4, 8, 16, 24 or 32
+  if (NP == 1 && nq <= 4) ps_launch<NP, JT, 4>(v, X, Qp, l, part, NC, ctr, base, err, st);
+  else if (NP == 1 && nq <= 8) ps_launch<NP, JT, 8>(v, X, Qp, l, part, NC, ctr, base, err, st);
+  else if (nq <= 16) ps_launch<NP, JT, 16>(v, X, Qp, l, part, NC, ctr, base, err, st);
   else if (nq <= 24) ps_launch<NP, JT, 24>(v, X, Qp, l, part, NC, ctr, base, err, st);
   else ps_launch<NP, JT, 32>(v, X, Qp, l, part, NC, ctr, base, err, st);
 }
