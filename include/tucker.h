@@ -206,10 +206,14 @@ int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_
  * place: if Sigma(l,l) > alpha then alpha = (Sigma(l,l) + alpha) / 2.
  * `out` must not alias Q. EINVAL / EWORKSPACE as for tucker_sketch, plus
  * null Q, alpha or (non-raw) sigma.
- * FP32 unfoldings viewed as P x n x S with S >= 64, S and n multiples of 4,
- * n <= 512, n <= m and l <= 48 form both products in one pass over X (the
- * same pass the solves use for their FP32 power steps); the others run the
- * two products one after the other. */
+ * Unfoldings viewed as P x n x S with n <= m form both products in one pass
+ * over X (the same pass the solves use for their power steps) where a
+ * one-pass kernel applies: on the BF16 matrix cores for S >= 32, S a multiple
+ * of 4, l <= 64 and n <= 1024 (BF16 operands at any such n; FP32 products,
+ * taken through the three-piece BF16 split, at n > 256); with FP32
+ * instructions when the solve's options select native FP32 products (S >= 64,
+ * S and n multiples of 4, n <= 512, l <= 48). The others run the two products
+ * one after the other. */
 int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X, int64_t l,
                          const void* Q, double* alpha, int32_t flags, tucker_precision prec,
                          void* out, double* sigma, void* ws, size_t ws_bytes, hipStream_t stream);
@@ -372,8 +376,9 @@ int tucker_rthosvd_pve(const tucker_shape* shape, const void* A, const int64_t* 
 #define TUCKER_KC_ORTH 2        /* one whole svd(Y, econ) sequence */
 #define TUCKER_KC_FILL 3        /* Gaussian test-matrix fill */
 #define TUCKER_KC_REDUCE 4      /* split-partial reduction with the -alpha Q term */
-#define TUCKER_KC_POWERSTEP 5   /* X_(k) (X_(k)^T Q) in one pass over X (FP32 power steps, S > 1, n <= 512,
-                                   l <= 48); bytes: X once plus Q; flops 4 * numel * l */
+#define TUCKER_KC_POWERSTEP 5   /* X_(k) (X_(k)^T Q) in one pass over X (the power steps that take a
+                                   one-pass kernel, see tucker_shifted_power); bytes: X once plus Q;
+                                   flops 4 * numel * l */
 /* EINVAL: bad class or capacity outside 1..2^20. EDEVICE: event creation failed. */
 int tucker_timing_enable(int32_t kernel_class, int32_t capacity);
 /* Waits for the recorded events; total device milliseconds, launch count,

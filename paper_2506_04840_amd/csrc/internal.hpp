@@ -115,19 +115,22 @@ int colreduce_norm_slots(const View3& v, int nsplit);
 
 // Both products of a power step, Y' = X_(k) (X_(k)^T Q) as split partials
 // (part[split][i][j], FP32 or FP64 as the column reduction's), from Q given
-// j-major in the storage precision (qt[j * n + i]). FP32 steps that the
-// fused pass takes (power_fused_launch_splits > 0: S >= 64, n <= 512, l <= 48,
-// and n > 256 where FP32 products go through the BF16 split) run one pass
-// over X (part needs power_fused_part_bytes; ctr: a chunk counter, zeroed
-// together with *fused_count = 0 before a series of launches on this (v, l);
-// each fused launch counts itself in *fused_count; z may be null); the others
-// run the row contraction into z (j-major, P S x l; hipErrorInvalidValue when
-// z is null) and the column reduction with nsplit splits. *nsplit_used: the
-// split count to reduce. err (may be null): a fused launch whose counter
-// disagrees with the base ors TUCKER_INFO_INTERNAL into it.
-// power_fused_splits: the chunk count of the fused pass for the shape alone
-// (it sizes the partials); power_fused_launch_splits: the same, or 0 where the
-// launch takes the two split kernels instead.
+// j-major in the storage precision (qt[j * n + i]). Steps that a one-pass
+// kernel takes (power_fused_launch_splits > 0: on the BF16 matrix cores for
+// BF16 operands at n <= 1024 and FP32 products through the split at
+// 256 < n <= 1024, S >= 32, l <= 64; with FP32 instructions for native FP32
+// products, S >= 64, n <= 512, l <= 48) run one pass over X (part needs
+// power_fused_part_bytes, which also holds Q's pieces; ctr: a chunk counter,
+// zeroed together with *fused_count = 0 before a series of launches on this
+// (v, l); each one-pass launch counts itself in *fused_count; z may be null);
+// the others run the row contraction into z (j-major, P S x l;
+// hipErrorInvalidValue when z is null) and the column reduction with nsplit
+// splits. *nsplit_used: the split count to reduce. err (may be null): a
+// one-pass launch whose counter disagrees with the base ors
+// TUCKER_INFO_INTERNAL into it.
+// power_fused_splits: the chunk count of the FP32 one-pass kernel for the
+// shape alone; power_fused_launch_splits: the chunk count of the pass the
+// launch takes, or 0 for the two-kernel path.
 int power_fused_splits(const View3& v, int l, tucker_precision prec);
 int power_fused_launch_splits(const View3& v, int l, tucker_precision prec);
 size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec);
