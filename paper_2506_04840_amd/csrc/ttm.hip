@@ -1823,15 +1823,22 @@ hipError_t launch_transpose_f32(const float* Q, int64_t n, int l, float* Qt, hip
   return hipGetLastError();
 }
 
+// The one-pass kernels hold a whole CU per workgroup (LDS, or every register)
+// for the launch's duration. Their grids stop short of the 256 CUs so that a
+// small SVD launched beside them on a side stream always finds a CU (when it
+// found none, it waited for the whole power step: 2.3 ms for a 0.5 ms SVD at
+// 1000^3): at most 248 chunks plus four spare workgroups, 252 CUs.
+constexpr int64_t kOnePassChunks = 248;
+
 // Chunks (split partials) of the fused power step: the fewest rounds over the
-// blocks with at most 252 chunks (one workgroup per CU of the 256), then as
+// blocks with at most kOnePassChunks chunks (one workgroup per CU), then as
 // few chunks as give that many rounds. A function of the shape only, so the
 // plan that sizes the partials and the launch agree. 0 when the fused kernel
 // does not apply.
 int power_fused_splits(const View3& v, int l, tucker_precision prec) {
   if (prec != TUCKER_FP32 || v.S < 64 || v.S % 4 != 0 || v.n % 4 != 0 || v.n > PF_NMAX || l > 48 || l < 1)
     return 0;
-  constexpr int64_t kMaxGroups = 256 - 4;
+  constexpr int64_t kMaxGroups = kOnePassChunks;
   const int64_t nblocks = v.P * ((v.S + 63) / 64);
   const int64_t rounds = (nblocks + kMaxGroups - 1) / kMaxGroups;
   return (int)((nblocks + rounds - 1) / rounds);
@@ -2218,7 +2225,7 @@ __global__ __launch_bounds__(256) void k_q_pieces(const float* __restrict__ Qt, 
 static int power_split_chunks(const View3& v, int l, tucker_precision prec) {
   if ((prec != TUCKER_FP32 && prec != TUCKER_BF16) || v.S < 32 || v.S % 4 != 0 || v.n > PS_NMAX || l < 1 || l > 64)
     return 0;
-  constexpr int64_t kMaxGroups = 256 - 4;
+  constexpr int64_t kMaxGroups = kOnePassChunks;
   const int64_t nblocks = v.P * ((v.S + 31) / 32);
   const int64_t rounds = (nblocks + kMaxGroups - 1) / kMaxGroups;
   return (int)((nblocks + rounds - 1) / rounds);
@@ -2269,8 +2276,9 @@ size_t power_fused_part_bytes(const View3& v, int l, tucker_precision prec) {
 }
 
 // Grid: the chunks plus four spare workgroups (at most one per CU), which
-// take the chunks of workgroups that start late.
-static int pf_grid(int NC) { return std::min(256, NC + 4); }
+// take the chunks of workgroups that start late; at most 252 (see
+// kOnePassChunks).
+static int pf_grid(int NC) { return std::min<int>(kOnePassChunks + 4, NC + 4); }
 
 template <int JT, int GW>
 static void pf_launch(const View3& v, const float* X, const float* Qt, int l, float* part, int NC, int* ctr,
