@@ -481,12 +481,12 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   const bool log_sketch = q > 0 && side != nullptr;
   const OrthWs ows0 = log_sketch ? orth_log_set(ows) : orth_step_set(ows, 0);
   // Step 1 factors the unrotated iterate, so that it need not wait for the
-  // sketch's SVD; its own SVD then starts from a dense R (at l = 60 it took
-  // 0.8-2.3 ms beside the products, half a millisecond of it on step 2's
-  // path at 1000^3). In a mode whose products take longer than the sketch's
-  // SVD, step 1 waits for that SVD after its products and rotates its
-  // iterate by the sketch's J like every later step (the wait is hidden behind
-  // the products, and step 1's SVD starts from a nearly diagonal R).
+  // sketch's SVD; its own SVD then starts from a dense R (about 0.5 ms at
+  // l = 60, against 0.13 ms from a rotated iterate). In a mode whose products
+  // take longer than the sketch's SVD, step 1 waits for that SVD after its
+  // products and rotates its iterate by the sketch's J like every later step
+  // (the wait is hidden behind the products, and step 1's SVD starts from a
+  // nearly diagonal R).
   const bool rot1 = log_sketch && (double)v.P * (double)v.n * (double)v.S >= kRotateStep1Numel;
   if (e == hipSuccess) e = launch_orth_qr(n, l, w.y64, nullptr, step_prec(0), w.qt, ows0, cseed, 0, st);
   if (e == hipSuccess && log_sketch) {
