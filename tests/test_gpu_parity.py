@@ -131,7 +131,10 @@ def test_power_step_raw_matches_oracle(T, prec, dims, mode, l):
 # 204), P > 1 (modes in the middle), n = 512, a row half with no group
 # (n = 16) and widths of one to three 16-column tiles.
 FUSED = [((400, 130, 128), 0, 40), ((100, 36, 50), 0, 17), ((30, 400, 100), 1, 48), ((8, 44, 68, 3), 1, 1),
-         ((8, 44, 68, 3), 1, 44), ((512, 70, 40), 0, 48), ((16, 12, 64), 0, 16), ((260, 24, 20), 0, 33)]
+         ((8, 44, 68, 3), 1, 44), ((512, 70, 40), 0, 48), ((16, 12, 64), 0, 16), ((260, 24, 20), 0, 33),
+         # the split one-pass kernel's limits: 1024 rows with no padding and l = 64; 257 rows (one row past
+         # a staged group), one 32-column block and l = 1; P > 1 with a 4-column last block
+         ((1024, 36, 4), 0, 64), ((257, 8, 4), 0, 1), ((3, 260, 36), 1, 17)]
 
 
 @pytest.mark.parametrize("dims,mode,l", FUSED)
@@ -1015,7 +1018,7 @@ _AWKWARD = [
     ((100, 262208), 0, 60),
     # n > 256: the one-pass power step on the BF16 matrix cores at each staged
     # row count (512, 768, 1024 rows), ragged rows and last blocks, P > 1
-    ((300, 40, 36), 0, 24), ((700, 37, 12), 0, 60), ((6, 1000, 44), 1, 40),
+    ((300, 40, 36), 0, 24), ((700, 37, 12), 0, 60), ((6, 1000, 44), 1, 40), ((1024, 36, 4), 0, 64),
 ]
 
 
