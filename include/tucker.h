@@ -393,8 +393,8 @@ int tucker_timing_disable(void);
 
 /* ---- Batched solves: many small shifted randomized ST-HOSVDs at once ------
  * Algorithm 3 for a set of requests of one order d and one power count q,
- * FP32 storage (Section 3.1; the same arithmetic as tucker_rsthosvd with FP32,
- * shift as given). Every phase of the method runs as one persistent launch
+ * FP32 storage (Section 3.1; the same arithmetic as tucker_rsthosvd with FP32
+ * and the default TUCKER_FP32_SPLIT products, shift as given). Every phase of the method runs as one persistent launch
  * over all requests of the batch (a fixed grid looping over a table of work
  * items), so a batch costs the same number of launches as one request.
  *

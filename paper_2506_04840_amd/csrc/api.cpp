@@ -886,13 +886,13 @@ std::vector<BatchKind> batch_phases(int d, int q) {
   std::vector<BatchKind> ph{BK_INIT};
   const BatchKind orth[] = {BK_GRAM, BK_PASS, BK_PASS, BK_PASS, BK_SVD};
   for (int k = 0; k < d; ++k) {
-    for (BatchKind b : {BK_FILL, BK_CR_LDS, BK_CR_COLS, BK_REDUCE}) ph.push_back(b);
+    for (BatchKind b : {BK_FILL, BK_CR_SPLIT, BK_CR_COLS, BK_REDUCE}) ph.push_back(b);
     for (BatchKind b : orth) ph.push_back(b);
     for (int t = 1; t <= q; ++t) {
-      for (BatchKind b : {BK_RC_ROWS, BK_RC_COLS, BK_CR_LDS, BK_CR_COLS, BK_REDUCE}) ph.push_back(b);
+      for (BatchKind b : {BK_RC_SPLIT, BK_RC_COLS, BK_CR_SPLIT, BK_CR_COLS, BK_REDUCE}) ph.push_back(b);
       for (BatchKind b : orth) ph.push_back(b);
     }
-    for (BatchKind b : {BK_ROTATE, BK_SIGNFIX, BK_RC_ROWS, BK_RC_COLS}) ph.push_back(b);
+    for (BatchKind b : {BK_ROTATE, BK_SIGNFIX, BK_RC_SPLIT, BK_RC_COLS}) ph.push_back(b);
   }
   return ph;
 }
@@ -935,8 +935,8 @@ int batch_item_plan(const tucker_batch_item* it, int32_t p, int32_t q, Plan* pl)
 void batch_phase_work(BatchKind kind, int k, int role, const Plan& pl, double* bytes, double* flops) {
   const View3 v = pl.v[k];
   const double N = (double)v.P * v.n * v.S, m = (double)pl.m[k];
-  const bool cr = (kind == BK_CR_LDS && v.S > 1) || (kind == BK_CR_COLS && v.S == 1);
-  const bool rc = (kind == BK_RC_ROWS && v.S > 1) || (kind == BK_RC_COLS && v.S == 1);
+  const bool cr = (kind == BK_CR_SPLIT && v.S > 1) || (kind == BK_CR_COLS && v.S == 1);
+  const bool rc = (kind == BK_RC_SPLIT && v.S > 1) || (kind == BK_RC_COLS && v.S == 1);
   if (!cr && !rc) return;
   const double w = rc && role == 1 ? (double)pl.r[k] : (double)pl.l[k];
   *bytes += 4.0 * (N + m * w);
@@ -944,7 +944,7 @@ void batch_phase_work(BatchKind kind, int k, int role, const Plan& pl, double* b
 }
 
 // Splits of a request's column reduction inside a batch: the batch already
-// fills the device, so a split covers at least 32 stages (S > 1) or 8 steps
+// fills the device, so a split covers at least 2048 columns (S > 1) or 8 steps
 // (S == 1), and never more splits than the request's own workspace holds.
 // Depends on the request's shape only, so a request computes the same alone
 // and in any mix.
@@ -990,13 +990,16 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
       b->cols = l;
       return (m * ((l + 3) / 4) + 255) / 256;
     }
-    case BK_CR_LDS:
+    case BK_CR_SPLIT:
     case BK_CR_COLS: {
       int64_t nsteps, spp;
       int nrb;
-      cr_geometry(v, &nsteps, &spp, &nrb);
-      if (kind == BK_CR_LDS) {
-        BCrLds* b = (BCrLds*)dst;
+      if (kind == BK_CR_SPLIT)
+        cr_split_geometry(v, &nsteps, &spp, &nrb);
+      else
+        cr_geometry(v, &nsteps, &spp, &nrb);
+      if (kind == BK_CR_SPLIT) {
+        BCrSplit* b = (BCrSplit*)dst;
         b->X = (const float*)X;
         b->Bt = (const float*)w.omz;
         b->part = (float*)w.part;
@@ -1008,7 +1011,7 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
         b->l = l;
         b->nsplit = nsplit;
         b->nrb = nrb;
-        return v.S > 1 ? cr_lds_items(n, nsplit) : 0;
+        return v.S > 1 ? cr_split_items(n, nsplit) : 0;
       }
       BCrCols* b = (BCrCols*)dst;
       b->X = (const float*)X;
@@ -1032,19 +1035,17 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
       b->nsplit = nsplit;
       return (n * l + 31) / 32;
     }
-    case BK_RC_ROWS:
+    case BK_RC_SPLIT:
     case BK_RC_COLS: {
       // power step (role 0): Z = X_(k)^T Q3, j-major; core (role 1): X x_k U_k^T
       const bool core = role == 1;
       const int lw = core ? r : l;
       const void* W = core ? w.ut : w.qt;
       void* out = core ? (k == d - 1 ? it.G : w.xbuf[k & 1]) : w.omz;
-      if (kind == BK_RC_ROWS) {
-        BRcRows* b = (BRcRows*)dst;
-        int ksplit;
+      if (kind == BK_RC_SPLIT) {
+        BRcSplit* b = (BRcSplit*)dst;
         int64_t tpp;
-        const int64_t ntiles = rc_rows_tiles(v, &ksplit, &tpp);
-        ksplit = 0;  // in a batch each wave owns a tile and all n rows (longer streams, no LDS reduction)
+        const int64_t ntiles = rc_split_tiles(v, &tpp);  // each wave owns a tile and all n rows
         b->X = (const float*)X;
         b->W = (const float*)W;
         b->out = (float*)out;
@@ -1057,8 +1058,7 @@ int64_t batch_desc(BatchKind kind, int k, int t, int role, const Plan& pl, const
         b->osp = core ? (int64_t)lw * v.S : v.S;
         b->osj = core ? v.S : m;
         b->lw = lw;
-        b->ksplit = ksplit;
-        return v.S > 1 ? (ksplit ? ntiles : (ntiles + 3) / 4) : 0;
+        return v.S > 1 ? (ntiles + 3) / 4 : 0;
       }
       BRcCols* b = (BRcCols*)dst;
       b->X = (const float*)X;
@@ -1538,8 +1538,8 @@ int tucker_batch_step(const void* plan, hipStream_t stream) {
       e = launch_batch_orth(kind, h->lclass, hdr, desc, stream);
       continue;
     }
-    const int cls = (kind == BK_CR_LDS || kind == BK_CR_COLS) ? KC_COLREDUCE
-                    : (kind == BK_RC_ROWS || kind == BK_RC_COLS) ? KC_ROWCONTRACT
+    const int cls = (kind == BK_CR_SPLIT || kind == BK_CR_COLS) ? KC_COLREDUCE
+                    : (kind == BK_RC_SPLIT || kind == BK_RC_COLS) ? KC_ROWCONTRACT
                     : kind == BK_REDUCE ? KC_REDUCE : KC_FILL;
     TimingScope ts(cls, stream, pr[i].bytes, pr[i].flops, true);
     e = launch_batch_ttm(kind, h->lclass, hdr, desc, stream);

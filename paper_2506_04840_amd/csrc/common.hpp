@@ -144,8 +144,8 @@ __device__ __forceinline__ void lds_barrier() {
 // so the request of the previous item bounds the search for the next one
 // (no search while the item stays in the same request). A barrier separates
 // consecutive items so a body may leave some waves early and reuse LDS.
-template <typename D, void (*F)(const D&, int)>
-__global__ __launch_bounds__(256) void k_persist(const int* __restrict__ hdr, const D* __restrict__ desc) {
+template <typename D, void (*F)(const D&, int), int MINB = 1>
+__global__ __launch_bounds__(256, MINB) void k_persist(const int* __restrict__ hdr, const D* __restrict__ desc) {
   const int nreq = hdr[0];
   const int total = hdr[1 + nreq];
   int b = 0;

@@ -287,7 +287,7 @@ struct BFill {
   uint32_t mode;
   int32_t cols;
 };
-struct BCrLds {
+struct BCrSplit {
   const float* X;
   const float* Bt;
   float* part;
@@ -309,12 +309,12 @@ struct BReduce {
   int64_t nl;
   int32_t nsplit;
 };
-struct BRcRows {
+struct BRcSplit {
   const float* X;
   const float* W;
   float* out;
   int64_t n, S, wsi, wsj, tpp, ntiles, osp, osj;
-  int32_t lw, ksplit;
+  int32_t lw;
 };
 struct BRcCols {
   const float* X;
@@ -371,16 +371,17 @@ struct BSignfix {
   int32_t l, r;
 };
 enum BatchKind {
-  BK_INIT = 0, BK_FILL, BK_CR_LDS, BK_CR_COLS, BK_REDUCE, BK_RC_ROWS, BK_RC_COLS,
+  BK_INIT = 0, BK_FILL, BK_CR_SPLIT, BK_CR_COLS, BK_REDUCE, BK_RC_SPLIT, BK_RC_COLS,
   BK_GRAM, BK_PASS, BK_SVD, BK_ROTATE, BK_SIGNFIX, BK_COUNT
 };
 size_t batch_desc_bytes(BatchKind kind);
 hipError_t launch_batch_ttm(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
 hipError_t launch_batch_orth(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
 // Work items (workgroups) of one request for the geometry-driven kinds.
-int64_t cr_lds_items(int64_t n, int nsplit);
+int64_t cr_split_items(int64_t n, int nsplit);
 int64_t cr_cols_items(int64_t n, int nsplit);
 void cr_geometry(const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks);
-int64_t rc_rows_tiles(const View3& v, int* ksplit, int64_t* tpp);
+void cr_split_geometry(const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks);
+int64_t rc_split_tiles(const View3& v, int64_t* tpp);
 
 }  // namespace tk

@@ -1254,10 +1254,10 @@ size_t batch_desc_bytes(BatchKind kind) {
   switch (kind) {
     case BK_INIT: return sizeof(BInit);
     case BK_FILL: return sizeof(BFill);
-    case BK_CR_LDS: return sizeof(BCrLds);
+    case BK_CR_SPLIT: return sizeof(BCrSplit);
     case BK_CR_COLS: return sizeof(BCrCols);
     case BK_REDUCE: return sizeof(BReduce);
-    case BK_RC_ROWS: return sizeof(BRcRows);
+    case BK_RC_SPLIT: return sizeof(BRcSplit);
     case BK_RC_COLS: return sizeof(BRcCols);
     case BK_GRAM: return sizeof(BGram);
     case BK_PASS: return sizeof(BPass);

@@ -467,11 +467,13 @@ struct BfProducts<3> {
   static constexpr int A[6] = {2, 1, 0, 1, 0, 0}, B[6] = {0, 1, 2, 0, 1, 0};
 };
 
+// The body takes one (split, 128-row block) item; the kernel below maps its
+// workgroups onto items XCD by XCD, the batched launch through its item table.
 template <int NP, int NJ, int EDGE, bool NORM>
-__global__ __launch_bounds__(256, 2) void k_cr_split(const float* __restrict__ X, const float* __restrict__ Bt, int64_t n,
-                                                  int64_t S, int l, int64_t m, int64_t spp, int64_t nsteps,
-                                                  int nsplit, int nrblocks, int nslots, float* __restrict__ part,
-                                                  double* __restrict__ npart) {
+__device__ __forceinline__ void cr_split_body(const float* __restrict__ X, const float* __restrict__ Bt, int64_t n,
+                                              int64_t S, int l, int64_t m, int64_t spp, int64_t nsteps, int nsplit,
+                                              int nslots, float* __restrict__ part, double* __restrict__ npart,
+                                              int split, int rb) {
   constexpr int KT = 32;
   constexpr int NJB = (NJ + 1) & ~1;       // Bt rows staged per stage: whole 32-row units
   constexpr int BU = NJB / 2;              // 16-byte Bt units per thread per stage
@@ -479,8 +481,6 @@ __global__ __launch_bounds__(256, 2) void k_cr_split(const float* __restrict__ X
   using PR = BfProducts<NP>;
   __shared__ __align__(16) __bf16 bs[2][NP][16 * NJB][LS];
   __shared__ double nred[4];
-  int split, rb;
-  if (!xcd_decode((int)blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
   const int64_t r0 = (int64_t)rb * 128 + 32 * wave;
@@ -707,6 +707,16 @@ __global__ __launch_bounds__(256, 2) void k_cr_split(const float* __restrict__ X
         const int col = 16 * u + mm;
         if (row < n && col < l) part[((int64_t)split * n + row) * l + col] = acc[h][u][v];
       }
+}
+
+template <int NP, int NJ, int EDGE, bool NORM>
+__global__ __launch_bounds__(256, 2) void k_cr_split(const float* __restrict__ X, const float* __restrict__ Bt, int64_t n,
+                                                  int64_t S, int l, int64_t m, int64_t spp, int64_t nsteps,
+                                                  int nsplit, int nrblocks, int nslots, float* __restrict__ part,
+                                                  double* __restrict__ npart) {
+  int split, rb;
+  if (!xcd_decode((int)blockIdx.x, nsplit, nrblocks, &split, &rb)) return;
+  cr_split_body<NP, NJ, EDGE, NORM>(X, Bt, n, S, l, m, spp, nsteps, nsplit, nslots, part, npart, split, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -1234,15 +1244,16 @@ constexpr int RCS_COLS = 32;  // output columns s per wave
 typedef float f2u_t __attribute__((ext_vector_type(2), aligned(4)));
 
 template <int NP, int NJ, bool WVEC>
-__global__ __launch_bounds__(256) void k_rc_split(const float* __restrict__ X, const float* __restrict__ W, int64_t n,
-                                                  int64_t S, int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
-                                                  int64_t ntiles, float* __restrict__ out, int64_t osp, int64_t osj) {
+__device__ __forceinline__ void rc_split_body(const float* __restrict__ X, const float* __restrict__ W, int64_t n,
+                                              int64_t S, int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
+                                              int64_t ntiles, float* __restrict__ out, int64_t osp, int64_t osj,
+                                              int bid) {
   constexpr int LS = 32 + 8;  // padded LDS row (BF16 elements)
   using PR = BfProducts<NP>;
   __shared__ __align__(16) __bf16 ws[2][NP][16 * NJ][LS];
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int mm = lane & 15, g = lane >> 4;
-  const int64_t traw = (int64_t)blockIdx.x * 4 + wave;
+  const int64_t traw = (int64_t)bid * 4 + wave;
   const bool live = traw < ntiles;
   const int64_t tile = live ? traw : ntiles - 1;
   const int64_t p = tile / tiles_per_p;
@@ -1406,6 +1417,13 @@ __global__ __launch_bounds__(256) void k_rc_split(const float* __restrict__ X, c
       }
     }
   }
+}
+
+template <int NP, int NJ, bool WVEC>
+__global__ __launch_bounds__(256) void k_rc_split(const float* __restrict__ X, const float* __restrict__ W, int64_t n,
+                                                  int64_t S, int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
+                                                  int64_t ntiles, float* __restrict__ out, int64_t osp, int64_t osj) {
+  rc_split_body<NP, NJ, WVEC>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, out, osp, osj, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -2601,13 +2619,19 @@ hipError_t launch_convert_from_f64(tucker_precision prec, const double* src, int
 void cr_geometry(const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
   cr_geom(TUCKER_FP32, v, nsteps, spp, nrblocks);
 }
-int64_t cr_lds_items(int64_t n, int nsplit) { return (int64_t)nsplit * ((n + 63) / 64); }
+// A batch's column reduction (S > 1) runs the split kernel's body: stages of
+// 32 columns, items of 128 rows per split.
+void cr_split_geometry(const View3& v, int64_t* nsteps, int64_t* spp, int* nrblocks) {
+  *spp = (v.S + 31) / 32;
+  *nsteps = v.P * *spp;
+  *nrblocks = (int)((v.n + 127) / 128);
+}
+int64_t cr_split_items(int64_t n, int nsplit) { return (int64_t)nsplit * ((n + 127) / 128); }
 int64_t cr_cols_items(int64_t n, int nsplit) { return (int64_t)nsplit * ((n + 255) / 256); }
-int64_t rc_rows_tiles(const View3& v, int* ksplit, int64_t* tpp) {
-  *tpp = (v.S + 63) / 64;
-  const int64_t ntiles = v.P * *tpp;
-  *ksplit = ntiles < 4096 ? 1 : 0;
-  return ntiles;
+// A batch's row contraction (S > 1): 32-column tiles, one per wave.
+int64_t rc_split_tiles(const View3& v, int64_t* tpp) {
+  *tpp = (v.S + RCS_COLS - 1) / RCS_COLS;
+  return v.P * *tpp;
 }
 
 __device__ __forceinline__ void b_fill(const BFill& d, int bid) {
@@ -2628,11 +2652,14 @@ __device__ __forceinline__ void batch_split_rb(int it, int nsplit, int nrb, int*
     *rb = it % nrb;
   }
 }
+// FP32 products through the three-piece split (the one-request path's
+// default); EDGE 2 takes any S and row address.
 template <int NJ>
-__device__ __forceinline__ void b_cr_lds(const BCrLds& d, int bid) {
+__device__ __forceinline__ void b_cr_split(const BCrSplit& d, int bid) {
   int split, rb;
   batch_split_rb(bid, d.nsplit, d.nrb, &split, &rb);
-  cr_lds_body<MF_F32, NJ, 2>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, d.part, split, rb);
+  cr_split_body<3, NJ, 2, false>(d.X, d.Bt, d.n, d.S, d.l, d.m, d.spp, d.nsteps, d.nsplit, 0, d.part, nullptr, split,
+                                 rb);
 }
 template <int NJ>
 __device__ __forceinline__ void b_cr_cols(const BCrCols& d, int bid) {
@@ -2644,10 +2671,8 @@ __device__ __forceinline__ void b_reduce(const BReduce& d, int bid) {
   reduce_splits_body<float, double>(d.part, d.nsplit, d.nl, d.qsub, d.alpha, d.Y, bid);
 }
 template <int NJ>
-__device__ __forceinline__ void b_rc_rows(const BRcRows& d, int bid) {
-  // a batch always gives each wave a tile and all n rows (d.ksplit is 0)
-  rc_rows_body<MF_F32, NJ, true, false>(d.X, d.W, d.n, d.S, d.lw, d.wsi, d.wsj, d.tpp, d.ntiles, d.out, d.osp,
-                                        d.osj, bid);
+__device__ __forceinline__ void b_rc_split(const BRcSplit& d, int bid) {
+  rc_split_body<3, NJ, true>(d.X, d.W, d.n, d.S, d.lw, d.wsi, d.wsj, d.tpp, d.ntiles, d.out, d.osp, d.osj, bid);
 }
 template <int NJ>
 __device__ __forceinline__ void b_rc_cols(const BRcCols& d, int bid) {
@@ -2656,23 +2681,25 @@ __device__ __forceinline__ void b_rc_cols(const BRcCols& d, int bid) {
 
 template <int NJ>
 static hipError_t batch_ttm_nj(BatchKind kind, const int* hdr, const void* desc, hipStream_t st) {
-#define TK_PERSIST(D, F)                                                                                      \
+#define TK_PERSIST_N(D, F, MINB)                                                                              \
   {                                                                                                           \
-    auto kern = k_persist<D, F>;                                                                              \
+    auto kern = k_persist<D, F, MINB>;                                                                        \
     TK_LAUNCH(kern, dim3(resident_grid(kern)), dim3(256), 0, st, hdr, (const D*)desc);                        \
   }                                                                                                           \
   break
+#define TK_PERSIST(D, F) TK_PERSIST_N(D, F, 1)
   switch (kind) {
     case BK_FILL: TK_PERSIST(BFill, b_fill);
-    case BK_CR_LDS: TK_PERSIST(BCrLds, b_cr_lds<NJ>);
+    case BK_CR_SPLIT: TK_PERSIST_N(BCrSplit, b_cr_split<NJ>, 2);  // the split kernel's occupancy
     case BK_CR_COLS: TK_PERSIST(BCrCols, b_cr_cols<NJ>);
     case BK_REDUCE: TK_PERSIST(BReduce, b_reduce);
-    case BK_RC_ROWS: TK_PERSIST(BRcRows, b_rc_rows<NJ>);
+    case BK_RC_SPLIT: TK_PERSIST(BRcSplit, b_rc_split<NJ>);
     case BK_RC_COLS: TK_PERSIST(BRcCols, b_rc_cols<NJ>);
     default:
       return hipErrorInvalidValue;
   }
 #undef TK_PERSIST
+#undef TK_PERSIST_N
   return hipGetLastError();
 }
 

@@ -25,8 +25,8 @@ CLASSES = {
     "rowcontract": r"tk::k_rc_(rows|cols|split)<",
     "powerstep": r"tk::k_power_(fused|split)<",
     # persistent batched kernels: the profiler may print them mangled
-    "batched_colreduce": r"k_persist<tk::BCr(Lds|Cols),|k_persistINS_\d+BCr(Lds|Cols)E",
-    "batched_rowcontract": r"k_persist<tk::BRc(Rows|Cols),|k_persistINS_\d+BRc(Rows|Cols)E",
+    "batched_colreduce": r"k_persist<tk::BCr(Split|Lds|Cols),|k_persistINS_\d+BCr(Split|Lds|Cols)E",
+    "batched_rowcontract": r"k_persist<tk::BRc(Split|Rows|Cols),|k_persistINS_\d+BRc(Split|Rows|Cols)E",
 }
 COPY = r"__amd_rocclr_copyBuffer"
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
