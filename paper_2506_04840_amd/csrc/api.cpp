@@ -907,7 +907,7 @@ size_t batch_table_layout(int cap, int d, int q, std::vector<PhaseRec>* recs) {
     r.pad = 0;
     r.bytes = r.flops = 0.0;
     r.hdr_off = off;
-    off += align_up((size_t)(cap + 2) * sizeof(int));
+    off += align_up((size_t)(cap + 10) * sizeof(int));  // item table and the 8 claim counters
     r.desc_off = off;
     off += align_up((size_t)cap * batch_desc_bytes(k));
     if (recs) recs->push_back(r);
@@ -1494,6 +1494,7 @@ int tucker_batch_plan(int32_t capacity, int32_t order, int32_t lclass, int32_t n
       batch_phase_work((BatchKind)r.kind, k, role, pls[b], &r.bytes, &r.flops);
     }
     hdr[1 + nitems] = (int)acc;
+    for (int x = 0; x < 8; ++x) hdr[2 + nitems + x] = 0;  // claim counters, zero at every upload
     return acc < (1ll << 31);
   };
   bool ok = fill_phase(0, 0, 0);  // init
@@ -1530,7 +1531,7 @@ int tucker_batch_step(const void* plan, hipStream_t stream) {
   hipError_t e = hipMemcpyAsync(h->ws, img, h->table_bytes, hipMemcpyHostToDevice, stream);
   for (int i = 0; i < h->nphases && e == hipSuccess; ++i) {
     const BatchKind kind = (BatchKind)pr[i].kind;
-    const int* hdr = (const int*)(h->ws + pr[i].hdr_off);
+    int* hdr = (int*)(h->ws + pr[i].hdr_off);
     const void* desc = h->ws + pr[i].desc_off;
     const bool orth = kind == BK_INIT || kind == BK_GRAM || kind == BK_PASS || kind == BK_SVD || kind == BK_ROTATE ||
                       kind == BK_SIGNFIX;

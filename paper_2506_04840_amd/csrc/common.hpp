@@ -140,16 +140,30 @@ __device__ __forceinline__ void lds_barrier() {
 // Persistent batched launch: the grid's workgroups loop over the work items
 // of all requests in the table (hdr[0] = requests, hdr[1 + b] = first item of
 // request b, hdr[1 + nreq] = total) and run the request's workgroup body F
-// with the request-local block index. A workgroup's items only move forward,
-// so the request of the previous item bounds the search for the next one
-// (no search while the item stays in the same request). A barrier separates
+// with the request-local block index. A workgroup starts with the item of its
+// own index. With CLAIM (items long against an atomic's round trip: the
+// product phases) it then claims the next unclaimed item of its residue class
+// mod 8 (the class of the XCD it runs on, so items that share an operand
+// through the index mod 8 keep sharing that XCD's L2) from the class's counter
+// hdr[2 + nreq + class], which every upload of the table sets to zero:
+// workgroups that drew short items take more, and the launch ends with the
+// last item rather than with the longest static share. Without CLAIM it
+// strides by the grid. The result of an item does not depend on which
+// workgroup runs it. A workgroup's items only move forward, so the request of
+// the previous item bounds the search for the next one. A barrier separates
 // consecutive items so a body may leave some waves early and reuse LDS.
-template <typename D, void (*F)(const D&, int), int MINB = 1>
-__global__ __launch_bounds__(256, MINB) void k_persist(const int* __restrict__ hdr, const D* __restrict__ desc) {
+template <typename D, void (*F)(const D&, int), int MINB = 1, bool CLAIM = false>
+__global__ __launch_bounds__(256, MINB) void k_persist(int* __restrict__ hdr, const D* __restrict__ desc) {
+  __shared__ int next_s;
   const int nreq = hdr[0];
   const int total = hdr[1 + nreq];
+  const int cls = (int)(blockIdx.x & 7);
+  // the first item of the class past the static ones (indices below the grid)
+  const int first = cls + 8 * (((int)gridDim.x - cls + 7) >> 3);
+  int* const ctr = hdr + 2 + nreq + cls;
   int b = 0;
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  int w = (int)blockIdx.x;
+  while (w < total) {
     if (hdr[2 + b] <= w) {
       int lo = b + 1, hi = nreq - 1;
       while (lo < hi) {
@@ -163,6 +177,13 @@ __global__ __launch_bounds__(256, MINB) void k_persist(const int* __restrict__ h
     }
     F(desc[b], w - hdr[1 + b]);
     __syncthreads();
+    if constexpr (CLAIM) {
+      if (threadIdx.x == 0) next_s = first + 8 * atomicAdd(ctr, 1);
+      __syncthreads();
+      w = next_s;
+    } else {
+      w += (int)gridDim.x;
+    }
   }
 }
 

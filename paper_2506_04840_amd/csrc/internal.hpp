@@ -375,8 +375,8 @@ enum BatchKind {
   BK_GRAM, BK_PASS, BK_SVD, BK_ROTATE, BK_SIGNFIX, BK_COUNT
 };
 size_t batch_desc_bytes(BatchKind kind);
-hipError_t launch_batch_ttm(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
-hipError_t launch_batch_orth(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st);
+hipError_t launch_batch_ttm(BatchKind kind, int lclass, int* hdr, const void* desc, hipStream_t st);
+hipError_t launch_batch_orth(BatchKind kind, int lclass, int* hdr, const void* desc, hipStream_t st);
 // Work items (workgroups) of one request for the geometry-driven kinds.
 int64_t cr_split_items(int64_t n, int nsplit);
 int64_t cr_cols_items(int64_t n, int nsplit);

@@ -1269,7 +1269,7 @@ size_t batch_desc_bytes(BatchKind kind) {
 }
 
 template <int LP, int RPT>
-static hipError_t batch_orth_lp(BatchKind kind, const int* hdr, const void* desc, hipStream_t st) {
+static hipError_t batch_orth_lp(BatchKind kind, int* hdr, const void* desc, hipStream_t st) {
 #define TK_PERSIST(D, F)                                                                                      \
   {                                                                                                           \
     auto kern = k_persist<D, F>;                                                                              \
@@ -1290,7 +1290,7 @@ static hipError_t batch_orth_lp(BatchKind kind, const int* hdr, const void* desc
   return hipGetLastError();
 }
 
-hipError_t launch_batch_orth(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st) {
+hipError_t launch_batch_orth(BatchKind kind, int lclass, int* hdr, const void* desc, hipStream_t st) {
   switch (lclass) {
     case 16: return batch_orth_lp<16, 2>(kind, hdr, desc, st);
     case 32: return batch_orth_lp<32, 4>(kind, hdr, desc, st);

@@ -2680,20 +2680,20 @@ __device__ __forceinline__ void b_rc_cols(const BRcCols& d, int bid) {
 }
 
 template <int NJ>
-static hipError_t batch_ttm_nj(BatchKind kind, const int* hdr, const void* desc, hipStream_t st) {
-#define TK_PERSIST_N(D, F, MINB)                                                                              \
+static hipError_t batch_ttm_nj(BatchKind kind, int* hdr, const void* desc, hipStream_t st) {
+#define TK_PERSIST_N(D, F, MINB, CLAIM)                                                                       \
   {                                                                                                           \
-    auto kern = k_persist<D, F, MINB>;                                                                        \
+    auto kern = k_persist<D, F, MINB, CLAIM>;                                                                 \
     TK_LAUNCH(kern, dim3(resident_grid(kern)), dim3(256), 0, st, hdr, (const D*)desc);                        \
   }                                                                                                           \
   break
-#define TK_PERSIST(D, F) TK_PERSIST_N(D, F, 1)
+#define TK_PERSIST(D, F) TK_PERSIST_N(D, F, 1, false)
   switch (kind) {
     case BK_FILL: TK_PERSIST(BFill, b_fill);
-    case BK_CR_SPLIT: TK_PERSIST_N(BCrSplit, b_cr_split<NJ>, 2);  // the split kernel's occupancy
+    case BK_CR_SPLIT: TK_PERSIST_N(BCrSplit, b_cr_split<NJ>, 2, true);  // the split kernel's occupancy
     case BK_CR_COLS: TK_PERSIST(BCrCols, b_cr_cols<NJ>);
     case BK_REDUCE: TK_PERSIST(BReduce, b_reduce);
-    case BK_RC_SPLIT: TK_PERSIST(BRcSplit, b_rc_split<NJ>);
+    case BK_RC_SPLIT: TK_PERSIST(BRcSplit, b_rc_split<NJ>);  // short items: claiming costs more than it evens out
     case BK_RC_COLS: TK_PERSIST(BRcCols, b_rc_cols<NJ>);
     default:
       return hipErrorInvalidValue;
@@ -2703,7 +2703,7 @@ static hipError_t batch_ttm_nj(BatchKind kind, const int* hdr, const void* desc,
   return hipGetLastError();
 }
 
-hipError_t launch_batch_ttm(BatchKind kind, int lclass, const int* hdr, const void* desc, hipStream_t st) {
+hipError_t launch_batch_ttm(BatchKind kind, int lclass, int* hdr, const void* desc, hipStream_t st) {
   switch (lclass) {
     case 16: return batch_ttm_nj<1>(kind, hdr, desc, st);
     case 32: return batch_ttm_nj<2>(kind, hdr, desc, st);
