@@ -945,14 +945,22 @@ void batch_phase_work(BatchKind kind, int k, int role, const Plan& pl, double* b
 
 // Splits of a request's column reduction inside a batch: the batch already
 // fills the device, so a split covers at least 2048 columns (S > 1) or 8 steps
-// (S == 1), and never more splits than the request's own workspace holds.
-// Depends on the request's shape only, so a request computes the same alone
-// and in any mix.
+// (S == 1). A small unfolding (fewer than 8 such splits) takes up to 8 splits of
+// at least 16 stages of 32 columns, as long as the partials (n x l per split)
+// stay within 1/16 of the unfolding's bytes: its few long items would
+// otherwise end the launch. Never more splits than the request's own workspace
+// holds. Depends on the request's shape only, so a request computes the same
+// alone and in any mix.
 int batch_colreduce_splits(const View3& v, int l) {
   int64_t nsteps, spp;
   int nrb;
   cr_geometry(v, &nsteps, &spp, &nrb);
   int64_t ns = std::max<int64_t>(1, nsteps / (v.S > 1 ? 32 : 8));
+  if (v.S > 1 && ns < 8) {
+    int64_t ns32, spp32;
+    cr_split_geometry(v, &ns32, &spp32, &nrb);
+    ns = std::max<int64_t>(ns, std::min<int64_t>({8, ns32 / 16, v.P * v.S / (16 * (int64_t)l)}));
+  }
   ns = std::min<int64_t>(ns, colreduce_splits(v, l));
   // a multiple of 8 from 8 up: the row blocks of one split then share an XCD
   // (and its L2 copy of the split's slice of the skinny operand)
