@@ -200,3 +200,28 @@ def test_serving_loop_width_classes(T):
     for j in out[::3]:
         Gs, Us = _single(T, j.A, j.ranks, j.seed)
         _close(j.G, j.U, Gs, Us, j.A)
+
+
+@pytest.mark.parametrize("dims,ranks,lclass", [((70, 45, 38), (12, 10, 9), 16), ((150, 131, 20), (30, 24, 12), 32)])
+def test_batch_sketch_uses_the_requests_omega(T, dims, ranks, lclass):
+    """The batched sketch and the one-request solve take the same Omega_k
+    (tucker_fill_gaussian of the request's seed and mode). On a Gaussian
+    tensor (flat spectrum) with p = 0 and q = 0 each U_k spans X_(k) Omega_k
+    itself, so another Omega would give another subspace (O(1) apart), while
+    the same Omega gives the same span up to FP32 rounding (dims with
+    S % 4 != 0 and a ragged last stage)."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device="cpu").manual_seed(23)
+    A = torch.randn(dims, generator=g, dtype=torch.float32).to(dev)
+    seed = 4242
+    solver = T.BatchSolver(2, 3, 0, 0, lclass, 1 << 28, "adaptive", "cuda:0")
+    G, U = _outputs(A, ranks)
+    solver.plan([T.BatchSolver.item(A, G, U, ranks, seed)])
+    solver.step()
+    torch.cuda.synchronize()
+    Gs, Us, _ = T.rsthosvd(A, ranks, p=0, q=0, shift="adaptive", seed=seed, precision="fp32")
+    for k in range(3):
+        u, us = U[k].double().cpu(), Us[k].double().cpu()
+        dproj = (u @ u.T - us @ us.T).abs().max().item()
+        print("mode", k, "projector difference", dproj, flush=True)
+        assert dproj < 1e-4, (k, dproj)
