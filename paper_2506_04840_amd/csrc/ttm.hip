@@ -1236,7 +1236,8 @@ __global__ __launch_bounds__(256) void k_rc_rows(const typename Pol<MK>::T* __re
 // guarded loads; the full batches follow with unconditional ones. Waves past
 // the last tile work on the last tile (their loads stay in bounds and they
 // take part in the barriers) and write nothing. The small per-wave state
-// (two tiles) keeps three waves on each SIMD.
+// (two tiles) fits three waves on each SIMD, which the launch bound asks for
+// (without it the compiler took 172 registers, two waves).
 // WVEC: W contiguous along i (wsi = 1), a unit's 8 rows are two 16-byte loads.
 // ---------------------------------------------------------------------------
 constexpr int RCS_COLS = 32;  // output columns s per wave
@@ -1420,7 +1421,7 @@ __device__ __forceinline__ void rc_split_body(const float* __restrict__ X, const
 }
 
 template <int NP, int NJ, bool WVEC>
-__global__ __launch_bounds__(256) void k_rc_split(const float* __restrict__ X, const float* __restrict__ W, int64_t n,
+__global__ __launch_bounds__(256, 3) void k_rc_split(const float* __restrict__ X, const float* __restrict__ W, int64_t n,
                                                   int64_t S, int lw, int64_t wsi, int64_t wsj, int64_t tiles_per_p,
                                                   int64_t ntiles, float* __restrict__ out, int64_t osp, int64_t osj) {
   rc_split_body<NP, NJ, WVEC>(X, W, n, S, lw, wsi, wsj, tiles_per_p, ntiles, out, osp, osj, (int)blockIdx.x);
@@ -2693,7 +2694,9 @@ static hipError_t batch_ttm_nj(BatchKind kind, int* hdr, const void* desc, hipSt
     case BK_CR_SPLIT: TK_PERSIST_N(BCrSplit, b_cr_split<NJ>, 2, true);  // the split kernel's occupancy
     case BK_CR_COLS: TK_PERSIST(BCrCols, b_cr_cols<NJ>);
     case BK_REDUCE: TK_PERSIST(BReduce, b_reduce);
-    case BK_RC_SPLIT: TK_PERSIST(BRcSplit, b_rc_split<NJ>);  // short items: claiming costs more than it evens out
+    // three workgroups per CU as the one-request kernel; short items: claiming
+    // would cost more than it evens out
+    case BK_RC_SPLIT: TK_PERSIST_N(BRcSplit, b_rc_split<NJ>, 3, false);
     case BK_RC_COLS: TK_PERSIST(BRcCols, b_rc_cols<NJ>);
     default:
       return hipErrorInvalidValue;
