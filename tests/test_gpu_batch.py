@@ -225,3 +225,26 @@ def test_batch_sketch_uses_the_requests_omega(T, dims, ranks, lclass):
         dproj = (u @ u.T - us @ us.T).abs().max().item()
         print("mode", k, "projector difference", dproj, flush=True)
         assert dproj < 1e-4, (k, dproj)
+
+
+def test_same_plan_stepped_twice(T):
+    """The product phases claim their items from counters in the plan's table;
+    each step uploads the table again, so a second step of the same plan (its
+    outputs reset to NaN in between) gives bitwise the same results."""
+    reqs, tensors = _requests(6, seed=29, n_lo=40, n_hi=120)
+    solver = _solver(T, 8, 1 << 30)
+    outs, _ = _batch(T, solver, tensors, reqs, range(6))
+    solver.step()
+    torch.cuda.synchronize()
+    first = [(G.clone(), [u.clone() for u in U]) for G, U in outs]
+    for G, U in outs:
+        G.fill_(float("nan"))
+        for u in U:
+            u.fill_(float("nan"))
+    solver.step()
+    torch.cuda.synchronize()
+    for (G, U), (G1, U1) in zip(outs, first):
+        assert torch.isfinite(G1).all()
+        assert torch.equal(G, G1)
+        for a, b in zip(U, U1):
+            assert torch.equal(a, b)
