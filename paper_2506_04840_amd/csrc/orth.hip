@@ -587,7 +587,8 @@ __global__ __launch_bounds__(256) void k_pass(const double* Qin, int64_t n, int 
 
 // C = A B for 64-wide LDS matrices (full product; the zero triangles add
 // exact zeros), thread grid (ta, tb) owning C[ta + 16 i][tb + 16 j].
-__device__ __forceinline__ void tile_matmul(const double (*Am)[OR_LS], const double (*Bm)[OR_LS], int l,
+template <int LS>
+__device__ __forceinline__ void tile_matmul(const double (*Am)[LS], const double (*Bm)[LS], int l,
                                             double (&c)[4][4]) {
   const int ta = threadIdx.x >> 4, tb = threadIdx.x & 15;
 #pragma unroll
@@ -658,8 +659,14 @@ __device__ __forceinline__ void small_svd_body(const double* __restrict__ Rg, in
                                                    const double* __restrict__ alpha_prev, double* __restrict__ sig_hat,
                                                    int* __restrict__ stop, double* __restrict__ vright, int bid,
                                                    bool last = true) {
-  __shared__ double A[kMaxL][OR_LS];  // A[a][x] = column a of R^T = row a of R
-  __shared__ double J[kMaxL][OR_LS];  // J[a][x] = column a of the rotation
+  // Row stride of A and J: 72 doubles, 16 banks apart from row to row (of 32,
+  // or of 64), so the column pairs of a round, whose rows run consecutively
+  // through the circle, read and write their eight lanes' runs of row pa (and
+  // of row pb) in disjoint banks. With a stride of 65 they shared banks, and
+  // bank conflicts took about half of the kernel's LDS cycles.
+  constexpr int SV_LS = kMaxL + 8;
+  __shared__ double A[kMaxL][SV_LS];  // A[a][x] = column a of R^T = row a of R
+  __shared__ double J[kMaxL][SV_LS];  // J[a][x] = column a of the rotation
   __shared__ double sv[kMaxL];
   __shared__ int perm[kMaxL];
   __shared__ int rotf[3];
