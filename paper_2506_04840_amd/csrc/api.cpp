@@ -445,7 +445,7 @@ int mode_factor(const Plan& pl, int k, const void* X, int q, tucker_shift shift,
   const View3 v = pl.v[k];
   const int l = pl.l[k];
   const int64_t n = v.n, m = pl.m[k];
-  const int nsplit = colreduce_splits(v, l);
+  const int nsplit = colreduce_splits_for(v, l, prec);
   const OrthWs ows = carve_orth(w.orth, n, l);
   const uint64_t cseed = completion_seed(seed, k);
   double* alpha = w.alpha + k;
@@ -551,7 +551,7 @@ int mode_factor_pve(const Plan& pl, int k, const void* X, int q_max, double tol,
   const View3 v = pl.v[k];
   const int l = pl.l[k];
   const int64_t n = v.n, m = pl.m[k];
-  const int nsplit = colreduce_splits(v, l);
+  const int nsplit = colreduce_splits_for(v, l, prec);
   const OrthWs ows = carve_orth(w.orth, n, l);
   const uint64_t cseed = completion_seed(seed, k);
   double* alpha = w.alpha + k;
@@ -1215,7 +1215,7 @@ int tucker_sketch(const tucker_shape* shape, int32_t mode, const void* X, int64_
   const size_t need = op_ws_layout(v, m, (int)l, prec, nullptr, &w);
   if (ws == nullptr || ws_bytes < need) return fail(TUCKER_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
   op_ws_layout(v, m, (int)l, prec, (char*)ws, &w);
-  const int nsplit = colreduce_splits(v, (int)l);
+  const int nsplit = colreduce_splits_for(v, (int)l, prec);
   hipError_t e = launch_fill_gaussian(prec == TUCKER_FP64 ? TUCKER_FP64 : TUCKER_FP32, seed, (uint32_t)mode, 0, m,
                                       (int)l, true, w.omz, stream);
   if (e == hipSuccess) e = launch_colreduce(prec, v, X, w.omz, (int)l, w.part, nsplit, stream);
@@ -1241,7 +1241,7 @@ int tucker_shifted_power(const tucker_shape* shape, int32_t mode, const void* X,
   const size_t need = op_ws_layout(v, m, (int)l, prec, nullptr, &w);
   if (ws == nullptr || ws_bytes < need) return fail(TUCKER_EWORKSPACE, "workspace %zu < %zu", ws_bytes, need);
   op_ws_layout(v, m, (int)l, prec, (char*)ws, &w);
-  const int nsplit = colreduce_splits(v, (int)l);
+  const int nsplit = colreduce_splits_for(v, (int)l, prec);
   double* y = raw ? (double*)out : w.y64;
   hipError_t e;
   int ns_used = nsplit;

@@ -105,6 +105,7 @@ hipError_t launch_fill_omega(const OmegaSpec& sp, tucker_precision prec, uint64_
 // X_(k)[i, c] * B[c, j], B stored j-major as Bt[j * m + c] (m = P S).
 // Output type: double for FP64, float otherwise.
 int colreduce_splits(const View3& v, int l);
+int colreduce_splits_for(const View3& v, int l, tucker_precision prec);
 size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec);
 // npart (S > 1 only; ignored for S == 1): also ||X||_F^2 as colreduce_norm_slots
 // FP64 partial sums, one per workgroup, each over the elements that workgroup

@@ -845,6 +845,25 @@ int colreduce_splits(const View3& v, int l) {
   return colreduce_splits_prec(v, TUCKER_FP32);
 }
 
+// The split count a column reduction of this precision launches with. The
+// split kernel (FP32 products, S > 1) runs 128-row workgroups, two resident
+// per CU (512 on the 256 CUs): the rule above, made for 64-row workgroups,
+// gives it about 1.5 rounds of them, and the half-full last round costs a
+// quarter of the time. Here it takes the splits that fill one round (each at
+// least 8 stages; never more than the rule above, which sizes the workspace).
+int colreduce_splits_for(const View3& v, int l, tucker_precision prec) {
+  const int ns = colreduce_splits(v, l);
+  if (prec != TUCKER_FP32 || v.S == 1 || !fp32_split_products()) return ns;
+  constexpr int64_t kResident = 512;
+  int64_t nsteps, spp;
+  int nrb;
+  cr_split_geometry(v, &nsteps, &spp, &nrb);
+  int64_t t = std::max<int64_t>(1, kResident / nrb);
+  t = std::min<int64_t>(t, std::max<int64_t>(1, nsteps / 8));
+  if (t > 8) t = t / 8 * 8;
+  return (int)std::min<int64_t>(t, ns);
+}
+
 size_t colreduce_part_bytes(const View3& v, int l, tucker_precision prec) {
   const int ns = std::max(colreduce_splits_prec(v, prec), colreduce_splits_prec(v, TUCKER_FP32));
   const size_t b = (size_t)ns * (size_t)v.n * (size_t)l * elem_bytes(prec);
