@@ -851,9 +851,20 @@ int colreduce_splits(const View3& v, int l) {
 // gives it about 1.5 rounds of them, and the half-full last round costs a
 // quarter of the time. Here it takes the splits that fill one round (each at
 // least 8 stages; never more than the rule above, which sizes the workspace).
+// The BF16-operand kernel (64-row workgroups) holds four per CU at l <= 32
+// (128 registers) and two above: where the rule gives it between one and two
+// rounds, it takes one as well.
 int colreduce_splits_for(const View3& v, int l, tucker_precision prec) {
   const int ns = colreduce_splits(v, l);
-  if (prec != TUCKER_FP32 || v.S == 1 || !fp32_split_products()) return ns;
+  if (v.S == 1) return ns;
+  if (prec == TUCKER_BF16) {
+    const int64_t resident = l <= 32 ? 1024 : 512, nrb = (v.n + 63) / 64;
+    if ((int64_t)ns * nrb <= resident || (int64_t)ns * nrb >= 2 * resident) return ns;
+    int64_t t = std::max<int64_t>(1, resident / nrb);
+    if (t > 8) t = t / 8 * 8;
+    return (int)std::min<int64_t>(t, ns);
+  }
+  if (prec != TUCKER_FP32 || !fp32_split_products()) return ns;
   constexpr int64_t kResident = 512;
   int64_t nsteps, spp;
   int nrb;
